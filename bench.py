@@ -1,0 +1,220 @@
+#!/usr/bin/env python
+"""Benchmark of the RBFGS hot path on one MI355X.
+
+Workload: the ill-conditioned ridge Hessian A = B^T B / m + lam I (n = 16384,
+m = 32768, columns of the Gaussian B scaled log-uniformly in [1e-2, 1e2],
+lam = 1e-2), FP32 A resident in HBM, sketch size q = 256.  A step is one full
+RBFGS iteration (sketch, A S, G and its Cholesky-based inverse, X A S, the q x q
+products, the estimator and the symmetric rank-2q update of X).
+
+Prints ONE JSON line: iterations/s of the mixed-precision path (value), the FP64
+GPU path beside it, effective TFLOP/s from the algorithmic flop count, the
+roofline figure of the dominant kernel timed live with HIP events on the
+library's stream, and the FP64 CPU oracle timed on a bounded sample.
+
+    python bench.py [--steps K] [--warmup W] [--variant fixed|adaptive] [--sketch gauss|coord]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+FP64_PEAK_TFLOPS = 78.6
+
+
+def alg_flops(n, q, variant, sketch):
+    """Algorithmic flops of one iteration (products counted once, symmetric update on one triangle).
+
+    fixed/gauss: A S, X Y (2 n^2 q each), rank-2q update on n(n+1)/2 entries (2 n^2 q),
+                 G, H, S G^-1, U H (2 n q^2 each)
+    fixed/coord: X Y (2 n^2 q) and the row/column update (4 n q), H, G^-1 H, R = G^-1 W'^T
+    adaptive/gauss: L S~, A S, L^T Y, rank-q update of L (2 n^2 q each) + 4 panel products (2 n q^2)
+    adaptive/coord: A S, L^T Y, update (2 n^2 q each) + 2 panel products
+    """
+    n2q, nq2 = 2.0 * n * n * q, 2.0 * n * q * q
+    if variant == "fixed":
+        return 3 * n2q + 4 * nq2 if sketch == "gauss" else n2q + 2 * nq2 + 4.0 * n * q
+    return 4 * n2q + 4 * nq2 if sketch == "gauss" else 3 * n2q + 2 * nq2
+
+
+def phase_roofline(name, n, q, variant, sketch):
+    """(bound, algorithmic units per launch, unit) of one profiled phase.
+
+    Bytes count each HBM-resident n x n operand once (4 B/entry, FP32):
+      AS, XY, LS, LtY: read the n x n matrix once                    -> 4 n^2 B
+      update (fixed):  read the lower triangle of X, write all of X  -> 6 n^2 B
+      update (adaptive): read and write L                            -> 8 n^2 B
+    Their algorithmic intensity (2 n^2 q flops over these bytes) is below the
+    bf16 ridge point (2500 TFLOP/s / 8 TB/s = 312 flop/B) for q <= 256, so the
+    roofline that bounds them is HBM bandwidth.
+    """
+    nn = float(n) * n
+    if name in ("AS", "XY", "LS", "LtY"):
+        return "hbm", 4.0 * nn, "GB/s"
+    if name == "update":
+        return "hbm", (6.0 if variant == "fixed" else 8.0) * nn, "GB/s"
+    return None
+
+
+def make_A(n, seed, device):
+    from workloads import ridge_hessian
+    return ridge_hessian(n, seed, m=2 * n, lam=1e-2, device=device)
+
+
+def timed_steps(Solver, A_dev, q, seed, sketch, variant, precision, warmup, steps, torch):
+    s = Solver(A_dev, q, seed, sketch=sketch, variant=variant, precision=precision)
+    s.step(warmup)
+    s.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    s.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return s, (t1 - t0)
+
+
+def cpu_baseline(A32, q, seed, sketch, variant, steps):
+    """The FP64 oracle on the host: `steps` iterations from X_0 = I (or L_0 = I)."""
+    import numpy as np
+    from oracle import rbfgs as R, sketch as sk
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([p.get("num_threads", 1) for p in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        threads = os.cpu_count()
+    A = np.asarray(A32, dtype=np.float64)
+    n = A.shape[0]
+    kind = "cols" if sketch == "coord" else "gauss"
+    M = np.eye(n)
+    t0 = time.perf_counter()
+    for k in range(steps):
+        S = sk.sketch(seed, k, n, q, kind)
+        M = R.fixed_step(M, A, S) if variant == "fixed" else R.ada_step(M, A, S)
+    t = time.perf_counter() - t0
+    X = M if variant == "fixed" else M @ M.T
+    return steps / t, threads, X
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--q", type=int, default=256)
+    ap.add_argument("--seed", type=int, default=2016)
+    ap.add_argument("--variant", default="fixed", choices=["fixed", "adaptive"])
+    ap.add_argument("--sketch", default="gauss", choices=["gauss", "coord"])
+    ap.add_argument("--fp64-steps", type=int, default=8)
+    ap.add_argument("--profile-steps", type=int, default=10)
+    ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps for the CPU baseline (0: skip)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the sharded row-block "
+                                   "design is described, not built)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1602_01768_amd import rbfgs
+
+    dev = "cuda"
+    n, q = args.n, args.q
+    t_gen = time.perf_counter()
+    A32 = make_A(n, args.seed, dev)
+    t_gen = time.perf_counter() - t_gen
+    A_dev = torch.from_numpy(A32).to(dev)
+    A64_dev = A_dev.to(torch.float64)
+    torch.cuda.synchronize()
+
+    # ---- timed region: mixed precision
+    s_mixed, dt = timed_steps(rbfgs.Solver, A_dev, q, args.seed, args.sketch, args.variant, "mixed",
+                              args.warmup, args.steps, torch)
+    ips = args.steps / dt
+    flops = alg_flops(n, q, args.variant, args.sketch)
+
+    # ---- per-phase timing with HIP events on the library's stream (separate window)
+    s_mixed.profile(True)
+    s_mixed.step(args.profile_steps)
+    rep = s_mixed.profile_report()
+    s_mixed.profile(False)
+    phases = {k: {"avg_ms": v[0] / max(v[1], 1), "count": v[1]} for k, v in rep.items()}
+    dominant = max((k for k in rep if phase_roofline(k, n, q, args.variant, args.sketch)),
+                   key=lambda k: rep[k][0], default=None)
+    roof = None
+    if dominant:
+        bound, units, unit = phase_roofline(dominant, n, q, args.variant, args.sketch)
+        avg_s = rep[dominant][0] / rep[dominant][1] / 1e3
+        achieved = units / avg_s / 1e9
+        peak = HBM_PEAK_GBS
+        roof = {"bound": bound, "kernel": dominant, "achieved": round(achieved, 1), "peak": peak, "unit": unit,
+                "frac": round(achieved / peak, 4), "traffic": None, "avg_ms": round(avg_s * 1e3, 4),
+                "alg_bytes_per_launch": units}
+    s_mixed.close()
+
+    # ---- FP64 GPU path on the same matrix
+    s64, dt64 = timed_steps(rbfgs.Solver, A64_dev, q, args.seed, args.sketch, args.variant, "fp64", 1,
+                            args.fp64_steps, torch)
+    ips64 = args.fp64_steps / dt64
+    s64.close()
+    del A64_dev
+
+    # ---- CPU oracle baseline (bounded sample) and parity of the same steps
+    cpu = None
+    parity = None
+    if args.cpu_steps > 0:
+        cps, threads, Xo = cpu_baseline(A32, q, args.seed, args.sketch, args.variant, args.cpu_steps)
+        cpu = {"value": round(cps, 4), "unit": "iters/s", "cores": threads, "kind": "oracle",
+               "sample": f"{args.cpu_steps} FP64 oracle iterations from X_0 = I on the same A (n={n}, q={q})"}
+        for prec in ("mixed", "fp64"):
+            Ause = A_dev if prec == "mixed" else A_dev.to(torch.float64)
+            with rbfgs.Solver(Ause, q, args.seed, sketch=args.sketch, variant=args.variant, precision=prec) as s:
+                s.step(args.cpu_steps)
+                Xg = s.x().cpu().numpy()
+            err = float(np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo))
+            parity = parity or {}
+            parity[prec] = {"steps": args.cpu_steps, "rel_fro_err_vs_oracle": err}
+            del Xg
+
+    out = {
+        "metric": "RBFGS iters/s + TFLOP/s (n=16384,q=256) mixed vs FP64; p50/p99 solve latency",
+        "value": round(ips, 3),
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16-split/f32 (f64 q x q)",
+        "data": "synthetic",
+        "config": {"workload": f"ridge Hessian B^T B/m + 1e-2 I, n={n}, m={2 * n}, q={q}, "
+                               f"{args.variant} RBFGS, {args.sketch} sketch, seed={args.seed}",
+                   "n": n, "q": q, "variant": args.variant, "sketch": args.sketch, "precision": "mixed"},
+        "tflops_effective": round(flops * ips / 1e12, 3),
+        "alg_flops_per_step": flops,
+        "fp64": {"value": round(ips64, 3), "unit": "iters/s", "ms_per_step": round(dt64 / args.fp64_steps * 1e3, 3),
+                 "tflops_effective": round(flops * ips64 / 1e12, 3), "steps": args.fp64_steps},
+        "mixed_over_fp64_per_step": round(ips / ips64, 3),
+        "roofline": roof,
+        "phases_ms": {k: round(v["avg_ms"], 4) for k, v in phases.items()},
+        "cpu_baseline": cpu,
+        "parity": parity,
+        "input_gen_s": round(t_gen, 1),
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,186 @@
+/*
+ * rbfgs.h -- C ABI of an MI355X (gfx950) library for randomized block BFGS
+ * matrix inversion: Gower & Richtarik, "Randomized Quasi-Newton Updates are
+ * Linearly Convergent Matrix Inversion Algorithms" (arXiv 1602.01768).
+ *
+ * Problem (Sec. 4, inverse equation AX = I; Sec. 5, symmetric iterates): given a
+ * symmetric positive definite A in R^{n x n}, a sketch size q and a seed, return
+ * X ~ A^-1.  Two methods:
+ *
+ *   RBFGS_FIXED     randomized block BFGS, Sec. 8.7 eq. (qunac):
+ *                   X+ = S G^-1 S^T + (I - S G^-1 S^T A) X (I - A S G^-1 S^T),
+ *                   G = S^T A S, with a fresh i.i.d. sketch S every iteration.
+ *   RBFGS_ADAPTIVE  AdaRBFGS, Sec. 9.3 Alg. 4 / eq. (Cholimprov): X = L L^T,
+ *                   S = L S~ with S~ i.i.d.; L+ = L + S R (C S~^T - R^T S^T A L),
+ *                   R = L_G^-T (G = L_G L_G^T), C = L_M^-1 (S~^T S~ = L_M L_M^T).
+ *
+ * Sketch distributions (Sec. 10): RBFGS_SKETCH_GAUSS, S~ n x q with i.i.d.
+ * N(0,1) entries; RBFGS_SKETCH_COORD, q distinct coordinate vectors drawn
+ * uniformly.  Both come from a counter-based stream keyed by (seed, iteration),
+ * so a run is reproducible bit for bit and can be resumed from (X_k, k):
+ *   key = (seed, 0), counter = (block, k, kind, 0), Philox4x64-10;
+ *   gauss: entry e = j*n + i uses block e>>2, word e&3, Box-Muller pairs on
+ *          words (0,1), (2,3) with u = ((x>>11)+0.5) 2^-53, rounded to 8
+ *          significant bits (bfloat16 values) nearest-even;
+ *   coord: Floyd's algorithm with Lemire's bounded draws on the word stream,
+ *          indices sorted ascending.
+ *
+ * Starting point: X_0 = I, L_0 = I (the experiments' choice, Sec. 10).
+ *
+ * Precision (rbfgs_precision):
+ *   RBFGS_FP64   every step in FP64 on the GPU.
+ *   RBFGS_MIXED  A and X (or L) stored in FP32; the n x n x q contractions and
+ *                the n^2 update run on bf16 MFMA with FP32 accumulation, each
+ *                FP32 operand presented as a split bf16 pair (hi + lo; A as
+ *                hi + mid + lo when S is an exact bf16 matrix).  G = S^T A S, its
+ *                Cholesky factor and the q x q triangular inverses, and the
+ *                residual ||I - AX||_F are FP64.
+ *
+ * Conventions for every call:
+ *   - Matrices are dense, row-major with a leading dimension (for symmetric A
+ *     and X the distinction is moot; L is general and row-major).
+ *   - Device pointers are HIP device addresses on the context's device;
+ *     host pointers are ordinary host memory.
+ *   - No call allocates memory owned by the caller; outputs go to caller
+ *     buffers.  The context owns all of its device memory.
+ *   - Calls return an rbfgs_status; no C++ exception crosses the ABI.  Kernel
+ *     detected failures (G not positive definite, non-finite values) are
+ *     recorded on the device and returned by the next call that synchronises.
+ *   - A context is bound to the HIP stream given at creation and is not
+ *     thread safe; distinct contexts may be used from distinct threads.
+ *   - Results are deterministic: the same (A, params) on the same device and
+ *     build gives bitwise identical iterates.
+ */
+#ifndef RBFGS_H
+#define RBFGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rbfgs_ctx rbfgs_ctx;
+
+typedef enum {
+  RBFGS_OK = 0,
+  RBFGS_E_INVALID_ARG = 1,   /* bad size, pointer, enum, or A not symmetric/finite */
+  RBFGS_E_OOM = 2,           /* device allocation failed */
+  RBFGS_E_NOT_SPD = 3,       /* Cholesky of G = S^T A S (or S~^T S~) met a pivot <= 0 */
+  RBFGS_E_NONFINITE = 4,     /* NaN/Inf appeared in the iteration */
+  RBFGS_E_NOT_CONVERGED = 5, /* rbfgs_invert hit max_iters above tolerance */
+  RBFGS_E_DEVICE = 6         /* a HIP runtime call failed */
+} rbfgs_status;
+
+typedef enum { RBFGS_SKETCH_GAUSS = 0, RBFGS_SKETCH_COORD = 1 } rbfgs_sketch;
+typedef enum { RBFGS_FIXED = 0, RBFGS_ADAPTIVE = 1 } rbfgs_variant;
+typedef enum { RBFGS_FP64 = 0, RBFGS_MIXED = 1 } rbfgs_precision;
+typedef enum { RBFGS_F32 = 0, RBFGS_F64 = 1 } rbfgs_dtype;
+
+typedef struct {
+  int64_t n;            /* matrix order, n >= 1 */
+  int32_t q;            /* sketch size, 1 <= q <= min(n, 1024) */
+  uint64_t seed;        /* sketch stream key */
+  int32_t sketch;       /* rbfgs_sketch */
+  int32_t variant;      /* rbfgs_variant */
+  int32_t precision;    /* rbfgs_precision */
+  int32_t check_every;  /* rbfgs_invert: iterations between estimator reads (>= 1; 0 = 16) */
+} rbfgs_params;
+
+/* Create a context: validate params, copy A into library-owned device memory
+ * (converted to FP32 in mixed mode, FP64 in FP64 mode), set X_0 = I (L_0 = I).
+ *   A          n x n matrix, row-major, leading dimension lda >= n, element type
+ *              a_dtype; host memory if a_on_device == 0, else device memory.
+ *              Must be symmetric (checked exactly on the stored type) and
+ *              finite; positive definiteness is detected during iteration.
+ *   hip_stream hipStream_t to run on (NULL = the default stream).
+ *   out        receives the context; set to NULL on failure.
+ * Errors: E_INVALID_ARG (sizes, NULL pointers, asymmetric or non-finite A),
+ *         E_OOM, E_DEVICE. */
+rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_dtype,
+                          int64_t lda, int32_t a_on_device, void* hip_stream,
+                          rbfgs_ctx** out);
+
+/* Enqueue `nsteps` iterations k -> k+1 (Alg. 3 with W = A^-1, or Alg. 4) on the
+ * context's stream.  Asynchronous: returns once the work is enqueued; a
+ * device-side failure of these steps is returned by the next synchronising
+ * call (rbfgs_sync, rbfgs_invert, rbfgs_residual, rbfgs_get_x).  After such a
+ * failure the iterate is undefined: call rbfgs_set_state or re-create. */
+rbfgs_status rbfgs_step(rbfgs_ctx* ctx, int64_t nsteps);
+
+/* Wait for enqueued work; return the first device-side failure, if any. */
+rbfgs_status rbfgs_sync(rbfgs_ctx* ctx);
+
+/* Iterate until ||I - A X_k||_F / sqrt(n) <= tol or max_iters total iterations
+ * (Sec. 10 stops on a residual threshold).  Every check_every iterations the
+ * per-step unbiased estimate of ||I - X A||_F^2 (from S - X A S, no extra
+ * products; for the adaptive method it estimates ||I - L^T A L||_F^2) is read;
+ * when it falls below (tol^2 n) the exact FP64 residual is computed and decides.
+ * iters_out: iterations performed by this call; resid_out: last exact
+ * ||I - AX||_F / sqrt(n) (NaN if never computed).  Either may be NULL.
+ * Returns OK on convergence, E_NOT_CONVERGED at max_iters, or a device error. */
+rbfgs_status rbfgs_invert(rbfgs_ctx* ctx, double tol, int64_t max_iters,
+                          int64_t* iters_out, double* resid_out);
+
+/* Exact ||I - A X_k||_F (unnormalised) in FP64 on the device (X = L L^T for the
+ * adaptive method); synchronises. */
+rbfgs_status rbfgs_residual(rbfgs_ctx* ctx, double* fro_out);
+
+/* Last per-step estimator value sum||S - XAS||^2 scaled to estimate ||I-XA||_F^2
+ * (gauss: /q, coord: *n/q); synchronises. NaN before the first step. */
+rbfgs_status rbfgs_estimate(rbfgs_ctx* ctx, double* est_out);
+
+/* Copy X_k (X = L L^T formed in FP64 for the adaptive method) into X, row-major,
+ * leading dimension ldx >= n, element type x_dtype, host or device memory.
+ * Synchronises. */
+rbfgs_status rbfgs_get_x(rbfgs_ctx* ctx, void* X, int32_t x_dtype, int64_t ldx,
+                         int32_t on_device);
+
+/* Copy the factor L_k of the adaptive method (E_INVALID_ARG for the fixed one). */
+rbfgs_status rbfgs_get_l(rbfgs_ctx* ctx, void* L, int32_t l_dtype, int64_t ldl,
+                         int32_t on_device);
+
+/* Replace the state by (M, k): M is X_k for the fixed method, L_k for the
+ * adaptive one (row-major, leading dimension ldm, element type m_dtype, host
+ * or device).  Used for checkpoint/resume: the sketch of iteration k depends
+ * only on (seed, k), so resuming reproduces the uninterrupted run. */
+rbfgs_status rbfgs_set_state(rbfgs_ctx* ctx, const void* M, int32_t m_dtype, int64_t ldm,
+                             int32_t on_device, int64_t k);
+
+/* Iterations performed so far (k of X_k). */
+rbfgs_status rbfgs_get_iter(const rbfgs_ctx* ctx, int64_t* k_out);
+
+/* Release all device memory of the context (waits for its stream). NULL is a no-op. */
+void rbfgs_destroy(rbfgs_ctx* ctx);
+
+/* Human-readable description of the last error on ctx ("" if none).  The
+ * string is owned by the context and valid until the next call on it. */
+const char* rbfgs_last_error(const rbfgs_ctx* ctx);
+
+/* ---- timing of the iteration's phases (tracing aid) ----
+ * rbfgs_profile: enable (1) or disable (0) per-phase timing of subsequent
+ * iterations with HIP events recorded on the context's stream, and clear the
+ * accumulated totals.  Phases: sketch, gather, AS, LS, gram_G, chol_inv, XY,
+ * LtY, gram_H, estimator, panels, coord_update, update.
+ * rbfgs_profile_report: synchronise and write a JSON object
+ * {"phase": [total_ms, count], ...} (NUL-terminated) into buf of buflen bytes;
+ * E_INVALID_ARG if it does not fit. */
+rbfgs_status rbfgs_profile(rbfgs_ctx* ctx, int32_t enable);
+rbfgs_status rbfgs_profile_report(rbfgs_ctx* ctx, char* buf, int64_t buflen);
+
+/* ---- sketch stream (Sec. 10 sketch distributions), for testing and reuse ----
+ * Write the iteration-k sketch of the stream (seed) to device memory on `hip_stream`.
+ *   rbfgs_sketch_gauss: S n x q column-major (entry (i,j) at S[j*n + i]) as
+ *                       float (dtype F32) or double (F64); values are bfloat16.
+ *   rbfgs_sketch_coord: q sorted distinct int32 indices in [0, n).
+ * Asynchronous; E_INVALID_ARG for bad sizes/pointers. */
+rbfgs_status rbfgs_sketch_gauss(uint64_t seed, int64_t k, int64_t n, int32_t q,
+                                void* S_dev, int32_t dtype, void* hip_stream);
+rbfgs_status rbfgs_sketch_coord(uint64_t seed, int64_t k, int64_t n, int32_t q,
+                                int32_t* idx_dev, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBFGS_H */

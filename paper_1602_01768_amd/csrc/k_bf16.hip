@@ -1,0 +1,385 @@
+// Mixed-precision GEMM on gfx950 bf16 MFMA (v_mfma_f32_32x32x16_bf16) with FP32
+// accumulation.  Each FP32 operand is presented to the matrix cores as a sum of
+// bf16 pieces (hi + lo, or hi + mid + lo), and the product is the sum of the piece
+// products whose combined weight is at least 2^-(8*pmax): for two 2-piece operands
+// hi*hi + hi*lo + lo*hi (3 passes); for a 3-piece operand times an exact bf16
+// matrix all 3 passes are exact.
+#include <algorithm>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rb {
+
+namespace {
+
+constexpr int BK = 32;
+constexpr int PITCH = BK + 8;  // bf16 elements per LDS row (80 bytes)
+
+template <int NP>
+RB_DEV void split_n(float x, __bf16 (&o)[NP]) {
+  if constexpr (NP == 1) {
+    o[0] = f2bf(x);
+  } else if constexpr (NP == 2) {
+    split2(x, o[0], o[1]);
+  } else {
+    split3(x, o[0], o[1], o[2]);
+  }
+}
+
+RB_DEV void tri_index32(int64_t t, int64_t& ti, int64_t& tj) {
+  int64_t i = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (i * (i + 1) / 2 > t) --i;
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  ti = i;
+  tj = t - i * (i + 1) / 2;
+}
+
+// Loader for one operand tile of ROWS (m or n) x BK into LDS planes [NP][ROWS][PITCH].
+template <int ROWS, int NP, int KIND>
+struct TileLoader {
+  // registers held between the global load and the LDS store
+  static constexpr int F4 = (KIND == OK_BF16_KC) ? 1 : ROWS * BK / 4 / 256;     // float4 per thread
+  static constexpr int V8 = (KIND == OK_BF16_KC) ? (ROWS * 4 + 255) / 256 : 1;  // 16-byte chunks per plane
+  float4 f[F4 > 0 ? F4 : 1];
+  bf16x8 h[NP][V8];
+
+  RB_DEV void load(const void* base, int64_t ld, int64_t plane, int64_t r0, int64_t k0, int tid) {
+    if constexpr (KIND == OK_F32_KC) {
+      const float* A = (const float*)base;
+#pragma unroll
+      for (int i = 0; i < F4; ++i) {
+        const int e = tid + 256 * i;
+        const int row = e >> 3, c4 = (e & 7) * 4;
+        f[i] = *(const float4*)(A + (r0 + row) * ld + k0 + c4);
+      }
+    } else if constexpr (KIND == OK_F32_MC) {
+      const float* A = (const float*)base;
+#pragma unroll
+      for (int i = 0; i < F4; ++i) {
+        const int e = tid + 256 * i;
+        const int kk = e / (ROWS / 4), m4 = (e % (ROWS / 4)) * 4;
+        f[i] = *(const float4*)(A + (k0 + kk) * ld + r0 + m4);
+      }
+    } else {
+      const __bf16* A = (const __bf16*)base;
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int i = 0; i < V8; ++i) {
+          const int e = tid + 256 * i;
+          if (e < ROWS * 4) {
+            const int row = e >> 2, c8 = (e & 3) * 8;
+            h[p][i] = *(const bf16x8*)(A + p * plane + (r0 + row) * ld + k0 + c8);
+          }
+        }
+    }
+  }
+
+  RB_DEV void store(__bf16* lds, int tid) {
+    if constexpr (KIND == OK_F32_KC) {
+#pragma unroll
+      for (int i = 0; i < F4; ++i) {
+        const int e = tid + 256 * i;
+        const int row = e >> 3, c4 = (e & 7) * 4;
+        __bf16 p0[NP], p1[NP], p2[NP], p3[NP];
+        split_n<NP>(f[i].x, p0);
+        split_n<NP>(f[i].y, p1);
+        split_n<NP>(f[i].z, p2);
+        split_n<NP>(f[i].w, p3);
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+          bf16x4 v = {p0[p], p1[p], p2[p], p3[p]};
+          *(bf16x4*)(lds + (p * ROWS + row) * PITCH + c4) = v;
+        }
+      }
+    } else if constexpr (KIND == OK_F32_MC) {
+#pragma unroll
+      for (int i = 0; i < F4; ++i) {
+        const int e = tid + 256 * i;
+        const int kk = e / (ROWS / 4), m4 = (e % (ROWS / 4)) * 4;
+        const float vals[4] = {f[i].x, f[i].y, f[i].z, f[i].w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          __bf16 pc[NP];
+          split_n<NP>(vals[j], pc);
+#pragma unroll
+          for (int p = 0; p < NP; ++p) lds[(p * ROWS + m4 + j) * PITCH + kk] = pc[p];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < NP; ++p)
+#pragma unroll
+        for (int i = 0; i < V8; ++i) {
+          const int e = tid + 256 * i;
+          if (e < ROWS * 4) {
+            const int row = e >> 2, c8 = (e & 3) * 8;
+            *(bf16x8*)(lds + (p * ROWS + row) * PITCH + c8) = h[p][i];
+          }
+        }
+    }
+  }
+};
+
+// 256 threads = 4 waves as WAVES_M x (4 / WAVES_M); wave tile WM x WN of 32 x 32 blocks.
+// v_mfma_f32_32x32x16_bf16: lane l holds A(l%32, 8*(l/32) .. +7), B(8*(l/32) .. +7, l%32);
+// output column l%32, rows 8*(r/4) + 4*(l/32) + r%4 for r = 0..15.
+template <int BM, int BN, int WAVES_M, int NA, int NB, int PMAX, int AK, int BKD>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  constexpr int WAVES_N = 4 / WAVES_M;
+  constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
+  constexpr int FM = WM / 32, FN = WN / 32;
+  constexpr int LOOP_E = (NA * BM + NB * BN) * PITCH;                 // bf16 elements
+  constexpr int EPI_E = 2 * 4 * 32 * (WM + 1);                       // floats as bf16 pairs
+  constexpr int SM = LOOP_E > EPI_E ? LOOP_E : EPI_E;
+  __shared__ __attribute__((aligned(16))) __bf16 smem[SM];
+  __bf16* As = smem;
+  __bf16* Bs = smem + NA * BM * PITCH;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+  const int64_t MT = g.M / BM;
+  int64_t mt, nt;
+  int kc = 0;
+  bool diag = false;
+  const int64_t bid = blockIdx.x;
+  if (g.epi == EPI_SYMUPD) {
+    tri_index32(bid, mt, nt);
+    diag = (mt == nt);
+  } else {
+    kc = (int)(bid % g.splitk);
+    const int64_t r = bid / g.splitk;
+    mt = r % MT;
+    nt = r / MT;
+  }
+  const int64_t kchunk = g.K / g.splitk;
+  const int64_t kbeg = kc * kchunk, kend = kbeg + kchunk;
+  const int64_t m0 = mt * BM, n0 = nt * BN;
+
+  TileLoader<BM, NA, AK> la;
+  TileLoader<BN, NB, BKD> lb;
+
+  f32x16 acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+
+  la.load(g.A, g.lda, g.a_plane, m0, kbeg, tid);
+  lb.load(g.B, g.ldb, g.b_plane, n0, kbeg, tid);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    __syncthreads();
+    la.store(As, tid);
+    lb.store(Bs, tid);
+    __syncthreads();
+    if (k0 + BK < kend) {
+      la.load(g.A, g.lda, g.a_plane, m0, k0 + BK, tid);
+      lb.load(g.B, g.ldb, g.b_plane, n0, k0 + BK, tid);
+    }
+#pragma unroll
+    for (int s = 0; s < BK / 16; ++s) {
+      const int kofs = s * 16 + 8 * (lane >> 5);
+      bf16x8 av[NA][FM], bv[NB][FN];
+#pragma unroll
+      for (int p = 0; p < NA; ++p)
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+          av[p][a] = *(const bf16x8*)(As + (p * BM + wm * WM + a * 32 + (lane & 31)) * PITCH + kofs);
+#pragma unroll
+      for (int p = 0; p < NB; ++p)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+          bv[p][b] = *(const bf16x8*)(Bs + (p * BN + wn * WN + b * 32 + (lane & 31)) * PITCH + kofs);
+      // smallest pieces first
+#pragma unroll
+      for (int lvl = PMAX; lvl >= 0; --lvl)
+#pragma unroll
+        for (int pa = 0; pa < NA; ++pa) {
+          const int pb = lvl - pa;
+          if (pb < 0 || pb >= NB) continue;
+#pragma unroll
+          for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b)
+              acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[pa][a], bv[pb][b], acc[a][b], 0, 0, 0);
+        }
+    }
+  }
+
+  // ---------------------------------------------------------------- epilogue
+  const int lr = (lane >> 5) * 4, lc = lane & 31;
+  if (g.epi == EPI_SYMUPD) {
+    __syncthreads();
+    float* R = (float*)smem + wave * 32 * (WM + 1);
+    float* X = (float*)g.C;
+    const float c2 = (float)g.c2;
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+      const int64_t nb = n0 + wn * WN + b * 32;
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int ml = a * 32 + (r >> 2) * 8 + lr + (r & 3);
+          const int64_t m = m0 + wm * WM + ml, n = nb + lc;
+          const int64_t idx = m * g.ldc + n;
+          const float nv = X[idx] + c2 * acc[a][b][r];
+          if (!diag || m >= n) X[idx] = nv;
+          R[lc * (WM + 1) + ml] = nv;
+        }
+      __syncthreads();
+      if (lane < WM) {
+        const int64_t mrow = m0 + wm * WM + lane;
+#pragma unroll 4
+        for (int c = 0; c < 32; ++c) {
+          const int64_t ncol = nb + c;
+          if (!diag || mrow > ncol) X[ncol * g.ldc + mrow] = R[c * (WM + 1) + lane];
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t m = m0 + wm * WM + a * 32 + (r >> 2) * 8 + lr + (r & 3);
+        const int64_t n = n0 + wn * WN + b * 32 + lc;
+        const float v = acc[a][b][r];
+        if (g.epi == EPI_PARTIAL) {
+          ((float*)g.C)[(int64_t)kc * g.M * g.N + n * g.M + m] = v;
+        } else if (g.epi == EPI_ADDROW) {
+          float* C = (float*)g.C;
+          const int64_t idx = m * g.ldc + n;
+          C[idx] = C[idx] + (float)g.c2 * v;
+        }
+      }
+}
+
+__global__ void k_reduce_partials_f32(GemmArgs g, const float* P) {
+  const int64_t MN = g.M * g.N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MN; e += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0;
+    for (int k = 0; k < g.splitk; ++k) s += (double)P[(int64_t)k * MN + e];
+    const int64_t m = e % g.M, n = e / g.M;
+    double o = g.c2 * s;
+    if (g.B0) o += g.c0 * (double)((const float*)g.B0)[m + n * g.ld01];
+    ((float*)g.C)[m + n * g.ldc] = (float)o;
+  }
+}
+
+// Column-major FP32 panel -> row-major bf16 hi/lo planes, through a 32 x 64 LDS tile.
+__global__ void k_pack_split2(const float* in, int64_t ld_in, int64_t rows, int64_t cols, __bf16* hi, __bf16* lo,
+                              int64_t ld_out, int64_t col_off) {
+  __shared__ float t[32][65];
+  const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 256 threads: 64 x 4
+  for (int c = ty; c < 32; c += 4) {
+    const int64_t r = r0 + tx, cc = c0 + c;
+    t[c][tx] = (r < rows && cc < cols) ? in[r + cc * ld_in] : 0.0f;
+  }
+  __syncthreads();
+  const int cx = threadIdx.x & 31, ry = threadIdx.x >> 5;  // 32 x 8
+  for (int r = ry; r < 64; r += 8) {
+    const int64_t rr = r0 + r, cc = c0 + cx;
+    if (rr < rows && cc < cols) {
+      __bf16 h, l;
+      split2(t[cx][r], h, l);
+      hi[rr * ld_out + col_off + cc] = h;
+      lo[rr * ld_out + col_off + cc] = l;
+    }
+  }
+}
+
+template <int BN, int WAVES_M, int NA, int NB, int PMAX, int AK, int BKD>
+void launch_ts(const GemmArgs& g, int64_t blocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_gemm_bf16<128, BN, WAVES_M, NA, NB, PMAX, AK, BKD>), dim3(blocks), dim3(256), 0, s, g);
+}
+
+template <int NA, int NB, int PMAX, int AK, int BKD>
+hipError_t launch_tall(const GemmArgs& g, int bn, int64_t blocks, hipStream_t s) {
+  switch (bn) {
+    case 256: launch_ts<256, 2, NA, NB, PMAX, AK, BKD>(g, blocks, s); break;
+    case 128: launch_ts<128, 2, NA, NB, PMAX, AK, BKD>(g, blocks, s); break;
+    case 64: launch_ts<64, 2, NA, NB, PMAX, AK, BKD>(g, blocks, s); break;
+    default: launch_ts<32, 4, NA, NB, PMAX, AK, BKD>(g, blocks, s); break;
+  }
+  return hipGetLastError();
+}
+
+int pick_bn(int64_t N) {
+  if (N % 256 == 0) return 256;
+  if (N % 128 == 0) return 128;
+  if (N % 64 == 0) return 64;
+  return 32;
+}
+
+}  // namespace
+
+int64_t gemm_bf16_blocks(const MixedGemm& mg) {
+  const GemmArgs& g = mg.g;
+  if (g.epi == EPI_SYMUPD) {
+    const int64_t T = g.M / 128;
+    return T * (T + 1) / 2;
+  }
+  if (g.epi == EPI_ADDROW) return (g.M / 128) * (g.N / 128);
+  return (g.M / 128) * (g.N / pick_bn(g.N)) * g.splitk;
+}
+
+hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
+  const GemmArgs& g = mg.g;
+  if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipSuccess;
+  if (g.M % 128 || g.N % 32 || g.splitk < 1 || g.K % ((int64_t)BK * g.splitk)) return hipErrorInvalidValue;
+  if (g.epi == EPI_SYMUPD || g.epi == EPI_ADDROW) {
+    if (g.N % 128 || mg.a_kind != OK_BF16_KC || mg.b_kind != OK_BF16_KC || mg.na != 2 || mg.nb != 2 ||
+        mg.pmax != 1 || g.splitk != 1)
+      return hipErrorInvalidValue;
+    if (g.epi == EPI_SYMUPD && g.M != g.N) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC>), dim3(gemm_bf16_blocks(mg)),
+                       dim3(256), 0, s, g);
+    return hipGetLastError();
+  }
+  if (g.epi != EPI_COLSTORE || !partial_ws) return hipErrorInvalidValue;
+  GemmArgs run = g;
+  run.epi = EPI_PARTIAL;
+  run.C = partial_ws;
+  const int bn = pick_bn(g.N);
+  const int64_t blocks = gemm_bf16_blocks(mg);
+  hipError_t e;
+#define RB_TALL(NA_, NB_, PM_, AK_, BK_)                                                               \
+  if (mg.na == NA_ && mg.nb == NB_ && mg.pmax == PM_ && mg.a_kind == AK_ && mg.b_kind == BK_)         \
+    e = launch_tall<NA_, NB_, PM_, AK_, BK_>(run, bn, blocks, s);                                     \
+  else
+  RB_TALL(3, 1, 2, OK_F32_KC, OK_BF16_KC)  // A S with an exact bf16 sketch, L S~
+  RB_TALL(2, 2, 1, OK_F32_KC, OK_F32_KC)   // X Y
+  RB_TALL(3, 2, 2, OK_F32_KC, OK_F32_KC)   // A S with S = L S~ (FP32)
+  RB_TALL(2, 3, 2, OK_F32_MC, OK_F32_KC)   // L^T Y
+  RB_TALL(3, 3, 2, OK_F32_KC, OK_F32_KC)
+  RB_TALL(2, 2, 1, OK_F32_MC, OK_F32_KC)
+  return hipErrorInvalidValue;
+#undef RB_TALL
+  if (e != hipSuccess) return e;
+  return reduce_partials_f32(g, (const float*)partial_ws, s);
+}
+
+hipError_t reduce_partials_f32(const GemmArgs& g, const float* P, hipStream_t s) {
+  const int64_t MN = g.M * g.N;
+  const int64_t blocks = std::min<int64_t>((MN + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_reduce_partials_f32, dim3(blocks), dim3(256), 0, s, g, P);
+  return hipGetLastError();
+}
+
+hipError_t pack_split2(const float* in, int64_t ld_in, int64_t rows, int64_t cols, __bf16* hi, __bf16* lo,
+                       int64_t ld_out, int64_t col_off, hipStream_t s) {
+  dim3 grid((unsigned)ceil_div(rows, 64), (unsigned)ceil_div(cols, 32));
+  hipLaunchKernelGGL(k_pack_split2, grid, dim3(256), 0, s, in, ld_in, rows, cols, hi, lo, ld_out, col_off);
+  return hipGetLastError();
+}
+
+}  // namespace rb

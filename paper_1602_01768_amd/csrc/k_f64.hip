@@ -1,0 +1,660 @@
+// FP64 kernels: tiled FP64-MFMA GEMM with epilogues, the q x q Cholesky-based
+// inverse, gathers, the per-step estimator and small elementwise kernels.
+#include <math.h>
+
+#include <algorithm>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rb {
+
+RB_DEV double load_any(const void* p, int dt, int64_t i) {
+  if (dt == DT_F32) return (double)((const float*)p)[i];
+  if (dt == DT_BF16) return (double)(float)((const __bf16*)p)[i];
+  return ((const double*)p)[i];
+}
+RB_DEV void store_any(void* p, int dt, int64_t i, double v) {
+  if (dt == DT_F32) ((float*)p)[i] = (float)v;
+  else ((double*)p)[i] = v;
+}
+RB_DEV double round_to(int dt, double v) { return dt == DT_F32 ? (double)(float)v : v; }
+
+// Lower-triangular tile index t -> (ti, tj), ti >= tj, row by row.
+RB_DEV void tri_index(int64_t t, int64_t& ti, int64_t& tj) {
+  int64_t i = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while (i * (i + 1) / 2 > t) --i;
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  ti = i;
+  tj = t - i * (i + 1) / 2;
+}
+
+// Block-wide sum of one double per thread (blockDim = 256); result valid in thread 0.
+RB_DEV double block_sum_256(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0) s = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  return s;
+}
+
+// ------------------------------------------------------------------ GEMM
+// 256 threads, 4 waves as 2 x 2; wave tile (BM/2) x (BN/2) of 16 x 16 MFMA blocks
+// (v_mfma_f64_16x16x4f64: lane l holds A(l%16, l/16), B(l/16, l%16) and the
+// output column l%16, rows l/16 + 4r).  BK = 16 staged through LDS with a
+// one-tile register prefetch.
+template <int BM, int BN, bool AKC, bool BKC>
+__global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
+  constexpr int BK = 16;
+  constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+  constexpr int AP = BM * BK / 256, BP = BN * BK / 256;
+  constexpr int LOOP_D = BK * (BM + 1) + BK * (BN + 1);
+  constexpr int EPI_D = 4 * 16 * (WM + 1);
+  constexpr int SM = LOOP_D > EPI_D ? LOOP_D : EPI_D;
+  __shared__ double smem[SM];
+  double* As = smem;
+  double* Bs = smem + BK * (BM + 1);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int64_t MT = g.M / BM;
+  int64_t mt, nt;
+  int kc = 0;
+  bool diag = false;
+  const int64_t bid = blockIdx.x;
+  if (g.epi == EPI_SYMUPD) {
+    tri_index(bid, mt, nt);
+    diag = (mt == nt);
+  } else {
+    kc = (int)(bid % g.splitk);
+    const int64_t r = bid / g.splitk;
+    mt = r % MT;
+    nt = r / MT;
+  }
+  const int64_t kchunk = g.K / g.splitk;
+  const int64_t kbeg = kc * kchunk, kend = kbeg + kchunk;
+  const int64_t m0 = mt * BM, n0 = nt * BN;
+
+  double ra[AP], rbv[BP];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < AP; ++i) {
+      const int e = tid + 256 * i;
+      int mm, kk;
+      if (AKC) { mm = e / BK; kk = e % BK; ra[i] = load_any(g.A, g.a_dt, (m0 + mm) * g.lda + k0 + kk); }
+      else { kk = e / BM; mm = e % BM; ra[i] = load_any(g.A, g.a_dt, (k0 + kk) * g.lda + m0 + mm); }
+    }
+#pragma unroll
+    for (int i = 0; i < BP; ++i) {
+      const int e = tid + 256 * i;
+      int nn, kk;
+      if (BKC) { nn = e / BK; kk = e % BK; rbv[i] = load_any(g.B, g.b_dt, (n0 + nn) * g.ldb + k0 + kk); }
+      else { kk = e / BN; nn = e % BN; rbv[i] = load_any(g.B, g.b_dt, (k0 + kk) * g.ldb + n0 + nn); }
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int i = 0; i < AP; ++i) {
+      const int e = tid + 256 * i;
+      const int mm = AKC ? e / BK : e % BM, kk = AKC ? e % BK : e / BM;
+      As[kk * (BM + 1) + mm] = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < BP; ++i) {
+      const int e = tid + 256 * i;
+      const int nn = BKC ? e / BK : e % BN, kk = BKC ? e % BK : e / BN;
+      Bs[kk * (BN + 1) + nn] = rbv[i];
+    }
+  };
+
+  f64x4 acc[FM][FN];
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
+
+  gload(kbeg);
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+    __syncthreads();
+    sstore();
+    __syncthreads();
+    if (k0 + BK < kend) gload(k0 + BK);
+#pragma unroll
+    for (int k4 = 0; k4 < BK / 4; ++k4) {
+      const int kr = k4 * 4 + (lane >> 4);
+      double av[FM], bv[FN];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) av[a] = As[kr * (BM + 1) + wm * WM + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < FN; ++b) bv[b] = Bs[kr * (BN + 1) + wn * WN + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+  }
+
+  // ---------------------------------------------------------------- epilogue
+  const int lr = lane >> 4, lc = lane & 15;
+  if (g.epi == EPI_RESID) {
+    double s = 0;
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t m = m0 + wm * WM + a * 16 + lr + 4 * r, n = n0 + wn * WN + b * 16 + lc;
+          if (m < g.nvalid && n < g.nvalid) {
+            const double d = (m == n ? 1.0 : 0.0) - acc[a][b][r];
+            s += d * d;
+          }
+        }
+    __syncthreads();
+    const double t = block_sum_256(s, smem);
+    if (tid == 0) g.red[bid] = t;
+    return;
+  }
+  if (g.epi == EPI_SYMUPD) {
+    __syncthreads();
+    double* R = smem + wave * 16 * (WM + 1);
+#pragma unroll
+    for (int b = 0; b < FN; ++b) {
+      const int64_t nb = n0 + wn * WN + b * 16;
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int ml = a * 16 + lr + 4 * r;
+          const int64_t m = m0 + wm * WM + ml, n = nb + lc;
+          const int64_t idx = m * g.ldc + n;
+          const double nv = round_to(g.c_dt, load_any(g.C, g.c_dt, idx) + g.c2 * acc[a][b][r]);
+          if (!diag || m >= n) store_any(g.C, g.c_dt, idx, nv);
+          R[lc * (WM + 1) + ml] = nv;
+        }
+      __syncthreads();
+      if (lane < WM) {
+        const int64_t mrow = m0 + wm * WM + lane;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const int64_t ncol = nb + c;
+          if (!diag || mrow > ncol) store_any(g.C, g.c_dt, ncol * g.ldc + mrow, R[c * (WM + 1) + lane]);
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < FM; ++a)
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + wm * WM + a * 16 + lr + 4 * r, n = n0 + wn * WN + b * 16 + lc;
+        const double v = acc[a][b][r];
+        switch (g.epi) {
+          case EPI_PARTIAL:
+            ((double*)g.C)[(int64_t)kc * g.M * g.N + n * g.M + m] = v;
+            break;
+          case EPI_COLSTORE: {
+            double o = g.c2 * v;
+            if (g.B0) o += g.c0 * load_any(g.B0, g.b0_dt, m + n * g.ld01);
+            if (g.B1) o += g.c1 * load_any(g.B1, g.b1_dt, m + n * g.ld01);
+            store_any(g.C, g.c_dt, m + n * g.ldc, o);
+          } break;
+          case EPI_ADDROW: {
+            const int64_t idx = m * g.ldc + n;
+            store_any(g.C, g.c_dt, idx, load_any(g.C, g.c_dt, idx) + g.c2 * v);
+          } break;
+          case EPI_ROWSTORE:
+            store_any(g.C, g.c_dt, m * g.ldc + n, g.c2 * v);
+            break;
+        }
+      }
+}
+
+__global__ void k_reduce_partials_f64(GemmArgs g, const double* P) {
+  const int64_t MN = g.M * g.N;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MN; e += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0;
+    for (int k = 0; k < g.splitk; ++k) s += P[(int64_t)k * MN + e];
+    const int64_t m = e % g.M, n = e / g.M;
+    double o = g.c2 * s;
+    if (g.B0) o += g.c0 * load_any(g.B0, g.b0_dt, m + n * g.ld01);
+    if (g.B1) o += g.c1 * load_any(g.B1, g.b1_dt, m + n * g.ld01);
+    store_any(g.C, g.c_dt, m + n * g.ldc, o);
+  }
+}
+
+static int pick_tile(int64_t x) { return (x % 128 == 0) ? 128 : 32; }
+
+int64_t gemm_f64_blocks(const GemmArgs& g) {
+  const int BM = pick_tile(g.M), BN = pick_tile(g.N);
+  if (g.epi == EPI_SYMUPD) {
+    const int64_t T = g.M / BM;
+    return T * (T + 1) / 2;
+  }
+  return (g.M / BM) * (g.N / BN) * g.splitk;
+}
+
+template <int BM, int BN>
+static void launch_f64(const GemmArgs& g, int64_t blocks, hipStream_t s) {
+  if (g.a_kc && g.b_kc) hipLaunchKernelGGL((k_gemm_f64<BM, BN, true, true>), dim3(blocks), dim3(256), 0, s, g);
+  else if (g.a_kc) hipLaunchKernelGGL((k_gemm_f64<BM, BN, true, false>), dim3(blocks), dim3(256), 0, s, g);
+  else if (g.b_kc) hipLaunchKernelGGL((k_gemm_f64<BM, BN, false, true>), dim3(blocks), dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((k_gemm_f64<BM, BN, false, false>), dim3(blocks), dim3(256), 0, s, g);
+}
+
+hipError_t gemm_f64(const GemmArgs& gin, void* partial_ws, hipStream_t s) {
+  GemmArgs g = gin;
+  if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipSuccess;
+  if (g.M % 32 || g.N % 32 || g.K % 16 || g.splitk < 1 || (g.K / g.splitk) % 16 || g.K % g.splitk)
+    return hipErrorInvalidValue;
+  if (g.epi == EPI_SYMUPD && g.M != g.N) return hipErrorInvalidValue;
+  const bool split = g.splitk > 1;
+  GemmArgs run = g;
+  if (split) {
+    if (g.epi != EPI_COLSTORE || !partial_ws) return hipErrorInvalidValue;
+    run.epi = EPI_PARTIAL;
+    run.C = partial_ws;
+  }
+  int BM = pick_tile(g.M), BN = pick_tile(g.N);
+  if (g.epi == EPI_SYMUPD) BN = BM;
+  const int64_t blocks = gemm_f64_blocks(run);
+  if (BM == 128 && BN == 128) launch_f64<128, 128>(run, blocks, s);
+  else if (BM == 128) launch_f64<128, 32>(run, blocks, s);
+  else if (BN == 128) launch_f64<32, 128>(run, blocks, s);
+  else launch_f64<32, 32>(run, blocks, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !split) return e;
+  return reduce_partials_f64(g, (const double*)partial_ws, s);
+}
+
+hipError_t reduce_partials_f64(const GemmArgs& g, const double* P, hipStream_t s) {
+  const int64_t MN = g.M * g.N;
+  const int64_t blocks = std::min<int64_t>((MN + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_reduce_partials_f64, dim3(blocks), dim3(256), 0, s, g, P);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- q x q SPD inverse
+// One workgroup of 1024 threads on a block of order nb <= 128 held in LDS
+// (pitch nb+1).  Entries with index >= qv are the identity (zero-padded sizes).
+//   1. right-looking Cholesky G = L L^T in place (lower triangle);
+//   2. Z = L^-1 by forward substitution, row by row: Z[i][c] = (delta_ic -
+//      sum_{m<i} L[i][m] Z[m][c]) / L[i][i]; Z[i][c] (c < i) is kept in the
+//      upper triangle at [c][i], its diagonal in zd[];
+//   3. optionally Ginv = Z^T Z: Ginv[i][k] = sum_{m >= max(i,k)} Z[m][i] Z[m][k].
+__global__ __launch_bounds__(1024) void k_chol_inv_leaf(const double* G, int64_t ldg, int nb, int qv,
+                                                        double* Z, int64_t ldz, double* Ginv,
+                                                        int64_t ldi, int* status) {
+  extern __shared__ double lds[];
+  const int P = nb + 1;
+  double* a = lds;            // nb x P
+  double* zd = lds + nb * P;  // nb
+  double* part = zd + nb;     // 1024 partial sums
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nb * nb; e += 1024) {
+    const int i = e / nb, k = e % nb;
+    double v;
+    if (i < qv && k < qv) v = G[(int64_t)i * ldg + k];
+    else v = (i == k) ? 1.0 : 0.0;
+    a[i * P + k] = v;
+  }
+  __syncthreads();
+  const int tx = tid & 31, ty = tid >> 5;
+  // 1. Cholesky, lower triangle in place.
+  for (int j = 0; j < nb; ++j) {
+    const double d = a[j * P + j];
+    if (!(d > 0.0)) {
+      if (tid == 0) atomicCAS(status, 0, 3);
+      return;  // uniform: every thread read the same d
+    }
+    const double sd = sqrt(d);
+    __syncthreads();
+    for (int i = j + 1 + tid; i < nb; i += 1024) a[i * P + j] /= sd;
+    if (tid == 0) a[j * P + j] = sd;
+    __syncthreads();
+    for (int i = j + 1 + ty; i < nb; i += 32) {
+      const double lij = a[i * P + j];
+      for (int k = j + 1 + tx; k <= i; k += 32) a[i * P + k] -= lij * a[k * P + j];
+    }
+    __syncthreads();
+  }
+  // 2. Z = L^-1, rows in order; 8 threads per column share the dot product.
+  const int c = tid >> 3, part_id = tid & 7;
+  for (int i = 0; i < nb; ++i) {
+    double s = 0.0;
+    if (c < i) {
+      // sum_{m=c}^{i-1} L[i][m] Z[m][c];  Z[c][c] = zd[c], Z[m][c] = a[c][m] for m > c
+      for (int m = c + part_id; m < i; m += 8) {
+        const double zmc = (m == c) ? zd[c] : a[c * P + m];
+        s += a[i * P + m] * zmc;
+      }
+    }
+    part[tid] = s;
+    __syncthreads();
+    if (c < i && part_id == 0) {
+      double t = 0.0;
+      for (int p = 0; p < 8; ++p) t += part[tid + p];
+      a[c * P + i] = -t / a[i * P + i];  // Z[i][c] stored at [c][i]
+    }
+    if (tid == 0) zd[i] = 1.0 / a[i * P + i];
+    __syncthreads();
+  }
+  // Z out (lower, row-major), pad entries zero.
+  for (int e = tid; e < nb * nb; e += 1024) {
+    const int i = e / nb, k = e % nb;
+    double v = 0.0;
+    if (i < qv && k < qv) v = (k < i) ? a[k * P + i] : (k == i ? zd[i] : 0.0);
+    Z[(int64_t)i * ldz + k] = v;
+  }
+  if (!Ginv) return;
+  // 3. Ginv = Z^T Z (symmetric; pad entries zero).
+  for (int e = tid; e < nb * nb; e += 1024) {
+    const int i = e / nb, k = e % nb;
+    double v = 0.0;
+    if (i < qv && k < qv) {
+      const int m0 = i > k ? i : k;
+      for (int m = m0; m < qv; ++m) {
+        const double zmi = (m == i) ? zd[i] : a[i * P + m];
+        const double zmk = (m == k) ? zd[k] : a[k * P + m];
+        v += zmi * zmk;
+      }
+    }
+    Ginv[(int64_t)i * ldi + k] = v;
+  }
+}
+
+__global__ void k_zero_pad_sq(double* M, int64_t ld, int q, int qp) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)qp * qp;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / qp, k = e % qp;
+    if (i >= q || k >= q) M[i * ld + k] = 0.0;
+  }
+}
+
+static size_t leaf_lds_bytes(int nb) { return sizeof(double) * ((size_t)nb * (nb + 1) + nb + 1024); }
+
+size_t chol_inv_work_doubles(int q) {
+  const int64_t qp = ((int64_t)q + 31) / 32 * 32;
+  return (size_t)(4 * qp * qp + 1024);
+}
+
+// Recursive 2 x 2 block inverse-Cholesky on the padded block [off, off+size):
+//   Z11 = chol(G11)^-1;  L21 = G21 Z11^T;  G22' = G22 - L21 L21^T;  Z22 = chol(G22')^-1;
+//   Z21 = -Z22 L21 Z11.   (Z = L^-1 with L = [[L11, 0], [L21, L22]].)
+static hipError_t chol_rec(const double* G, int64_t ldg, int size, int qv, double* Z, int64_t ldz,
+                           double* work, int* status, hipStream_t s) {
+  if (size <= 128) {
+    hipLaunchKernelGGL(k_chol_inv_leaf, dim3(1), dim3(1024), leaf_lds_bytes(size), s, G, ldg, size,
+                       qv < 0 ? 0 : (qv > size ? size : qv), Z, ldz, (double*)nullptr, (int64_t)0, status);
+    return hipGetLastError();
+  }
+  const int s1 = ((size / 2 + 31) / 32) * 32, s2 = size - s1;
+  hipError_t e;
+  if ((e = chol_rec(G, ldg, s1, qv, Z, ldz, work, status, s)) != hipSuccess) return e;
+  double* L21 = work;                        // s2 x s1 row-major
+  double* G22 = L21 + (int64_t)s2 * s1;      // s2 x s2
+  double* T = G22 + (int64_t)s2 * s2;        // s2 x s1
+  double* next = T + (int64_t)s2 * s1;
+  // L21 = G21 Z11^T : Aop(m,k) = G21[m][k], Bop(k,n) = Z11[n][k]
+  GemmArgs g;
+  g.M = s2; g.N = s1; g.K = s1;
+  g.A = G + (int64_t)s1 * ldg; g.lda = ldg; g.a_kc = true;
+  g.B = Z; g.ldb = ldz; g.b_kc = true;
+  g.epi = EPI_ROWSTORE; g.C = L21; g.ldc = s1; g.c2 = 1.0;
+  // rows >= qv of G are padding: G stores zeros there; Z11 has zero pad too.
+  if ((e = gemm_f64(g, nullptr, s)) != hipSuccess) return e;
+  // G22' = G22 - L21 L21^T (symmetric, so column-major store == row-major)
+  GemmArgs h;
+  h.M = s2; h.N = s2; h.K = s1;
+  h.A = L21; h.lda = s1; h.a_kc = true;
+  h.B = L21; h.ldb = s1; h.b_kc = true;
+  h.epi = EPI_COLSTORE; h.C = G22; h.ldc = s2; h.c2 = -1.0;
+  h.B0 = G + (int64_t)s1 * ldg + s1; h.ld01 = ldg; h.c0 = 1.0;
+  if ((e = gemm_f64(h, nullptr, s)) != hipSuccess) return e;
+  if ((e = chol_rec(G22, s2, s2, qv - s1, Z + (int64_t)s1 * ldz + s1, ldz, next, status, s)) != hipSuccess)
+    return e;
+  // T = L21 Z11
+  GemmArgs t;
+  t.M = s2; t.N = s1; t.K = s1;
+  t.A = L21; t.lda = s1; t.a_kc = true;
+  t.B = Z; t.ldb = ldz; t.b_kc = false;
+  t.epi = EPI_ROWSTORE; t.C = T; t.ldc = s1; t.c2 = 1.0;
+  if ((e = gemm_f64(t, nullptr, s)) != hipSuccess) return e;
+  // Z21 = -Z22 T
+  GemmArgs z;
+  z.M = s2; z.N = s1; z.K = s2;
+  z.A = Z + (int64_t)s1 * ldz + s1; z.lda = ldz; z.a_kc = true;
+  z.B = T; z.ldb = s1; z.b_kc = false;
+  z.epi = EPI_ROWSTORE; z.C = Z + (int64_t)s1 * ldz; z.ldc = ldz; z.c2 = -1.0;
+  return gemm_f64(z, nullptr, s);
+}
+
+hipError_t chol_inv(const double* G, int64_t ldg, int q, double* Z, double* Ginv, int64_t ld,
+                    double* work, int* status, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_chol_inv_leaf, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)leaf_lds_bytes(128));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const int qp = (q + 31) / 32 * 32;
+  if (qp <= 128) {
+    hipLaunchKernelGGL(k_chol_inv_leaf, dim3(1), dim3(1024), leaf_lds_bytes(qp), s, G, ldg, qp, q, Z,
+                       ld, Ginv, ld, status);
+    return hipGetLastError();
+  }
+  hipError_t e = chol_rec(G, ldg, qp, q, Z, ld, work, status, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_zero_pad_sq, dim3(64), dim3(256), 0, s, Z, ld, q, qp);
+  if (!Ginv) return hipGetLastError();
+  // Ginv = Z^T Z : Aop(i,k) = Z[k][i], Bop(k,j) = Z[k][j]
+  GemmArgs g;
+  g.M = qp; g.N = qp; g.K = qp;
+  g.A = Z; g.lda = ld; g.a_kc = false;
+  g.B = Z; g.ldb = ld; g.b_kc = false;
+  g.epi = EPI_ROWSTORE; g.C = Ginv; g.ldc = ld; g.c2 = 1.0;
+  return gemm_f64(g, nullptr, s);
+}
+
+// ------------------------------------------------------------- small kernels
+__global__ void k_gather_cols_sym(const void* A, int a_dt, int64_t lda, const int32_t* C, int q, int64_t np,
+                                  void* Y, int y_dt, int64_t ldy, double* G, int64_t ldg) {
+  const int j = blockIdx.y;
+  const int64_t row = (int64_t)C[j] * lda;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x)
+    store_any(Y, y_dt, i + j * ldy, load_any(A, a_dt, row + i));
+  if (G && blockIdx.x == 0)
+    for (int b = threadIdx.x; b < q; b += blockDim.x) G[(int64_t)j * ldg + b] = load_any(A, a_dt, row + C[b]);
+}
+
+hipError_t gather_cols_sym(const void* A, int a_dt, int64_t lda, const int32_t* C, int q, int64_t np,
+                           void* Y, int y_dt, int64_t ldy, double* G, int64_t ldg, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_cols_sym, dim3((unsigned)std::min<int64_t>(ceil_div(np, 256), 64), q), dim3(256), 0, s,
+                     A, a_dt, lda, C, q, np, Y, y_dt, ldy, G, ldg);
+  return hipGetLastError();
+}
+
+__global__ void k_gather_cols_gen(const void* L, int l_dt, int64_t ldl, const int32_t* C, int64_t np, void* S,
+                                  int s_dt, int64_t lds) {
+  const int j = blockIdx.y;
+  const int64_t col = C[j];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x)
+    store_any(S, s_dt, i + j * lds, load_any(L, l_dt, i * ldl + col));
+}
+
+hipError_t gather_cols_gen(const void* L, int l_dt, int64_t ldl, const int32_t* C, int q, int64_t np, void* S,
+                           int s_dt, int64_t lds, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_cols_gen, dim3((unsigned)std::min<int64_t>(ceil_div(np, 256), 64), q), dim3(256), 0, s,
+                     L, l_dt, ldl, C, np, S, s_dt, lds);
+  return hipGetLastError();
+}
+
+// Per-block partial sums of (Sk - V)^2 over the n x q block.
+__global__ void k_est_partial(const void* Sk, int sk_dt, const int32_t* C, const void* V, int v_dt, int64_t ld,
+                              int64_t n, int q, double* red) {
+  __shared__ double sh[4];
+  const int64_t total = n * q;
+  double s = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / n, i = e % n;
+    const double sv = C ? (C[j] == i ? 1.0 : 0.0) : load_any(Sk, sk_dt, i + j * ld);
+    const double d = sv - load_any(V, v_dt, i + j * ld);
+    s += d * d;
+  }
+  const double t = block_sum_256(s, sh);
+  if (threadIdx.x == 0) red[blockIdx.x] = t;
+}
+
+__global__ void k_reduce_sum(const double* in, int64_t count, double* out, double scale, int* status) {
+  __shared__ double sh[4];
+  double s = 0;
+  for (int64_t e = threadIdx.x; e < count; e += 256) s += in[e];
+  const double t = block_sum_256(s, sh);
+  if (threadIdx.x == 0) {
+    *out = t * scale;
+    if (status && !isfinite(t)) atomicCAS(status, 0, 4);
+  }
+}
+
+hipError_t reduce_sum(const double* in, int64_t count, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, in, count, out, 1.0, (int*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t estimator(const void* Sk, int sk_dt, const int32_t* C, const void* V, int v_dt, int64_t ld, int64_t n,
+                     int q, double scale, double* red, double* est, int* status, hipStream_t s) {
+  const int blocks = 512;
+  hipLaunchKernelGGL(k_est_partial, dim3(blocks), dim3(256), 0, s, Sk, sk_dt, C, V, v_dt, ld, n, q, red);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, red, (int64_t)blocks, est, scale, status);
+  return hipGetLastError();
+}
+
+__global__ void k_coord_wprime_fix(void* W, int w_dt, int64_t ld, const int32_t* C, int q, const double* GH,
+                                   int64_t ldgh) {
+  const int a = blockIdx.x;
+  const int64_t row = C[a];
+  for (int b = threadIdx.x; b < q; b += blockDim.x) {
+    const int64_t idx = row + b * ld;
+    const double v = load_any(W, w_dt, idx) - 0.5 * (a == b ? 1.0 : 0.0) - 0.5 * GH[(int64_t)a * ldgh + b];
+    store_any(W, w_dt, idx, v);
+  }
+}
+
+hipError_t coord_wprime_fix(void* W, int w_dt, int64_t ld, const int32_t* C, int q, const double* GH, int64_t ldgh,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_coord_wprime_fix, dim3(q), dim3(256), 0, s, W, w_dt, ld, C, q, GH, ldgh);
+  return hipGetLastError();
+}
+
+__global__ void k_coord_add_rows(void* Qt, int dt, int64_t ld, const int32_t* C, int q, const double* M, int64_t ldm) {
+  const int a = blockIdx.x;
+  const int64_t row = C[a];
+  for (int b = threadIdx.x; b < q; b += blockDim.x) {
+    const int64_t idx = row + b * ld;
+    store_any(Qt, dt, idx, load_any(Qt, dt, idx) + M[(int64_t)a * ldm + b]);
+  }
+}
+
+hipError_t coord_add_rows(void* Qt, int dt, int64_t ld, const int32_t* C, int q, const double* M, int64_t ldm,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(k_coord_add_rows, dim3(q), dim3(256), 0, s, Qt, dt, ld, C, q, M, ldm);
+  return hipGetLastError();
+}
+
+__global__ void k_pos_set(int32_t* pos, const int32_t* C, int q, int value_is_index) {
+  for (int a = threadIdx.x; a < q; a += blockDim.x) pos[C[a]] = value_is_index ? a : -1;
+}
+
+// rows C_a: X[C_a, j] -= (R[a, j] + (j == C_b ? R[b, C_a] : 0)); the sum R[a,C_b] + R[b,C_a]
+// is commutative, so the C x C block stays exactly symmetric.
+__global__ void k_coord_rows(void* X, int x_dt, int64_t ldx, const int32_t* C, const int32_t* pos, int64_t np,
+                             const void* R, int r_dt, int64_t ldr) {
+  const int a = blockIdx.y;
+  const int64_t ca = C[a];
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < np; j += (int64_t)gridDim.x * blockDim.x) {
+    double d = load_any(R, r_dt, (int64_t)a * ldr + j);
+    const int b = pos[j];
+    if (b >= 0) d = d + load_any(R, r_dt, (int64_t)b * ldr + ca);
+    const int64_t idx = ca * ldx + j;
+    store_any(X, x_dt, idx, load_any(X, x_dt, idx) - d);
+  }
+}
+
+// columns C_a at rows j not in C: X[j, C_a] = X[C_a, j]
+__global__ void k_coord_mirror(void* X, int x_dt, int64_t ldx, const int32_t* C, const int32_t* pos, int64_t np) {
+  const int a = blockIdx.y;
+  const int64_t ca = C[a];
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < np; j += (int64_t)gridDim.x * blockDim.x) {
+    if (pos[j] >= 0) continue;
+    store_any(X, x_dt, j * ldx + ca, load_any(X, x_dt, ca * ldx + j));
+  }
+}
+
+hipError_t coord_sym_update(void* X, int x_dt, int64_t ldx, const int32_t* C, int32_t* pos, int q, int64_t np,
+                            const void* R, int r_dt, int64_t ldr, hipStream_t s) {
+  hipLaunchKernelGGL(k_pos_set, dim3(1), dim3(256), 0, s, pos, C, q, 1);
+  const unsigned gx = (unsigned)std::min<int64_t>(ceil_div(np, 256), 64);
+  hipLaunchKernelGGL(k_coord_rows, dim3(gx, q), dim3(256), 0, s, X, x_dt, ldx, C, (const int32_t*)pos, np, R, r_dt,
+                     ldr);
+  hipLaunchKernelGGL(k_coord_mirror, dim3(gx, q), dim3(256), 0, s, X, x_dt, ldx, C, (const int32_t*)pos, np);
+  hipLaunchKernelGGL(k_pos_set, dim3(1), dim3(256), 0, s, pos, C, q, 0);
+  return hipGetLastError();
+}
+
+__global__ void k_set_identity(void* X, int dt, int64_t ld, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    store_any(X, dt, i * ld + i, 1.0);
+}
+
+hipError_t set_identity(void* X, int dt, int64_t ld, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_identity, dim3((unsigned)std::min<int64_t>(ceil_div(n, 256), 1024)), dim3(256), 0, s, X,
+                     dt, ld, n);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_convert(const void* src, int s_dt, int64_t lds, void* dst, int d_dt, int64_t ldd, int64_t rows,
+                               int64_t cols) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / cols, j = e % cols;
+    store_any(dst, d_dt, i * ldd + j, load_any(src, s_dt, i * lds + j));
+  }
+}
+
+hipError_t copy_convert(const void* src, int s_dt, int64_t lds, void* dst, int d_dt, int64_t ldd, int64_t rows,
+                        int64_t cols, hipStream_t s) {
+  const int64_t total = rows * cols;
+  hipLaunchKernelGGL(k_copy_convert, dim3((unsigned)std::min<int64_t>(ceil_div(total, 256), 8192)), dim3(256), 0, s,
+                     src, s_dt, lds, dst, d_dt, ldd, rows, cols);
+  return hipGetLastError();
+}
+
+__global__ void k_check_sym_finite(const void* A, int dt, int64_t lda, int64_t n, int* flag) {
+  const int64_t total = n * n;
+  int bad = 0;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / n, j = e % n;
+    const double v = load_any(A, dt, i * lda + j);
+    if (!isfinite(v) || v != load_any(A, dt, j * lda + i)) bad = 1;
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+hipError_t check_sym_finite(const void* A, int dt, int64_t lda, int64_t n, int* flag, hipStream_t s) {
+  const int64_t total = n * n;
+  hipLaunchKernelGGL(k_check_sym_finite, dim3((unsigned)std::min<int64_t>(ceil_div(total, 256), 8192)), dim3(256), 0,
+                     s, A, dt, lda, n, flag);
+  return hipGetLastError();
+}
+
+}  // namespace rb

@@ -1,0 +1,121 @@
+// Sketch generation on the device from the counter-based stream (see rbfgs.h):
+// Gaussian sketches (Box-Muller on Philox4x64-10 words, rounded to bf16 values)
+// and coordinate sketches (Floyd's sampling with Lemire's bounded draws).
+#include <algorithm>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace rb {
+
+__global__ void k_sketch_gauss(uint64_t seed, uint64_t k, int64_t n, int64_t q, void* S, int dt, int64_t ld) {
+  const int64_t total = n * q;
+  const int64_t nblocks = (total + 3) / 4;
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nblocks; b += (int64_t)gridDim.x * blockDim.x) {
+    const u64x4 w = philox4x64_10((uint64_t)b, k, KIND_GAUSS, 0, seed, 0);
+#pragma unroll
+    for (int word = 0; word < 4; ++word) {
+      const int64_t e = 4 * b + word;
+      if (e >= total) break;
+      const double z = gauss_entry_from_block(w, word);
+      const int64_t i = e % n, j = e / n;
+      const int64_t idx = i + j * ld;
+      if (dt == DT_F64) ((double*)S)[idx] = z;
+      else if (dt == DT_F32) ((float*)S)[idx] = (float)z;
+      else ((__bf16*)S)[idx] = (__bf16)(float)z;  // z is already a bf16 value: exact
+    }
+  }
+}
+
+hipError_t sketch_gauss(uint64_t seed, int64_t k, int64_t n, int32_t q, void* S, int dt, int64_t ld, hipStream_t s) {
+  const int64_t nblocks = (n * (int64_t)q + 3) / 4;
+  const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(nblocks, 256), 4096));
+  hipLaunchKernelGGL(k_sketch_gauss, dim3(grid), dim3(256), 0, s, seed, (uint64_t)k, n, (int64_t)q, S, dt, ld);
+  return hipGetLastError();
+}
+
+// Sequential reader of the 64-bit words of one iteration's coordinate stream.
+struct WordStream {
+  uint64_t seed, k, pos, block;
+  u64x4 w;
+  RB_DEV uint64_t next() {
+    const uint64_t b = pos >> 2;
+    if (b != block) {
+      w = philox4x64_10(b, k, KIND_COORD, 0, seed, 0);
+      block = b;
+    }
+    const int i = (int)(pos & 3);
+    ++pos;
+    return i == 0 ? w.x : (i == 1 ? w.y : (i == 2 ? w.z : w.w));
+  }
+  // Uniform integer in [0, m), m >= 1: Lemire's multiply with rejection.
+  RB_DEV uint64_t bounded(uint64_t m) {
+    uint64_t x = next();
+    uint64_t lo = x * m;
+    if (lo < m) {
+      const uint64_t thresh = (0ull - m) % m;
+      while (lo < thresh) {
+        x = next();
+        lo = x * m;
+      }
+    }
+    return __umul64hi(x, m);
+  }
+};
+
+// One workgroup: Floyd's algorithm on thread 0 over a bitmap of [0, n) in LDS,
+// then a block-wide scan of the bitmap writes the chosen indices in ascending order.
+__global__ __launch_bounds__(256) void k_sketch_coord(uint64_t seed, uint64_t k, int64_t n, int q, int32_t* idx) {
+  extern __shared__ uint32_t bits[];
+  __shared__ int counts[256];
+  const int nwords = (int)((n + 31) / 32);
+  for (int i = threadIdx.x; i < nwords; i += blockDim.x) bits[i] = 0u;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    WordStream st{seed, k, 0ull, ~0ull, {0, 0, 0, 0}};
+    for (int64_t j = n - q; j < n; ++j) {
+      const int64_t t = (int64_t)st.bounded((uint64_t)(j + 1));
+      const uint32_t tb = 1u << (t & 31);
+      const int64_t pick = (bits[t >> 5] & tb) ? j : t;
+      bits[pick >> 5] |= 1u << (pick & 31);
+    }
+  }
+  __syncthreads();
+  const int per = (nwords + 255) / 256;
+  const int w0 = threadIdx.x * per, w1 = min(nwords, w0 + per);
+  int c = 0;
+  for (int w = w0; w < w1; ++w) c += __popc(bits[w]);
+  counts[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int i = 0; i < 256; ++i) {
+      const int v = counts[i];
+      counts[i] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  int out = counts[threadIdx.x];
+  for (int w = w0; w < w1; ++w) {
+    uint32_t m = bits[w];
+    while (m) {
+      const int b = __ffs(m) - 1;
+      m &= m - 1;
+      idx[out++] = w * 32 + b;
+    }
+  }
+}
+
+hipError_t sketch_coord(uint64_t seed, int64_t k, int64_t n, int32_t q, int32_t* idx, hipStream_t s) {
+  const size_t lds = sizeof(uint32_t) * (size_t)((n + 31) / 32);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)k_sketch_coord, hipFuncAttributeMaxDynamicSharedMemorySize, 131072);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_sketch_coord, dim3(1), dim3(256), lds, s, seed, (uint64_t)k, n, (int)q, idx);
+  return hipGetLastError();
+}
+
+}  // namespace rb

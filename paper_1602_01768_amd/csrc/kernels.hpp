@@ -1,0 +1,118 @@
+// Launchers of the RBFGS HIP kernels (host side).  Every matrix handled here is
+// zero-padded: the matrix order n to np (a multiple of 256), the sketch size q to
+// qp (a multiple of 32), and every pad entry of every operand is zero, so tiles
+// never need bounds checks and pad entries stay zero through every product.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rb {
+
+enum DType : int { DT_F32 = 0, DT_F64 = 1, DT_BF16 = 2 };
+
+// ------------------------------------------------------------- FP64 MFMA GEMM
+// C = sum_k Aop(m,k) Bop(k,n) over m < M, n < N, k < K (all multiples of the tile).
+//   Aop(m,k) = A[m*lda + k] (a_kc) or A[k*lda + m]
+//   Bop(k,n) = B[n*ldb + k] (b_kc) or B[k*ldb + n]
+// Inputs of type F32/F64/BF16 are converted to FP64; accumulation is FP64 MFMA.
+enum Epi : int {
+  EPI_PARTIAL = 0,  // split-K partial sums, double, [split][n*M + m] (reduce_partials finishes)
+  EPI_COLSTORE = 1, // C[m + n*ldc] = c2*acc + c0*B0[m + n*ld01] + c1*B1[m + n*ld01]
+  EPI_SYMUPD = 2,   // X += c2*acc on lower tiles, mirrored to keep X exactly symmetric
+  EPI_ADDROW = 3,   // C[m*ldc + n] += c2*acc
+  EPI_RESID = 4,    // red[block] = sum over m,n < nvalid of (delta_mn - acc)^2
+  EPI_ROWSTORE = 5  // C[m*ldc + n] = c2*acc
+};
+
+struct GemmArgs {
+  int64_t M = 0, N = 0, K = 0;
+  const void* A = nullptr; int64_t lda = 0; int a_dt = DT_F64; bool a_kc = true;
+  const void* B = nullptr; int64_t ldb = 0; int b_dt = DT_F64; bool b_kc = true;
+  int splitk = 1;
+  int epi = EPI_COLSTORE;
+  void* C = nullptr; int64_t ldc = 0; int c_dt = DT_F64;
+  const void* B0 = nullptr; int b0_dt = DT_F64;
+  const void* B1 = nullptr; int b1_dt = DT_F64;
+  int64_t ld01 = 0;
+  double c0 = 0, c1 = 0, c2 = 1;
+  double* red = nullptr;
+  int64_t nvalid = 0;
+  // bf16 GEMM only: plane strides of pre-split operands, split counts
+  int64_t a_plane = 0, b_plane = 0;
+};
+
+hipError_t gemm_f64(const GemmArgs& g, void* partial_ws, hipStream_t s);
+// Sum split-K partials ([split][M*N] double, column-major M x N) into the
+// COLSTORE epilogue of g (which may read B0/B1).
+hipError_t reduce_partials_f64(const GemmArgs& g, const double* partial, hipStream_t s);
+int64_t gemm_f64_blocks(const GemmArgs& g);
+
+// ------------------------------------------------------------ bf16 MFMA GEMM
+// Operand kinds for the mixed-precision GEMM.
+enum OpKind : int {
+  OK_F32_KC = 0,    // FP32, contiguous along k, split into bf16 pieces on load
+  OK_F32_MC = 1,    // FP32, contiguous along m (or n), split on load
+  OK_BF16_KC = 2    // pre-split bf16 planes, contiguous along k (plane p at base + p*plane)
+};
+struct MixedGemm {
+  GemmArgs g;
+  int a_kind = OK_F32_KC, b_kind = OK_F32_KC;
+  int na = 2, nb = 2;   // pieces per operand
+  int pmax = 1;         // passes: all piece pairs (i, j) with i + j <= pmax
+};
+hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s);
+hipError_t reduce_partials_f32(const GemmArgs& g, const float* partial, hipStream_t s);
+int64_t gemm_bf16_blocks(const MixedGemm& mg);
+
+// Pack an FP32 column-major panel (rows x cols, ld_in) into bf16 hi/lo planes,
+// row-major with leading dimension ld_out, starting at column col_off.
+hipError_t pack_split2(const float* in, int64_t ld_in, int64_t rows, int64_t cols,
+                       __bf16* hi, __bf16* lo, int64_t ld_out, int64_t col_off, hipStream_t s);
+
+// ------------------------------------------------------------------ sketches
+hipError_t sketch_gauss(uint64_t seed, int64_t k, int64_t n, int32_t q, void* S, int dt,
+                        int64_t ld, hipStream_t s);
+hipError_t sketch_coord(uint64_t seed, int64_t k, int64_t n, int32_t q, int32_t* idx,
+                        hipStream_t s);
+
+// ------------------------------------------------------------ small kernels
+// q x q SPD inverse through Cholesky: Z = L^-1 (lower) and Ginv = Z^T Z, both
+// qp x qp row-major with zero pad; *status set to 3 on a pivot <= 0 or NaN.
+// q <= 128 runs in one workgroup; larger q recurses on 2 x 2 blocks with FP64 GEMMs.
+hipError_t chol_inv(const double* G, int64_t ldg, int q, double* Z, double* Ginv,
+                    int64_t ld, double* work, int* status, hipStream_t s);
+size_t chol_inv_work_doubles(int q);
+
+// Y[i + j*ldy] = A[C_j*lda + i] (A symmetric), G[a*ldg + b] = A[C_a*lda + C_b].
+hipError_t gather_cols_sym(const void* A, int a_dt, int64_t lda, const int32_t* C, int q,
+                           int64_t np, void* Y, int y_dt, int64_t ldy, double* G, int64_t ldg,
+                           hipStream_t s);
+// S[i + j*lds] = L[i*ldl + C_j] (general L).
+hipError_t gather_cols_gen(const void* L, int l_dt, int64_t ldl, const int32_t* C, int q,
+                           int64_t np, void* S, int s_dt, int64_t lds, hipStream_t s);
+// sum (Sk - V)^2 over the n x q block, Sk dense (sk_dt) or coordinate (C != null).
+// Writes est = sum * scale to *est, sets *status = 4 when not finite.
+hipError_t estimator(const void* Sk, int sk_dt, const int32_t* C, const void* V, int v_dt,
+                     int64_t ld, int64_t n, int q, double scale, double* red, double* est,
+                     int* status, hipStream_t s);
+// Deterministic sum of `count` doubles into *out (single workgroup).
+hipError_t reduce_sum(const double* in, int64_t count, double* out, hipStream_t s);
+// rows C_a of W' (col-major, ld): W'[C_a + b*ld] -= 0.5*(a==b) + 0.5*GH[a*ldgh + b]
+hipError_t coord_wprime_fix(void* W, int w_dt, int64_t ld, const int32_t* C, int q,
+                            const double* GH, int64_t ldgh, hipStream_t s);
+// rows C_a of Q^T (col-major): Qt[C_a + b*ld] += M[a*ldm + b]
+hipError_t coord_add_rows(void* Qt, int dt, int64_t ld, const int32_t* C, int q,
+                          const double* M, int64_t ldm, hipStream_t s);
+// Fixed-sketch coordinate update of symmetric X given R = Ginv W'^T (q x np, row-major):
+// rows C_a: X[C_a, j] -= R[a, j] + (j = C_b ? R[b, C_a] : 0), then columns mirrored.
+hipError_t coord_sym_update(void* X, int x_dt, int64_t ldx, const int32_t* C, int32_t* pos,
+                            int q, int64_t np, const void* R, int r_dt, int64_t ldr, hipStream_t s);
+// X = I on the leading n x n block of the np x np zero matrix.
+hipError_t set_identity(void* X, int dt, int64_t ld, int64_t n, hipStream_t s);
+// Copy (with conversion) an n x n row-major matrix between element types.
+hipError_t copy_convert(const void* src, int s_dt, int64_t lds, void* dst, int d_dt, int64_t ldd,
+                        int64_t rows, int64_t cols, hipStream_t s);
+// 1 if any of the n x n entries is non-finite or A[i][j] != A[j][i] (exact), accumulated into *flag.
+hipError_t check_sym_finite(const void* A, int dt, int64_t lda, int64_t n, int* flag, hipStream_t s);
+
+}  // namespace rb

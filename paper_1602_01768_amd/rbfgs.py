@@ -1,0 +1,292 @@
+"""Python binding of librbfgs.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module passes pointers, sizes and
+flags through ctypes.  The functions mirror the C ABI of include/rbfgs.h
+(rbfgs_create, rbfgs_step, rbfgs_invert, rbfgs_residual, ...); `Solver` wraps a
+context.  Device buffers are torch tensors on the current HIP device and stream.
+
+The library must be built (python -m paper_1602_01768_amd.build); importing this
+module raises if it is missing -- there is no fallback path.
+"""
+import ctypes
+import math
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librbfgs.so")
+
+OK, E_INVALID_ARG, E_OOM, E_NOT_SPD, E_NONFINITE, E_NOT_CONVERGED, E_DEVICE = range(7)
+STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_OOM", 3: "E_NOT_SPD", 4: "E_NONFINITE",
+                5: "E_NOT_CONVERGED", 6: "E_DEVICE"}
+SKETCH = {"gauss": 0, "coord": 1, "cols": 1}
+VARIANT = {"fixed": 0, "adaptive": 1, "ada": 1}
+PRECISION = {"fp64": 0, "mixed": 1}
+F32, F64 = 0, 1
+
+
+class RbfgsError(RuntimeError):
+    def __init__(self, status, msg=""):
+        self.status = status
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+
+
+class rbfgs_params(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("q", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("sketch", ctypes.c_int32), ("variant", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+EXPORTS = {
+    "rbfgs_create": (ctypes.c_int, [ctypes.POINTER(rbfgs_params), ctypes.c_void_p, ctypes.c_int32,
+                                    ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                    ctypes.POINTER(ctypes.c_void_p)]),
+    "rbfgs_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "rbfgs_sync": (ctypes.c_int, [ctypes.c_void_p]),
+    "rbfgs_invert": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_int64,
+                                    ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
+    "rbfgs_residual": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "rbfgs_estimate": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "rbfgs_get_x": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                   ctypes.c_int32]),
+    "rbfgs_get_l": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                   ctypes.c_int32]),
+    "rbfgs_set_state": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                       ctypes.c_int32, ctypes.c_int64]),
+    "rbfgs_get_iter": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)]),
+    "rbfgs_destroy": (None, [ctypes.c_void_p]),
+    "rbfgs_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "rbfgs_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "rbfgs_profile_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]),
+    "rbfgs_sketch_gauss": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
+    "rbfgs_sketch_coord": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
+}
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load librbfgs.so and declare its exports (loading needs no GPU)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_1602_01768_amd.build`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(status, ctx=None):
+    if status != OK:
+        msg = ""
+        if ctx:
+            raw = load_library().rbfgs_last_error(ctx)
+            msg = raw.decode() if raw else ""
+        raise RbfgsError(status, msg)
+
+
+def _matrix_arg(M):
+    """(pointer, dtype code, leading dim, on_device, keepalive) for a 2-D torch tensor or numpy array."""
+    try:
+        import torch
+        is_torch = isinstance(M, torch.Tensor)
+    except ImportError:
+        is_torch = False
+    if is_torch:
+        if M.dim() != 2 or M.stride(1) != 1:
+            raise ValueError("need a 2-D row-major tensor")
+        if M.dtype not in (torch.float32, torch.float64):
+            raise ValueError("dtype must be float32 or float64")
+        code = F32 if M.dtype == torch.float32 else F64
+        return ctypes.c_void_p(M.data_ptr()), code, M.stride(0), int(M.is_cuda), M
+    a = np.ascontiguousarray(M)
+    if a.dtype not in (np.float32, np.float64):
+        a = a.astype(np.float64)
+    code = F32 if a.dtype == np.float32 else F64
+    return ctypes.c_void_p(a.ctypes.data), code, a.shape[1], 0, a
+
+
+# ----------------------------------------------------- same-name C ABI wrappers
+def rbfgs_create(A, q, seed, sketch="gauss", variant="fixed", precision="fp64", check_every=16, stream=None):
+    lib = load_library()
+    ptr, code, ld, on_dev, keep = _matrix_arg(A)
+    n = int(A.shape[0])
+    p = rbfgs_params(n=n, q=int(q), seed=int(seed), sketch=SKETCH[sketch], variant=VARIANT[variant],
+                     precision=PRECISION[precision], check_every=int(check_every))
+    out = ctypes.c_void_p()
+    st = lib.rbfgs_create(ctypes.byref(p), ptr, code, ld, on_dev, _stream_handle(stream), ctypes.byref(out))
+    del keep
+    _check(st)
+    return out.value
+
+
+def rbfgs_step(ctx, nsteps=1):
+    _check(load_library().rbfgs_step(ctx, int(nsteps)), ctx)
+
+
+def rbfgs_sync(ctx):
+    _check(load_library().rbfgs_sync(ctx), ctx)
+
+
+def rbfgs_invert(ctx, tol, max_iters):
+    it = ctypes.c_int64()
+    r = ctypes.c_double()
+    st = load_library().rbfgs_invert(ctx, float(tol), int(max_iters), ctypes.byref(it), ctypes.byref(r))
+    if st not in (OK, E_NOT_CONVERGED):
+        _check(st, ctx)
+    return st == OK, it.value, r.value
+
+
+def rbfgs_residual(ctx):
+    r = ctypes.c_double()
+    _check(load_library().rbfgs_residual(ctx, ctypes.byref(r)), ctx)
+    return r.value
+
+
+def rbfgs_estimate(ctx):
+    r = ctypes.c_double()
+    _check(load_library().rbfgs_estimate(ctx, ctypes.byref(r)), ctx)
+    return r.value
+
+
+def _get_matrix(fn, ctx, n, dtype, device):
+    import torch
+    tdt = torch.float64 if dtype == F64 else torch.float32
+    out = torch.empty((n, n), dtype=tdt, device=device)
+    _check(fn(ctx, ctypes.c_void_p(out.data_ptr()), dtype, n, int(out.is_cuda)), ctx)
+    return out
+
+
+def rbfgs_get_x(ctx, n, dtype=F64, device="cuda"):
+    return _get_matrix(load_library().rbfgs_get_x, ctx, n, dtype, device)
+
+
+def rbfgs_get_l(ctx, n, dtype=F64, device="cuda"):
+    return _get_matrix(load_library().rbfgs_get_l, ctx, n, dtype, device)
+
+
+def rbfgs_set_state(ctx, M, k):
+    ptr, code, ld, on_dev, keep = _matrix_arg(M)
+    _check(load_library().rbfgs_set_state(ctx, ptr, code, ld, on_dev, int(k)), ctx)
+    del keep
+
+
+def rbfgs_get_iter(ctx):
+    k = ctypes.c_int64()
+    _check(load_library().rbfgs_get_iter(ctx, ctypes.byref(k)), ctx)
+    return k.value
+
+
+def rbfgs_destroy(ctx):
+    if ctx:
+        load_library().rbfgs_destroy(ctx)
+
+
+def rbfgs_profile(ctx, enable=True):
+    _check(load_library().rbfgs_profile(ctx, int(bool(enable))), ctx)
+
+
+def rbfgs_profile_report(ctx):
+    """{phase: (total_ms, count)} accumulated since profiling was enabled."""
+    import json
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(load_library().rbfgs_profile_report(ctx, buf, len(buf)), ctx)
+    return {k: (v[0], v[1]) for k, v in json.loads(buf.value.decode()).items()}
+
+
+def rbfgs_sketch_gauss(seed, k, n, q, dtype=F64, stream=None):
+    import torch
+    out = torch.zeros((q, n), dtype=torch.float64 if dtype == F64 else torch.float32, device="cuda")
+    _check(load_library().rbfgs_sketch_gauss(int(seed), int(k), int(n), int(q), ctypes.c_void_p(out.data_ptr()),
+                                             dtype, _stream_handle(stream)))
+    return out.T  # n x q view of the column-major buffer
+
+
+def rbfgs_sketch_coord(seed, k, n, q, stream=None):
+    import torch
+    out = torch.zeros(q, dtype=torch.int32, device="cuda")
+    _check(load_library().rbfgs_sketch_coord(int(seed), int(k), int(n), int(q), ctypes.c_void_p(out.data_ptr()),
+                                             _stream_handle(stream)))
+    return out
+
+
+class Solver:
+    """One inversion context (library-owned device state for A and X or L)."""
+
+    def __init__(self, A, q, seed, sketch="gauss", variant="fixed", precision="fp64", check_every=16,
+                 stream=None):
+        self.n = int(A.shape[0])
+        self.q, self.seed = int(q), int(seed)
+        self.sketch, self.variant, self.precision = sketch, variant, precision
+        self.ctx = rbfgs_create(A, q, seed, sketch, variant, precision, check_every, stream)
+
+    def step(self, nsteps=1):
+        rbfgs_step(self.ctx, nsteps)
+        return self
+
+    def sync(self):
+        rbfgs_sync(self.ctx)
+
+    def invert(self, tol=1e-3, max_iters=20000):
+        """(converged, iterations, ||I - AX||_F / sqrt(n))"""
+        return rbfgs_invert(self.ctx, tol, max_iters)
+
+    def residual(self):
+        return rbfgs_residual(self.ctx)
+
+    def estimate(self):
+        return rbfgs_estimate(self.ctx)
+
+    def x(self, dtype=F64, device="cuda"):
+        return rbfgs_get_x(self.ctx, self.n, dtype, device)
+
+    def factor(self, dtype=F64, device="cuda"):
+        return rbfgs_get_l(self.ctx, self.n, dtype, device)
+
+    def set_state(self, M, k):
+        rbfgs_set_state(self.ctx, M, k)
+
+    def profile(self, enable=True):
+        rbfgs_profile(self.ctx, enable)
+
+    def profile_report(self):
+        return rbfgs_profile_report(self.ctx)
+
+    @property
+    def iteration(self):
+        return rbfgs_get_iter(self.ctx)
+
+    def close(self):
+        if self.ctx:
+            rbfgs_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def relative_residual(fro, n):
+    return fro / math.sqrt(n)

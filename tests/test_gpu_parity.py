@@ -1,0 +1,191 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Bars: bitwise for the sketch stream (indices and bf16 values); relative Frobenius
+error of X (or L) <= 1e-10 in FP64 mode and <= 1e-4 in mixed mode at a fixed
+iteration count.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import rbfgs as R, sketch as sk
+from workloads import spectral_spd, gram_ridge
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+MIXED_TOL = 1e-4
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def gpu_x(lib, A, q, seed, kind, variant, precision, steps):
+    import torch
+    with lib.Solver(A, q, seed, sketch=kind, variant=variant, precision=precision) as s:
+        s.step(steps)
+        s.sync()
+        X = s.x().cpu().numpy()
+        L = s.factor().cpu().numpy() if variant == "adaptive" else None
+    torch.cuda.synchronize()
+    return X, L
+
+
+def oracle_x(A, q, seed, kind, variant, steps):
+    kind_o = "cols" if kind == "coord" else kind
+    A64 = np.asarray(A, dtype=np.float64)
+    if variant == "fixed":
+        return R.run_fixed(A64, q, seed, kind_o, steps), None
+    L = R.run_ada(A64, q, seed, kind_o, steps)
+    return L @ L.T, L
+
+
+# ----------------------------------------------------------------- sketches
+@pytest.mark.parametrize("seed,k,n,q", [(1, 0, 1, 1), (7, 3, 37, 5), (123, 999, 300, 17), (5, 12, 4096, 64),
+                                        (2 ** 63 + 11, 2 ** 40, 1001, 3)])
+def test_gauss_sketch_bitwise(lib, seed, k, n, q):
+    S = lib.rbfgs_sketch_gauss(seed, k, n, q, dtype=lib.F64).cpu().numpy()
+    ref = sk.gaussian_sketch(seed, k, n, q)
+    assert np.array_equal(S, ref)
+
+
+@pytest.mark.parametrize("seed,k,n,q", [(1, 0, 1, 1), (3, 1, 10, 10), (9, 5, 1000, 64), (11, 7, 16384, 256),
+                                        (2, 3, 100000, 512), (4, 8, 5, 2)])
+def test_coord_sketch_bitwise(lib, seed, k, n, q):
+    idx = lib.rbfgs_sketch_coord(seed, k, n, q).cpu().numpy()
+    assert np.array_equal(idx, sk.coord_sketch(seed, k, n, q))
+
+
+# ------------------------------------------------------------- FP64 parity
+@pytest.mark.parametrize("variant", ["fixed", "adaptive"])
+@pytest.mark.parametrize("kind", ["gauss", "coord"])
+@pytest.mark.parametrize("n,q,steps", [(1, 1, 2), (37, 5, 20), (300, 17, 40), (257, 130, 6)])
+def test_fp64_parity_small(lib, variant, kind, n, q, steps):
+    A, _ = spectral_spd(n, n + q, 1.0, 100.0)
+    Xg, Lg = gpu_x(lib, A, q, 5, kind, variant, "fp64", steps)
+    Xo, Lo = oracle_x(A, q, 5, kind, variant, steps)
+    assert rel(Xg, Xo) <= FP64_TOL
+    if Lo is not None:
+        assert rel(Lg, Lo) <= FP64_TOL
+
+
+@pytest.mark.parametrize("kind", ["gauss", "coord"])
+def test_fp64_parity_c1(lib, kind):
+    """Config 1: n = 256 spectral SPD (lambda log-uniform in [1, 1e3]), q = 16, 300 steps."""
+    A, Ainv = spectral_spd(256, 1, 1.0, 1e3)
+    Xg, _ = gpu_x(lib, A, 16, 1, kind, "fixed", "fp64", 300)
+    Xo, _ = oracle_x(A, 16, 1, kind, "fixed", 300)
+    assert rel(Xg, Xo) <= FP64_TOL
+    # the iteration approaches the closed-form inverse
+    assert np.linalg.norm(Xg - Ainv) < np.linalg.norm(np.eye(256) - Ainv)
+
+
+# ------------------------------------------------------------ mixed parity
+@pytest.mark.parametrize("variant", ["fixed", "adaptive"])
+@pytest.mark.parametrize("kind", ["gauss", "coord"])
+def test_mixed_parity_small(lib, variant, kind):
+    n, q, steps = 520, 40, 60
+    A = gram_ridge(n, 3)
+    Xg, _ = gpu_x(lib, A, q, 2, kind, variant, "mixed", steps)
+    Xo, _ = oracle_x(A, q, 2, kind, variant, steps)
+    assert rel(Xg, Xo) <= MIXED_TOL
+
+
+# ---------------------------------------------------------- residual, API
+def test_residual_matches_oracle(lib):
+    A, _ = spectral_spd(300, 4, 1.0, 50.0)
+    for variant in ("fixed", "adaptive"):
+        with lib.Solver(A, 20, 3, variant=variant) as s:
+            s.step(10)
+            r = s.residual()
+        Xo, _ = oracle_x(A, 20, 3, "gauss", variant, 10)
+        assert abs(r - R.residual_fro(A, Xo)) <= 1e-9 * r
+
+
+def test_estimator_matches_oracle(lib):
+    A, _ = spectral_spd(200, 6, 1.0, 50.0)
+    X = R.run_fixed(A, 10, 8, "gauss", 4)
+    S = sk.gaussian_sketch(8, 4, 200, 10)
+    with lib.Solver(A, 10, 8) as s:
+        s.step(5)
+        est = s.estimate()
+    assert abs(est - R.estimator(X, A, S, "gauss")) <= 1e-9 * est
+
+
+def test_one_step_exact_when_q_equals_n(lib):
+    A, Ainv = spectral_spd(64, 2, 1.0, 10.0)
+    Xg, _ = gpu_x(lib, A, 64, 1, "gauss", "fixed", "fp64", 1)
+    assert rel(Xg, Ainv) <= 1e-9
+
+
+def test_invert_converges_and_reports(lib):
+    A, Ainv = spectral_spd(128, 3, 1.0, 10.0)
+    with lib.Solver(A, 32, 1, variant="adaptive", check_every=4) as s:
+        ok, iters, resid = s.invert(tol=1e-8, max_iters=400)
+        assert ok and resid <= 1e-8 and iters <= 400
+        X = s.x().cpu().numpy()
+    assert R.residual_fro(A, X) / math.sqrt(128) <= 1e-8
+
+
+def test_checkpoint_resume_bitwise(lib):
+    A, _ = spectral_spd(200, 7, 1.0, 30.0)
+    for variant in ("fixed", "adaptive"):
+        with lib.Solver(A, 12, 9, variant=variant) as s1:
+            s1.step(10)
+            full = s1.factor() if variant == "adaptive" else s1.x()
+        with lib.Solver(A, 12, 9, variant=variant) as s2:
+            s2.step(4)
+            mid = s2.factor() if variant == "adaptive" else s2.x()
+        with lib.Solver(A, 12, 9, variant=variant) as s3:
+            s3.set_state(mid, 4)
+            s3.step(6)
+            assert s3.iteration == 10
+            res = s3.factor() if variant == "adaptive" else s3.x()
+        assert np.array_equal(full.cpu().numpy(), res.cpu().numpy())
+
+
+def test_deterministic(lib):
+    A = gram_ridge(384, 5)
+    outs = []
+    for _ in range(2):
+        with lib.Solver(A, 32, 4, precision="mixed") as s:
+            s.step(5)
+            outs.append(s.x(dtype=lib.F32).cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_not_spd_reported(lib):
+    A = -np.eye(40)
+    with lib.Solver(A, 4, 1) as s:
+        s.step(1)
+        with pytest.raises(lib.RbfgsError) as ei:
+            s.sync()
+        assert ei.value.status == lib.E_NOT_SPD
+
+
+def test_invalid_matrices_rejected(lib):
+    A, _ = spectral_spd(16, 1)
+    B = A.copy()
+    B[0, 1] += 1e-3
+    with pytest.raises(lib.RbfgsError) as ei:
+        lib.Solver(B, 4, 1)
+    assert ei.value.status == lib.E_INVALID_ARG
+    C = A.copy()
+    C[2, 2] = np.nan
+    with pytest.raises(lib.RbfgsError):
+        lib.Solver(C, 4, 1)
+    with pytest.raises(lib.RbfgsError):
+        lib.Solver(A, 17, 1)
+
+
+def test_device_input_and_float32(lib):
+    import torch
+    A = gram_ridge(256, 8)
+    At = torch.from_numpy(A).cuda()
+    with lib.Solver(At, 16, 2, precision="mixed") as s:
+        s.step(8)
+        Xg = s.x().cpu().numpy()
+    Xo, _ = oracle_x(A, 16, 2, "gauss", "fixed", 8)
+    assert rel(Xg, Xo) <= MIXED_TOL
