@@ -1,5 +1,12 @@
 // C ABI of the RBFGS library: context management and the per-iteration
 // orchestration of the kernels.  See include/rbfgs.h for the contract.
+//
+// Two HIP streams ("lanes") per context.  Everything of iteration k that depends
+// only on the sketch -- S, A S, G = S^T A S and its Cholesky-based inverse, and
+// U = S G^-1 for the fixed method; S~^T S~ and its factor for the adaptive one --
+// is computed on the side lane into one of two slots while the main lane runs
+// the X- (or L-) dependent part of iteration k-1.  Events order the two lanes;
+// every slot is double-buffered.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -15,40 +22,59 @@
 
 using namespace rb;
 
+namespace {
+
+struct Lane {  // one stream with its own split-K, reduction and Cholesky workspaces
+  hipStream_t s = nullptr;
+  void* partial = nullptr;
+  size_t partial_bytes = 0;
+  double* red = nullptr;
+  double* cwork = nullptr;
+};
+
+struct Slot {  // sketch-dependent quantities of one iteration
+  void* Sk = nullptr;        // Gaussian sketch (S or S~), bf16 in mixed mode, FP64 otherwise
+  int32_t* C = nullptr;      // coordinate indices
+  void* Y = nullptr;         // fixed: A S
+  double* G = nullptr;       // fixed: S^T A S;  adaptive: S~^T S~
+  double* Ginv = nullptr;    // fixed: G^-1
+  double* Z = nullptr;       // inverse Cholesky factor of G (fixed) or of S~^T S~ (adaptive)
+  void* U = nullptr;         // fixed: U = S G^-1 (mixed: FP32 n x q; FP64: panels [U | W' | U])
+  __bf16* planes = nullptr;  // mixed fixed: bf16 hi/lo planes of [U | W' | U], row-major
+  hipEvent_t ready = nullptr;     // side lane: slot complete
+  hipEvent_t released = nullptr;  // main lane: iteration that used the slot complete
+  bool released_valid = false;
+};
+
+}  // namespace
+
 struct rbfgs_ctx {
   rbfgs_params p{};
   int64_t n = 0, np = 0, qp = 0;
   int q = 0;
   bool mixed = false, ada = false, coord = false;
   int mdt = DT_F64;  // element type of A, X/L and the n x q panels
-  hipStream_t stream = nullptr;
   int device = 0;
   int64_t k = 0;
   std::string err;
-  // device buffers
+  Lane main, side;
+  Slot slot[2];
+  hipEvent_t ev_begin = nullptr;
+  // main-lane buffers
   void* A = nullptr;
   void* X = nullptr;        // X (fixed) or L (adaptive)
-  void* Sk = nullptr;       // sketch (S, or S~ for the adaptive method); bf16 in mixed mode
-  int32_t* C = nullptr;     // coordinate indices
-  int32_t* pos = nullptr;   // inverse map of C (-1 elsewhere)
+  int32_t* pos = nullptr;   // inverse map of the coordinate set (-1 elsewhere)
   void* Sa = nullptr;       // adaptive: S = L S~
-  void* Y = nullptr;
+  void* Y = nullptr;        // adaptive: Y = A S
   void* V = nullptr;        // V = X Y (fixed) or T^T = L^T Y (adaptive)
-  void* U = nullptr;        // fixed: U = S G^-1 (mixed) / panel [U | W' | U] (FP64)
-  void* W = nullptr;        // fixed: W' (mixed); adaptive: Q^T
-  __bf16* planes = nullptr; // mixed: bf16 hi/lo planes of the update operands
+  void* W = nullptr;        // fixed: W' (mixed) / copy of V (coordinates); adaptive: Q^T
+  __bf16* planes = nullptr; // adaptive mixed: bf16 planes of S and Q^T
   void* R = nullptr;        // fixed coordinate: R = G^-1 W'^T (qp x np)
-  double *G = nullptr, *H = nullptr, *Ginv = nullptr, *Z = nullptr, *GH = nullptr, *Zm = nullptr,
-         *Mm = nullptr, *Mq = nullptr;
-  double* cwork = nullptr;
-  void* partial = nullptr;
-  size_t partial_bytes = 0;
-  double* red = nullptr;
-  int64_t red_count = 0;
+  double *G = nullptr, *H = nullptr, *Ginv = nullptr, *Z = nullptr, *GH = nullptr, *Mq = nullptr;
   double* est = nullptr;
   int* status = nullptr;
   std::vector<void*> allocs;
-  // per-phase timing with HIP events on the context's stream (rbfgs_profile)
+  // per-phase timing with HIP events on the lanes' streams (rbfgs_profile)
   struct ProfRec {
     const char* name;
     hipEvent_t a, b;
@@ -80,7 +106,7 @@ void* dalloc(rbfgs_ctx* ctx, size_t bytes) {
   void* p = nullptr;
   HIPCHK(hipMalloc(&p, bytes ? bytes : 16));
   ctx->allocs.push_back(p);
-  HIPCHK(hipMemsetAsync(p, 0, bytes ? bytes : 16, ctx->stream));
+  HIPCHK(hipMemsetAsync(p, 0, bytes ? bytes : 16, ctx->main.s));
   return p;
 }
 
@@ -95,15 +121,16 @@ hipEvent_t prof_event(rbfgs_ctx* ctx) {
   return e;
 }
 
-// Scope that brackets the kernels of one phase of an iteration with events.
+// Scope that brackets the kernels of one phase with events on one lane.
 struct Phase {
   rbfgs_ctx* ctx;
+  hipStream_t s;
   const char* name;
   hipEvent_t a = nullptr;
-  Phase(rbfgs_ctx* c, const char* n) : ctx(c), name(n) {
+  Phase(rbfgs_ctx* c, const Lane& L, const char* n) : ctx(c), s(L.s), name(n) {
     if (ctx->prof) {
       a = prof_event(ctx);
-      HIPCHK(hipEventRecord(a, ctx->stream));
+      HIPCHK(hipEventRecord(a, s));
     }
   }
   ~Phase() {
@@ -115,13 +142,14 @@ struct Phase {
     } else if (hipEventCreate(&b) != hipSuccess) {
       return;
     }
-    if (hipEventRecord(b, ctx->stream) == hipSuccess) ctx->prof_pending.push_back({name, a, b});
+    if (hipEventRecord(b, s) == hipSuccess) ctx->prof_pending.push_back({name, a, b});
   }
 };
 
 void prof_flush(rbfgs_ctx* ctx) {
   if (ctx->prof_pending.empty()) return;
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->main.s));
+  HIPCHK(hipStreamSynchronize(ctx->side.s));
   for (auto& r : ctx->prof_pending) {
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
@@ -134,43 +162,46 @@ void prof_flush(rbfgs_ctx* ctx) {
   ctx->prof_pending.clear();
 }
 
-int pick_split(int64_t tiles, int64_t K, int kmul) {
+// Split-K factor: enough workgroups to fill the chip (>= 1024) with K chunks of at
+// least min_chunk; at most max_split partial buffers.
+int pick_split(int64_t tiles, int64_t K, int kmul, int max_split = 8, int64_t min_chunk = 256) {
   int s = 1;
-  while (s < 8 && tiles * s < 1024 && K % ((int64_t)kmul * s * 2) == 0 && K / (s * 2) >= 256) s *= 2;
+  while (s < max_split && tiles * s < 1024 && K % ((int64_t)kmul * s * 2) == 0 && K / (s * 2) >= min_chunk) s *= 2;
   return s;
 }
 
 int64_t f64_tile(int64_t x) { return x % 128 == 0 ? 128 : 32; }
 int64_t bf_bn(int64_t N) { return N % 256 == 0 ? 256 : (N % 128 == 0 ? 128 : (N % 64 == 0 ? 64 : 32)); }
 
-// C(M x N, col-major, ldc) = Aop * Bop in FP64 (tall-skinny or q x q products).
-void f64_gemm(rbfgs_ctx* ctx, GemmArgs g) {
+// FP64-MFMA product on one lane; column-store products get a split-K.
+void f64_gemm(rbfgs_ctx* ctx, const Lane& L, GemmArgs g) {
   if (g.epi == EPI_COLSTORE) {
     const int64_t tiles = (g.M / f64_tile(g.M)) * (g.N / f64_tile(g.N));
-    g.splitk = pick_split(tiles, g.K, 16);
+    const bool small_out = g.M * g.N <= (int64_t)1024 * 1024;  // q x q products: split deep
+    g.splitk = small_out ? pick_split(tiles, g.K, 16, 128, 128) : pick_split(tiles, g.K, 16);
     const size_t need = (size_t)g.splitk * g.M * g.N * sizeof(double);
-    if (g.splitk > 1 && need > ctx->partial_bytes) g.splitk = 1;
+    if (g.splitk > 1 && need > L.partial_bytes) g.splitk = 1;
   }
-  HIPCHK(gemm_f64(g, ctx->partial, ctx->stream));
+  HIPCHK(gemm_f64(g, L.partial, L.s));
 }
 
-// C(M x N, col-major float, ldc) = Aop * Bop on bf16 MFMA pieces.
-void bf_gemm(rbfgs_ctx* ctx, MixedGemm mg) {
+// bf16-MFMA product on one lane (tall-skinny products get a split-K).
+void bf_gemm(rbfgs_ctx* ctx, const Lane& L, MixedGemm mg) {
   GemmArgs& g = mg.g;
   if (g.epi == EPI_COLSTORE) {
     const int64_t tiles = (g.M / 128) * (g.N / bf_bn(g.N));
     g.splitk = pick_split(tiles, g.K, 32);
     const size_t need = (size_t)g.splitk * g.M * g.N * sizeof(float);
-    if (need > ctx->partial_bytes) g.splitk = 1;
+    if (need > L.partial_bytes) g.splitk = 1;
   }
-  HIPCHK(gemm_bf16(mg, ctx->partial, ctx->stream));
+  HIPCHK(gemm_bf16(mg, L.partial, L.s));
 }
 
 // out = M * P for an n x n matrix M (A, X or L) and an n x q panel P, per precision.
 // transpose: Aop = M^T (T^T = L^T Y).  In mixed mode (na, nb, pmax) choose the bf16
 // pieces of each operand and the passes kept (all piece pairs with i + j <= pmax).
-void nn_times_panel(rbfgs_ctx* ctx, const void* M, bool transpose, const void* P, int p_dt, void* out, int na = 2,
-                    int nb = 2, int pmax = 1) {
+void nn_times_panel(rbfgs_ctx* ctx, const Lane& L, const void* M, bool transpose, const void* P, int p_dt, void* out,
+                    int na = 2, int nb = 2, int pmax = 1) {
   if (ctx->mixed) {
     MixedGemm mg;
     GemmArgs& g = mg.g;
@@ -181,187 +212,203 @@ void nn_times_panel(rbfgs_ctx* ctx, const void* M, bool transpose, const void* P
     mg.a_kind = transpose ? OK_F32_MC : OK_F32_KC;
     mg.b_kind = p_dt == DT_BF16 ? OK_BF16_KC : OK_F32_KC;
     mg.na = na; mg.nb = p_dt == DT_BF16 ? 1 : nb; mg.pmax = pmax;
-    bf_gemm(ctx, mg);
+    bf_gemm(ctx, L, mg);
   } else {
     GemmArgs g;
     g.M = ctx->np; g.N = ctx->qp; g.K = ctx->np;
     g.A = M; g.lda = ctx->np; g.a_dt = DT_F64; g.a_kc = !transpose;
     g.B = P; g.ldb = ctx->np; g.b_dt = p_dt; g.b_kc = true;
     g.epi = EPI_COLSTORE; g.C = out; g.ldc = ctx->np; g.c_dt = DT_F64; g.c2 = 1.0;
-    f64_gemm(ctx, g);
+    f64_gemm(ctx, L, g);
   }
 }
 
 // q x q Gram C = P1^T P2 of two n x q column-major panels, FP64 accumulation.
-void gram(rbfgs_ctx* ctx, const void* P1, int dt1, const void* P2, int dt2, double* out) {
+void gram(rbfgs_ctx* ctx, const Lane& L, const void* P1, int dt1, const void* P2, int dt2, double* out) {
   GemmArgs g;
   g.M = ctx->qp; g.N = ctx->qp; g.K = ctx->np;
   g.A = P1; g.lda = ctx->np; g.a_dt = dt1; g.a_kc = true;
   g.B = P2; g.ldb = ctx->np; g.b_dt = dt2; g.b_kc = true;
   g.epi = EPI_COLSTORE; g.C = out; g.ldc = ctx->qp; g.c_dt = DT_F64; g.c2 = 1.0;
-  f64_gemm(ctx, g);
+  f64_gemm(ctx, L, g);
 }
 
 // out(n x q) = c2 * P(n x q, col-major) * M(q x q, row-major) [+ c0*B0 + c1*B1]
-void panel_times_small(rbfgs_ctx* ctx, const void* P, int p_dt, const double* M, void* out, int out_dt, double c2,
-                       const void* B0 = nullptr, int b0_dt = DT_F64, double c0 = 0, const void* B1 = nullptr,
-                       int b1_dt = DT_F64, double c1 = 0) {
+void panel_times_small(rbfgs_ctx* ctx, const Lane& L, const void* P, int p_dt, const double* M, void* out, int out_dt,
+                       double c2, const void* B0 = nullptr, int b0_dt = DT_F64, double c0 = 0,
+                       const void* B1 = nullptr, int b1_dt = DT_F64, double c1 = 0) {
   GemmArgs g;
   g.M = ctx->np; g.N = ctx->qp; g.K = ctx->qp;
   g.A = P; g.lda = ctx->np; g.a_dt = p_dt; g.a_kc = false;
   g.B = M; g.ldb = ctx->qp; g.b_dt = DT_F64; g.b_kc = false;
   g.epi = EPI_COLSTORE; g.C = out; g.ldc = ctx->np; g.c_dt = out_dt; g.c2 = c2;
   g.B0 = B0; g.b0_dt = b0_dt; g.c0 = c0; g.B1 = B1; g.b1_dt = b1_dt; g.c1 = c1; g.ld01 = ctx->np;
-  f64_gemm(ctx, g);
+  f64_gemm(ctx, L, g);
 }
 
 // out(q x q, row-major) = Aop * Bop with row-major q x q inputs (transposes by flag).
-void small_small(rbfgs_ctx* ctx, const double* A, bool at, const double* B, double* out) {
+void small_small(rbfgs_ctx* ctx, const Lane& L, const double* A, bool at, const double* B, double* out) {
   GemmArgs g;
   g.M = ctx->qp; g.N = ctx->qp; g.K = ctx->qp;
   g.A = A; g.lda = ctx->qp; g.a_dt = DT_F64; g.a_kc = !at;
   g.B = B; g.ldb = ctx->qp; g.b_dt = DT_F64; g.b_kc = false;
   g.epi = EPI_ROWSTORE; g.C = out; g.ldc = ctx->qp; g.c_dt = DT_F64; g.c2 = 1.0;
-  f64_gemm(ctx, g);
-}
-
-void do_sketch(rbfgs_ctx* ctx, int64_t k) {
-  if (ctx->coord) {
-    HIPCHK(sketch_coord(ctx->p.seed, k, ctx->n, ctx->q, ctx->C, ctx->stream));
-  } else {
-    HIPCHK(sketch_gauss(ctx->p.seed, k, ctx->n, ctx->q, ctx->Sk, ctx->mixed ? DT_BF16 : DT_F64, ctx->np,
-                        ctx->stream));
-  }
+  f64_gemm(ctx, L, g);
 }
 
 int sk_dt(const rbfgs_ctx* ctx) { return ctx->mixed ? DT_BF16 : DT_F64; }
 
-// One fixed-sketch RBFGS iteration, eq. (qunac) as the symmetric rank-2q update
-//   X+ = X - (U W'^T + W' U^T),  U = S G^-1,  W' = V - S/2 - U H/2,
-//   Y = A S,  G = S^T Y,  V = X Y,  H = Y^T V.
-void step_fixed(rbfgs_ctx* ctx) {
+// ---------------------------------------------------------------- side lane
+// Sketch-dependent part of iteration k into slot S (side lane).
+void side_chain(rbfgs_ctx* ctx, int64_t k, Slot& S) {
+  const Lane& L = ctx->side;
   const int64_t np = ctx->np, qp = ctx->qp;
   const int mdt = ctx->mdt;
-  { Phase ph(ctx, "sketch"); do_sketch(ctx, ctx->k); }
-  if (ctx->coord) {
-    Phase ph(ctx, "gather");
-    HIPCHK(gather_cols_sym(ctx->A, mdt, np, ctx->C, ctx->q, np, ctx->Y, mdt, np, ctx->G, qp, ctx->stream));
-  } else {
-    { Phase ph(ctx, "AS"); nn_times_panel(ctx, ctx->A, false, ctx->Sk, sk_dt(ctx), ctx->Y, 3, 1, 2); }  // exact products
-    Phase ph(ctx, "gram_G");
-    gram(ctx, ctx->Sk, sk_dt(ctx), ctx->Y, mdt, ctx->G);
+  {
+    Phase ph(ctx, L, "sketch");
+    if (ctx->coord) HIPCHK(sketch_coord(ctx->p.seed, k, ctx->n, ctx->q, S.C, L.s));
+    else HIPCHK(sketch_gauss(ctx->p.seed, k, ctx->n, ctx->q, S.Sk, sk_dt(ctx), np, L.s));
   }
-  { Phase ph(ctx, "chol_inv"); HIPCHK(chol_inv(ctx->G, qp, ctx->q, ctx->Z, ctx->Ginv, qp, ctx->cwork, ctx->status, ctx->stream)); }
-  { Phase ph(ctx, "XY"); nn_times_panel(ctx, ctx->X, false, ctx->Y, mdt, ctx->V); }
-  { Phase ph(ctx, "gram_H"); gram(ctx, ctx->Y, mdt, ctx->V, mdt, ctx->H); }
+  if (ctx->ada) {
+    if (!ctx->coord) {  // factor of S~^T S~ for C = L_M^-1
+      Phase ph(ctx, L, "sketch_gram");
+      gram(ctx, L, S.Sk, sk_dt(ctx), S.Sk, sk_dt(ctx), S.G);
+      HIPCHK(chol_inv(S.G, qp, ctx->q, S.Z, nullptr, qp, L.cwork, ctx->status, L.s));
+    }
+    return;
+  }
+  if (ctx->coord) {
+    Phase ph(ctx, L, "gather");
+    HIPCHK(gather_cols_sym(ctx->A, mdt, np, S.C, ctx->q, np, S.Y, mdt, np, S.G, qp, L.s));
+  } else {
+    { Phase ph(ctx, L, "AS"); nn_times_panel(ctx, L, ctx->A, false, S.Sk, sk_dt(ctx), S.Y, 3, 1, 2); }  // exact
+    Phase ph(ctx, L, "gram_G");
+    gram(ctx, L, S.Sk, sk_dt(ctx), S.Y, mdt, S.G);
+  }
+  { Phase ph(ctx, L, "chol_inv"); HIPCHK(chol_inv(S.G, qp, ctx->q, S.Z, S.Ginv, qp, L.cwork, ctx->status, L.s)); }
+  if (ctx->coord) return;
+  Phase ph(ctx, L, "panel_U");
+  if (ctx->mixed) {
+    float* U = (float*)S.U;
+    panel_times_small(ctx, L, S.Sk, DT_BF16, S.Ginv, U, DT_F32, 1.0);
+    const int64_t ldp = 3 * qp, plane = np * ldp;
+    HIPCHK(pack_split2(U, np, np, qp, S.planes, S.planes + plane, ldp, 0, L.s));
+    HIPCHK(pack_split2(U, np, np, qp, S.planes, S.planes + plane, ldp, 2 * qp, L.s));
+  } else {
+    double* U = (double*)S.U;
+    panel_times_small(ctx, L, S.Sk, DT_F64, S.Ginv, U, DT_F64, 1.0);
+    HIPCHK(hipMemcpyAsync(U + 2 * np * qp, U, (size_t)np * qp * sizeof(double), hipMemcpyDeviceToDevice, L.s));
+  }
+}
+
+// ---------------------------------------------------------------- main lane
+// X-dependent part of one fixed-sketch RBFGS iteration, eq. (qunac) as the
+// symmetric rank-2q update X+ = X - (U W'^T + W' U^T), U = S G^-1,
+// W' = V - S/2 - U H/2, V = X Y, H = Y^T V (Y = A S and G = S^T Y from the slot).
+void main_fixed(rbfgs_ctx* ctx, Slot& S) {
+  const Lane& L = ctx->main;
+  const int64_t np = ctx->np, qp = ctx->qp;
+  const int mdt = ctx->mdt;
+  { Phase ph(ctx, L, "XY"); nn_times_panel(ctx, L, ctx->X, false, S.Y, mdt, ctx->V); }
+  { Phase ph(ctx, L, "gram_H"); gram(ctx, L, S.Y, mdt, ctx->V, mdt, ctx->H); }
   const double scale = ctx->coord ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
   {
-    Phase ph(ctx, "estimator");
-    HIPCHK(estimator(ctx->coord ? nullptr : ctx->Sk, sk_dt(ctx), ctx->coord ? ctx->C : nullptr, ctx->V, mdt, np,
-                     ctx->n, ctx->q, scale, ctx->red, ctx->est, ctx->status, ctx->stream));
+    Phase ph(ctx, L, "estimator");
+    HIPCHK(estimator(ctx->coord ? nullptr : S.Sk, sk_dt(ctx), ctx->coord ? S.C : nullptr, ctx->V, mdt, np, ctx->n,
+                     ctx->q, scale, L.red, ctx->est, ctx->status, L.s));
   }
   if (ctx->coord) {
-    Phase ph(ctx, "coord_update");
     // U = E_C G^-1 is not formed: W' = V - E_C/2 - E_C (G^-1 H)/2 and R = G^-1 W'^T;
     // the update touches only rows and columns C.
-    small_small(ctx, ctx->Ginv, false, ctx->H, ctx->GH);
-    HIPCHK(hipMemcpyAsync(ctx->W, ctx->V, (size_t)np * qp * dt_size(mdt), hipMemcpyDeviceToDevice, ctx->stream));
-    HIPCHK(coord_wprime_fix(ctx->W, mdt, np, ctx->C, ctx->q, ctx->GH, qp, ctx->stream));
+    Phase ph(ctx, L, "coord_update");
+    small_small(ctx, L, S.Ginv, false, ctx->H, ctx->GH);
+    HIPCHK(hipMemcpyAsync(ctx->W, ctx->V, (size_t)np * qp * dt_size(mdt), hipMemcpyDeviceToDevice, L.s));
+    HIPCHK(coord_wprime_fix(ctx->W, mdt, np, S.C, ctx->q, ctx->GH, qp, L.s));
     GemmArgs g;
     g.M = qp; g.N = np; g.K = qp;
-    g.A = ctx->Ginv; g.lda = qp; g.a_dt = DT_F64; g.a_kc = true;
+    g.A = S.Ginv; g.lda = qp; g.a_dt = DT_F64; g.a_kc = true;
     g.B = ctx->W; g.ldb = np; g.b_dt = mdt; g.b_kc = false;
     g.epi = EPI_ROWSTORE; g.C = ctx->R; g.ldc = np; g.c_dt = mdt; g.c2 = 1.0;
-    f64_gemm(ctx, g);
-    HIPCHK(coord_sym_update(ctx->X, mdt, np, ctx->C, ctx->pos, ctx->q, np, ctx->R, mdt, np, ctx->stream));
+    f64_gemm(ctx, L, g);
+    HIPCHK(coord_sym_update(ctx->X, mdt, np, S.C, ctx->pos, ctx->q, np, ctx->R, mdt, np, L.s));
     return;
   }
   if (ctx->mixed) {
-    float* U = (float*)ctx->U;
     float* W = (float*)ctx->W;
-    const int64_t ldp = 3 * qp, plane = np * ldp;  // operand planes [U | W' | U], row-major
-    __bf16* hi = ctx->planes;
-    __bf16* lo = ctx->planes + plane;
+    const int64_t ldp = 3 * qp, plane = np * ldp;
     {
-      Phase ph(ctx, "panels");
-      panel_times_small(ctx, ctx->Sk, DT_BF16, ctx->Ginv, U, DT_F32, 1.0);
-      panel_times_small(ctx, U, DT_F32, ctx->H, W, DT_F32, -0.5, ctx->V, DT_F32, 1.0, ctx->Sk, DT_BF16, -0.5);
-      HIPCHK(pack_split2(U, np, np, qp, hi, lo, ldp, 0, ctx->stream));
-      HIPCHK(pack_split2(W, np, np, qp, hi, lo, ldp, qp, ctx->stream));
-      HIPCHK(pack_split2(U, np, np, qp, hi, lo, ldp, 2 * qp, ctx->stream));
+      Phase ph(ctx, L, "panels");
+      panel_times_small(ctx, L, S.U, DT_F32, ctx->H, W, DT_F32, -0.5, ctx->V, DT_F32, 1.0, S.Sk, DT_BF16, -0.5);
+      HIPCHK(pack_split2(W, np, np, qp, S.planes, S.planes + plane, ldp, qp, L.s));
     }
-    Phase ph(ctx, "update");
+    Phase ph(ctx, L, "update");
     MixedGemm mg;
     GemmArgs& g = mg.g;
     g.M = np; g.N = np; g.K = 2 * qp;
-    g.A = hi; g.lda = ldp; g.a_plane = plane;
-    g.B = hi + qp; g.ldb = ldp; g.b_plane = plane;
+    g.A = S.planes; g.lda = ldp; g.a_plane = plane;
+    g.B = S.planes + qp; g.ldb = ldp; g.b_plane = plane;
     g.epi = EPI_SYMUPD; g.C = ctx->X; g.ldc = np; g.c2 = -1.0;
     mg.a_kind = OK_BF16_KC; mg.b_kind = OK_BF16_KC; mg.na = 2; mg.nb = 2; mg.pmax = 1;
-    bf_gemm(ctx, mg);
+    bf_gemm(ctx, L, mg);
   } else {
-    double* PQ = (double*)ctx->U;  // [U | W' | U], column-major, ld = np
-    double* U = PQ;
-    double* W = PQ + np * qp;
+    double* PQ = (double*)S.U;  // [U | W' | U], column-major, ld = np
     {
-      Phase ph(ctx, "panels");
-      panel_times_small(ctx, ctx->Sk, DT_F64, ctx->Ginv, U, DT_F64, 1.0);
-      panel_times_small(ctx, U, DT_F64, ctx->H, W, DT_F64, -0.5, ctx->V, DT_F64, 1.0, ctx->Sk, DT_F64, -0.5);
-      HIPCHK(hipMemcpyAsync(PQ + 2 * np * qp, U, (size_t)np * qp * sizeof(double), hipMemcpyDeviceToDevice,
-                            ctx->stream));
+      Phase ph(ctx, L, "panels");
+      panel_times_small(ctx, L, PQ, DT_F64, ctx->H, PQ + np * qp, DT_F64, -0.5, ctx->V, DT_F64, 1.0, S.Sk, DT_F64,
+                        -0.5);
     }
-    Phase ph(ctx, "update");
+    Phase ph(ctx, L, "update");
     GemmArgs g;
     g.M = np; g.N = np; g.K = 2 * qp;
     g.A = PQ; g.lda = np; g.a_dt = DT_F64; g.a_kc = false;
     g.B = PQ + np * qp; g.ldb = np; g.b_dt = DT_F64; g.b_kc = false;
     g.epi = EPI_SYMUPD; g.C = ctx->X; g.ldc = np; g.c_dt = DT_F64; g.c2 = -1.0;
-    f64_gemm(ctx, g);
+    f64_gemm(ctx, L, g);
   }
 }
 
-// One AdaRBFGS iteration, eq. (Cholimprov) with R = L_G^-T, C = L_M^-1:
+// L-dependent part of one AdaRBFGS iteration, eq. (Cholimprov) with R = L_G^-T,
+// C = L_M^-1 (L_M^-1 from the slot):
 //   S = L S~,  Y = A S,  G = S^T Y = L_G L_G^T,  T^T = L^T Y,
 //   Q^T = S~ (L_M^-T L_G^-1) - T^T G^-1,  L+ = L + S Q.
-void step_adaptive(rbfgs_ctx* ctx) {
+void main_adaptive(rbfgs_ctx* ctx, Slot& S) {
+  const Lane& L = ctx->main;
   const int64_t np = ctx->np, qp = ctx->qp;
   const int mdt = ctx->mdt;
-  { Phase ph(ctx, "sketch"); do_sketch(ctx, ctx->k); }
   if (ctx->coord) {
-    Phase ph(ctx, "gather");
-    HIPCHK(gather_cols_gen(ctx->X, mdt, np, ctx->C, ctx->q, np, ctx->Sa, mdt, np, ctx->stream));
+    Phase ph(ctx, L, "gather");
+    HIPCHK(gather_cols_gen(ctx->X, mdt, np, S.C, ctx->q, np, ctx->Sa, mdt, np, L.s));
   } else {
-    Phase ph(ctx, "LS");
-    nn_times_panel(ctx, ctx->X, false, ctx->Sk, sk_dt(ctx), ctx->Sa, 3, 1, 2);  // S = L S~, exact products
+    Phase ph(ctx, L, "LS");
+    nn_times_panel(ctx, L, ctx->X, false, S.Sk, sk_dt(ctx), ctx->Sa, 3, 1, 2);  // S = L S~, exact products
   }
-  { Phase ph(ctx, "AS"); nn_times_panel(ctx, ctx->A, false, ctx->Sa, mdt, ctx->Y, 3, 2, 2); }
-  { Phase ph(ctx, "gram_G"); gram(ctx, ctx->Sa, mdt, ctx->Y, mdt, ctx->G); }
-  { Phase ph(ctx, "chol_inv"); HIPCHK(chol_inv(ctx->G, qp, ctx->q, ctx->Z, ctx->Ginv, qp, ctx->cwork, ctx->status, ctx->stream)); }
-  { Phase ph(ctx, "LtY"); nn_times_panel(ctx, ctx->X, true, ctx->Y, mdt, ctx->V, 2, 3, 2); }  // T^T = L^T Y
+  { Phase ph(ctx, L, "AS"); nn_times_panel(ctx, L, ctx->A, false, ctx->Sa, mdt, ctx->Y, 3, 2, 2); }
+  { Phase ph(ctx, L, "gram_G"); gram(ctx, L, ctx->Sa, mdt, ctx->Y, mdt, ctx->G); }
+  {
+    Phase ph(ctx, L, "chol_inv");
+    HIPCHK(chol_inv(ctx->G, qp, ctx->q, ctx->Z, ctx->Ginv, qp, L.cwork, ctx->status, L.s));
+  }
+  { Phase ph(ctx, L, "LtY"); nn_times_panel(ctx, L, ctx->X, true, ctx->Y, mdt, ctx->V, 2, 3, 2); }  // T^T = L^T Y
   const double scale = ctx->coord ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
   {
-    Phase ph(ctx, "panels");
-    HIPCHK(estimator(ctx->coord ? nullptr : ctx->Sk, sk_dt(ctx), ctx->coord ? ctx->C : nullptr, ctx->V, mdt, np,
-                     ctx->n, ctx->q, scale, ctx->red, ctx->est, ctx->status, ctx->stream));
-    // Q^T = -T^T G^-1 (+ S~ Mq)
-    panel_times_small(ctx, ctx->V, mdt, ctx->Ginv, ctx->W, mdt, -1.0);
+    Phase ph(ctx, L, "panels");
+    HIPCHK(estimator(ctx->coord ? nullptr : S.Sk, sk_dt(ctx), ctx->coord ? S.C : nullptr, ctx->V, mdt, np, ctx->n,
+                     ctx->q, scale, L.red, ctx->est, ctx->status, L.s));
+    panel_times_small(ctx, L, ctx->V, mdt, ctx->Ginv, ctx->W, mdt, -1.0);  // Q^T = -T^T G^-1
     if (ctx->coord) {
-      HIPCHK(coord_add_rows(ctx->W, mdt, np, ctx->C, ctx->q, ctx->Z, qp, ctx->stream));  // Mq = Z_G
+      HIPCHK(coord_add_rows(ctx->W, mdt, np, S.C, ctx->q, ctx->Z, qp, L.s));  // + E_C L_G^-1
     } else {
-      gram(ctx, ctx->Sk, sk_dt(ctx), ctx->Sk, sk_dt(ctx), ctx->Mm);
-      HIPCHK(chol_inv(ctx->Mm, qp, ctx->q, ctx->Zm, nullptr, qp, ctx->cwork, ctx->status, ctx->stream));
-      small_small(ctx, ctx->Zm, true, ctx->Z, ctx->Mq);  // Mq = Z_M^T Z_G
-      panel_times_small(ctx, ctx->Sk, sk_dt(ctx), ctx->Mq, ctx->W, mdt, 1.0, ctx->W, mdt, 1.0);
+      small_small(ctx, L, S.Z, true, ctx->Z, ctx->Mq);  // Mq = L_M^-T L_G^-1
+      panel_times_small(ctx, L, S.Sk, sk_dt(ctx), ctx->Mq, ctx->W, mdt, 1.0, ctx->W, mdt, 1.0);
     }
   }
-  // L += S Q
-  Phase ph(ctx, "update");
+  Phase ph(ctx, L, "update");  // L += S Q
   if (ctx->mixed) {
     const int64_t plane = np * qp;
     __bf16* shi = ctx->planes;
     __bf16* qhi = ctx->planes + 2 * plane;
-    HIPCHK(pack_split2((const float*)ctx->Sa, np, np, qp, shi, shi + plane, qp, 0, ctx->stream));
-    HIPCHK(pack_split2((const float*)ctx->W, np, np, qp, qhi, qhi + plane, qp, 0, ctx->stream));
+    HIPCHK(pack_split2((const float*)ctx->Sa, np, np, qp, shi, shi + plane, qp, 0, L.s));
+    HIPCHK(pack_split2((const float*)ctx->W, np, np, qp, qhi, qhi + plane, qp, 0, L.s));
     MixedGemm mg;
     GemmArgs& g = mg.g;
     g.M = np; g.N = np; g.K = qp;
@@ -369,14 +416,39 @@ void step_adaptive(rbfgs_ctx* ctx) {
     g.B = qhi; g.ldb = qp; g.b_plane = plane;
     g.epi = EPI_ADDROW; g.C = ctx->X; g.ldc = np; g.c2 = 1.0;
     mg.a_kind = OK_BF16_KC; mg.b_kind = OK_BF16_KC; mg.na = 2; mg.nb = 2; mg.pmax = 1;
-    bf_gemm(ctx, mg);
+    bf_gemm(ctx, L, mg);
   } else {
     GemmArgs g;
     g.M = np; g.N = np; g.K = qp;
     g.A = ctx->Sa; g.lda = np; g.a_dt = DT_F64; g.a_kc = false;
     g.B = ctx->W; g.ldb = np; g.b_dt = DT_F64; g.b_kc = false;
     g.epi = EPI_ADDROW; g.C = ctx->X; g.ldc = np; g.c_dt = DT_F64; g.c2 = 1.0;
-    f64_gemm(ctx, g);
+    f64_gemm(ctx, L, g);
+  }
+}
+
+// Enqueue iterations k .. k+nsteps-1: the side lane runs one iteration ahead.
+void enqueue_steps(rbfgs_ctx* ctx, int64_t nsteps) {
+  if (nsteps <= 0) return;
+  HIPCHK(hipEventRecord(ctx->ev_begin, ctx->main.s));
+  HIPCHK(hipStreamWaitEvent(ctx->side.s, ctx->ev_begin, 0));
+  auto side = [&](int64_t k) {
+    Slot& S = ctx->slot[k & 1];
+    if (S.released_valid) HIPCHK(hipStreamWaitEvent(ctx->side.s, S.released, 0));
+    side_chain(ctx, k, S);
+    HIPCHK(hipEventRecord(S.ready, ctx->side.s));
+  };
+  side(ctx->k);
+  for (int64_t i = 0; i < nsteps; ++i) {
+    const int64_t k = ctx->k;
+    if (i + 1 < nsteps) side(k + 1);
+    Slot& S = ctx->slot[k & 1];
+    HIPCHK(hipStreamWaitEvent(ctx->main.s, S.ready, 0));
+    if (ctx->ada) main_adaptive(ctx, S);
+    else main_fixed(ctx, S);
+    HIPCHK(hipEventRecord(S.released, ctx->main.s));
+    S.released_valid = true;
+    ++ctx->k;
   }
 }
 
@@ -387,8 +459,9 @@ rbfgs_status fail(rbfgs_ctx* ctx, rbfgs_status st, const std::string& msg) {
 
 rbfgs_status read_status(rbfgs_ctx* ctx) {
   int st = 0;
-  HIPCHK(hipMemcpyAsync(&st, ctx->status, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipStreamSynchronize(ctx->side.s));
+  HIPCHK(hipMemcpyAsync(&st, ctx->status, sizeof(int), hipMemcpyDeviceToHost, ctx->main.s));
+  HIPCHK(hipStreamSynchronize(ctx->main.s));
   if (st == 3) return fail(ctx, RBFGS_E_NOT_SPD, "Cholesky of S^T A S met a non-positive pivot (A not SPD?)");
   if (st == 4) return fail(ctx, RBFGS_E_NONFINITE, "non-finite value in the iteration");
   if (st) return fail(ctx, RBFGS_E_DEVICE, "unknown device status");
@@ -397,6 +470,7 @@ rbfgs_status read_status(rbfgs_ctx* ctx) {
 
 double exact_residual(rbfgs_ctx* ctx) {
   const int64_t np = ctx->np;
+  const Lane& L = ctx->main;
   void* tmp = nullptr;
   GemmArgs g;
   g.M = np; g.N = np; g.K = np;
@@ -407,19 +481,63 @@ double exact_residual(rbfgs_ctx* ctx) {
     GemmArgs b = g;
     b.B = ctx->X; b.ldb = np; b.b_dt = ctx->mdt; b.b_kc = false;
     b.epi = EPI_ROWSTORE; b.C = tmp; b.ldc = np; b.c_dt = DT_F64; b.c2 = 1.0;
-    HIPCHK(gemm_f64(b, nullptr, ctx->stream));
+    HIPCHK(gemm_f64(b, nullptr, L.s));
     g.A = tmp; g.a_dt = DT_F64;
   }
   g.B = ctx->X; g.ldb = np; g.b_dt = ctx->mdt; g.b_kc = true;  // X symmetric; for L: Bop(k,j) = L[j][k]
-  g.epi = EPI_RESID; g.red = ctx->red; g.nvalid = ctx->n;
+  g.epi = EPI_RESID; g.red = L.red; g.nvalid = ctx->n;
   const int64_t blocks = gemm_f64_blocks(g);
-  HIPCHK(gemm_f64(g, nullptr, ctx->stream));
-  HIPCHK(reduce_sum(ctx->red, blocks, ctx->est + 1, ctx->stream));
+  HIPCHK(gemm_f64(g, nullptr, L.s));
+  HIPCHK(reduce_sum(L.red, blocks, ctx->est + 1, L.s));
   double r2 = 0;
-  HIPCHK(hipMemcpyAsync(&r2, ctx->est + 1, sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipMemcpyAsync(&r2, ctx->est + 1, sizeof(double), hipMemcpyDeviceToHost, L.s));
+  HIPCHK(hipStreamSynchronize(L.s));
   if (tmp) HIPCHK(hipFree(tmp));
   return sqrt(r2);
+}
+
+void make_lane(rbfgs_ctx* ctx, Lane& L, size_t partial_bytes, size_t red_count) {
+  L.partial_bytes = partial_bytes;
+  L.partial = dalloc(ctx, partial_bytes);
+  L.red = (double*)dalloc(ctx, red_count * sizeof(double));
+  L.cwork = (double*)dalloc(ctx, chol_inv_work_doubles(ctx->q) * sizeof(double));
+}
+
+void make_slot(rbfgs_ctx* ctx, Slot& S) {
+  const int64_t np = ctx->np, qp = ctx->qp;
+  const size_t es = dt_size(ctx->mdt), qq = (size_t)qp * qp * sizeof(double);
+  S.Sk = dalloc(ctx, np * qp * dt_size(sk_dt(ctx)));
+  S.C = (int32_t*)dalloc(ctx, qp * sizeof(int32_t));
+  S.G = (double*)dalloc(ctx, qq);
+  S.Z = (double*)dalloc(ctx, qq);
+  if (!ctx->ada) {
+    S.Y = dalloc(ctx, np * qp * es);
+    S.Ginv = (double*)dalloc(ctx, qq);
+    if (!ctx->coord) {
+      S.U = dalloc(ctx, (ctx->mixed ? 1 : 3) * np * qp * es);
+      if (ctx->mixed) S.planes = (__bf16*)dalloc(ctx, (size_t)2 * 3 * np * qp * sizeof(__bf16));
+    }
+  }
+  HIPCHK(hipEventCreateWithFlags(&S.ready, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&S.released, hipEventDisableTiming));
+}
+
+void release(rbfgs_ctx* ctx) {
+  (void)hipStreamSynchronize(ctx->main.s);
+  if (ctx->side.s) (void)hipStreamSynchronize(ctx->side.s);
+  for (auto& r : ctx->prof_pending) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  for (Slot& S : ctx->slot) {
+    if (S.ready) (void)hipEventDestroy(S.ready);
+    if (S.released) (void)hipEventDestroy(S.released);
+  }
+  if (ctx->ev_begin) (void)hipEventDestroy(ctx->ev_begin);
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  if (ctx->side.s) (void)hipStreamDestroy(ctx->side.s);
+  delete ctx;
 }
 
 }  // namespace
@@ -448,23 +566,30 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
   ctx->ada = p.variant == RBFGS_ADAPTIVE;
   ctx->coord = p.sketch == RBFGS_SKETCH_COORD;
   ctx->mdt = ctx->mixed ? DT_F32 : DT_F64;
-  ctx->stream = (hipStream_t)hip_stream;
+  ctx->main.s = (hipStream_t)hip_stream;
   try {
     HIPCHK(hipGetDevice(&ctx->device));
+    HIPCHK(hipStreamCreateWithFlags(&ctx->side.s, hipStreamNonBlocking));  // default priority
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_begin, hipEventDisableTiming));
     const int64_t np = ctx->np, qp = ctx->qp;
     const size_t es = dt_size(ctx->mdt);
+    const size_t partial = std::max<size_t>((size_t)8 * np * qp * 8, (size_t)128 * qp * qp * sizeof(double));
+    const size_t red = (size_t)std::max<int64_t>(4096, (np / 32) * (np / 32) + 16);
+    make_lane(ctx, ctx->main, partial, red);
+    make_lane(ctx, ctx->side, partial, 4096);
+    make_slot(ctx, ctx->slot[0]);
+    make_slot(ctx, ctx->slot[1]);
     ctx->A = dalloc(ctx, np * np * es);
     ctx->X = dalloc(ctx, np * np * es);
-    ctx->Sk = dalloc(ctx, np * qp * dt_size(sk_dt(ctx)));
-    ctx->C = (int32_t*)dalloc(ctx, qp * sizeof(int32_t));
     ctx->pos = (int32_t*)dalloc(ctx, np * sizeof(int32_t));
-    HIPCHK(hipMemsetAsync(ctx->pos, 0xff, np * sizeof(int32_t), ctx->stream));  // -1
-    ctx->Y = dalloc(ctx, np * qp * es);
+    HIPCHK(hipMemsetAsync(ctx->pos, 0xff, np * sizeof(int32_t), ctx->main.s));  // -1
     ctx->V = dalloc(ctx, np * qp * es);
     ctx->W = dalloc(ctx, np * qp * es);
-    if (ctx->ada) ctx->Sa = dalloc(ctx, np * qp * es);
-    if (!ctx->ada) ctx->U = dalloc(ctx, (ctx->mixed ? 1 : 3) * np * qp * es);
-    if (ctx->mixed) ctx->planes = (__bf16*)dalloc(ctx, (size_t)2 * 3 * np * qp * sizeof(__bf16));
+    if (ctx->ada) {
+      ctx->Sa = dalloc(ctx, np * qp * es);
+      ctx->Y = dalloc(ctx, np * qp * es);
+      if (ctx->mixed) ctx->planes = (__bf16*)dalloc(ctx, (size_t)4 * np * qp * sizeof(__bf16));
+    }
     if (!ctx->ada && ctx->coord) ctx->R = dalloc(ctx, qp * np * es);
     const size_t qq = (size_t)qp * qp * sizeof(double);
     ctx->G = (double*)dalloc(ctx, qq);
@@ -472,14 +597,7 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
     ctx->Ginv = (double*)dalloc(ctx, qq);
     ctx->Z = (double*)dalloc(ctx, qq);
     ctx->GH = (double*)dalloc(ctx, qq);
-    ctx->Zm = (double*)dalloc(ctx, qq);
-    ctx->Mm = (double*)dalloc(ctx, qq);
     ctx->Mq = (double*)dalloc(ctx, qq);
-    ctx->cwork = (double*)dalloc(ctx, chol_inv_work_doubles(ctx->q) * sizeof(double));
-    ctx->partial_bytes = std::max<size_t>((size_t)8 * np * qp * es, (size_t)64 * qp * qp * sizeof(double));
-    ctx->partial = dalloc(ctx, ctx->partial_bytes);
-    ctx->red_count = std::max<int64_t>(4096, (np / 32) * (np / 32) + 16);
-    ctx->red = (double*)dalloc(ctx, ctx->red_count * sizeof(double));
     ctx->est = (double*)dalloc(ctx, 4 * sizeof(double));
     ctx->status = (int*)dalloc(ctx, sizeof(int));
     // copy A (n x n, lda) into the padded np x np buffer, converting its type
@@ -489,36 +607,31 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
     void* staging = nullptr;
     if (!a_on_device) {
       HIPCHK(hipMalloc(&staging, (size_t)p.n * lda * ses));
-      HIPCHK(hipMemcpyAsync(staging, A, (size_t)p.n * lda * ses, hipMemcpyHostToDevice, ctx->stream));
+      HIPCHK(hipMemcpyAsync(staging, A, (size_t)p.n * lda * ses, hipMemcpyHostToDevice, ctx->main.s));
       Adev = staging;
     }
     int* flag = ctx->status;
-    HIPCHK(check_sym_finite(Adev, sdt, lda, p.n, flag, ctx->stream));
-    HIPCHK(copy_convert(Adev, sdt, lda, ctx->A, ctx->mdt, np, p.n, p.n, ctx->stream));
+    HIPCHK(check_sym_finite(Adev, sdt, lda, p.n, flag, ctx->main.s));
+    HIPCHK(copy_convert(Adev, sdt, lda, ctx->A, ctx->mdt, np, p.n, p.n, ctx->main.s));
     int bad = 0;
-    HIPCHK(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->main.s));
+    HIPCHK(hipStreamSynchronize(ctx->main.s));
     if (staging) HIPCHK(hipFree(staging));
+    if (!bad && ctx->mixed) {  // the stored FP32 A must also be symmetric and finite
+      HIPCHK(check_sym_finite(ctx->A, DT_F32, np, p.n, flag, ctx->main.s));
+      HIPCHK(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->main.s));
+      HIPCHK(hipStreamSynchronize(ctx->main.s));
+    }
     if (bad) {
-      rbfgs_destroy(ctx);
+      release(ctx);
       return RBFGS_E_INVALID_ARG;
     }
-    if (ctx->mixed) {
-      // the stored FP32 A must also be symmetric and finite
-      HIPCHK(check_sym_finite(ctx->A, DT_F32, np, p.n, flag, ctx->stream));
-      HIPCHK(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
-      HIPCHK(hipStreamSynchronize(ctx->stream));
-      if (bad) {
-        rbfgs_destroy(ctx);
-        return RBFGS_E_INVALID_ARG;
-      }
-    }
-    HIPCHK(set_identity(ctx->X, ctx->mdt, np, p.n, ctx->stream));
+    HIPCHK(set_identity(ctx->X, ctx->mdt, np, p.n, ctx->main.s));
     const double nanv = NAN;
-    HIPCHK(hipMemcpyAsync(ctx->est, &nanv, sizeof(double), hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->est, &nanv, sizeof(double), hipMemcpyHostToDevice, ctx->main.s));
+    HIPCHK(hipStreamSynchronize(ctx->main.s));
   } catch (const Fail& f) {
-    rbfgs_destroy(ctx);
+    release(ctx);
     return f.st;
   }
   *out = ctx;
@@ -528,11 +641,7 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
 rbfgs_status rbfgs_step(rbfgs_ctx* ctx, int64_t nsteps) {
   if (!ctx || nsteps < 0) return RBFGS_E_INVALID_ARG;
   try {
-    for (int64_t i = 0; i < nsteps; ++i) {
-      if (ctx->ada) step_adaptive(ctx);
-      else step_fixed(ctx);
-      ++ctx->k;
-    }
+    enqueue_steps(ctx, nsteps);
   } catch (const Fail& f) {
     return f.st;
   }
@@ -581,10 +690,9 @@ rbfgs_status rbfgs_invert(rbfgs_ctx* ctx, double tol, int64_t max_iters, int64_t
   try {
     while (done < max_iters) {
       const int64_t m = std::min<int64_t>(ctx->p.check_every, max_iters - done);
-      rbfgs_status st = rbfgs_step(ctx, m);
-      if (st != RBFGS_OK) { result = st; break; }
+      enqueue_steps(ctx, m);
       done += m;
-      st = read_status(ctx);
+      rbfgs_status st = read_status(ctx);
       if (st != RBFGS_OK) { result = st; break; }
       double est = 0;
       HIPCHK(hipMemcpy(&est, ctx->est, sizeof(double), hipMemcpyDeviceToHost));
@@ -609,16 +717,17 @@ static rbfgs_status copy_out(rbfgs_ctx* ctx, const void* src, int src_dt, int64_
                              int64_t ldd, int32_t on_device) {
   const int ddt = d_dtype == RBFGS_F32 ? DT_F32 : DT_F64;
   const int64_t n = ctx->n;
+  hipStream_t s = ctx->main.s;
   if (on_device) {
-    HIPCHK(copy_convert(src, src_dt, lds, dst, ddt, ldd, n, n, ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(copy_convert(src, src_dt, lds, dst, ddt, ldd, n, n, s));
+    HIPCHK(hipStreamSynchronize(s));
     return RBFGS_OK;
   }
   void* tmp = nullptr;
   HIPCHK(hipMalloc(&tmp, (size_t)n * ldd * dt_size(ddt)));
-  HIPCHK(copy_convert(src, src_dt, lds, tmp, ddt, ldd, n, n, ctx->stream));
-  HIPCHK(hipMemcpyAsync(dst, tmp, (size_t)n * ldd * dt_size(ddt), hipMemcpyDeviceToHost, ctx->stream));
-  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(copy_convert(src, src_dt, lds, tmp, ddt, ldd, n, n, s));
+  HIPCHK(hipMemcpyAsync(dst, tmp, (size_t)n * ldd * dt_size(ddt), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipFree(tmp));
   return RBFGS_OK;
 }
@@ -637,7 +746,7 @@ rbfgs_status rbfgs_get_x(rbfgs_ctx* ctx, void* X, int32_t x_dtype, int64_t ldx, 
     g.A = ctx->X; g.lda = np; g.a_dt = ctx->mdt; g.a_kc = true;
     g.B = ctx->X; g.ldb = np; g.b_dt = ctx->mdt; g.b_kc = true;  // Bop(k,j) = L[j][k]
     g.epi = EPI_ROWSTORE; g.C = tmp; g.ldc = np; g.c_dt = DT_F64; g.c2 = 1.0;
-    HIPCHK(gemm_f64(g, nullptr, ctx->stream));
+    HIPCHK(gemm_f64(g, nullptr, ctx->main.s));
     st = copy_out(ctx, tmp, DT_F64, np, X, x_dtype, ldx, on_device);
     HIPCHK(hipFree(tmp));
     return st;
@@ -667,14 +776,15 @@ rbfgs_status rbfgs_set_state(rbfgs_ctx* ctx, const void* M, int32_t m_dtype, int
     const int64_t n = ctx->n;
     const void* src = M;
     void* staging = nullptr;
+    HIPCHK(hipStreamSynchronize(ctx->side.s));
     if (!on_device) {
       HIPCHK(hipMalloc(&staging, (size_t)n * ldm * dt_size(sdt)));
-      HIPCHK(hipMemcpyAsync(staging, M, (size_t)n * ldm * dt_size(sdt), hipMemcpyHostToDevice, ctx->stream));
+      HIPCHK(hipMemcpyAsync(staging, M, (size_t)n * ldm * dt_size(sdt), hipMemcpyHostToDevice, ctx->main.s));
       src = staging;
     }
-    HIPCHK(copy_convert(src, sdt, ldm, ctx->X, ctx->mdt, ctx->np, n, n, ctx->stream));
-    HIPCHK(hipMemsetAsync(ctx->status, 0, sizeof(int), ctx->stream));
-    HIPCHK(hipStreamSynchronize(ctx->stream));
+    HIPCHK(copy_convert(src, sdt, ldm, ctx->X, ctx->mdt, ctx->np, n, n, ctx->main.s));
+    HIPCHK(hipMemsetAsync(ctx->status, 0, sizeof(int), ctx->main.s));
+    HIPCHK(hipStreamSynchronize(ctx->main.s));
     if (staging) HIPCHK(hipFree(staging));
     ctx->k = k;
   } catch (const Fail& f) {
@@ -690,15 +800,7 @@ rbfgs_status rbfgs_get_iter(const rbfgs_ctx* ctx, int64_t* k_out) {
 }
 
 void rbfgs_destroy(rbfgs_ctx* ctx) {
-  if (!ctx) return;
-  (void)hipStreamSynchronize(ctx->stream);
-  for (auto& r : ctx->prof_pending) {
-    (void)hipEventDestroy(r.a);
-    (void)hipEventDestroy(r.b);
-  }
-  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
-  for (void* p : ctx->allocs) (void)hipFree(p);
-  delete ctx;
+  if (ctx) release(ctx);
 }
 
 rbfgs_status rbfgs_profile(rbfgs_ctx* ctx, int32_t enable) {

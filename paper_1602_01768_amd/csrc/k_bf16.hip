@@ -14,6 +14,12 @@ namespace rb {
 namespace {
 
 constexpr int BK = 32;
+#ifndef RB_TS_PF
+#define RB_TS_PF 2  // register prefetch depth of the tall-skinny products
+#endif
+#ifndef RB_UPD_TILE
+#define RB_UPD_TILE 256
+#endif
 constexpr int PITCH = BK + 8;  // bf16 elements per LDS row (80 bytes)
 
 template <int NP>
@@ -36,11 +42,11 @@ RB_DEV void tri_index32(int64_t t, int64_t& ti, int64_t& tj) {
 }
 
 // Loader for one operand tile of ROWS (m or n) x BK into LDS planes [NP][ROWS][PITCH].
-template <int ROWS, int NP, int KIND>
+template <int ROWS, int NP, int KIND, int NT>
 struct TileLoader {
   // registers held between the global load and the LDS store
-  static constexpr int F4 = (KIND == OK_BF16_KC) ? 1 : ROWS * BK / 4 / 256;     // float4 per thread
-  static constexpr int V8 = (KIND == OK_BF16_KC) ? (ROWS * 4 + 255) / 256 : 1;  // 16-byte chunks per plane
+  static constexpr int F4 = (KIND == OK_BF16_KC) ? 1 : ROWS * BK / 4 / NT;     // float4 per thread
+  static constexpr int V8 = (KIND == OK_BF16_KC) ? (ROWS * (BK / 8) + NT - 1) / NT : 1;  // 16-byte chunks per plane
   float4 f[F4 > 0 ? F4 : 1];
   bf16x8 h[NP][V8];
 
@@ -49,15 +55,15 @@ struct TileLoader {
       const float* A = (const float*)base;
 #pragma unroll
       for (int i = 0; i < F4; ++i) {
-        const int e = tid + 256 * i;
-        const int row = e >> 3, c4 = (e & 7) * 4;
+        const int e = tid + NT * i;
+        const int row = e / (BK / 4), c4 = (e % (BK / 4)) * 4;
         f[i] = *(const float4*)(A + (r0 + row) * ld + k0 + c4);
       }
     } else if constexpr (KIND == OK_F32_MC) {
       const float* A = (const float*)base;
 #pragma unroll
       for (int i = 0; i < F4; ++i) {
-        const int e = tid + 256 * i;
+        const int e = tid + NT * i;
         const int kk = e / (ROWS / 4), m4 = (e % (ROWS / 4)) * 4;
         f[i] = *(const float4*)(A + (k0 + kk) * ld + r0 + m4);
       }
@@ -67,9 +73,9 @@ struct TileLoader {
       for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int i = 0; i < V8; ++i) {
-          const int e = tid + 256 * i;
-          if (e < ROWS * 4) {
-            const int row = e >> 2, c8 = (e & 3) * 8;
+          const int e = tid + NT * i;
+          if (ROWS * (BK / 8) % NT == 0 || e < ROWS * (BK / 8)) {
+            const int row = e / (BK / 8), c8 = (e % (BK / 8)) * 8;
             h[p][i] = *(const bf16x8*)(A + p * plane + (r0 + row) * ld + k0 + c8);
           }
         }
@@ -80,8 +86,8 @@ struct TileLoader {
     if constexpr (KIND == OK_F32_KC) {
 #pragma unroll
       for (int i = 0; i < F4; ++i) {
-        const int e = tid + 256 * i;
-        const int row = e >> 3, c4 = (e & 7) * 4;
+        const int e = tid + NT * i;
+        const int row = e / (BK / 4), c4 = (e % (BK / 4)) * 4;
         __bf16 p0[NP], p1[NP], p2[NP], p3[NP];
         split_n<NP>(f[i].x, p0);
         split_n<NP>(f[i].y, p1);
@@ -96,7 +102,7 @@ struct TileLoader {
     } else if constexpr (KIND == OK_F32_MC) {
 #pragma unroll
       for (int i = 0; i < F4; ++i) {
-        const int e = tid + 256 * i;
+        const int e = tid + NT * i;
         const int kk = e / (ROWS / 4), m4 = (e % (ROWS / 4)) * 4;
         const float vals[4] = {f[i].x, f[i].y, f[i].z, f[i].w};
 #pragma unroll
@@ -112,9 +118,9 @@ struct TileLoader {
       for (int p = 0; p < NP; ++p)
 #pragma unroll
         for (int i = 0; i < V8; ++i) {
-          const int e = tid + 256 * i;
-          if (e < ROWS * 4) {
-            const int row = e >> 2, c8 = (e & 3) * 8;
+          const int e = tid + NT * i;
+          if (ROWS * (BK / 8) % NT == 0 || e < ROWS * (BK / 8)) {
+            const int row = e / (BK / 8), c8 = (e % (BK / 8)) * 8;
             *(bf16x8*)(lds + (p * ROWS + row) * PITCH + c8) = h[p][i];
           }
         }
@@ -122,16 +128,19 @@ struct TileLoader {
   }
 };
 
-// 256 threads = 4 waves as WAVES_M x (4 / WAVES_M); wave tile WM x WN of 32 x 32 blocks.
+// NT = 64 * WAVES_M * WAVES_N threads; wave tile WM x WN of 32 x 32 blocks.
 // v_mfma_f32_32x32x16_bf16: lane l holds A(l%32, 8*(l/32) .. +7), B(8*(l/32) .. +7, l%32);
 // output column l%32, rows 8*(r/4) + 4*(l/32) + r%4 for r = 0..15.
-template <int BM, int BN, int WAVES_M, int NA, int NB, int PMAX, int AK, int BKD>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
-  constexpr int WAVES_N = 4 / WAVES_M;
+// DBUF: read the fragments of the next 16-wide k sub-step while the current MFMAs
+// issue (costs registers); launch bounds ask for two waves per SIMD (<= 256 VGPRs).
+template <int BM, int BN, int WAVES_M, int WAVES_N, int NA, int NB, int PMAX, int AK, int BKD, bool DBUF, int EPI,
+          int PF>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArgs g) {
+  constexpr int NT = 64 * WAVES_M * WAVES_N;
   constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
   constexpr int FM = WM / 32, FN = WN / 32;
   constexpr int LOOP_E = (NA * BM + NB * BN) * PITCH;                 // bf16 elements
-  constexpr int EPI_E = 2 * 4 * 32 * (WM + 1);                       // floats as bf16 pairs
+  constexpr int EPI_E = 2 * WAVES_M * WAVES_N * 32 * 33;  // per-wave 32 x 33 float transpose buffers
   constexpr int SM = LOOP_E > EPI_E ? LOOP_E : EPI_E;
   __shared__ __attribute__((aligned(16))) __bf16 smem[SM];
   __bf16* As = smem;
@@ -144,8 +153,13 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   int kc = 0;
   bool diag = false;
   const int64_t bid = blockIdx.x;
-  if (g.epi == EPI_SYMUPD) {
-    tri_index32(bid, mt, nt);
+  if constexpr (EPI == EPI_SYMUPD) {
+    // lower-triangular tiles; each XCD (blockIdx % 8) takes a contiguous run of the
+    // row-major tile order so that consecutive tiles on it share their row panel in L2
+    const int64_t T = g.M / BM, NTT = T * (T + 1) / 2, per = (NTT + 7) / 8;
+    const int64_t t = (bid % 8) * per + bid / 8;
+    if (t >= NTT) return;
+    tri_index32(t, mt, nt);
     diag = (mt == nt);
   } else {
     kc = (int)(bid % g.splitk);
@@ -157,9 +171,6 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   const int64_t kbeg = kc * kchunk, kend = kbeg + kchunk;
   const int64_t m0 = mt * BM, n0 = nt * BN;
 
-  TileLoader<BM, NA, AK> la;
-  TileLoader<BN, NB, BKD> lb;
-
   f32x16 acc[FM][FN];
 #pragma unroll
   for (int a = 0; a < FM; ++a)
@@ -168,98 +179,139 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
-  la.load(g.A, g.lda, g.a_plane, m0, kbeg, tid);
-  lb.load(g.B, g.ldb, g.b_plane, n0, kbeg, tid);
-  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+  // One k tile: stage the registers of tile k0 into LDS, start the global loads of
+  // tile k0 + PF*BK into the same registers, then run the MFMAs on LDS.
+  auto k_tile = [&](auto& la, auto& lb, int64_t k0) {
     __syncthreads();
     la.store(As, tid);
     lb.store(Bs, tid);
     __syncthreads();
-    if (k0 + BK < kend) {
-      la.load(g.A, g.lda, g.a_plane, m0, k0 + BK, tid);
-      lb.load(g.B, g.ldb, g.b_plane, n0, k0 + BK, tid);
+    if (k0 + PF * BK < kend) {
+      la.load(g.A, g.lda, g.a_plane, m0, k0 + PF * BK, tid);
+      lb.load(g.B, g.ldb, g.b_plane, n0, k0 + PF * BK, tid);
     }
-#pragma unroll
-    for (int s = 0; s < BK / 16; ++s) {
-      const int kofs = s * 16 + 8 * (lane >> 5);
-      bf16x8 av[NA][FM], bv[NB][FN];
-#pragma unroll
-      for (int p = 0; p < NA; ++p)
-#pragma unroll
-        for (int a = 0; a < FM; ++a)
-          av[p][a] = *(const bf16x8*)(As + (p * BM + wm * WM + a * 32 + (lane & 31)) * PITCH + kofs);
-#pragma unroll
-      for (int p = 0; p < NB; ++p)
-#pragma unroll
-        for (int b = 0; b < FN; ++b)
-          bv[p][b] = *(const bf16x8*)(Bs + (p * BN + wn * WN + b * 32 + (lane & 31)) * PITCH + kofs);
-      // smallest pieces first
-#pragma unroll
-      for (int lvl = PMAX; lvl >= 0; --lvl)
-#pragma unroll
-        for (int pa = 0; pa < NA; ++pa) {
-          const int pb = lvl - pa;
-          if (pb < 0 || pb >= NB) continue;
-#pragma unroll
+      constexpr int NBUF = DBUF ? 2 : 1;
+      bf16x8 av[NBUF][NA][FM], bv[NBUF][NB][FN];
+      auto read_frags = [&](int s, int buf) {
+        const int kofs = s * 16 + 8 * (lane >> 5);
+  #pragma unroll
+        for (int p = 0; p < NA; ++p)
+  #pragma unroll
           for (int a = 0; a < FM; ++a)
-#pragma unroll
-            for (int b = 0; b < FN; ++b)
-              acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[pa][a], bv[pb][b], acc[a][b], 0, 0, 0);
-        }
+            av[buf][p][a] = *(const bf16x8*)(As + (p * BM + wm * WM + a * 32 + (lane & 31)) * PITCH + kofs);
+  #pragma unroll
+        for (int p = 0; p < NB; ++p)
+  #pragma unroll
+          for (int b = 0; b < FN; ++b)
+            bv[buf][p][b] = *(const bf16x8*)(Bs + (p * BN + wn * WN + b * 32 + (lane & 31)) * PITCH + kofs);
+      };
+      if (DBUF) read_frags(0, 0);
+  #pragma unroll
+      for (int s = 0; s < BK / 16; ++s) {
+        const int cur = DBUF ? (s & 1) : 0;
+        if (!DBUF) read_frags(s, 0);
+        else if (s + 1 < BK / 16) read_frags(s + 1, cur ^ 1);
+        // smallest pieces first
+  #pragma unroll
+        for (int lvl = PMAX; lvl >= 0; --lvl)
+  #pragma unroll
+          for (int pa = 0; pa < NA; ++pa) {
+            const int pb = lvl - pa;
+            if (pb < 0 || pb >= NB) continue;
+  #pragma unroll
+            for (int a = 0; a < FM; ++a)
+  #pragma unroll
+              for (int b = 0; b < FN; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[cur][pa][a], bv[cur][pb][b], acc[a][b], 0, 0, 0);
+          }
+      }
+
+  };
+
+  TileLoader<BM, NA, AK, NT> la0;
+  TileLoader<BN, NB, BKD, NT> lb0;
+  la0.load(g.A, g.lda, g.a_plane, m0, kbeg, tid);
+  lb0.load(g.B, g.ldb, g.b_plane, n0, kbeg, tid);
+  if constexpr (PF == 1) {
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) k_tile(la0, lb0, k0);
+  } else {
+    // two register stages in flight: tiles k0 and k0 + BK
+    TileLoader<BM, NA, AK, NT> la1;
+    TileLoader<BN, NB, BKD, NT> lb1;
+    if (kbeg + BK < kend) {
+      la1.load(g.A, g.lda, g.a_plane, m0, kbeg + BK, tid);
+      lb1.load(g.B, g.ldb, g.b_plane, n0, kbeg + BK, tid);
+    }
+    for (int64_t k0 = kbeg; k0 < kend; k0 += 2 * BK) {
+      k_tile(la0, lb0, k0);
+      if (k0 + BK < kend) k_tile(la1, lb1, k0 + BK);
     }
   }
 
   // ---------------------------------------------------------------- epilogue
   const int lr = (lane >> 5) * 4, lc = lane & 31;
-  if (g.epi == EPI_SYMUPD) {
-    __syncthreads();
-    float* R = (float*)smem + wave * 32 * (WM + 1);
-    float* X = (float*)g.C;
+  if constexpr (EPI == EPI_SYMUPD) {
+    // X += c2 * acc on the lower tile, one 32 x 32 block at a time: the old values
+    // of the block are loaded together, the new values go to X directly and,
+    // through a per-wave LDS transpose, to the mirrored positions as 128-byte rows.
+    __syncthreads();  // LDS is free once every wave left the k loop
+    float* R = (float*)smem + wave * 32 * 33;
+    const int ld = (int)g.ldc;
+    float* Xd = (float*)g.C + (m0 + wm * WM) * g.ldc + (n0 + wn * WN);  // this wave's block origin
+    float* Xm = (float*)g.C + (n0 + wn * WN) * g.ldc + (m0 + wm * WM);  // mirrored origin
     const float c2 = (float)g.c2;
+    const int dofs = (int)((m0 + wm * WM) - (n0 + wn * WN));           // m - n at the wave origin
 #pragma unroll
-    for (int b = 0; b < FN; ++b) {
-      const int64_t nb = n0 + wn * WN + b * 32;
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-      for (int a = 0; a < FM; ++a)
+      for (int b = 0; b < FN; ++b) {
+        float old[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r)
+          old[r] = Xd[(a * 32 + (r >> 2) * 8 + lr + (r & 3)) * ld + b * 32 + lc];
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int ml = a * 32 + (r >> 2) * 8 + lr + (r & 3);
-          const int64_t m = m0 + wm * WM + ml, n = nb + lc;
-          const int64_t idx = m * g.ldc + n;
-          const float nv = X[idx] + c2 * acc[a][b][r];
-          if (!diag || m >= n) X[idx] = nv;
-          R[lc * (WM + 1) + ml] = nv;
+          const int ml = (r >> 2) * 8 + lr + (r & 3);
+          const float nv = old[r] + c2 * acc[a][b][r];
+          // element (m, n): m - n = dofs + a*32 + ml - b*32 - lc
+          if (!diag || dofs + a * 32 + ml - b * 32 - lc >= 0) Xd[(a * 32 + ml) * ld + b * 32 + lc] = nv;
+          R[lc * 33 + ml] = nv;
         }
-      __syncthreads();
-      if (lane < WM) {
-        const int64_t mrow = m0 + wm * WM + lane;
-#pragma unroll 4
-        for (int c = 0; c < 32; ++c) {
-          const int64_t ncol = nb + c;
-          if (!diag || mrow > ncol) X[ncol * g.ldc + mrow] = R[c * (WM + 1) + lane];
+        __syncthreads();
+        if (lane < 32) {
+#pragma unroll 8
+          for (int c = 0; c < 32; ++c)
+            if (!diag || dofs + a * 32 + lane - b * 32 - c > 0) Xm[(b * 32 + c) * ld + a * 32 + lane] = R[c * 33 + lane];
         }
+        __syncthreads();
       }
-      __syncthreads();
-    }
     return;
   }
+  if constexpr (EPI == EPI_PARTIAL) {
+    // column-major partial sums of split kc: P[kc][n * M + m]
+    float* P = (float*)g.C + (int64_t)kc * g.M * g.N + (n0 + wn * WN) * g.M + (m0 + wm * WM);
+    const int ldp = (int)g.M;
 #pragma unroll
-  for (int a = 0; a < FM; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < FN; ++b)
+      for (int b = 0; b < FN; ++b)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t m = m0 + wm * WM + a * 32 + (r >> 2) * 8 + lr + (r & 3);
-        const int64_t n = n0 + wn * WN + b * 32 + lc;
-        const float v = acc[a][b][r];
-        if (g.epi == EPI_PARTIAL) {
-          ((float*)g.C)[(int64_t)kc * g.M * g.N + n * g.M + m] = v;
-        } else if (g.epi == EPI_ADDROW) {
-          float* C = (float*)g.C;
-          const int64_t idx = m * g.ldc + n;
-          C[idx] = C[idx] + (float)g.c2 * v;
+        for (int r = 0; r < 16; ++r)
+          P[(b * 32 + lc) * ldp + a * 32 + (r >> 2) * 8 + lr + (r & 3)] = acc[a][b][r];
+  } else if constexpr (EPI == EPI_ADDROW) {
+    float* C = (float*)g.C + (m0 + wm * WM) * g.ldc + (n0 + wn * WN);
+    const int ld = (int)g.ldc;
+    const float c2 = (float)g.c2;
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int o = (a * 32 + (r >> 2) * 8 + lr + (r & 3)) * ld + b * 32 + lc;
+          C[o] = C[o] + c2 * acc[a][b][r];
         }
-      }
+  }
 }
 
 __global__ void k_reduce_partials_f32(GemmArgs g, const float* P) {
@@ -297,18 +349,19 @@ __global__ void k_pack_split2(const float* in, int64_t ld_in, int64_t rows, int6
   }
 }
 
-template <int BN, int WAVES_M, int NA, int NB, int PMAX, int AK, int BKD>
+template <int BN, int WAVES_M, int WAVES_N, int NA, int NB, int PMAX, int AK, int BKD>
 void launch_ts(const GemmArgs& g, int64_t blocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_gemm_bf16<128, BN, WAVES_M, NA, NB, PMAX, AK, BKD>), dim3(blocks), dim3(256), 0, s, g);
+  hipLaunchKernelGGL((k_gemm_bf16<128, BN, WAVES_M, WAVES_N, NA, NB, PMAX, AK, BKD, false, EPI_PARTIAL, RB_TS_PF>), dim3(blocks),
+                     dim3(64 * WAVES_M * WAVES_N), 0, s, g);
 }
 
 template <int NA, int NB, int PMAX, int AK, int BKD>
 hipError_t launch_tall(const GemmArgs& g, int bn, int64_t blocks, hipStream_t s) {
   switch (bn) {
-    case 256: launch_ts<256, 2, NA, NB, PMAX, AK, BKD>(g, blocks, s); break;
-    case 128: launch_ts<128, 2, NA, NB, PMAX, AK, BKD>(g, blocks, s); break;
-    case 64: launch_ts<64, 2, NA, NB, PMAX, AK, BKD>(g, blocks, s); break;
-    default: launch_ts<32, 4, NA, NB, PMAX, AK, BKD>(g, blocks, s); break;
+    case 256: launch_ts<256, 2, 4, NA, NB, PMAX, AK, BKD>(g, blocks, s); break;
+    case 128: launch_ts<128, 2, 2, NA, NB, PMAX, AK, BKD>(g, blocks, s); break;
+    case 64: launch_ts<64, 2, 2, NA, NB, PMAX, AK, BKD>(g, blocks, s); break;
+    default: launch_ts<32, 4, 1, NA, NB, PMAX, AK, BKD>(g, blocks, s); break;
   }
   return hipGetLastError();
 }
@@ -322,11 +375,14 @@ int pick_bn(int64_t N) {
 
 }  // namespace
 
+// Square-update tile: 256 x 256 with 8 waves when the order allows it.
+static int sq_tile(int64_t M) { return (RB_UPD_TILE == 256 && M % 256 == 0) ? 256 : 128; }
+
 int64_t gemm_bf16_blocks(const MixedGemm& mg) {
   const GemmArgs& g = mg.g;
   if (g.epi == EPI_SYMUPD) {
-    const int64_t T = g.M / 128;
-    return T * (T + 1) / 2;
+    const int64_t T = g.M / sq_tile(g.M);
+    return (T * (T + 1) / 2 + 7) / 8 * 8;
   }
   if (g.epi == EPI_ADDROW) return (g.M / 128) * (g.N / 128);
   return (g.M / 128) * (g.N / pick_bn(g.N)) * g.splitk;
@@ -341,8 +397,15 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
         mg.pmax != 1 || g.splitk != 1)
       return hipErrorInvalidValue;
     if (g.epi == EPI_SYMUPD && g.M != g.N) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC>), dim3(gemm_bf16_blocks(mg)),
-                       dim3(256), 0, s, g);
+    if (g.epi == EPI_SYMUPD && sq_tile(g.M) == 256)
+      hipLaunchKernelGGL((k_gemm_bf16<256, 256, 2, 4, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, false, EPI_SYMUPD, 1>),
+                         dim3(gemm_bf16_blocks(mg)), dim3(512), 0, s, g);
+    else if (g.epi == EPI_SYMUPD)
+      hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, false, EPI_SYMUPD, 1>),
+                         dim3(gemm_bf16_blocks(mg)), dim3(256), 0, s, g);
+    else
+      hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, false, EPI_ADDROW, 1>),
+                         dim3(gemm_bf16_blocks(mg)), dim3(256), 0, s, g);
     return hipGetLastError();
   }
   if (g.epi != EPI_COLSTORE || !partial_ws) return hipErrorInvalidValue;
@@ -360,8 +423,6 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
   RB_TALL(2, 2, 1, OK_F32_KC, OK_F32_KC)   // X Y
   RB_TALL(3, 2, 2, OK_F32_KC, OK_F32_KC)   // A S with S = L S~ (FP32)
   RB_TALL(2, 3, 2, OK_F32_MC, OK_F32_KC)   // L^T Y
-  RB_TALL(3, 3, 2, OK_F32_KC, OK_F32_KC)
-  RB_TALL(2, 2, 1, OK_F32_MC, OK_F32_KC)
   return hipErrorInvalidValue;
 #undef RB_TALL
   if (e != hipSuccess) return e;

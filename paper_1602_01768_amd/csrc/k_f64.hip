@@ -47,8 +47,10 @@ RB_DEV double block_sum_256(double v, double* sh) {
 // (v_mfma_f64_16x16x4f64: lane l holds A(l%16, l/16), B(l/16, l%16) and the
 // output column l%16, rows l/16 + 4r).  BK = 16 staged through LDS with a
 // one-tile register prefetch.
-template <int BM, int BN, bool AKC, bool BKC>
-__global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
+// 128 x 128 tiles hold 64 FP64 accumulators per lane and run one wave per SIMD;
+// smaller tiles ask for two.
+template <int BM, int BN, bool AKC, bool BKC, int EPI>
+__global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void k_gemm_f64(GemmArgs g) {
   constexpr int BK = 16;
   constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
   constexpr int AP = BM * BK / 256, BP = BN * BK / 256;
@@ -66,7 +68,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
   int kc = 0;
   bool diag = false;
   const int64_t bid = blockIdx.x;
-  if (g.epi == EPI_SYMUPD) {
+  if constexpr (EPI == EPI_SYMUPD) {
     tri_index(bid, mt, nt);
     diag = (mt == nt);
   } else {
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
 
   // ---------------------------------------------------------------- epilogue
   const int lr = lane >> 4, lc = lane & 15;
-  if (g.epi == EPI_RESID) {
+  if constexpr (EPI == EPI_RESID) {
     double s = 0;
 #pragma unroll
     for (int a = 0; a < FM; ++a)
@@ -160,7 +162,7 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
     if (tid == 0) g.red[bid] = t;
     return;
   }
-  if (g.epi == EPI_SYMUPD) {
+  if constexpr (EPI == EPI_SYMUPD) {
     __syncthreads();
     double* R = smem + wave * 16 * (WM + 1);
 #pragma unroll
@@ -190,33 +192,45 @@ __global__ __launch_bounds__(256) void k_gemm_f64(GemmArgs g) {
     }
     return;
   }
+  // element (a, b, r) of the wave tile: row a*16 + lr + 4r, column b*16 + lc
+  const int64_t wm0 = m0 + wm * WM, wn0 = n0 + wn * WN;
+  if constexpr (EPI == EPI_PARTIAL) {
+    double* P = (double*)g.C + (int64_t)kc * g.M * g.N + wn0 * g.M + wm0;
+    const int ldp = (int)g.M;
 #pragma unroll
-  for (int a = 0; a < FM; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-    for (int b = 0; b < FN; ++b)
+      for (int b = 0; b < FN; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t m = m0 + wm * WM + a * 16 + lr + 4 * r, n = n0 + wn * WN + b * 16 + lc;
-        const double v = acc[a][b][r];
-        switch (g.epi) {
-          case EPI_PARTIAL:
-            ((double*)g.C)[(int64_t)kc * g.M * g.N + n * g.M + m] = v;
-            break;
-          case EPI_COLSTORE: {
-            double o = g.c2 * v;
-            if (g.B0) o += g.c0 * load_any(g.B0, g.b0_dt, m + n * g.ld01);
-            if (g.B1) o += g.c1 * load_any(g.B1, g.b1_dt, m + n * g.ld01);
-            store_any(g.C, g.c_dt, m + n * g.ldc, o);
-          } break;
-          case EPI_ADDROW: {
-            const int64_t idx = m * g.ldc + n;
-            store_any(g.C, g.c_dt, idx, load_any(g.C, g.c_dt, idx) + g.c2 * v);
-          } break;
-          case EPI_ROWSTORE:
-            store_any(g.C, g.c_dt, m * g.ldc + n, g.c2 * v);
-            break;
+        for (int r = 0; r < 4; ++r) P[(b * 16 + lc) * ldp + a * 16 + lr + 4 * r] = acc[a][b][r];
+  } else if constexpr (EPI == EPI_COLSTORE) {
+    const int ldc = (int)g.ldc, ld01 = (int)g.ld01;
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t m = wm0 + a * 16 + lr + 4 * r, n = wn0 + b * 16 + lc;
+          double o = g.c2 * acc[a][b][r];
+          if (g.B0) o += g.c0 * load_any(g.B0, g.b0_dt, m + n * ld01);
+          if (g.B1) o += g.c1 * load_any(g.B1, g.b1_dt, m + n * ld01);
+          store_any(g.C, g.c_dt, m + n * ldc, o);
         }
-      }
+  } else {  // EPI_ADDROW, EPI_ROWSTORE
+    const int ldc = (int)g.ldc;
+    const int64_t base = wm0 * g.ldc + wn0;
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t idx = base + (a * 16 + lr + 4 * r) * ldc + b * 16 + lc;
+          if constexpr (EPI == EPI_ADDROW) store_any(g.C, g.c_dt, idx, load_any(g.C, g.c_dt, idx) + g.c2 * acc[a][b][r]);
+          else store_any(g.C, g.c_dt, idx, g.c2 * acc[a][b][r]);
+        }
+  }
 }
 
 __global__ void k_reduce_partials_f64(GemmArgs g, const double* P) {
@@ -243,12 +257,23 @@ int64_t gemm_f64_blocks(const GemmArgs& g) {
   return (g.M / BM) * (g.N / BN) * g.splitk;
 }
 
-template <int BM, int BN>
+template <int BM, int BN, int EPI>
 static void launch_f64(const GemmArgs& g, int64_t blocks, hipStream_t s) {
-  if (g.a_kc && g.b_kc) hipLaunchKernelGGL((k_gemm_f64<BM, BN, true, true>), dim3(blocks), dim3(256), 0, s, g);
-  else if (g.a_kc) hipLaunchKernelGGL((k_gemm_f64<BM, BN, true, false>), dim3(blocks), dim3(256), 0, s, g);
-  else if (g.b_kc) hipLaunchKernelGGL((k_gemm_f64<BM, BN, false, true>), dim3(blocks), dim3(256), 0, s, g);
-  else hipLaunchKernelGGL((k_gemm_f64<BM, BN, false, false>), dim3(blocks), dim3(256), 0, s, g);
+  if (g.a_kc && g.b_kc) hipLaunchKernelGGL((k_gemm_f64<BM, BN, true, true, EPI>), dim3(blocks), dim3(256), 0, s, g);
+  else if (g.a_kc) hipLaunchKernelGGL((k_gemm_f64<BM, BN, true, false, EPI>), dim3(blocks), dim3(256), 0, s, g);
+  else if (g.b_kc) hipLaunchKernelGGL((k_gemm_f64<BM, BN, false, true, EPI>), dim3(blocks), dim3(256), 0, s, g);
+  else hipLaunchKernelGGL((k_gemm_f64<BM, BN, false, false, EPI>), dim3(blocks), dim3(256), 0, s, g);
+}
+
+template <int BM, int BN>
+static hipError_t launch_f64_epi(const GemmArgs& g, int64_t blocks, hipStream_t s) {
+  switch (g.epi) {
+    case EPI_PARTIAL: launch_f64<BM, BN, EPI_PARTIAL>(g, blocks, s); break;
+    case EPI_COLSTORE: launch_f64<BM, BN, EPI_COLSTORE>(g, blocks, s); break;
+    case EPI_ROWSTORE: launch_f64<BM, BN, EPI_ROWSTORE>(g, blocks, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipSuccess;
 }
 
 hipError_t gemm_f64(const GemmArgs& gin, void* partial_ws, hipStream_t s) {
@@ -267,11 +292,24 @@ hipError_t gemm_f64(const GemmArgs& gin, void* partial_ws, hipStream_t s) {
   int BM = pick_tile(g.M), BN = pick_tile(g.N);
   if (g.epi == EPI_SYMUPD) BN = BM;
   const int64_t blocks = gemm_f64_blocks(run);
-  if (BM == 128 && BN == 128) launch_f64<128, 128>(run, blocks, s);
-  else if (BM == 128) launch_f64<128, 32>(run, blocks, s);
-  else if (BN == 128) launch_f64<32, 128>(run, blocks, s);
-  else launch_f64<32, 32>(run, blocks, s);
-  hipError_t e = hipGetLastError();
+  hipError_t e = hipSuccess;
+  if (run.epi == EPI_SYMUPD || run.epi == EPI_ADDROW || run.epi == EPI_RESID) {
+    // n x n products: the order is a multiple of 256, always 128 x 128 tiles
+    if (BM != 128 || BN != 128) return hipErrorInvalidValue;
+    if (run.epi == EPI_SYMUPD && !run.a_kc && !run.b_kc)
+      hipLaunchKernelGGL((k_gemm_f64<128, 128, false, false, EPI_SYMUPD>), dim3(blocks), dim3(256), 0, s, run);
+    else if (run.epi == EPI_ADDROW && !run.a_kc && !run.b_kc)
+      hipLaunchKernelGGL((k_gemm_f64<128, 128, false, false, EPI_ADDROW>), dim3(blocks), dim3(256), 0, s, run);
+    else if (run.epi == EPI_RESID && run.a_kc && run.b_kc)
+      hipLaunchKernelGGL((k_gemm_f64<128, 128, true, true, EPI_RESID>), dim3(blocks), dim3(256), 0, s, run);
+    else
+      return hipErrorInvalidValue;
+  } else if (BM == 128 && BN == 128) e = launch_f64_epi<128, 128>(run, blocks, s);
+  else if (BM == 128) e = launch_f64_epi<128, 32>(run, blocks, s);
+  else if (BN == 128) e = launch_f64_epi<32, 128>(run, blocks, s);
+  else e = launch_f64_epi<32, 32>(run, blocks, s);
+  if (e != hipSuccess) return e;
+  e = hipGetLastError();
   if (e != hipSuccess || !split) return e;
   return reduce_partials_f64(g, (const double*)partial_ws, s);
 }
