@@ -22,6 +22,10 @@
 
 using namespace rb;
 
+#ifndef RB_SUPER_TILES
+#define RB_SUPER_TILES 4  // super-tile edge of the n x n update order (4 x 4 tiles share panels in L2)
+#endif
+
 namespace {
 
 struct Lane {  // one stream with its own split-K, reduction and Cholesky workspaces
@@ -73,6 +77,8 @@ struct rbfgs_ctx {
   double *G = nullptr, *H = nullptr, *Ginv = nullptr, *Z = nullptr, *GH = nullptr, *Mq = nullptr;
   double* est = nullptr;
   int* status = nullptr;
+  int2* tiles = nullptr;    // tile order of the n x n update (super-tiles, see make_tile_order)
+  int64_t ntiles = 0;
   std::vector<void*> allocs;
   // per-phase timing with HIP events on the lanes' streams (rbfgs_profile)
   struct ProfRec {
@@ -348,6 +354,7 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S) {
     g.A = S.planes; g.lda = ldp; g.a_plane = plane;
     g.B = S.planes + qp; g.ldb = ldp; g.b_plane = plane;
     g.epi = EPI_SYMUPD; g.C = ctx->X; g.ldc = np; g.c2 = -1.0;
+    g.tiles = ctx->tiles; g.ntiles = ctx->ntiles;
     mg.a_kind = OK_BF16_KC; mg.b_kind = OK_BF16_KC; mg.na = 2; mg.nb = 2; mg.pmax = 1;
     bf_gemm(ctx, L, mg);
   } else {
@@ -363,6 +370,7 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S) {
     g.A = PQ; g.lda = np; g.a_dt = DT_F64; g.a_kc = false;
     g.B = PQ + np * qp; g.ldb = np; g.b_dt = DT_F64; g.b_kc = false;
     g.epi = EPI_SYMUPD; g.C = ctx->X; g.ldc = np; g.c_dt = DT_F64; g.c2 = -1.0;
+    g.tiles = ctx->tiles; g.ntiles = ctx->ntiles;
     f64_gemm(ctx, L, g);
   }
 }
@@ -415,6 +423,7 @@ void main_adaptive(rbfgs_ctx* ctx, Slot& S) {
     g.A = shi; g.lda = qp; g.a_plane = plane;
     g.B = qhi; g.ldb = qp; g.b_plane = plane;
     g.epi = EPI_ADDROW; g.C = ctx->X; g.ldc = np; g.c2 = 1.0;
+    g.tiles = ctx->tiles; g.ntiles = ctx->ntiles;
     mg.a_kind = OK_BF16_KC; mg.b_kind = OK_BF16_KC; mg.na = 2; mg.nb = 2; mg.pmax = 1;
     bf_gemm(ctx, L, mg);
   } else {
@@ -423,6 +432,7 @@ void main_adaptive(rbfgs_ctx* ctx, Slot& S) {
     g.A = ctx->Sa; g.lda = np; g.a_dt = DT_F64; g.a_kc = false;
     g.B = ctx->W; g.ldb = np; g.b_dt = DT_F64; g.b_kc = false;
     g.epi = EPI_ADDROW; g.C = ctx->X; g.ldc = np; g.c_dt = DT_F64; g.c2 = 1.0;
+    g.tiles = ctx->tiles; g.ntiles = ctx->ntiles;
     f64_gemm(ctx, L, g);
   }
 }
@@ -600,6 +610,16 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
     ctx->Mq = (double*)dalloc(ctx, qq);
     ctx->est = (double*)dalloc(ctx, 4 * sizeof(double));
     ctx->status = (int*)dalloc(ctx, sizeof(int));
+    {  // tile order of the n x n update: lower triangle (fixed) or full square (adaptive)
+      const int epi = ctx->ada ? EPI_ADDROW : EPI_SYMUPD;
+      const int T = (int)(np / (ctx->mixed ? bf16_square_tile(np, epi) : 128));
+      std::vector<int2> order((size_t)make_tile_order(T, RB_SUPER_TILES, !ctx->ada, nullptr));
+      ctx->ntiles = make_tile_order(T, RB_SUPER_TILES, !ctx->ada, order.data());
+      ctx->tiles = (int2*)dalloc(ctx, order.size() * sizeof(int2));
+      HIPCHK(hipMemcpyAsync(ctx->tiles, order.data(), order.size() * sizeof(int2), hipMemcpyHostToDevice,
+                            ctx->main.s));
+      HIPCHK(hipStreamSynchronize(ctx->main.s));
+    }
     // copy A (n x n, lda) into the padded np x np buffer, converting its type
     const int sdt = a_dtype == RBFGS_F32 ? DT_F32 : DT_F64;
     const size_t ses = dt_size(sdt);

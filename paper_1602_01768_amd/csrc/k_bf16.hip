@@ -13,14 +13,16 @@ namespace rb {
 
 namespace {
 
-constexpr int BK = 32;
+#ifndef RB_TS_BK
+#define RB_TS_BK 32  // k depth of one LDS stage for the tall-skinny products
+#endif
 #ifndef RB_TS_PF
-#define RB_TS_PF 2  // register prefetch depth of the tall-skinny products
+#define RB_TS_PF 1  // register prefetch depth of the tall-skinny products (1 measured faster than 2)
 #endif
 #ifndef RB_UPD_TILE
-#define RB_UPD_TILE 256
+#define RB_UPD_TILE 128  // square-update tile (128 measured faster than 256)
 #endif
-constexpr int PITCH = BK + 8;  // bf16 elements per LDS row (80 bytes)
+// LDS rows hold BK + 8 bf16 (16-byte aligned, rows 8 apart land on distinct banks)
 
 template <int NP>
 RB_DEV void split_n(float x, __bf16 (&o)[NP]) {
@@ -42,10 +44,14 @@ RB_DEV void tri_index32(int64_t t, int64_t& ti, int64_t& tj) {
 }
 
 // Loader for one operand tile of ROWS (m or n) x BK into LDS planes [NP][ROWS][PITCH].
-template <int ROWS, int NP, int KIND, int NT>
+template <int ROWS, int NP, int KIND, int NT, int BK>
 struct TileLoader {
+  static constexpr int PITCH = BK + 8;
   // registers held between the global load and the LDS store
-  static constexpr int F4 = (KIND == OK_BF16_KC) ? 1 : ROWS * BK / 4 / NT;     // float4 per thread
+  // F32_KC: float4 per thread; F32_MC: 4 x 4 micro-blocks per thread, 4 float4 each
+  static constexpr int MBLK = ROWS * BK / 16;
+  static constexpr int F4 = (KIND == OK_BF16_KC) ? 1
+                            : (KIND == OK_F32_MC) ? 4 * ((MBLK + NT - 1) / NT) : ROWS * BK / 4 / NT;
   static constexpr int V8 = (KIND == OK_BF16_KC) ? (ROWS * (BK / 8) + NT - 1) / NT : 1;  // 16-byte chunks per plane
   float4 f[F4 > 0 ? F4 : 1];
   bf16x8 h[NP][V8];
@@ -60,12 +66,16 @@ struct TileLoader {
         f[i] = *(const float4*)(A + (r0 + row) * ld + k0 + c4);
       }
     } else if constexpr (KIND == OK_F32_MC) {
+      // micro-block b: columns m4..m4+3 (contiguous in memory) of rows kk..kk+3
       const float* A = (const float*)base;
 #pragma unroll
-      for (int i = 0; i < F4; ++i) {
-        const int e = tid + NT * i;
-        const int kk = e / (ROWS / 4), m4 = (e % (ROWS / 4)) * 4;
-        f[i] = *(const float4*)(A + (k0 + kk) * ld + r0 + m4);
+      for (int i = 0; i < F4 / 4; ++i) {
+        const int b = tid + NT * i;
+        if (MBLK % NT == 0 || b < MBLK) {
+          const int m4 = (b % (ROWS / 4)) * 4, kk = (b / (ROWS / 4)) * 4;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) f[4 * i + j] = *(const float4*)(A + (k0 + kk + j) * ld + r0 + m4);
+        }
       }
     } else {
       const __bf16* A = (const __bf16*)base;
@@ -100,17 +110,30 @@ struct TileLoader {
         }
       }
     } else if constexpr (KIND == OK_F32_MC) {
+      // transpose the 4 x 4 micro-block in registers: LDS row m gets k = kk..kk+3
 #pragma unroll
-      for (int i = 0; i < F4; ++i) {
-        const int e = tid + NT * i;
-        const int kk = e / (ROWS / 4), m4 = (e % (ROWS / 4)) * 4;
-        const float vals[4] = {f[i].x, f[i].y, f[i].z, f[i].w};
+      for (int i = 0; i < F4 / 4; ++i) {
+        const int b = tid + NT * i;
+        if (MBLK % NT == 0 || b < MBLK) {
+          const int m4 = (b % (ROWS / 4)) * 4, kk = (b / (ROWS / 4)) * 4;
+          const float4* fb = &f[4 * i];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          __bf16 pc[NP];
-          split_n<NP>(vals[j], pc);
+          for (int mm = 0; mm < 4; ++mm) {
+            const float v0 = mm == 0 ? fb[0].x : mm == 1 ? fb[0].y : mm == 2 ? fb[0].z : fb[0].w;
+            const float v1 = mm == 0 ? fb[1].x : mm == 1 ? fb[1].y : mm == 2 ? fb[1].z : fb[1].w;
+            const float v2 = mm == 0 ? fb[2].x : mm == 1 ? fb[2].y : mm == 2 ? fb[2].z : fb[2].w;
+            const float v3 = mm == 0 ? fb[3].x : mm == 1 ? fb[3].y : mm == 2 ? fb[3].z : fb[3].w;
+            __bf16 p0[NP], p1[NP], p2[NP], p3[NP];
+            split_n<NP>(v0, p0);
+            split_n<NP>(v1, p1);
+            split_n<NP>(v2, p2);
+            split_n<NP>(v3, p3);
 #pragma unroll
-          for (int p = 0; p < NP; ++p) lds[(p * ROWS + m4 + j) * PITCH + kk] = pc[p];
+            for (int p = 0; p < NP; ++p) {
+              bf16x4 v = {p0[p], p1[p], p2[p], p3[p]};
+              *(bf16x4*)(lds + (p * ROWS + m4 + mm) * PITCH + kk) = v;
+            }
+          }
         }
       }
     } else {
@@ -134,9 +157,10 @@ struct TileLoader {
 // DBUF: read the fragments of the next 16-wide k sub-step while the current MFMAs
 // issue (costs registers); launch bounds ask for two waves per SIMD (<= 256 VGPRs).
 template <int BM, int BN, int WAVES_M, int WAVES_N, int NA, int NB, int PMAX, int AK, int BKD, bool DBUF, int EPI,
-          int PF>
+          int PF, int BK>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArgs g) {
   constexpr int NT = 64 * WAVES_M * WAVES_N;
+  constexpr int PITCH = BK + 8;
   constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
   constexpr int FM = WM / 32, FN = WN / 32;
   constexpr int LOOP_E = (NA * BM + NB * BN) * PITCH;                 // bf16 elements
@@ -153,14 +177,23 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArg
   int kc = 0;
   bool diag = false;
   const int64_t bid = blockIdx.x;
-  if constexpr (EPI == EPI_SYMUPD) {
-    // lower-triangular tiles; each XCD (blockIdx % 8) takes a contiguous run of the
-    // row-major tile order so that consecutive tiles on it share their row panel in L2
-    const int64_t T = g.M / BM, NTT = T * (T + 1) / 2, per = (NTT + 7) / 8;
-    const int64_t t = (bid % 8) * per + bid / 8;
+  if constexpr (EPI == EPI_SYMUPD || EPI == EPI_ADDROW) {
+    // square products: each XCD (blockIdx % 8) takes a contiguous run of the tile
+    // order, so the workgroups resident on it share their panel blocks in its L2
+    const int64_t T = g.M / BM;
+    const int64_t NTT = g.tiles ? g.ntiles : (EPI == EPI_SYMUPD ? T * (T + 1) / 2 : T * T);
+    const int64_t per = (NTT + 7) / 8, t = (bid % 8) * per + bid / 8;
     if (t >= NTT) return;
-    tri_index32(t, mt, nt);
-    diag = (mt == nt);
+    if (g.tiles) {
+      mt = g.tiles[t].x;
+      nt = g.tiles[t].y;
+    } else if (EPI == EPI_SYMUPD) {
+      tri_index32(t, mt, nt);
+    } else {
+      mt = t / T;
+      nt = t % T;
+    }
+    diag = (EPI == EPI_SYMUPD) && (mt == nt);
   } else {
     kc = (int)(bid % g.splitk);
     const int64_t r = bid / g.splitk;
@@ -228,16 +261,16 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArg
 
   };
 
-  TileLoader<BM, NA, AK, NT> la0;
-  TileLoader<BN, NB, BKD, NT> lb0;
+  TileLoader<BM, NA, AK, NT, BK> la0;
+  TileLoader<BN, NB, BKD, NT, BK> lb0;
   la0.load(g.A, g.lda, g.a_plane, m0, kbeg, tid);
   lb0.load(g.B, g.ldb, g.b_plane, n0, kbeg, tid);
   if constexpr (PF == 1) {
     for (int64_t k0 = kbeg; k0 < kend; k0 += BK) k_tile(la0, lb0, k0);
   } else {
     // two register stages in flight: tiles k0 and k0 + BK
-    TileLoader<BM, NA, AK, NT> la1;
-    TileLoader<BN, NB, BKD, NT> lb1;
+    TileLoader<BM, NA, AK, NT, BK> la1;
+    TileLoader<BN, NB, BKD, NT, BK> lb1;
     if (kbeg + BK < kend) {
       la1.load(g.A, g.lda, g.a_plane, m0, kbeg + BK, tid);
       lb1.load(g.B, g.ldb, g.b_plane, n0, kbeg + BK, tid);
@@ -351,7 +384,7 @@ __global__ void k_pack_split2(const float* in, int64_t ld_in, int64_t rows, int6
 
 template <int BN, int WAVES_M, int WAVES_N, int NA, int NB, int PMAX, int AK, int BKD>
 void launch_ts(const GemmArgs& g, int64_t blocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_gemm_bf16<128, BN, WAVES_M, WAVES_N, NA, NB, PMAX, AK, BKD, false, EPI_PARTIAL, RB_TS_PF>), dim3(blocks),
+  hipLaunchKernelGGL((k_gemm_bf16<128, BN, WAVES_M, WAVES_N, NA, NB, PMAX, AK, BKD, false, EPI_PARTIAL, RB_TS_PF, RB_TS_BK>), dim3(blocks),
                      dim3(64 * WAVES_M * WAVES_N), 0, s, g);
 }
 
@@ -378,33 +411,37 @@ int pick_bn(int64_t N) {
 // Square-update tile: 256 x 256 with 8 waves when the order allows it.
 static int sq_tile(int64_t M) { return (RB_UPD_TILE == 256 && M % 256 == 0) ? 256 : 128; }
 
+int bf16_square_tile(int64_t M, int epi) { return epi == EPI_SYMUPD ? sq_tile(M) : 128; }
+
 int64_t gemm_bf16_blocks(const MixedGemm& mg) {
   const GemmArgs& g = mg.g;
-  if (g.epi == EPI_SYMUPD) {
-    const int64_t T = g.M / sq_tile(g.M);
-    return (T * (T + 1) / 2 + 7) / 8 * 8;
+  if (g.epi == EPI_SYMUPD || g.epi == EPI_ADDROW) {
+    const int64_t T = g.M / (g.epi == EPI_SYMUPD ? sq_tile(g.M) : 128);
+    const int64_t NTT = g.tiles ? g.ntiles : (g.epi == EPI_SYMUPD ? T * (T + 1) / 2 : T * T);
+    return (NTT + 7) / 8 * 8;
   }
-  if (g.epi == EPI_ADDROW) return (g.M / 128) * (g.N / 128);
   return (g.M / 128) * (g.N / pick_bn(g.N)) * g.splitk;
 }
 
 hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
   const GemmArgs& g = mg.g;
   if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipSuccess;
-  if (g.M % 128 || g.N % 32 || g.splitk < 1 || g.K % ((int64_t)BK * g.splitk)) return hipErrorInvalidValue;
+  if (g.M % 128 || g.N % 32 || g.splitk < 1) return hipErrorInvalidValue;
+  const int64_t bk = (g.epi == EPI_SYMUPD || g.epi == EPI_ADDROW) ? 32 : RB_TS_BK;
+  if (g.K % (bk * g.splitk)) return hipErrorInvalidValue;
   if (g.epi == EPI_SYMUPD || g.epi == EPI_ADDROW) {
     if (g.N % 128 || mg.a_kind != OK_BF16_KC || mg.b_kind != OK_BF16_KC || mg.na != 2 || mg.nb != 2 ||
         mg.pmax != 1 || g.splitk != 1)
       return hipErrorInvalidValue;
     if (g.epi == EPI_SYMUPD && g.M != g.N) return hipErrorInvalidValue;
     if (g.epi == EPI_SYMUPD && sq_tile(g.M) == 256)
-      hipLaunchKernelGGL((k_gemm_bf16<256, 256, 2, 4, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, false, EPI_SYMUPD, 1>),
+      hipLaunchKernelGGL((k_gemm_bf16<256, 256, 2, 4, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, false, EPI_SYMUPD, 1, 32>),
                          dim3(gemm_bf16_blocks(mg)), dim3(512), 0, s, g);
     else if (g.epi == EPI_SYMUPD)
-      hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, false, EPI_SYMUPD, 1>),
+      hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, false, EPI_SYMUPD, 1, 32>),
                          dim3(gemm_bf16_blocks(mg)), dim3(256), 0, s, g);
     else
-      hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, false, EPI_ADDROW, 1>),
+      hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, false, EPI_ADDROW, 1, 32>),
                          dim3(gemm_bf16_blocks(mg)), dim3(256), 0, s, g);
     return hipGetLastError();
   }
@@ -434,6 +471,19 @@ hipError_t reduce_partials_f32(const GemmArgs& g, const float* P, hipStream_t s)
   const int64_t blocks = std::min<int64_t>((MN + 255) / 256, 8192);
   hipLaunchKernelGGL(k_reduce_partials_f32, dim3(blocks), dim3(256), 0, s, g, P);
   return hipGetLastError();
+}
+
+int64_t make_tile_order(int T, int S, bool lower, int2* out) {
+  int64_t c = 0;
+  for (int I = 0; I < T; I += S)
+    for (int J = 0; J <= (lower ? I : T - 1); J += S)
+      for (int i = I; i < I + S && i < T; ++i)
+        for (int j = J; j < J + S && j < T; ++j)
+          if (!lower || j <= i) {
+            if (out) out[c] = make_int2(i, j);
+            ++c;
+          }
+  return c;
 }
 
 hipError_t pack_split2(const float* in, int64_t ld_in, int64_t rows, int64_t cols, __bf16* hi, __bf16* lo,

@@ -68,9 +68,22 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void k_gemm_f6
   int kc = 0;
   bool diag = false;
   const int64_t bid = blockIdx.x;
-  if constexpr (EPI == EPI_SYMUPD) {
-    tri_index(bid, mt, nt);
-    diag = (mt == nt);
+  if constexpr (EPI == EPI_SYMUPD || EPI == EPI_ADDROW) {
+    // square products: each XCD (blockIdx % 8) takes a contiguous run of the tile order
+    const int64_t T = g.M / BM;
+    const int64_t NTT = g.tiles ? g.ntiles : (EPI == EPI_SYMUPD ? T * (T + 1) / 2 : T * T);
+    const int64_t per = (NTT + 7) / 8, t = (bid % 8) * per + bid / 8;
+    if (t >= NTT) return;
+    if (g.tiles) {
+      mt = g.tiles[t].x;
+      nt = g.tiles[t].y;
+    } else if (EPI == EPI_SYMUPD) {
+      tri_index(t, mt, nt);
+    } else {
+      mt = t / T;
+      nt = t % T;
+    }
+    diag = (EPI == EPI_SYMUPD) && (mt == nt);
   } else {
     kc = (int)(bid % g.splitk);
     const int64_t r = bid / g.splitk;
@@ -250,9 +263,10 @@ static int pick_tile(int64_t x) { return (x % 128 == 0) ? 128 : 32; }
 
 int64_t gemm_f64_blocks(const GemmArgs& g) {
   const int BM = pick_tile(g.M), BN = pick_tile(g.N);
-  if (g.epi == EPI_SYMUPD) {
+  if (g.epi == EPI_SYMUPD || g.epi == EPI_ADDROW) {
     const int64_t T = g.M / BM;
-    return T * (T + 1) / 2;
+    const int64_t NTT = g.tiles ? g.ntiles : (g.epi == EPI_SYMUPD ? T * (T + 1) / 2 : T * T);
+    return (NTT + 7) / 8 * 8;
   }
   return (g.M / BM) * (g.N / BN) * g.splitk;
 }

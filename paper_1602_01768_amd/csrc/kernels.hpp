@@ -39,7 +39,15 @@ struct GemmArgs {
   int64_t nvalid = 0;
   // bf16 GEMM only: plane strides of pre-split operands, split counts
   int64_t a_plane = 0, b_plane = 0;
+  // square products (EPI_SYMUPD, EPI_ADDROW): optional tile order (tile row, tile column),
+  // handed out so that each XCD (blockIdx % 8) takes a contiguous run of it
+  const int2* tiles = nullptr;
+  int64_t ntiles = 0;
 };
+
+// Tile order for an n x n product of T x T tiles: super-tiles of S x S tiles in row-major
+// order, tiles row-major inside each; lower triangle only when `lower`.  Returns the count.
+int64_t make_tile_order(int T, int S, bool lower, int2* out);
 
 hipError_t gemm_f64(const GemmArgs& g, void* partial_ws, hipStream_t s);
 // Sum split-K partials ([split][M*N] double, column-major M x N) into the
@@ -61,6 +69,8 @@ struct MixedGemm {
   int pmax = 1;         // passes: all piece pairs (i, j) with i + j <= pmax
 };
 hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s);
+// Tile edge of the bf16 square products (EPI_SYMUPD / EPI_ADDROW) for order M.
+int bf16_square_tile(int64_t M, int epi);
 hipError_t reduce_partials_f32(const GemmArgs& g, const float* partial, hipStream_t s);
 int64_t gemm_bf16_blocks(const MixedGemm& mg);
 
