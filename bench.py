@@ -44,23 +44,70 @@ def alg_flops(n, q, variant, sketch):
     return 4 * n2q + 4 * nq2 if sketch == "gauss" else 3 * n2q + 2 * nq2
 
 
-def phase_roofline(name, n, q, variant, sketch):
-    """(bound, algorithmic units per launch, unit) of one profiled phase.
+def phase_roofline(name, n, q, variant, sketch, precision="mixed"):
+    """(bound, algorithmic bytes per launch, unit) of one n x n product kernel.
 
-    Bytes count each HBM-resident n x n operand once (4 B/entry, FP32):
-      AS, XY, LS, LtY: read the n x n matrix once                    -> 4 n^2 B
-      update (fixed):  read the lower triangle of X, write all of X  -> 6 n^2 B
-      update (adaptive): read and write L                            -> 8 n^2 B
-    Their algorithmic intensity (2 n^2 q flops over these bytes) is below the
-    bf16 ridge point (2500 TFLOP/s / 8 TB/s = 312 flop/B) for q <= 256, so the
-    roofline that bounds them is HBM bandwidth.
+    Bytes count each operand once at its stored width (4 B in mixed mode, 8 B in FP64):
+      AS, XY, LS, LtY (tall-skinny, M(n x n) * P(n x q)): read M once, read P, write
+                       the n x q result                             -> e n^2 + 2 e n q
+      update (fixed):  read the lower triangle of X, write all of X, read the two
+                       n x 2q bf16 hi/lo panel pairs                -> 1.5 e n^2 + 16 n q
+      update (adaptive): read and write L, read the panels          -> 2 e n^2 + 8 n q
+    Their intensity (2 n^2 q algorithmic flops over these bytes) is below the bf16
+    ridge point (2500 TFLOP/s / 8 TB/s = 312 flop/B) for q <= 256, so the roofline
+    that bounds them is HBM bandwidth.
     """
-    nn = float(n) * n
+    e = 4.0 if precision == "mixed" else 8.0
+    nn, nq = float(n) * n, float(n) * q
     if name in ("AS", "XY", "LS", "LtY"):
-        return "hbm", 4.0 * nn, "GB/s"
+        return "hbm", e * nn + 2 * e * nq, "GB/s"
     if name == "update":
-        return "hbm", (6.0 if variant == "fixed" else 8.0) * nn, "GB/s"
+        return ("hbm", 1.5 * e * nn + 16 * nq, "GB/s") if variant == "fixed" else ("hbm", 2 * e * nn + 8 * nq, "GB/s")
     return None
+
+
+# kernel symbol (as rocprofv3 names it) of each product phase in mixed mode, fixed/Gaussian
+PHASE_KERNEL = {
+    "XY": "k_gemm_bf16<128, 256, 2, 4, 2, 2, 1, 0, 0, false, 0, 1, 32>",
+    "AS": "k_gemm_bf16<128, 256, 2, 4, 3, 1, 2, 0, 2, false, 0, 1, 32>",
+    "update": "k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, 2, 2, false, 2, 1, 32>",
+}
+KERNEL_SOURCES = ["paper_1602_01768_amd/csrc/k_bf16.hip", "paper_1602_01768_amd/csrc/common.hpp",
+                  "paper_1602_01768_amd/csrc/kernels.hpp"]
+COUNTERS_FILE = "profiles/hbm_counters_c3_fixed_gauss_mixed.txt"
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def counter_traffic(phase):
+    """HBM bytes per launch of the phase's kernel from the committed rocprofv3 counter
+    summary: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) each scaled by the factor the
+    same counter reads for a copy kernel of known size.  None when the summary is missing,
+    does not cover the kernel, or was taken from different kernel sources."""
+    path = os.path.join(ROOT, COUNTERS_FILE)
+    kern = PHASE_KERNEL.get(phase)
+    if not kern or not os.path.exists(path):
+        return None
+    kv, rows = {}, {}
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("sources_sha256=") or line.startswith("fetch_factor=") or line.startswith("write_factor="):
+            k, v = line.split("=", 1)
+            kv[k] = v
+        elif line.startswith("kernel="):
+            f = dict(x.split("=", 1) for x in line.split(" | "))
+            rows[f["kernel"]] = f
+    if kv.get("sources_sha256") != sources_sha256() or kern not in rows:
+        return None
+    r = rows[kern]
+    return (float(r["fetch_kib"]) * float(kv["fetch_factor"]) + float(r["write_kib"]) * float(kv["write_factor"])) * 1024.0
 
 
 def make_A(n, seed, device):
@@ -68,17 +115,24 @@ def make_A(n, seed, device):
     return ridge_hessian(n, seed, m=2 * n, lam=1e-2, device=device)
 
 
-def timed_steps(Solver, A_dev, q, seed, sketch, variant, precision, warmup, steps, torch):
+def timed_steps(Solver, A_dev, q, seed, sketch, variant, precision, warmup, steps, torch, events=False):
+    """Warm up, then time `steps` iterations.  With events, the n x n product kernels are
+    bracketed by HIP events on the stream each runs on during the timed steps."""
     s = Solver(A_dev, q, seed, sketch=sketch, variant=variant, precision=precision)
     s.step(warmup)
     s.sync()
+    if events:
+        s.profile(2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.step(steps)
     s.sync()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return s, (t1 - t0)
+    rep = s.profile_report() if events else {}
+    if events:
+        s.profile(0)
+    return s, (t1 - t0), rep
 
 
 def cpu_baseline(A32, q, seed, sketch, variant, steps):
@@ -137,34 +191,36 @@ def main():
     A64_dev = A_dev.to(torch.float64)
     torch.cuda.synchronize()
 
-    # ---- timed region: mixed precision
-    s_mixed, dt = timed_steps(rbfgs.Solver, A_dev, q, args.seed, args.sketch, args.variant, "mixed",
-                              args.warmup, args.steps, torch)
+    # ---- timed region: mixed precision; the product kernels timed live with HIP events
+    s_mixed, dt, live = timed_steps(rbfgs.Solver, A_dev, q, args.seed, args.sketch, args.variant, "mixed",
+                                    args.warmup, args.steps, torch, events=True)
     ips = args.steps / dt
     flops = alg_flops(n, q, args.variant, args.sketch)
-
-    # ---- per-phase timing with HIP events on the library's stream (separate window)
-    s_mixed.profile(True)
-    s_mixed.step(args.profile_steps)
-    rep = s_mixed.profile_report()
-    s_mixed.profile(False)
-    phases = {k: {"avg_ms": v[0] / max(v[1], 1), "count": v[1]} for k, v in rep.items()}
-    dominant = max((k for k in rep if phase_roofline(k, n, q, args.variant, args.sketch)),
-                   key=lambda k: rep[k][0], default=None)
+    products = {k: v for k, v in live.items() if phase_roofline(k, n, q, args.variant, args.sketch)}
+    dominant = max(products, key=lambda k: products[k][0], default=None)
     roof = None
     if dominant:
         bound, units, unit = phase_roofline(dominant, n, q, args.variant, args.sketch)
-        avg_s = rep[dominant][0] / rep[dominant][1] / 1e3
+        avg_s = products[dominant][0] / products[dominant][1] / 1e3
         achieved = units / avg_s / 1e9
-        peak = HBM_PEAK_GBS
-        roof = {"bound": bound, "kernel": dominant, "achieved": round(achieved, 1), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None, "avg_ms": round(avg_s * 1e3, 4),
-                "alg_bytes_per_launch": units}
+        traffic = counter_traffic(dominant) if args.sketch == "gauss" and args.variant == "fixed" else None
+        roof = {"bound": bound, "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": unit, "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic),
+                "launches": products[dominant][1], "avg_ms": round(avg_s * 1e3, 4), "alg_bytes_per_launch": units}
+    live_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in live.items()}
+
+    # ---- all phases timed in a separate window (informational)
+    s_mixed.profile(1)
+    s_mixed.step(args.profile_steps)
+    rep = s_mixed.profile_report()
+    s_mixed.profile(0)
+    phases = {k: {"avg_ms": v[0] / max(v[1], 1), "count": v[1]} for k, v in rep.items()}
     s_mixed.close()
 
     # ---- FP64 GPU path on the same matrix
-    s64, dt64 = timed_steps(rbfgs.Solver, A64_dev, q, args.seed, args.sketch, args.variant, "fp64", 1,
-                            args.fp64_steps, torch)
+    s64, dt64, _ = timed_steps(rbfgs.Solver, A64_dev, q, args.seed, args.sketch, args.variant, "fp64", 1,
+                               args.fp64_steps, torch)
     ips64 = args.fp64_steps / dt64
     s64.close()
     del A64_dev
@@ -208,6 +264,7 @@ def main():
                  "tflops_effective": round(flops * ips64 / 1e12, 3), "steps": args.fp64_steps},
         "mixed_over_fp64_per_step": round(ips / ips64, 3),
         "roofline": roof,
+        "products_ms_timed_region": live_ms,
         "phases_ms": {k: round(v["avg_ms"], 4) for k, v in phases.items()},
         "cpu_baseline": cpu,
         "parity": parity,

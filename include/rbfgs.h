@@ -158,10 +158,14 @@ void rbfgs_destroy(rbfgs_ctx* ctx);
 const char* rbfgs_last_error(const rbfgs_ctx* ctx);
 
 /* ---- timing of the iteration's phases (tracing aid) ----
- * rbfgs_profile: enable (1) or disable (0) per-phase timing of subsequent
- * iterations with HIP events recorded on the context's stream, and clear the
- * accumulated totals.  Phases: sketch, gather, AS, LS, gram_G, chol_inv, XY,
- * LtY, gram_H, estimator, panels, coord_update, update.
+ * rbfgs_profile: per-phase timing of subsequent iterations with HIP events
+ * recorded on the stream each phase runs on, and clear the accumulated totals.
+ * enable = 0 off, 1 every phase, 2 only the n x n products (AS, XY, LS, LtY,
+ * update: the fewest events, for timing inside a measured run); other values
+ * E_INVALID_ARG.  Phases: sketch, sketch_gram, gather, AS, LS, gram_G, chol_inv,
+ * panel_U, XY, LtY, gram_H, estimator, panels, coord_update, update; a split-K
+ * product also reports its reduction kernel as "<phase>.reduce", so that the
+ * phase itself times the product kernel alone.
  * rbfgs_profile_report: synchronise and write a JSON object
  * {"phase": [total_ms, count], ...} (NUL-terminated) into buf of buflen bytes;
  * E_INVALID_ARG if it does not fit. */

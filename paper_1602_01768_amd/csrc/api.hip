@@ -45,6 +45,7 @@ struct Slot {  // sketch-dependent quantities of one iteration
   double* Z = nullptr;       // inverse Cholesky factor of G (fixed) or of S~^T S~ (adaptive)
   void* U = nullptr;         // fixed: U = S G^-1 (mixed: FP32 n x q; FP64: panels [U | W' | U])
   __bf16* planes = nullptr;  // mixed fixed: bf16 hi/lo planes of [U | W' | U], row-major
+  hipEvent_t y_ready = nullptr;   // side lane: sketch and Y = A S written (fixed sketch)
   hipEvent_t ready = nullptr;     // side lane: slot complete
   hipEvent_t released = nullptr;  // main lane: iteration that used the slot complete
   bool released_valid = false;
@@ -82,10 +83,10 @@ struct rbfgs_ctx {
   std::vector<void*> allocs;
   // per-phase timing with HIP events on the lanes' streams (rbfgs_profile)
   struct ProfRec {
-    const char* name;
+    std::string name;
     hipEvent_t a, b;
   };
-  bool prof = false;
+  int prof = 0;  // 0 off, 1 every phase, 2 the n x n products only
   std::vector<ProfRec> prof_pending;
   std::vector<hipEvent_t> ev_pool;
   std::map<std::string, std::pair<double, int64_t>> prof_acc;
@@ -127,20 +128,27 @@ hipEvent_t prof_event(rbfgs_ctx* ctx) {
   return e;
 }
 
-// Scope that brackets the kernels of one phase with events on one lane.
+// Scope that brackets the kernels of one phase with events on one lane.  `product`
+// marks the n x n products (timed at profile level 2 as well); for those, mark()
+// gives an event that the split-K GEMM records between its product kernel and the
+// reduction, which is then reported as the separate phase "<name>.reduce".
 struct Phase {
   rbfgs_ctx* ctx;
   hipStream_t s;
   const char* name;
-  hipEvent_t a = nullptr;
-  Phase(rbfgs_ctx* c, const Lane& L, const char* n) : ctx(c), s(L.s), name(n) {
-    if (ctx->prof) {
+  hipEvent_t a = nullptr, mid = nullptr;
+  Phase(rbfgs_ctx* c, const Lane& L, const char* n, bool product = false) : ctx(c), s(L.s), name(n) {
+    if (ctx->prof == 1 || (ctx->prof == 2 && product)) {
       a = prof_event(ctx);
       HIPCHK(hipEventRecord(a, s));
     }
   }
+  hipEvent_t mark() {
+    if (a && !mid) mid = prof_event(ctx);
+    return mid;
+  }
   ~Phase() {
-    if (!ctx->prof || !a) return;
+    if (!a) return;
     hipEvent_t b = nullptr;
     if (!ctx->ev_pool.empty()) {
       b = ctx->ev_pool.back();
@@ -148,7 +156,13 @@ struct Phase {
     } else if (hipEventCreate(&b) != hipSuccess) {
       return;
     }
-    if (hipEventRecord(b, s) == hipSuccess) ctx->prof_pending.push_back({name, a, b});
+    if (hipEventRecord(b, s) != hipSuccess) return;
+    if (mid) {
+      ctx->prof_pending.push_back({name, a, mid});
+      ctx->prof_pending.push_back({std::string(name) + ".reduce", mid, b});
+    } else {
+      ctx->prof_pending.push_back({name, a, b});
+    }
   }
 };
 
@@ -156,15 +170,19 @@ void prof_flush(rbfgs_ctx* ctx) {
   if (ctx->prof_pending.empty()) return;
   HIPCHK(hipStreamSynchronize(ctx->main.s));
   HIPCHK(hipStreamSynchronize(ctx->side.s));
+  std::vector<hipEvent_t> used;
   for (auto& r : ctx->prof_pending) {
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, r.a, r.b));
     auto& acc = ctx->prof_acc[r.name];
     acc.first += ms;
     acc.second += 1;
-    ctx->ev_pool.push_back(r.a);
-    ctx->ev_pool.push_back(r.b);
+    used.push_back(r.a);
+    used.push_back(r.b);
   }
+  std::sort(used.begin(), used.end());
+  used.erase(std::unique(used.begin(), used.end()), used.end());
+  for (hipEvent_t e : used) ctx->ev_pool.push_back(e);
   ctx->prof_pending.clear();
 }
 
@@ -182,9 +200,13 @@ int64_t bf_bn(int64_t N) { return N % 256 == 0 ? 256 : (N % 128 == 0 ? 128 : (N 
 // FP64-MFMA product on one lane; column-store products get a split-K.
 void f64_gemm(rbfgs_ctx* ctx, const Lane& L, GemmArgs g) {
   if (g.epi == EPI_COLSTORE) {
-    const int64_t tiles = (g.M / f64_tile(g.M)) * (g.N / f64_tile(g.N));
     const bool small_out = g.M * g.N <= (int64_t)1024 * 1024;  // q x q products: split deep
-    g.splitk = small_out ? pick_split(tiles, g.K, 16, 128, 128) : pick_split(tiles, g.K, 16);
+    if (small_out) {
+      const int64_t t = (g.M % 64 == 0 && g.N % 64 == 0) ? 64 : 32;
+      g.splitk = pick_split((g.M / t) * (g.N / t), g.K, 16, 32, 256);
+    } else {
+      g.splitk = pick_split((g.M / f64_tile(g.M)) * (g.N / f64_tile(g.N)), g.K, 16);
+    }
     const size_t need = (size_t)g.splitk * g.M * g.N * sizeof(double);
     if (g.splitk > 1 && need > L.partial_bytes) g.splitk = 1;
   }
@@ -207,14 +229,14 @@ void bf_gemm(rbfgs_ctx* ctx, const Lane& L, MixedGemm mg) {
 // transpose: Aop = M^T (T^T = L^T Y).  In mixed mode (na, nb, pmax) choose the bf16
 // pieces of each operand and the passes kept (all piece pairs with i + j <= pmax).
 void nn_times_panel(rbfgs_ctx* ctx, const Lane& L, const void* M, bool transpose, const void* P, int p_dt, void* out,
-                    int na = 2, int nb = 2, int pmax = 1) {
+                    int na = 2, int nb = 2, int pmax = 1, hipEvent_t mark = nullptr) {
   if (ctx->mixed) {
     MixedGemm mg;
     GemmArgs& g = mg.g;
     g.M = ctx->np; g.N = ctx->qp; g.K = ctx->np;
     g.A = M; g.lda = ctx->np;
     g.B = P; g.ldb = ctx->np;
-    g.epi = EPI_COLSTORE; g.C = out; g.ldc = ctx->np; g.c2 = 1.0;
+    g.epi = EPI_COLSTORE; g.C = out; g.ldc = ctx->np; g.c2 = 1.0; g.mark = mark;
     mg.a_kind = transpose ? OK_F32_MC : OK_F32_KC;
     mg.b_kind = p_dt == DT_BF16 ? OK_BF16_KC : OK_F32_KC;
     mg.na = na; mg.nb = p_dt == DT_BF16 ? 1 : nb; mg.pmax = pmax;
@@ -224,7 +246,7 @@ void nn_times_panel(rbfgs_ctx* ctx, const Lane& L, const void* M, bool transpose
     g.M = ctx->np; g.N = ctx->qp; g.K = ctx->np;
     g.A = M; g.lda = ctx->np; g.a_dt = DT_F64; g.a_kc = !transpose;
     g.B = P; g.ldb = ctx->np; g.b_dt = p_dt; g.b_kc = true;
-    g.epi = EPI_COLSTORE; g.C = out; g.ldc = ctx->np; g.c_dt = DT_F64; g.c2 = 1.0;
+    g.epi = EPI_COLSTORE; g.C = out; g.ldc = ctx->np; g.c_dt = DT_F64; g.c2 = 1.0; g.mark = mark;
     f64_gemm(ctx, L, g);
   }
 }
@@ -286,8 +308,13 @@ void side_chain(rbfgs_ctx* ctx, int64_t k, Slot& S) {
   if (ctx->coord) {
     Phase ph(ctx, L, "gather");
     HIPCHK(gather_cols_sym(ctx->A, mdt, np, S.C, ctx->q, np, S.Y, mdt, np, S.G, qp, L.s));
+    HIPCHK(hipEventRecord(S.y_ready, L.s));
   } else {
-    { Phase ph(ctx, L, "AS"); nn_times_panel(ctx, L, ctx->A, false, S.Sk, sk_dt(ctx), S.Y, 3, 1, 2); }  // exact
+    {
+      Phase ph(ctx, L, "AS", true);
+      nn_times_panel(ctx, L, ctx->A, false, S.Sk, sk_dt(ctx), S.Y, 3, 1, 2, ph.mark());  // exact
+    }
+    HIPCHK(hipEventRecord(S.y_ready, L.s));
     Phase ph(ctx, L, "gram_G");
     gram(ctx, L, S.Sk, sk_dt(ctx), S.Y, mdt, S.G);
   }
@@ -315,7 +342,10 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S) {
   const Lane& L = ctx->main;
   const int64_t np = ctx->np, qp = ctx->qp;
   const int mdt = ctx->mdt;
-  { Phase ph(ctx, L, "XY"); nn_times_panel(ctx, L, ctx->X, false, S.Y, mdt, ctx->V); }
+  {
+    Phase ph(ctx, L, "XY", true);
+    nn_times_panel(ctx, L, ctx->X, false, S.Y, mdt, ctx->V, 2, 2, 1, ph.mark());
+  }
   { Phase ph(ctx, L, "gram_H"); gram(ctx, L, S.Y, mdt, ctx->V, mdt, ctx->H); }
   const double scale = ctx->coord ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
   {
@@ -323,6 +353,7 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S) {
     HIPCHK(estimator(ctx->coord ? nullptr : S.Sk, sk_dt(ctx), ctx->coord ? S.C : nullptr, ctx->V, mdt, np, ctx->n,
                      ctx->q, scale, L.red, ctx->est, ctx->status, L.s));
   }
+  HIPCHK(hipStreamWaitEvent(L.s, S.ready, 0));  // G^-1 and U of this slot
   if (ctx->coord) {
     // U = E_C G^-1 is not formed: W' = V - E_C/2 - E_C (G^-1 H)/2 and R = G^-1 W'^T;
     // the update touches only rows and columns C.
@@ -347,7 +378,7 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S) {
       panel_times_small(ctx, L, S.U, DT_F32, ctx->H, W, DT_F32, -0.5, ctx->V, DT_F32, 1.0, S.Sk, DT_BF16, -0.5);
       HIPCHK(pack_split2(W, np, np, qp, S.planes, S.planes + plane, ldp, qp, L.s));
     }
-    Phase ph(ctx, L, "update");
+    Phase ph(ctx, L, "update", true);
     MixedGemm mg;
     GemmArgs& g = mg.g;
     g.M = np; g.N = np; g.K = 2 * qp;
@@ -364,7 +395,7 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S) {
       panel_times_small(ctx, L, PQ, DT_F64, ctx->H, PQ + np * qp, DT_F64, -0.5, ctx->V, DT_F64, 1.0, S.Sk, DT_F64,
                         -0.5);
     }
-    Phase ph(ctx, L, "update");
+    Phase ph(ctx, L, "update", true);
     GemmArgs g;
     g.M = np; g.N = np; g.K = 2 * qp;
     g.A = PQ; g.lda = np; g.a_dt = DT_F64; g.a_kc = false;
@@ -387,16 +418,22 @@ void main_adaptive(rbfgs_ctx* ctx, Slot& S) {
     Phase ph(ctx, L, "gather");
     HIPCHK(gather_cols_gen(ctx->X, mdt, np, S.C, ctx->q, np, ctx->Sa, mdt, np, L.s));
   } else {
-    Phase ph(ctx, L, "LS");
-    nn_times_panel(ctx, L, ctx->X, false, S.Sk, sk_dt(ctx), ctx->Sa, 3, 1, 2);  // S = L S~, exact products
+    Phase ph(ctx, L, "LS", true);
+    nn_times_panel(ctx, L, ctx->X, false, S.Sk, sk_dt(ctx), ctx->Sa, 3, 1, 2, ph.mark());  // S = L S~, exact products
   }
-  { Phase ph(ctx, L, "AS"); nn_times_panel(ctx, L, ctx->A, false, ctx->Sa, mdt, ctx->Y, 3, 2, 2); }
+  {
+    Phase ph(ctx, L, "AS", true);
+    nn_times_panel(ctx, L, ctx->A, false, ctx->Sa, mdt, ctx->Y, 3, 2, 2, ph.mark());
+  }
   { Phase ph(ctx, L, "gram_G"); gram(ctx, L, ctx->Sa, mdt, ctx->Y, mdt, ctx->G); }
   {
     Phase ph(ctx, L, "chol_inv");
     HIPCHK(chol_inv(ctx->G, qp, ctx->q, ctx->Z, ctx->Ginv, qp, L.cwork, ctx->status, L.s));
   }
-  { Phase ph(ctx, L, "LtY"); nn_times_panel(ctx, L, ctx->X, true, ctx->Y, mdt, ctx->V, 2, 3, 2); }  // T^T = L^T Y
+  {
+    Phase ph(ctx, L, "LtY", true);
+    nn_times_panel(ctx, L, ctx->X, true, ctx->Y, mdt, ctx->V, 2, 3, 2, ph.mark());  // T^T = L^T Y
+  }
   const double scale = ctx->coord ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
   {
     Phase ph(ctx, L, "panels");
@@ -410,7 +447,7 @@ void main_adaptive(rbfgs_ctx* ctx, Slot& S) {
       panel_times_small(ctx, L, S.Sk, sk_dt(ctx), ctx->Mq, ctx->W, mdt, 1.0, ctx->W, mdt, 1.0);
     }
   }
-  Phase ph(ctx, L, "update");  // L += S Q
+  Phase ph(ctx, L, "update", true);  // L += S Q
   if (ctx->mixed) {
     const int64_t plane = np * qp;
     __bf16* shi = ctx->planes;
@@ -453,7 +490,7 @@ void enqueue_steps(rbfgs_ctx* ctx, int64_t nsteps) {
     const int64_t k = ctx->k;
     if (i + 1 < nsteps) side(k + 1);
     Slot& S = ctx->slot[k & 1];
-    HIPCHK(hipStreamWaitEvent(ctx->main.s, S.ready, 0));
+    HIPCHK(hipStreamWaitEvent(ctx->main.s, ctx->ada ? S.ready : S.y_ready, 0));
     if (ctx->ada) main_adaptive(ctx, S);
     else main_fixed(ctx, S);
     HIPCHK(hipEventRecord(S.released, ctx->main.s));
@@ -528,6 +565,7 @@ void make_slot(rbfgs_ctx* ctx, Slot& S) {
       if (ctx->mixed) S.planes = (__bf16*)dalloc(ctx, (size_t)2 * 3 * np * qp * sizeof(__bf16));
     }
   }
+  HIPCHK(hipEventCreateWithFlags(&S.y_ready, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&S.ready, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&S.released, hipEventDisableTiming));
 }
@@ -541,6 +579,7 @@ void release(rbfgs_ctx* ctx) {
   }
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   for (Slot& S : ctx->slot) {
+    if (S.y_ready) (void)hipEventDestroy(S.y_ready);
     if (S.ready) (void)hipEventDestroy(S.ready);
     if (S.released) (void)hipEventDestroy(S.released);
   }
@@ -831,7 +870,8 @@ rbfgs_status rbfgs_profile(rbfgs_ctx* ctx, int32_t enable) {
   } catch (const Fail& f) {
     return f.st;
   }
-  ctx->prof = enable != 0;
+  if (enable < 0 || enable > 2) return RBFGS_E_INVALID_ARG;
+  ctx->prof = enable;
   return RBFGS_OK;
 }
 

@@ -463,6 +463,7 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
   return hipErrorInvalidValue;
 #undef RB_TALL
   if (e != hipSuccess) return e;
+  if (g.mark && (e = hipEventRecord(g.mark, s)) != hipSuccess) return e;
   return reduce_partials_f32(g, (const float*)partial_ws, s);
 }
 

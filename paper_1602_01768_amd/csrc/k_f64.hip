@@ -259,15 +259,26 @@ __global__ void k_reduce_partials_f64(GemmArgs g, const double* P) {
   }
 }
 
-static int pick_tile(int64_t x) { return (x % 128 == 0) ? 128 : 32; }
+// Tile shape of the column/row-store products: the largest tile that still gives
+// enough workgroups (M, N multiples of 32).
+static void pick_tiles(const GemmArgs& g, int& BM, int& BN) {
+  const int64_t sk = g.splitk;
+  if (g.M % 128 == 0 && g.N % 128 == 0 && (g.M / 128) * (g.N / 128) * sk >= 256) { BM = BN = 128; return; }
+  if (g.M % 64 == 0 && g.N % 64 == 0 && (g.M / 64) * (g.N / 64) * sk >= 64) { BM = BN = 64; return; }
+  if (g.M % 128 == 0 && (g.M / 128) * (g.N / 32) * sk >= 256) { BM = 128; BN = 32; return; }
+  if (g.N % 128 == 0 && (g.M / 32) * (g.N / 128) * sk >= 256) { BM = 32; BN = 128; return; }
+  BM = BN = 32;
+}
 
 int64_t gemm_f64_blocks(const GemmArgs& g) {
-  const int BM = pick_tile(g.M), BN = pick_tile(g.N);
-  if (g.epi == EPI_SYMUPD || g.epi == EPI_ADDROW) {
-    const int64_t T = g.M / BM;
+  if (g.epi == EPI_SYMUPD || g.epi == EPI_ADDROW || g.epi == EPI_RESID) {
+    const int64_t T = g.M / 128;
+    if (g.epi == EPI_RESID) return T * (g.N / 128);
     const int64_t NTT = g.tiles ? g.ntiles : (g.epi == EPI_SYMUPD ? T * (T + 1) / 2 : T * T);
     return (NTT + 7) / 8 * 8;
   }
+  int BM, BN;
+  pick_tiles(g, BM, BN);
   return (g.M / BM) * (g.N / BN) * g.splitk;
 }
 
@@ -303,13 +314,13 @@ hipError_t gemm_f64(const GemmArgs& gin, void* partial_ws, hipStream_t s) {
     run.epi = EPI_PARTIAL;
     run.C = partial_ws;
   }
-  int BM = pick_tile(g.M), BN = pick_tile(g.N);
-  if (g.epi == EPI_SYMUPD) BN = BM;
+  int BM, BN;
+  pick_tiles(run, BM, BN);
   const int64_t blocks = gemm_f64_blocks(run);
   hipError_t e = hipSuccess;
   if (run.epi == EPI_SYMUPD || run.epi == EPI_ADDROW || run.epi == EPI_RESID) {
     // n x n products: the order is a multiple of 256, always 128 x 128 tiles
-    if (BM != 128 || BN != 128) return hipErrorInvalidValue;
+    if (g.M % 128 || g.N % 128) return hipErrorInvalidValue;
     if (run.epi == EPI_SYMUPD && !run.a_kc && !run.b_kc)
       hipLaunchKernelGGL((k_gemm_f64<128, 128, false, false, EPI_SYMUPD>), dim3(blocks), dim3(256), 0, s, run);
     else if (run.epi == EPI_ADDROW && !run.a_kc && !run.b_kc)
@@ -319,12 +330,15 @@ hipError_t gemm_f64(const GemmArgs& gin, void* partial_ws, hipStream_t s) {
     else
       return hipErrorInvalidValue;
   } else if (BM == 128 && BN == 128) e = launch_f64_epi<128, 128>(run, blocks, s);
+  else if (BM == 64) e = launch_f64_epi<64, 64>(run, blocks, s);
   else if (BM == 128) e = launch_f64_epi<128, 32>(run, blocks, s);
   else if (BN == 128) e = launch_f64_epi<32, 128>(run, blocks, s);
   else e = launch_f64_epi<32, 32>(run, blocks, s);
   if (e != hipSuccess) return e;
   e = hipGetLastError();
-  if (e != hipSuccess || !split) return e;
+  if (e != hipSuccess) return e;
+  if (g.mark && (e = hipEventRecord(g.mark, s)) != hipSuccess) return e;
+  if (!split) return hipSuccess;
   return reduce_partials_f64(g, (const double*)partial_ws, s);
 }
 
@@ -333,189 +347,6 @@ hipError_t reduce_partials_f64(const GemmArgs& g, const double* P, hipStream_t s
   const int64_t blocks = std::min<int64_t>((MN + 255) / 256, 4096);
   hipLaunchKernelGGL(k_reduce_partials_f64, dim3(blocks), dim3(256), 0, s, g, P);
   return hipGetLastError();
-}
-
-// ------------------------------------------------------- q x q SPD inverse
-// One workgroup of 1024 threads on a block of order nb <= 128 held in LDS
-// (pitch nb+1).  Entries with index >= qv are the identity (zero-padded sizes).
-//   1. right-looking Cholesky G = L L^T in place (lower triangle);
-//   2. Z = L^-1 by forward substitution, row by row: Z[i][c] = (delta_ic -
-//      sum_{m<i} L[i][m] Z[m][c]) / L[i][i]; Z[i][c] (c < i) is kept in the
-//      upper triangle at [c][i], its diagonal in zd[];
-//   3. optionally Ginv = Z^T Z: Ginv[i][k] = sum_{m >= max(i,k)} Z[m][i] Z[m][k].
-__global__ __launch_bounds__(1024) void k_chol_inv_leaf(const double* G, int64_t ldg, int nb, int qv,
-                                                        double* Z, int64_t ldz, double* Ginv,
-                                                        int64_t ldi, int* status) {
-  extern __shared__ double lds[];
-  const int P = nb + 1;
-  double* a = lds;            // nb x P
-  double* zd = lds + nb * P;  // nb
-  double* part = zd + nb;     // 1024 partial sums
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nb * nb; e += 1024) {
-    const int i = e / nb, k = e % nb;
-    double v;
-    if (i < qv && k < qv) v = G[(int64_t)i * ldg + k];
-    else v = (i == k) ? 1.0 : 0.0;
-    a[i * P + k] = v;
-  }
-  __syncthreads();
-  const int tx = tid & 31, ty = tid >> 5;
-  // 1. Cholesky, lower triangle in place.
-  for (int j = 0; j < nb; ++j) {
-    const double d = a[j * P + j];
-    if (!(d > 0.0)) {
-      if (tid == 0) atomicCAS(status, 0, 3);
-      return;  // uniform: every thread read the same d
-    }
-    const double sd = sqrt(d);
-    __syncthreads();
-    for (int i = j + 1 + tid; i < nb; i += 1024) a[i * P + j] /= sd;
-    if (tid == 0) a[j * P + j] = sd;
-    __syncthreads();
-    for (int i = j + 1 + ty; i < nb; i += 32) {
-      const double lij = a[i * P + j];
-      for (int k = j + 1 + tx; k <= i; k += 32) a[i * P + k] -= lij * a[k * P + j];
-    }
-    __syncthreads();
-  }
-  // 2. Z = L^-1, rows in order; 8 threads per column share the dot product.
-  const int c = tid >> 3, part_id = tid & 7;
-  for (int i = 0; i < nb; ++i) {
-    double s = 0.0;
-    if (c < i) {
-      // sum_{m=c}^{i-1} L[i][m] Z[m][c];  Z[c][c] = zd[c], Z[m][c] = a[c][m] for m > c
-      for (int m = c + part_id; m < i; m += 8) {
-        const double zmc = (m == c) ? zd[c] : a[c * P + m];
-        s += a[i * P + m] * zmc;
-      }
-    }
-    part[tid] = s;
-    __syncthreads();
-    if (c < i && part_id == 0) {
-      double t = 0.0;
-      for (int p = 0; p < 8; ++p) t += part[tid + p];
-      a[c * P + i] = -t / a[i * P + i];  // Z[i][c] stored at [c][i]
-    }
-    if (tid == 0) zd[i] = 1.0 / a[i * P + i];
-    __syncthreads();
-  }
-  // Z out (lower, row-major), pad entries zero.
-  for (int e = tid; e < nb * nb; e += 1024) {
-    const int i = e / nb, k = e % nb;
-    double v = 0.0;
-    if (i < qv && k < qv) v = (k < i) ? a[k * P + i] : (k == i ? zd[i] : 0.0);
-    Z[(int64_t)i * ldz + k] = v;
-  }
-  if (!Ginv) return;
-  // 3. Ginv = Z^T Z (symmetric; pad entries zero).
-  for (int e = tid; e < nb * nb; e += 1024) {
-    const int i = e / nb, k = e % nb;
-    double v = 0.0;
-    if (i < qv && k < qv) {
-      const int m0 = i > k ? i : k;
-      for (int m = m0; m < qv; ++m) {
-        const double zmi = (m == i) ? zd[i] : a[i * P + m];
-        const double zmk = (m == k) ? zd[k] : a[k * P + m];
-        v += zmi * zmk;
-      }
-    }
-    Ginv[(int64_t)i * ldi + k] = v;
-  }
-}
-
-__global__ void k_zero_pad_sq(double* M, int64_t ld, int q, int qp) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < (int64_t)qp * qp;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e / qp, k = e % qp;
-    if (i >= q || k >= q) M[i * ld + k] = 0.0;
-  }
-}
-
-static size_t leaf_lds_bytes(int nb) { return sizeof(double) * ((size_t)nb * (nb + 1) + nb + 1024); }
-
-size_t chol_inv_work_doubles(int q) {
-  const int64_t qp = ((int64_t)q + 31) / 32 * 32;
-  return (size_t)(4 * qp * qp + 1024);
-}
-
-// Recursive 2 x 2 block inverse-Cholesky on the padded block [off, off+size):
-//   Z11 = chol(G11)^-1;  L21 = G21 Z11^T;  G22' = G22 - L21 L21^T;  Z22 = chol(G22')^-1;
-//   Z21 = -Z22 L21 Z11.   (Z = L^-1 with L = [[L11, 0], [L21, L22]].)
-static hipError_t chol_rec(const double* G, int64_t ldg, int size, int qv, double* Z, int64_t ldz,
-                           double* work, int* status, hipStream_t s) {
-  if (size <= 128) {
-    hipLaunchKernelGGL(k_chol_inv_leaf, dim3(1), dim3(1024), leaf_lds_bytes(size), s, G, ldg, size,
-                       qv < 0 ? 0 : (qv > size ? size : qv), Z, ldz, (double*)nullptr, (int64_t)0, status);
-    return hipGetLastError();
-  }
-  const int s1 = ((size / 2 + 31) / 32) * 32, s2 = size - s1;
-  hipError_t e;
-  if ((e = chol_rec(G, ldg, s1, qv, Z, ldz, work, status, s)) != hipSuccess) return e;
-  double* L21 = work;                        // s2 x s1 row-major
-  double* G22 = L21 + (int64_t)s2 * s1;      // s2 x s2
-  double* T = G22 + (int64_t)s2 * s2;        // s2 x s1
-  double* next = T + (int64_t)s2 * s1;
-  // L21 = G21 Z11^T : Aop(m,k) = G21[m][k], Bop(k,n) = Z11[n][k]
-  GemmArgs g;
-  g.M = s2; g.N = s1; g.K = s1;
-  g.A = G + (int64_t)s1 * ldg; g.lda = ldg; g.a_kc = true;
-  g.B = Z; g.ldb = ldz; g.b_kc = true;
-  g.epi = EPI_ROWSTORE; g.C = L21; g.ldc = s1; g.c2 = 1.0;
-  // rows >= qv of G are padding: G stores zeros there; Z11 has zero pad too.
-  if ((e = gemm_f64(g, nullptr, s)) != hipSuccess) return e;
-  // G22' = G22 - L21 L21^T (symmetric, so column-major store == row-major)
-  GemmArgs h;
-  h.M = s2; h.N = s2; h.K = s1;
-  h.A = L21; h.lda = s1; h.a_kc = true;
-  h.B = L21; h.ldb = s1; h.b_kc = true;
-  h.epi = EPI_COLSTORE; h.C = G22; h.ldc = s2; h.c2 = -1.0;
-  h.B0 = G + (int64_t)s1 * ldg + s1; h.ld01 = ldg; h.c0 = 1.0;
-  if ((e = gemm_f64(h, nullptr, s)) != hipSuccess) return e;
-  if ((e = chol_rec(G22, s2, s2, qv - s1, Z + (int64_t)s1 * ldz + s1, ldz, next, status, s)) != hipSuccess)
-    return e;
-  // T = L21 Z11
-  GemmArgs t;
-  t.M = s2; t.N = s1; t.K = s1;
-  t.A = L21; t.lda = s1; t.a_kc = true;
-  t.B = Z; t.ldb = ldz; t.b_kc = false;
-  t.epi = EPI_ROWSTORE; t.C = T; t.ldc = s1; t.c2 = 1.0;
-  if ((e = gemm_f64(t, nullptr, s)) != hipSuccess) return e;
-  // Z21 = -Z22 T
-  GemmArgs z;
-  z.M = s2; z.N = s1; z.K = s2;
-  z.A = Z + (int64_t)s1 * ldz + s1; z.lda = ldz; z.a_kc = true;
-  z.B = T; z.ldb = s1; z.b_kc = false;
-  z.epi = EPI_ROWSTORE; z.C = Z + (int64_t)s1 * ldz; z.ldc = ldz; z.c2 = -1.0;
-  return gemm_f64(z, nullptr, s);
-}
-
-hipError_t chol_inv(const double* G, int64_t ldg, int q, double* Z, double* Ginv, int64_t ld,
-                    double* work, int* status, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_chol_inv_leaf, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)leaf_lds_bytes(128));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  const int qp = (q + 31) / 32 * 32;
-  if (qp <= 128) {
-    hipLaunchKernelGGL(k_chol_inv_leaf, dim3(1), dim3(1024), leaf_lds_bytes(qp), s, G, ldg, qp, q, Z,
-                       ld, Ginv, ld, status);
-    return hipGetLastError();
-  }
-  hipError_t e = chol_rec(G, ldg, qp, q, Z, ld, work, status, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_zero_pad_sq, dim3(64), dim3(256), 0, s, Z, ld, q, qp);
-  if (!Ginv) return hipGetLastError();
-  // Ginv = Z^T Z : Aop(i,k) = Z[k][i], Bop(k,j) = Z[k][j]
-  GemmArgs g;
-  g.M = qp; g.N = qp; g.K = qp;
-  g.A = Z; g.lda = ld; g.a_kc = false;
-  g.B = Z; g.ldb = ld; g.b_kc = false;
-  g.epi = EPI_ROWSTORE; g.C = Ginv; g.ldc = ld; g.c2 = 1.0;
-  return gemm_f64(g, nullptr, s);
 }
 
 // ------------------------------------------------------------- small kernels

@@ -43,6 +43,9 @@ struct GemmArgs {
   // handed out so that each XCD (blockIdx % 8) takes a contiguous run of it
   const int2* tiles = nullptr;
   int64_t ntiles = 0;
+  // optional event recorded on the stream between the product kernel and its split-K
+  // reduction (timing of the product kernel alone)
+  hipEvent_t mark = nullptr;
 };
 
 // Tile order for an n x n product of T x T tiles: super-tiles of S x S tiles in row-major

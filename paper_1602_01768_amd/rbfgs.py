@@ -197,7 +197,8 @@ def rbfgs_destroy(ctx):
 
 
 def rbfgs_profile(ctx, enable=True):
-    _check(load_library().rbfgs_profile(ctx, int(bool(enable))), ctx)
+    """enable: False/0 off, True/1 every phase, 2 the n x n products only."""
+    _check(load_library().rbfgs_profile(ctx, int(enable)), ctx)
 
 
 def rbfgs_profile_report(ctx):
