@@ -1,12 +1,13 @@
 // C ABI of the RBFGS library: context management and the per-iteration
 // orchestration of the kernels.  See include/rbfgs.h for the contract.
 //
-// Two HIP streams ("lanes") per context.  Everything of iteration k that depends
-// only on the sketch -- S, A S, G = S^T A S and its Cholesky-based inverse, and
-// U = S G^-1 for the fixed method; S~^T S~ and its factor for the adaptive one --
-// is computed on the side lane into one of two slots while the main lane runs
-// the X- (or L-) dependent part of iteration k-1.  Events order the two lanes;
-// every slot is double-buffered.
+// Three HIP streams ("lanes") per context.  Everything of iteration k that depends
+// only on the sketch is computed ahead of the X- (or L-) dependent part on the main
+// lane, into one of three slots: the side lane forms S, A S and G = S^T A S (fixed
+// method) or S~^T S~ (adaptive) up to two iterations ahead, the inverse lane the
+// Cholesky-based inverse and U = S G^-1 one iteration ahead, so the long
+// single-workgroup factorization of iteration k+1 overlaps the products of k+2
+// and the main lane's work on k.  Events order the lanes.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -33,6 +34,7 @@ struct Lane {  // one stream with its own split-K, reduction and Cholesky worksp
   void* partial = nullptr;
   size_t partial_bytes = 0;
   double* red = nullptr;
+  size_t red_count = 0;
   double* cwork = nullptr;
 };
 
@@ -46,7 +48,8 @@ struct Slot {  // sketch-dependent quantities of one iteration
   void* U = nullptr;         // fixed: U = S G^-1 (mixed: FP32 n x q; FP64: panels [U | W' | U])
   __bf16* planes = nullptr;  // mixed fixed: bf16 hi/lo planes of [U | W' | U], row-major
   hipEvent_t y_ready = nullptr;   // side lane: sketch and Y = A S written (fixed sketch)
-  hipEvent_t ready = nullptr;     // side lane: slot complete
+  hipEvent_t g_ready = nullptr;   // side lane: G (or S~^T S~) written
+  hipEvent_t ready = nullptr;     // inverse lane: slot complete
   hipEvent_t released = nullptr;  // main lane: iteration that used the slot complete
   bool released_valid = false;
 };
@@ -62,9 +65,11 @@ struct rbfgs_ctx {
   int device = 0;
   int64_t k = 0;
   std::string err;
-  Lane main, side;
-  Slot slot[2];
+  static constexpr int NSLOT = 3;
+  Lane main, side, inv;
+  Slot slot[NSLOT];
   hipEvent_t ev_begin = nullptr;
+  hipEvent_t ev_xy = nullptr;  // main lane: X Y of the current iteration enqueued before it
   // main-lane buffers
   void* A = nullptr;
   void* X = nullptr;        // X (fixed) or L (adaptive)
@@ -170,6 +175,7 @@ void prof_flush(rbfgs_ctx* ctx) {
   if (ctx->prof_pending.empty()) return;
   HIPCHK(hipStreamSynchronize(ctx->main.s));
   HIPCHK(hipStreamSynchronize(ctx->side.s));
+  HIPCHK(hipStreamSynchronize(ctx->inv.s));
   std::vector<hipEvent_t> used;
   for (auto& r : ctx->prof_pending) {
     float ms = 0;
@@ -228,8 +234,10 @@ void bf_gemm(rbfgs_ctx* ctx, const Lane& L, MixedGemm mg) {
 // out = M * P for an n x n matrix M (A, X or L) and an n x q panel P, per precision.
 // transpose: Aop = M^T (T^T = L^T Y).  In mixed mode (na, nb, pmax) choose the bf16
 // pieces of each operand and the passes kept (all piece pairs with i + j <= pmax).
+// est_S (mixed mode): the reduction of the product also accumulates per-workgroup sums
+// of (est_S - out)^2 into L.red (see reduce_blocks_f32).
 void nn_times_panel(rbfgs_ctx* ctx, const Lane& L, const void* M, bool transpose, const void* P, int p_dt, void* out,
-                    int na = 2, int nb = 2, int pmax = 1, hipEvent_t mark = nullptr) {
+                    int na = 2, int nb = 2, int pmax = 1, hipEvent_t mark = nullptr, const __bf16* est_S = nullptr) {
   if (ctx->mixed) {
     MixedGemm mg;
     GemmArgs& g = mg.g;
@@ -237,6 +245,10 @@ void nn_times_panel(rbfgs_ctx* ctx, const Lane& L, const void* M, bool transpose
     g.A = M; g.lda = ctx->np;
     g.B = P; g.ldb = ctx->np;
     g.epi = EPI_COLSTORE; g.C = out; g.ldc = ctx->np; g.c2 = 1.0; g.mark = mark;
+    if (est_S) {
+      g.est_S = est_S;
+      g.est_red = L.red;
+    }
     mg.a_kind = transpose ? OK_F32_MC : OK_F32_KC;
     mg.b_kind = p_dt == DT_BF16 ? OK_BF16_KC : OK_F32_KC;
     mg.na = na; mg.nb = p_dt == DT_BF16 ? 1 : nb; mg.pmax = pmax;
@@ -286,9 +298,11 @@ void small_small(rbfgs_ctx* ctx, const Lane& L, const double* A, bool at, const 
 
 int sk_dt(const rbfgs_ctx* ctx) { return ctx->mixed ? DT_BF16 : DT_F64; }
 
-// ---------------------------------------------------------------- side lane
-// Sketch-dependent part of iteration k into slot S (side lane).
-void side_chain(rbfgs_ctx* ctx, int64_t k, Slot& S) {
+// ---------------------------------------------------------------- side lanes
+// Sketch-dependent products of iteration k into slot S (side lane): the sketch, and
+// for the fixed method Y = A S (or the gathered columns) and G = S^T Y; for the
+// adaptive Gaussian method S~^T S~.
+void side_products(rbfgs_ctx* ctx, int64_t k, Slot& S) {
   const Lane& L = ctx->side;
   const int64_t np = ctx->np, qp = ctx->qp;
   const int mdt = ctx->mdt;
@@ -298,14 +312,11 @@ void side_chain(rbfgs_ctx* ctx, int64_t k, Slot& S) {
     else HIPCHK(sketch_gauss(ctx->p.seed, k, ctx->n, ctx->q, S.Sk, sk_dt(ctx), np, L.s));
   }
   if (ctx->ada) {
-    if (!ctx->coord) {  // factor of S~^T S~ for C = L_M^-1
+    if (!ctx->coord) {
       Phase ph(ctx, L, "sketch_gram");
       gram(ctx, L, S.Sk, sk_dt(ctx), S.Sk, sk_dt(ctx), S.G);
-      HIPCHK(chol_inv(S.G, qp, ctx->q, S.Z, nullptr, qp, L.cwork, ctx->status, L.s));
     }
-    return;
-  }
-  if (ctx->coord) {
+  } else if (ctx->coord) {
     Phase ph(ctx, L, "gather");
     HIPCHK(gather_cols_sym(ctx->A, mdt, np, S.C, ctx->q, np, S.Y, mdt, np, S.G, qp, L.s));
     HIPCHK(hipEventRecord(S.y_ready, L.s));
@@ -317,6 +328,22 @@ void side_chain(rbfgs_ctx* ctx, int64_t k, Slot& S) {
     HIPCHK(hipEventRecord(S.y_ready, L.s));
     Phase ph(ctx, L, "gram_G");
     gram(ctx, L, S.Sk, sk_dt(ctx), S.Y, mdt, S.G);
+  }
+  HIPCHK(hipEventRecord(S.g_ready, L.s));
+}
+
+// Inverse part of iteration k into slot S (inverse lane), after side_products: the
+// Cholesky-based inverse of G (fixed) or the factor of S~^T S~ (adaptive Gaussian),
+// and U = S G^-1 packed for the update (fixed Gaussian).
+void side_inverse(rbfgs_ctx* ctx, Slot& S) {
+  const Lane& L = ctx->inv;
+  const int64_t np = ctx->np, qp = ctx->qp;
+  if (ctx->ada) {
+    if (!ctx->coord) {  // factor of S~^T S~ for C = L_M^-1
+      Phase ph(ctx, L, "sketch_chol");
+      HIPCHK(chol_inv(S.G, qp, ctx->q, S.Z, nullptr, qp, L.cwork, ctx->status, L.s));
+    }
+    return;
   }
   { Phase ph(ctx, L, "chol_inv"); HIPCHK(chol_inv(S.G, qp, ctx->q, S.Z, S.Ginv, qp, L.cwork, ctx->status, L.s)); }
   if (ctx->coord) return;
@@ -338,20 +365,32 @@ void side_chain(rbfgs_ctx* ctx, int64_t k, Slot& S) {
 // X-dependent part of one fixed-sketch RBFGS iteration, eq. (qunac) as the
 // symmetric rank-2q update X+ = X - (U W'^T + W' U^T), U = S G^-1,
 // W' = V - S/2 - U H/2, V = X Y, H = Y^T V (Y = A S and G = S^T Y from the slot).
-void main_fixed(rbfgs_ctx* ctx, Slot& S) {
+// after_xy runs right after V = X Y is enqueued (the caller schedules the side lanes
+// from there).
+template <class F>
+void main_fixed(rbfgs_ctx* ctx, Slot& S, F&& after_xy) {
   const Lane& L = ctx->main;
   const int64_t np = ctx->np, qp = ctx->qp;
   const int mdt = ctx->mdt;
+  // mixed Gaussian: the estimator's sum of squares comes out of the product's reduction
+  GemmArgs shape;
+  shape.M = np; shape.N = qp;
+  const bool fused_est = ctx->mixed && !ctx->coord && (size_t)reduce_blocks_f32(shape) <= L.red_count;
   {
     Phase ph(ctx, L, "XY", true);
-    nn_times_panel(ctx, L, ctx->X, false, S.Y, mdt, ctx->V, 2, 2, 1, ph.mark());
+    nn_times_panel(ctx, L, ctx->X, false, S.Y, mdt, ctx->V, 2, 2, 1, ph.mark(),
+                   fused_est ? (const __bf16*)S.Sk : nullptr);
   }
+  after_xy();
   { Phase ph(ctx, L, "gram_H"); gram(ctx, L, S.Y, mdt, ctx->V, mdt, ctx->H); }
   const double scale = ctx->coord ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
   {
     Phase ph(ctx, L, "estimator");
-    HIPCHK(estimator(ctx->coord ? nullptr : S.Sk, sk_dt(ctx), ctx->coord ? S.C : nullptr, ctx->V, mdt, np, ctx->n,
-                     ctx->q, scale, L.red, ctx->est, ctx->status, L.s));
+    if (fused_est)
+      HIPCHK(reduce_sum_scaled(L.red, reduce_blocks_f32(shape), ctx->est, scale, ctx->status, L.s));
+    else
+      HIPCHK(estimator(ctx->coord ? nullptr : S.Sk, sk_dt(ctx), ctx->coord ? S.C : nullptr, ctx->V, mdt, np, ctx->n,
+                       ctx->q, scale, L.red, ctx->est, ctx->status, L.s));
   }
   HIPCHK(hipStreamWaitEvent(L.s, S.ready, 0));  // G^-1 and U of this slot
   if (ctx->coord) {
@@ -474,25 +513,50 @@ void main_adaptive(rbfgs_ctx* ctx, Slot& S) {
   }
 }
 
-// Enqueue iterations k .. k+nsteps-1: the side lane runs one iteration ahead.
+// Enqueue iterations k .. k+nsteps-1: the side lane runs up to two iterations ahead,
+// the inverse lane one.  For the fixed method the side lane's products of iteration
+// k+2 start once the main lane's X Y of iteration k is done, so that A S shares the
+// GPU with the main lane's small q-sized kernels rather than with X Y.
 void enqueue_steps(rbfgs_ctx* ctx, int64_t nsteps) {
   if (nsteps <= 0) return;
+  constexpr int NS = rbfgs_ctx::NSLOT;
   HIPCHK(hipEventRecord(ctx->ev_begin, ctx->main.s));
   HIPCHK(hipStreamWaitEvent(ctx->side.s, ctx->ev_begin, 0));
-  auto side = [&](int64_t k) {
-    Slot& S = ctx->slot[k & 1];
+  HIPCHK(hipStreamWaitEvent(ctx->inv.s, ctx->ev_begin, 0));
+  auto products = [&](int64_t k) {
+    Slot& S = ctx->slot[k % NS];
     if (S.released_valid) HIPCHK(hipStreamWaitEvent(ctx->side.s, S.released, 0));
-    side_chain(ctx, k, S);
-    HIPCHK(hipEventRecord(S.ready, ctx->side.s));
+    side_products(ctx, k, S);
   };
-  side(ctx->k);
+  auto inverse = [&](int64_t k) {
+    Slot& S = ctx->slot[k % NS];
+    HIPCHK(hipStreamWaitEvent(ctx->inv.s, S.g_ready, 0));
+    side_inverse(ctx, S);
+    HIPCHK(hipEventRecord(S.ready, ctx->inv.s));
+  };
+  const int64_t k0 = ctx->k;
+  products(k0);
+  if (nsteps > 1) products(k0 + 1);
+  inverse(k0);
   for (int64_t i = 0; i < nsteps; ++i) {
     const int64_t k = ctx->k;
-    if (i + 1 < nsteps) side(k + 1);
-    Slot& S = ctx->slot[k & 1];
-    HIPCHK(hipStreamWaitEvent(ctx->main.s, ctx->ada ? S.ready : S.y_ready, 0));
-    if (ctx->ada) main_adaptive(ctx, S);
-    else main_fixed(ctx, S);
+    auto ahead = [&]() {
+      if (i + 2 < nsteps) products(k + 2);
+      if (i + 1 < nsteps) inverse(k + 1);
+    };
+    Slot& S = ctx->slot[k % NS];
+    if (ctx->ada) {
+      ahead();
+      HIPCHK(hipStreamWaitEvent(ctx->main.s, S.ready, 0));
+      main_adaptive(ctx, S);
+    } else {
+      HIPCHK(hipStreamWaitEvent(ctx->main.s, S.y_ready, 0));
+      main_fixed(ctx, S, [&]() {
+        HIPCHK(hipEventRecord(ctx->ev_xy, ctx->main.s));
+        HIPCHK(hipStreamWaitEvent(ctx->side.s, ctx->ev_xy, 0));
+        ahead();
+      });
+    }
     HIPCHK(hipEventRecord(S.released, ctx->main.s));
     S.released_valid = true;
     ++ctx->k;
@@ -507,6 +571,7 @@ rbfgs_status fail(rbfgs_ctx* ctx, rbfgs_status st, const std::string& msg) {
 rbfgs_status read_status(rbfgs_ctx* ctx) {
   int st = 0;
   HIPCHK(hipStreamSynchronize(ctx->side.s));
+  HIPCHK(hipStreamSynchronize(ctx->inv.s));
   HIPCHK(hipMemcpyAsync(&st, ctx->status, sizeof(int), hipMemcpyDeviceToHost, ctx->main.s));
   HIPCHK(hipStreamSynchronize(ctx->main.s));
   if (st == 3) return fail(ctx, RBFGS_E_NOT_SPD, "Cholesky of S^T A S met a non-positive pivot (A not SPD?)");
@@ -547,6 +612,7 @@ void make_lane(rbfgs_ctx* ctx, Lane& L, size_t partial_bytes, size_t red_count) 
   L.partial_bytes = partial_bytes;
   L.partial = dalloc(ctx, partial_bytes);
   L.red = (double*)dalloc(ctx, red_count * sizeof(double));
+  L.red_count = red_count;
   L.cwork = (double*)dalloc(ctx, chol_inv_work_doubles(ctx->q) * sizeof(double));
 }
 
@@ -566,6 +632,7 @@ void make_slot(rbfgs_ctx* ctx, Slot& S) {
     }
   }
   HIPCHK(hipEventCreateWithFlags(&S.y_ready, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&S.g_ready, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&S.ready, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&S.released, hipEventDisableTiming));
 }
@@ -573,6 +640,7 @@ void make_slot(rbfgs_ctx* ctx, Slot& S) {
 void release(rbfgs_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->main.s);
   if (ctx->side.s) (void)hipStreamSynchronize(ctx->side.s);
+  if (ctx->inv.s) (void)hipStreamSynchronize(ctx->inv.s);
   for (auto& r : ctx->prof_pending) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -580,12 +648,15 @@ void release(rbfgs_ctx* ctx) {
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   for (Slot& S : ctx->slot) {
     if (S.y_ready) (void)hipEventDestroy(S.y_ready);
+    if (S.g_ready) (void)hipEventDestroy(S.g_ready);
     if (S.ready) (void)hipEventDestroy(S.ready);
     if (S.released) (void)hipEventDestroy(S.released);
   }
   if (ctx->ev_begin) (void)hipEventDestroy(ctx->ev_begin);
+  if (ctx->ev_xy) (void)hipEventDestroy(ctx->ev_xy);
   for (void* p : ctx->allocs) (void)hipFree(p);
   if (ctx->side.s) (void)hipStreamDestroy(ctx->side.s);
+  if (ctx->inv.s) (void)hipStreamDestroy(ctx->inv.s);
   delete ctx;
 }
 
@@ -619,15 +690,17 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
   try {
     HIPCHK(hipGetDevice(&ctx->device));
     HIPCHK(hipStreamCreateWithFlags(&ctx->side.s, hipStreamNonBlocking));  // default priority
+    HIPCHK(hipStreamCreateWithFlags(&ctx->inv.s, hipStreamNonBlocking));   // default priority
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_begin, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_xy, hipEventDisableTiming));
     const int64_t np = ctx->np, qp = ctx->qp;
     const size_t es = dt_size(ctx->mdt);
     const size_t partial = std::max<size_t>((size_t)8 * np * qp * 8, (size_t)128 * qp * qp * sizeof(double));
     const size_t red = (size_t)std::max<int64_t>(4096, (np / 32) * (np / 32) + 16);
     make_lane(ctx, ctx->main, partial, red);
     make_lane(ctx, ctx->side, partial, 4096);
-    make_slot(ctx, ctx->slot[0]);
-    make_slot(ctx, ctx->slot[1]);
+    make_lane(ctx, ctx->inv, partial, 4096);
+    for (Slot& S : ctx->slot) make_slot(ctx, S);
     ctx->A = dalloc(ctx, np * np * es);
     ctx->X = dalloc(ctx, np * np * es);
     ctx->pos = (int32_t*)dalloc(ctx, np * sizeof(int32_t));
@@ -836,6 +909,7 @@ rbfgs_status rbfgs_set_state(rbfgs_ctx* ctx, const void* M, int32_t m_dtype, int
     const void* src = M;
     void* staging = nullptr;
     HIPCHK(hipStreamSynchronize(ctx->side.s));
+    HIPCHK(hipStreamSynchronize(ctx->inv.s));
     if (!on_device) {
       HIPCHK(hipMalloc(&staging, (size_t)n * ldm * dt_size(sdt)));
       HIPCHK(hipMemcpyAsync(staging, M, (size_t)n * ldm * dt_size(sdt), hipMemcpyHostToDevice, ctx->main.s));

@@ -19,6 +19,12 @@ namespace {
 #ifndef RB_TS_PF
 #define RB_TS_PF 1  // register prefetch depth of the tall-skinny products (1 measured faster than 2)
 #endif
+#ifndef RB_TS_LDB
+#define RB_TS_LDB 1  // two LDS buffers in the tall-skinny products
+#endif
+#ifndef RB_TS_LDB_AS
+#define RB_TS_LDB_AS 0  // ... and in the product with an exact bf16 sketch (A S, L S~); 0 measured faster
+#endif
 #ifndef RB_UPD_TILE
 #define RB_UPD_TILE 128  // square-update tile (128 measured faster than 256)
 #endif
@@ -154,18 +160,18 @@ struct TileLoader {
 // NT = 64 * WAVES_M * WAVES_N threads; wave tile WM x WN of 32 x 32 blocks.
 // v_mfma_f32_32x32x16_bf16: lane l holds A(l%32, 8*(l/32) .. +7), B(8*(l/32) .. +7, l%32);
 // output column l%32, rows 8*(r/4) + 4*(l/32) + r%4 for r = 0..15.
-// DBUF: read the fragments of the next 16-wide k sub-step while the current MFMAs
-// issue (costs registers); launch bounds ask for two waves per SIMD (<= 256 VGPRs).
-template <int BM, int BN, int WAVES_M, int WAVES_N, int NA, int NB, int PMAX, int AK, int BKD, bool DBUF, int EPI,
+// LDB: two LDS buffers (one barrier per k tile, the next tile staged during the MFMAs);
+// launch bounds ask for two waves per SIMD (<= 256 VGPRs).
+template <int BM, int BN, int WAVES_M, int WAVES_N, int NA, int NB, int PMAX, int AK, int BKD, bool LDB, int EPI,
           int PF, int BK>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArgs g) {
   constexpr int NT = 64 * WAVES_M * WAVES_N;
   constexpr int PITCH = BK + 8;
   constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
   constexpr int FM = WM / 32, FN = WN / 32;
-  constexpr int LOOP_E = (NA * BM + NB * BN) * PITCH;                 // bf16 elements
+  constexpr int LOOP_E = (NA * BM + NB * BN) * PITCH;                 // bf16 elements of one buffer
   constexpr int EPI_E = 2 * WAVES_M * WAVES_N * 32 * 33;  // per-wave 32 x 33 float transpose buffers
-  constexpr int SM = LOOP_E > EPI_E ? LOOP_E : EPI_E;
+  constexpr int SM = (LDB ? 2 : 1) * LOOP_E > EPI_E ? (LDB ? 2 : 1) * LOOP_E : EPI_E;
   __shared__ __attribute__((aligned(16))) __bf16 smem[SM];
   __bf16* As = smem;
   __bf16* Bs = smem + NA * BM * PITCH;
@@ -212,8 +218,39 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArg
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
-  // One k tile: stage the registers of tile k0 into LDS, start the global loads of
-  // tile k0 + PF*BK into the same registers, then run the MFMAs on LDS.
+  const int lr = (lane >> 5) * 4, lc = lane & 31;  // MFMA output row group and column of this lane
+
+  // MFMAs of one 16-wide k sub-step s of the tile held in LDS at (As_, Bs_); piece
+  // products ordered smallest first.
+  auto substep = [&](const __bf16* As_, const __bf16* Bs_, int s) {
+    bf16x8 av[NA][FM], bv[NB][FN];
+    const int kofs = s * 16 + 8 * (lane >> 5);
+#pragma unroll
+    for (int p = 0; p < NA; ++p)
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+        av[p][a] = *(const bf16x8*)(As_ + (p * BM + wm * WM + a * 32 + (lane & 31)) * PITCH + kofs);
+#pragma unroll
+    for (int p = 0; p < NB; ++p)
+#pragma unroll
+      for (int b = 0; b < FN; ++b)
+        bv[p][b] = *(const bf16x8*)(Bs_ + (p * BN + wn * WN + b * 32 + (lane & 31)) * PITCH + kofs);
+#pragma unroll
+    for (int lvl = PMAX; lvl >= 0; --lvl)
+#pragma unroll
+      for (int pa = 0; pa < NA; ++pa) {
+        const int pb = lvl - pa;
+        if (pb < 0 || pb >= NB) continue;
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+          for (int b = 0; b < FN; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[pa][a], bv[pb][b], acc[a][b], 0, 0, 0);
+      }
+  };
+
+  // Single LDS buffer: stage the registers of tile k0 into LDS, start the global loads
+  // of tile k0 + PF*BK into the same registers, then run the MFMAs on LDS.
   auto k_tile = [&](auto& la, auto& lb, int64_t k0) {
     __syncthreads();
     la.store(As, tid);
@@ -223,49 +260,63 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArg
       la.load(g.A, g.lda, g.a_plane, m0, k0 + PF * BK, tid);
       lb.load(g.B, g.ldb, g.b_plane, n0, k0 + PF * BK, tid);
     }
-      constexpr int NBUF = DBUF ? 2 : 1;
-      bf16x8 av[NBUF][NA][FM], bv[NBUF][NB][FN];
-      auto read_frags = [&](int s, int buf) {
-        const int kofs = s * 16 + 8 * (lane >> 5);
-  #pragma unroll
-        for (int p = 0; p < NA; ++p)
-  #pragma unroll
-          for (int a = 0; a < FM; ++a)
-            av[buf][p][a] = *(const bf16x8*)(As + (p * BM + wm * WM + a * 32 + (lane & 31)) * PITCH + kofs);
-  #pragma unroll
-        for (int p = 0; p < NB; ++p)
-  #pragma unroll
-          for (int b = 0; b < FN; ++b)
-            bv[buf][p][b] = *(const bf16x8*)(Bs + (p * BN + wn * WN + b * 32 + (lane & 31)) * PITCH + kofs);
-      };
-      if (DBUF) read_frags(0, 0);
-  #pragma unroll
-      for (int s = 0; s < BK / 16; ++s) {
-        const int cur = DBUF ? (s & 1) : 0;
-        if (!DBUF) read_frags(s, 0);
-        else if (s + 1 < BK / 16) read_frags(s + 1, cur ^ 1);
-        // smallest pieces first
-  #pragma unroll
-        for (int lvl = PMAX; lvl >= 0; --lvl)
-  #pragma unroll
-          for (int pa = 0; pa < NA; ++pa) {
-            const int pb = lvl - pa;
-            if (pb < 0 || pb >= NB) continue;
-  #pragma unroll
-            for (int a = 0; a < FM; ++a)
-  #pragma unroll
-              for (int b = 0; b < FN; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[cur][pa][a], bv[cur][pb][b], acc[a][b], 0, 0, 0);
-          }
-      }
-
+#pragma unroll
+    for (int s = 0; s < BK / 16; ++s) substep(As, Bs, s);
   };
+
+  // square products: the old values of this wave's 32 x 32 output blocks are read two
+  // blocks ahead (the first two before the k loop), so their HBM latency hides behind
+  // the MFMAs and the stores of the blocks before them
+  constexpr bool RMW = (EPI == EPI_SYMUPD || EPI == EPI_ADDROW);
+  constexpr int NBLK = FM * FN;
+  float oldv[RMW ? 2 : 1][16];
+  const float* Cw = (const float*)g.C + (m0 + wm * WM) * g.ldc + (n0 + wn * WN);
+  auto load_old = [&](int i, float (&o)[16]) {
+    const int a = i / FN, b = i % FN;
+    const int ld = (int)g.ldc;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) o[r] = Cw[(a * 32 + (r >> 2) * 8 + lr + (r & 3)) * ld + b * 32 + lc];
+  };
+  if constexpr (RMW) {
+    load_old(0, oldv[0]);
+    if (NBLK > 1) load_old(1, oldv[1]);
+  }
 
   TileLoader<BM, NA, AK, NT, BK> la0;
   TileLoader<BN, NB, BKD, NT, BK> lb0;
   la0.load(g.A, g.lda, g.a_plane, m0, kbeg, tid);
   lb0.load(g.B, g.ldb, g.b_plane, n0, kbeg, tid);
-  if constexpr (PF == 1) {
+  if constexpr (LDB) {
+    // Two LDS buffers, one barrier per tile: while the MFMAs of tile t run on buffer
+    // t&1, tile t+1 (already in registers) is split into the other buffer and the
+    // global loads of tile t+2 start.  Buffer (t+1)&1 was last read in iteration t-1,
+    // which the barrier closing that iteration has finished.
+    la0.store(As, tid);
+    lb0.store(Bs, tid);
+    if (kbeg + BK < kend) {
+      la0.load(g.A, g.lda, g.a_plane, m0, kbeg + BK, tid);
+      lb0.load(g.B, g.ldb, g.b_plane, n0, kbeg + BK, tid);
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+      const __bf16* Ac = As + cur * LOOP_E;
+      const __bf16* Bc = Bs + cur * LOOP_E;
+      substep(Ac, Bc, 0);
+      if (k0 + BK < kend) {
+        la0.store(As + (cur ^ 1) * LOOP_E, tid);
+        lb0.store(Bs + (cur ^ 1) * LOOP_E, tid);
+        if (k0 + 2 * BK < kend) {
+          la0.load(g.A, g.lda, g.a_plane, m0, k0 + 2 * BK, tid);
+          lb0.load(g.B, g.ldb, g.b_plane, n0, k0 + 2 * BK, tid);
+        }
+      }
+#pragma unroll
+      for (int s = 1; s < BK / 16; ++s) substep(Ac, Bc, s);
+      __syncthreads();
+      cur ^= 1;
+    }
+  } else if constexpr (PF == 1) {
     for (int64_t k0 = kbeg; k0 < kend; k0 += BK) k_tile(la0, lb0, k0);
   } else {
     // two register stages in flight: tiles k0 and k0 + BK
@@ -282,7 +333,6 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArg
   }
 
   // ---------------------------------------------------------------- epilogue
-  const int lr = (lane >> 5) * 4, lc = lane & 31;
   if constexpr (EPI == EPI_SYMUPD) {
     // X += c2 * acc on the lower tile, one 32 x 32 block at a time: the old values
     // of the block are loaded together, the new values go to X directly and,
@@ -295,29 +345,28 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArg
     const float c2 = (float)g.c2;
     const int dofs = (int)((m0 + wm * WM) - (n0 + wn * WN));           // m - n at the wave origin
 #pragma unroll
-    for (int a = 0; a < FM; ++a)
+    for (int i = 0; i < NBLK; ++i) {
+      const int a = i / FN, b = i % FN;
+      float nvs[16];
 #pragma unroll
-      for (int b = 0; b < FN; ++b) {
-        float old[16];
+      for (int r = 0; r < 16; ++r) nvs[r] = oldv[i & 1][r] + c2 * acc[a][b][r];
+      if (i + 2 < NBLK) load_old(i + 2, oldv[i & 1]);
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-          old[r] = Xd[(a * 32 + (r >> 2) * 8 + lr + (r & 3)) * ld + b * 32 + lc];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int ml = (r >> 2) * 8 + lr + (r & 3);
-          const float nv = old[r] + c2 * acc[a][b][r];
-          // element (m, n): m - n = dofs + a*32 + ml - b*32 - lc
-          if (!diag || dofs + a * 32 + ml - b * 32 - lc >= 0) Xd[(a * 32 + ml) * ld + b * 32 + lc] = nv;
-          R[lc * 33 + ml] = nv;
-        }
-        __syncthreads();
-        if (lane < 32) {
-#pragma unroll 8
-          for (int c = 0; c < 32; ++c)
-            if (!diag || dofs + a * 32 + lane - b * 32 - c > 0) Xm[(b * 32 + c) * ld + a * 32 + lane] = R[c * 33 + lane];
-        }
-        __syncthreads();
+      for (int r = 0; r < 16; ++r) {
+        const int ml = (r >> 2) * 8 + lr + (r & 3);
+        const float nv = nvs[r];
+        // element (m, n): m - n = dofs + a*32 + ml - b*32 - lc
+        if (!diag || dofs + a * 32 + ml - b * 32 - lc >= 0) Xd[(a * 32 + ml) * ld + b * 32 + lc] = nv;
+        R[lc * 33 + ml] = nv;
       }
+      __syncthreads();
+      if (lane < 32) {
+#pragma unroll 8
+        for (int c = 0; c < 32; ++c)
+          if (!diag || dofs + a * 32 + lane - b * 32 - c > 0) Xm[(b * 32 + c) * ld + a * 32 + lane] = R[c * 33 + lane];
+      }
+      __syncthreads();
+    }
     return;
   }
   if constexpr (EPI == EPI_PARTIAL) {
@@ -336,26 +385,51 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArg
     const int ld = (int)g.ldc;
     const float c2 = (float)g.c2;
 #pragma unroll
-    for (int a = 0; a < FM; ++a)
+    for (int i = 0; i < NBLK; ++i) {
+      const int a = i / FN, b = i % FN;
+      float nvs[16];
 #pragma unroll
-      for (int b = 0; b < FN; ++b)
+      for (int r = 0; r < 16; ++r) nvs[r] = oldv[i & 1][r] + c2 * acc[a][b][r];
+      if (i + 2 < NBLK) load_old(i + 2, oldv[i & 1]);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int o = (a * 32 + (r >> 2) * 8 + lr + (r & 3)) * ld + b * 32 + lc;
-          C[o] = C[o] + c2 * acc[a][b][r];
-        }
+      for (int r = 0; r < 16; ++r) C[(a * 32 + (r >> 2) * 8 + lr + (r & 3)) * ld + b * 32 + lc] = nvs[r];
+    }
   }
 }
 
-__global__ void k_reduce_partials_f32(GemmArgs g, const float* P) {
-  const int64_t MN = g.M * g.N;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MN; e += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0;
-    for (int k = 0; k < g.splitk; ++k) s += (double)P[(int64_t)k * MN + e];
-    const int64_t m = e % g.M, n = e / g.M;
-    double o = g.c2 * s;
-    if (g.B0) o += g.c0 * (double)((const float*)g.B0)[m + n * g.ld01];
-    ((float*)g.C)[m + n * g.ldc] = (float)o;
+// C[m + n*ldc] = c2 * sum_k P[k][n*M + m] (+ c0 * B0[m + n*ld01]); grid (M / 1024, N),
+// four consecutive m per thread.  With est_red: per-workgroup sum of (est_S - C)^2.
+__global__ __launch_bounds__(256) void k_reduce_partials_f32(GemmArgs g, const float* P) {
+  const int64_t n = blockIdx.y, m = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  double e2 = 0.0;
+  if (m < g.M) {
+    const int64_t MN = g.M * g.N, o = n * g.M + m;
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+    for (int k = 0; k < g.splitk; ++k) {
+      const float4 v = *(const float4*)(P + (int64_t)k * MN + o);
+      s0 += v.x; s1 += v.y; s2 += v.z; s3 += v.w;
+    }
+    s0 *= g.c2; s1 *= g.c2; s2 *= g.c2; s3 *= g.c2;
+    if (g.B0) {
+      const float* b = (const float*)g.B0 + m + n * g.ld01;
+      s0 += g.c0 * (double)b[0]; s1 += g.c0 * (double)b[1]; s2 += g.c0 * (double)b[2]; s3 += g.c0 * (double)b[3];
+    }
+    const float4 r = {(float)s0, (float)s1, (float)s2, (float)s3};
+    *(float4*)((float*)g.C + m + n * g.ldc) = r;
+    if (g.est_red) {
+      const __bf16* sv = g.est_S + m + n * g.ldc;
+      const double d0 = (double)(float)sv[0] - r.x, d1 = (double)(float)sv[1] - r.y;
+      const double d2 = (double)(float)sv[2] - r.z, d3 = (double)(float)sv[3] - r.w;
+      e2 = (d0 * d0 + d1 * d1) + (d2 * d2 + d3 * d3);
+    }
+  }
+  if (g.est_red) {
+    __shared__ double sh[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) e2 += __shfl_xor(e2, o);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = e2;
+    __syncthreads();
+    if (threadIdx.x == 0) g.est_red[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
   }
 }
 
@@ -382,19 +456,21 @@ __global__ void k_pack_split2(const float* in, int64_t ld_in, int64_t rows, int6
   }
 }
 
-template <int BN, int WAVES_M, int WAVES_N, int NA, int NB, int PMAX, int AK, int BKD>
+template <int BN, int WAVES_M, int WAVES_N, int NA, int NB, int PMAX, int AK, int BKD, bool LDB>
 void launch_ts(const GemmArgs& g, int64_t blocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_gemm_bf16<128, BN, WAVES_M, WAVES_N, NA, NB, PMAX, AK, BKD, false, EPI_PARTIAL, RB_TS_PF, RB_TS_BK>), dim3(blocks),
-                     dim3(64 * WAVES_M * WAVES_N), 0, s, g);
+  // two LDS buffers when asked for and they fit in the 160 KiB of LDS
+  constexpr bool ldb = LDB && 2 * (NA * 128 + NB * BN) * (RB_TS_BK + 8) * 2 <= 160 * 1024;
+  hipLaunchKernelGGL((k_gemm_bf16<128, BN, WAVES_M, WAVES_N, NA, NB, PMAX, AK, BKD, ldb, EPI_PARTIAL, RB_TS_PF, RB_TS_BK>),
+                     dim3(blocks), dim3(64 * WAVES_M * WAVES_N), 0, s, g);
 }
 
-template <int NA, int NB, int PMAX, int AK, int BKD>
+template <int NA, int NB, int PMAX, int AK, int BKD, bool LDB>
 hipError_t launch_tall(const GemmArgs& g, int bn, int64_t blocks, hipStream_t s) {
   switch (bn) {
-    case 256: launch_ts<256, 2, 4, NA, NB, PMAX, AK, BKD>(g, blocks, s); break;
-    case 128: launch_ts<128, 2, 2, NA, NB, PMAX, AK, BKD>(g, blocks, s); break;
-    case 64: launch_ts<64, 2, 2, NA, NB, PMAX, AK, BKD>(g, blocks, s); break;
-    default: launch_ts<32, 4, 1, NA, NB, PMAX, AK, BKD>(g, blocks, s); break;
+    case 256: launch_ts<256, 2, 4, NA, NB, PMAX, AK, BKD, LDB>(g, blocks, s); break;
+    case 128: launch_ts<128, 2, 2, NA, NB, PMAX, AK, BKD, LDB>(g, blocks, s); break;
+    case 64: launch_ts<64, 2, 2, NA, NB, PMAX, AK, BKD, LDB>(g, blocks, s); break;
+    default: launch_ts<32, 4, 1, NA, NB, PMAX, AK, BKD, LDB>(g, blocks, s); break;
   }
   return hipGetLastError();
 }
@@ -434,10 +510,13 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
         mg.pmax != 1 || g.splitk != 1)
       return hipErrorInvalidValue;
     if (g.epi == EPI_SYMUPD && g.M != g.N) return hipErrorInvalidValue;
+#if RB_UPD_TILE == 256
     if (g.epi == EPI_SYMUPD && sq_tile(g.M) == 256)
       hipLaunchKernelGGL((k_gemm_bf16<256, 256, 2, 4, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, false, EPI_SYMUPD, 1, 32>),
                          dim3(gemm_bf16_blocks(mg)), dim3(512), 0, s, g);
-    else if (g.epi == EPI_SYMUPD)
+    else
+#endif
+    if (g.epi == EPI_SYMUPD)
       hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, false, EPI_SYMUPD, 1, 32>),
                          dim3(gemm_bf16_blocks(mg)), dim3(256), 0, s, g);
     else
@@ -452,14 +531,14 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
   const int bn = pick_bn(g.N);
   const int64_t blocks = gemm_bf16_blocks(mg);
   hipError_t e;
-#define RB_TALL(NA_, NB_, PM_, AK_, BK_)                                                               \
+#define RB_TALL(NA_, NB_, PM_, AK_, BK_, LDB_)                                                         \
   if (mg.na == NA_ && mg.nb == NB_ && mg.pmax == PM_ && mg.a_kind == AK_ && mg.b_kind == BK_)         \
-    e = launch_tall<NA_, NB_, PM_, AK_, BK_>(run, bn, blocks, s);                                     \
+    e = launch_tall<NA_, NB_, PM_, AK_, BK_, LDB_>(run, bn, blocks, s);                               \
   else
-  RB_TALL(3, 1, 2, OK_F32_KC, OK_BF16_KC)  // A S with an exact bf16 sketch, L S~
-  RB_TALL(2, 2, 1, OK_F32_KC, OK_F32_KC)   // X Y
-  RB_TALL(3, 2, 2, OK_F32_KC, OK_F32_KC)   // A S with S = L S~ (FP32)
-  RB_TALL(2, 3, 2, OK_F32_MC, OK_F32_KC)   // L^T Y
+  RB_TALL(3, 1, 2, OK_F32_KC, OK_BF16_KC, RB_TS_LDB_AS)  // A S with an exact bf16 sketch, L S~
+  RB_TALL(2, 2, 1, OK_F32_KC, OK_F32_KC, RB_TS_LDB)      // X Y
+  RB_TALL(3, 2, 2, OK_F32_KC, OK_F32_KC, RB_TS_LDB)      // A S with S = L S~ (FP32)
+  RB_TALL(2, 3, 2, OK_F32_MC, OK_F32_KC, RB_TS_LDB)      // L^T Y
   return hipErrorInvalidValue;
 #undef RB_TALL
   if (e != hipSuccess) return e;
@@ -467,10 +546,12 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
   return reduce_partials_f32(g, (const float*)partial_ws, s);
 }
 
+int64_t reduce_blocks_f32(const GemmArgs& g) { return (g.M + 1023) / 1024 * g.N; }
+
 hipError_t reduce_partials_f32(const GemmArgs& g, const float* P, hipStream_t s) {
-  const int64_t MN = g.M * g.N;
-  const int64_t blocks = std::min<int64_t>((MN + 255) / 256, 8192);
-  hipLaunchKernelGGL(k_reduce_partials_f32, dim3(blocks), dim3(256), 0, s, g, P);
+  if (g.M % 4 || g.ldc % 4 || (g.B0 && g.ld01 % 4)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_reduce_partials_f32, dim3((unsigned)((g.M + 1023) / 1024), (unsigned)g.N), dim3(256), 0, s, g,
+                     P);
   return hipGetLastError();
 }
 

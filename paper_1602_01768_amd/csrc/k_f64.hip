@@ -246,17 +246,17 @@ __global__ __launch_bounds__(256, (BM * BN >= 128 * 128) ? 1 : 2) void k_gemm_f6
   }
 }
 
+// C[m + n*ldc] = c2 * sum_k P[k][n*M + m] (+ c0 B0 + c1 B1); grid (M / 256, N).
 __global__ void k_reduce_partials_f64(GemmArgs g, const double* P) {
-  const int64_t MN = g.M * g.N;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < MN; e += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0;
-    for (int k = 0; k < g.splitk; ++k) s += P[(int64_t)k * MN + e];
-    const int64_t m = e % g.M, n = e / g.M;
-    double o = g.c2 * s;
-    if (g.B0) o += g.c0 * load_any(g.B0, g.b0_dt, m + n * g.ld01);
-    if (g.B1) o += g.c1 * load_any(g.B1, g.b1_dt, m + n * g.ld01);
-    store_any(g.C, g.c_dt, m + n * g.ldc, o);
-  }
+  const int64_t n = blockIdx.y, m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (m >= g.M) return;
+  const int64_t MN = g.M * g.N, o = n * g.M + m;
+  double s = 0;
+  for (int k = 0; k < g.splitk; ++k) s += P[(int64_t)k * MN + o];
+  double v = g.c2 * s;
+  if (g.B0) v += g.c0 * load_any(g.B0, g.b0_dt, m + n * g.ld01);
+  if (g.B1) v += g.c1 * load_any(g.B1, g.b1_dt, m + n * g.ld01);
+  store_any(g.C, g.c_dt, m + n * g.ldc, v);
 }
 
 // Tile shape of the column/row-store products: the largest tile that still gives
@@ -343,9 +343,7 @@ hipError_t gemm_f64(const GemmArgs& gin, void* partial_ws, hipStream_t s) {
 }
 
 hipError_t reduce_partials_f64(const GemmArgs& g, const double* P, hipStream_t s) {
-  const int64_t MN = g.M * g.N;
-  const int64_t blocks = std::min<int64_t>((MN + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_reduce_partials_f64, dim3(blocks), dim3(256), 0, s, g, P);
+  hipLaunchKernelGGL(k_reduce_partials_f64, dim3((unsigned)((g.M + 255) / 256), (unsigned)g.N), dim3(256), 0, s, g, P);
   return hipGetLastError();
 }
 
@@ -383,19 +381,23 @@ hipError_t gather_cols_gen(const void* L, int l_dt, int64_t ldl, const int32_t* 
 }
 
 // Per-block partial sums of (Sk - V)^2 over the n x q block.
+// Per-workgroup sum of (S - V)^2 over rows blockIdx.x*256 + t (< n) and 16 columns
+// from blockIdx.y*16 (< q); S dense (sk_dt) or coordinate (C: S[i][j] = [C_j == i]).
 __global__ void k_est_partial(const void* Sk, int sk_dt, const int32_t* C, const void* V, int v_dt, int64_t ld,
                               int64_t n, int q, double* red) {
   __shared__ double sh[4];
-  const int64_t total = n * q;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int j0 = blockIdx.y * 16;
   double s = 0;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t j = e / n, i = e % n;
-    const double sv = C ? (C[j] == i ? 1.0 : 0.0) : load_any(Sk, sk_dt, i + j * ld);
-    const double d = sv - load_any(V, v_dt, i + j * ld);
-    s += d * d;
+  if (i < n) {
+    for (int j = j0; j < j0 + 16 && j < q; ++j) {
+      const double sv = C ? (C[j] == i ? 1.0 : 0.0) : load_any(Sk, sk_dt, i + j * ld);
+      const double d = sv - load_any(V, v_dt, i + j * ld);
+      s += d * d;
+    }
   }
   const double t = block_sum_256(s, sh);
-  if (threadIdx.x == 0) red[blockIdx.x] = t;
+  if (threadIdx.x == 0) red[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
 }
 
 __global__ void k_reduce_sum(const double* in, int64_t count, double* out, double scale, int* status) {
@@ -416,9 +418,15 @@ hipError_t reduce_sum(const double* in, int64_t count, double* out, hipStream_t 
 
 hipError_t estimator(const void* Sk, int sk_dt, const int32_t* C, const void* V, int v_dt, int64_t ld, int64_t n,
                      int q, double scale, double* red, double* est, int* status, hipStream_t s) {
-  const int blocks = 512;
-  hipLaunchKernelGGL(k_est_partial, dim3(blocks), dim3(256), 0, s, Sk, sk_dt, C, V, v_dt, ld, n, q, red);
-  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, red, (int64_t)blocks, est, scale, status);
+  const dim3 grid((unsigned)((n + 255) / 256), (unsigned)((q + 15) / 16));
+  hipLaunchKernelGGL(k_est_partial, grid, dim3(256), 0, s, Sk, sk_dt, C, V, v_dt, ld, n, q, red);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, red, (int64_t)grid.x * grid.y, est, scale, status);
+  return hipGetLastError();
+}
+
+hipError_t reduce_sum_scaled(const double* in, int64_t count, double* out, double scale, int* status,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, in, count, out, scale, status);
   return hipGetLastError();
 }
 

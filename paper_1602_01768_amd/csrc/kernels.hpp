@@ -46,6 +46,11 @@ struct GemmArgs {
   // optional event recorded on the stream between the product kernel and its split-K
   // reduction (timing of the product kernel alone)
   hipEvent_t mark = nullptr;
+  // bf16 split-K reduction only: when est_red is set, the reduction also writes, per
+  // workgroup, the sum of (est_S - C)^2 over its part of C (est_S: bf16, column-major
+  // with leading dimension ldc) to est_red[workgroup]; reduce_blocks_f32 gives the count
+  const __bf16* est_S = nullptr;
+  double* est_red = nullptr;
 };
 
 // Tile order for an n x n product of T x T tiles: super-tiles of S x S tiles in row-major
@@ -75,6 +80,7 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s);
 // Tile edge of the bf16 square products (EPI_SYMUPD / EPI_ADDROW) for order M.
 int bf16_square_tile(int64_t M, int epi);
 hipError_t reduce_partials_f32(const GemmArgs& g, const float* partial, hipStream_t s);
+int64_t reduce_blocks_f32(const GemmArgs& g);
 int64_t gemm_bf16_blocks(const MixedGemm& mg);
 
 // Pack an FP32 column-major panel (rows x cols, ld_in) into bf16 hi/lo planes,
@@ -110,6 +116,9 @@ hipError_t estimator(const void* Sk, int sk_dt, const int32_t* C, const void* V,
                      int* status, hipStream_t s);
 // Deterministic sum of `count` doubles into *out (single workgroup).
 hipError_t reduce_sum(const double* in, int64_t count, double* out, hipStream_t s);
+// *out = scale * sum of `count` doubles; *status = 4 when the sum is not finite.
+hipError_t reduce_sum_scaled(const double* in, int64_t count, double* out, double scale, int* status,
+                             hipStream_t s);
 // rows C_a of W' (col-major, ld): W'[C_a + b*ld] -= 0.5*(a==b) + 0.5*GH[a*ldgh + b]
 hipError_t coord_wprime_fix(void* W, int w_dt, int64_t ld, const int32_t* C, int q,
                             const double* GH, int64_t ldgh, hipStream_t s);
