@@ -23,6 +23,12 @@
 
 using namespace rb;
 
+#ifndef RB_GATE
+#define RB_GATE 0  // where the fixed method releases the side lane's next products (see main_fixed)
+#endif
+#ifndef RB_BF16_Q
+#define RB_BF16_Q 1  // q-sized products of the mixed fixed Gaussian path in split bf16
+#endif
 #ifndef RB_SUPER_TILES
 #define RB_SUPER_TILES 4  // super-tile edge of the n x n update order (4 x 4 tiles share panels in L2)
 #endif
@@ -44,6 +50,7 @@ struct Slot {  // sketch-dependent quantities of one iteration
   void* Y = nullptr;         // fixed: A S
   double* G = nullptr;       // fixed: S^T A S;  adaptive: S~^T S~
   double* Ginv = nullptr;    // fixed: G^-1
+  float* Ginv32 = nullptr;   // fixed, q-sized products in bf16: G^-1 rounded to FP32
   double* Z = nullptr;       // inverse Cholesky factor of G (fixed) or of S~^T S~ (adaptive)
   void* U = nullptr;         // fixed: U = S G^-1 (mixed: FP32 n x q; FP64: panels [U | W' | U])
   __bf16* planes = nullptr;  // mixed fixed: bf16 hi/lo planes of [U | W' | U], row-major
@@ -81,6 +88,12 @@ struct rbfgs_ctx {
   __bf16* planes = nullptr; // adaptive mixed: bf16 planes of S and Q^T
   void* R = nullptr;        // fixed coordinate: R = G^-1 W'^T (qp x np)
   double *G = nullptr, *H = nullptr, *Ginv = nullptr, *Z = nullptr, *GH = nullptr, *Mq = nullptr;
+  float* H32 = nullptr;  // H in FP32 when H and U H run in bf16
+  // mixed fixed Gaussian with qp a multiple of 128: G = S^T Y and U = S G^-1 as split-bf16
+  // products (FP32 accumulation, FP64 sums of the split-K partials); H = Y^T V and U H too
+  // when q <= n/8 (for larger q/n on ill-conditioned A their FP32 accumulation measurably
+  // raised the error against the oracle, so they stay FP64 there)
+  bool bf16q = false, bf16h = false;
   double* est = nullptr;
   int* status = nullptr;
   int2* tiles = nullptr;    // tile order of the n x n update (super-tiles, see make_tile_order)
@@ -220,15 +233,31 @@ void f64_gemm(rbfgs_ctx* ctx, const Lane& L, GemmArgs g) {
 }
 
 // bf16-MFMA product on one lane (tall-skinny products get a split-K).
-void bf_gemm(rbfgs_ctx* ctx, const Lane& L, MixedGemm mg) {
+void bf_gemm(rbfgs_ctx* ctx, const Lane& L, MixedGemm mg, int max_split = 8, int64_t min_chunk = 256) {
   GemmArgs& g = mg.g;
   if (g.epi == EPI_COLSTORE) {
-    const int64_t tiles = (g.M / 128) * (g.N / bf_bn(g.N));
-    g.splitk = pick_split(tiles, g.K, 32);
+    const int64_t tiles = (g.M / 128) * (g.N / (g.bn ? g.bn : bf_bn(g.N)));
+    g.splitk = pick_split(tiles, g.K, 32, max_split, min_chunk);
     const size_t need = (size_t)g.splitk * g.M * g.N * sizeof(float);
     if (need > L.partial_bytes) g.splitk = 1;
   }
   HIPCHK(gemm_bf16(mg, L.partial, L.s));
+}
+
+// q x q Gram C = P1^T P2 of two n x q column-major panels as a split-bf16 product:
+// P1 in p1_pieces (1 for the exact bf16 sketch), P2 FP32 in 3 pieces, all piece pairs of
+// weight >= 2^-16; FP32 accumulation over 64-wide k chunks, chunks summed in double.
+void gram_bf16(rbfgs_ctx* ctx, const Lane& L, const void* P1, bool p1_bf16, const float* P2, void* out, int out_dt) {
+  MixedGemm mg;
+  GemmArgs& g = mg.g;
+  g.M = ctx->qp; g.N = ctx->qp; g.K = ctx->np;
+  g.A = P1; g.lda = ctx->np;
+  g.B = P2; g.ldb = ctx->np;
+  g.epi = EPI_COLSTORE; g.C = out; g.ldc = ctx->qp; g.c_dt = out_dt; g.c2 = 1.0;
+  g.bn = 128;
+  mg.a_kind = p1_bf16 ? OK_BF16_KC : OK_F32_KC; mg.b_kind = OK_F32_KC;
+  mg.na = p1_bf16 ? 1 : 3; mg.nb = 3; mg.pmax = 2;
+  bf_gemm(ctx, L, mg, 64, 256);
 }
 
 // out = M * P for an n x n matrix M (A, X or L) and an n x q panel P, per precision.
@@ -244,7 +273,7 @@ void nn_times_panel(rbfgs_ctx* ctx, const Lane& L, const void* M, bool transpose
     g.M = ctx->np; g.N = ctx->qp; g.K = ctx->np;
     g.A = M; g.lda = ctx->np;
     g.B = P; g.ldb = ctx->np;
-    g.epi = EPI_COLSTORE; g.C = out; g.ldc = ctx->np; g.c2 = 1.0; g.mark = mark;
+    g.epi = EPI_COLSTORE; g.C = out; g.ldc = ctx->np; g.c_dt = DT_F32; g.c2 = 1.0; g.mark = mark;
     if (est_S) {
       g.est_S = est_S;
       g.est_red = L.red;
@@ -327,7 +356,8 @@ void side_products(rbfgs_ctx* ctx, int64_t k, Slot& S) {
     }
     HIPCHK(hipEventRecord(S.y_ready, L.s));
     Phase ph(ctx, L, "gram_G");
-    gram(ctx, L, S.Sk, sk_dt(ctx), S.Y, mdt, S.G);
+    if (ctx->bf16q) gram_bf16(ctx, L, S.Sk, true, (const float*)S.Y, S.G, DT_F64);
+    else gram(ctx, L, S.Sk, sk_dt(ctx), S.Y, mdt, S.G);
   }
   HIPCHK(hipEventRecord(S.g_ready, L.s));
 }
@@ -350,7 +380,19 @@ void side_inverse(rbfgs_ctx* ctx, Slot& S) {
   Phase ph(ctx, L, "panel_U");
   if (ctx->mixed) {
     float* U = (float*)S.U;
-    panel_times_small(ctx, L, S.Sk, DT_BF16, S.Ginv, U, DT_F32, 1.0);
+    if (ctx->bf16q) {  // U = S G^-1: S exact bf16 (m-contiguous), G^-1 rounded to FP32 in 3 pieces
+      HIPCHK(copy_convert(S.Ginv, DT_F64, qp, S.Ginv32, DT_F32, qp, qp, qp, L.s));
+      MixedGemm mg;
+      GemmArgs& g = mg.g;
+      g.M = np; g.N = qp; g.K = qp;
+      g.A = S.Sk; g.lda = np;
+      g.B = S.Ginv32; g.ldb = qp;  // Bop(k, j) = G^-1[j][k] = G^-1[k][j]
+      g.epi = EPI_COLSTORE; g.C = U; g.ldc = np; g.c_dt = DT_F32; g.c2 = 1.0; g.bn = 128;
+      mg.a_kind = OK_BF16_MC; mg.b_kind = OK_F32_KC; mg.na = 1; mg.nb = 3; mg.pmax = 2;
+      bf_gemm(ctx, L, mg, 1);  // k = q is short: no split
+    } else {
+      panel_times_small(ctx, L, S.Sk, DT_BF16, S.Ginv, U, DT_F32, 1.0);
+    }
     const int64_t ldp = 3 * qp, plane = np * ldp;
     HIPCHK(pack_split2(U, np, np, qp, S.planes, S.planes + plane, ldp, 0, L.s));
     HIPCHK(pack_split2(U, np, np, qp, S.planes, S.planes + plane, ldp, 2 * qp, L.s));
@@ -365,11 +407,16 @@ void side_inverse(rbfgs_ctx* ctx, Slot& S) {
 // X-dependent part of one fixed-sketch RBFGS iteration, eq. (qunac) as the
 // symmetric rank-2q update X+ = X - (U W'^T + W' U^T), U = S G^-1,
 // W' = V - S/2 - U H/2, V = X Y, H = Y^T V (Y = A S and G = S^T Y from the slot).
-// after_xy runs right after V = X Y is enqueued (the caller schedules the side lanes
-// from there).
+// `ahead` is called once, at the point where the side lanes' work for later iterations
+// is to be released (RB_GATE: 0 after V = X Y, 1 before the update of X).
 template <class F>
-void main_fixed(rbfgs_ctx* ctx, Slot& S, F&& after_xy) {
+void main_fixed(rbfgs_ctx* ctx, Slot& S, F&& ahead) {
   const Lane& L = ctx->main;
+  bool fired = false;
+  auto release = [&]() {
+    if (!fired) ahead();
+    fired = true;
+  };
   const int64_t np = ctx->np, qp = ctx->qp;
   const int mdt = ctx->mdt;
   // mixed Gaussian: the estimator's sum of squares comes out of the product's reduction
@@ -381,8 +428,12 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, F&& after_xy) {
     nn_times_panel(ctx, L, ctx->X, false, S.Y, mdt, ctx->V, 2, 2, 1, ph.mark(),
                    fused_est ? (const __bf16*)S.Sk : nullptr);
   }
-  after_xy();
-  { Phase ph(ctx, L, "gram_H"); gram(ctx, L, S.Y, mdt, ctx->V, mdt, ctx->H); }
+  if (RB_GATE == 0) release();
+  {
+    Phase ph(ctx, L, "gram_H");
+    if (ctx->bf16h) gram_bf16(ctx, L, S.Y, false, (const float*)ctx->V, ctx->H32, DT_F32);
+    else gram(ctx, L, S.Y, mdt, ctx->V, mdt, ctx->H);
+  }
   const double scale = ctx->coord ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
   {
     Phase ph(ctx, L, "estimator");
@@ -396,6 +447,7 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, F&& after_xy) {
   if (ctx->coord) {
     // U = E_C G^-1 is not formed: W' = V - E_C/2 - E_C (G^-1 H)/2 and R = G^-1 W'^T;
     // the update touches only rows and columns C.
+    release();
     Phase ph(ctx, L, "coord_update");
     small_small(ctx, L, S.Ginv, false, ctx->H, ctx->GH);
     HIPCHK(hipMemcpyAsync(ctx->W, ctx->V, (size_t)np * qp * dt_size(mdt), hipMemcpyDeviceToDevice, L.s));
@@ -414,9 +466,22 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, F&& after_xy) {
     const int64_t ldp = 3 * qp, plane = np * ldp;
     {
       Phase ph(ctx, L, "panels");
-      panel_times_small(ctx, L, S.U, DT_F32, ctx->H, W, DT_F32, -0.5, ctx->V, DT_F32, 1.0, S.Sk, DT_BF16, -0.5);
+      if (ctx->bf16h) {  // W' = V - S/2 - (U H)/2, U in 3 pieces (m-contiguous), H in 3 pieces
+        MixedGemm mg;
+        GemmArgs& g = mg.g;
+        g.M = np; g.N = qp; g.K = qp;
+        g.A = S.U; g.lda = np;
+        g.B = ctx->H32; g.ldb = qp;  // Bop(k, j) = H[k][j] (column-major H)
+        g.epi = EPI_COLSTORE; g.C = W; g.ldc = np; g.c_dt = DT_F32; g.c2 = -0.5;
+        g.B0 = ctx->V; g.c0 = 1.0; g.B1 = S.Sk; g.b1_dt = DT_BF16; g.c1 = -0.5; g.ld01 = np; g.bn = 128;
+        mg.a_kind = OK_F32_MC; mg.b_kind = OK_F32_KC; mg.na = 3; mg.nb = 3; mg.pmax = 2;
+        bf_gemm(ctx, L, mg, 1);  // k = q is short: no split
+      } else {
+        panel_times_small(ctx, L, S.U, DT_F32, ctx->H, W, DT_F32, -0.5, ctx->V, DT_F32, 1.0, S.Sk, DT_BF16, -0.5);
+      }
       HIPCHK(pack_split2(W, np, np, qp, S.planes, S.planes + plane, ldp, qp, L.s));
     }
+    release();
     Phase ph(ctx, L, "update", true);
     MixedGemm mg;
     GemmArgs& g = mg.g;
@@ -434,6 +499,7 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, F&& after_xy) {
       panel_times_small(ctx, L, PQ, DT_F64, ctx->H, PQ + np * qp, DT_F64, -0.5, ctx->V, DT_F64, 1.0, S.Sk, DT_F64,
                         -0.5);
     }
+    release();
     Phase ph(ctx, L, "update", true);
     GemmArgs g;
     g.M = np; g.N = np; g.K = 2 * qp;
@@ -626,6 +692,7 @@ void make_slot(rbfgs_ctx* ctx, Slot& S) {
   if (!ctx->ada) {
     S.Y = dalloc(ctx, np * qp * es);
     S.Ginv = (double*)dalloc(ctx, qq);
+    if (ctx->bf16q) S.Ginv32 = (float*)dalloc(ctx, (size_t)qp * qp * sizeof(float));
     if (!ctx->coord) {
       S.U = dalloc(ctx, (ctx->mixed ? 1 : 3) * np * qp * es);
       if (ctx->mixed) S.planes = (__bf16*)dalloc(ctx, (size_t)2 * 3 * np * qp * sizeof(__bf16));
@@ -686,6 +753,8 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
   ctx->ada = p.variant == RBFGS_ADAPTIVE;
   ctx->coord = p.sketch == RBFGS_SKETCH_COORD;
   ctx->mdt = ctx->mixed ? DT_F32 : DT_F64;
+  ctx->bf16q = RB_BF16_Q && ctx->mixed && !ctx->ada && !ctx->coord && ctx->qp % 128 == 0;
+  ctx->bf16h = ctx->bf16q && 8 * ctx->qp <= ctx->np;
   ctx->main.s = (hipStream_t)hip_stream;
   try {
     HIPCHK(hipGetDevice(&ctx->device));
@@ -716,6 +785,7 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
     const size_t qq = (size_t)qp * qp * sizeof(double);
     ctx->G = (double*)dalloc(ctx, qq);
     ctx->H = (double*)dalloc(ctx, qq);
+    if (ctx->bf16h) ctx->H32 = (float*)dalloc(ctx, (size_t)qp * qp * sizeof(float));
     ctx->Ginv = (double*)dalloc(ctx, qq);
     ctx->Z = (double*)dalloc(ctx, qq);
     ctx->GH = (double*)dalloc(ctx, qq);

@@ -25,6 +25,15 @@ namespace {
 #ifndef RB_TS_LDB_AS
 #define RB_TS_LDB_AS 0  // ... and in the product with an exact bf16 sketch (A S, L S~); 0 measured faster
 #endif
+#ifndef RB_TS_WAVES256
+#define RB_TS_WAVES256 2, 4  // wave grid (along m, along n) of the 128 x 256 tall-skinny tile
+#endif
+#ifndef RB_TS_WAVES256_AS
+#define RB_TS_WAVES256_AS 4, 1  // ... for the product with an exact bf16 sketch (measured fastest)
+#endif
+#ifndef RB_UPD_LDB
+#define RB_UPD_LDB false  // two LDS buffers in the square updates (measured no faster)
+#endif
 #ifndef RB_UPD_TILE
 #define RB_UPD_TILE 128  // square-update tile (128 measured faster than 256)
 #endif
@@ -57,9 +66,12 @@ struct TileLoader {
   // F32_KC: float4 per thread; F32_MC: 4 x 4 micro-blocks per thread, 4 float4 each
   static constexpr int MBLK = ROWS * BK / 16;
   static constexpr int F4 = (KIND == OK_BF16_KC) ? 1
-                            : (KIND == OK_F32_MC) ? 4 * ((MBLK + NT - 1) / NT) : ROWS * BK / 4 / NT;
+                            : (KIND == OK_F32_MC || KIND == OK_BF16_MC) ? 4 * ((MBLK + NT - 1) / NT)
+                                                                         : ROWS * BK / 4 / NT;
+  static_assert(KIND != OK_BF16_MC || NP == 1, "an m-contiguous bf16 operand is exact: one piece");
   static constexpr int V8 = (KIND == OK_BF16_KC) ? (ROWS * (BK / 8) + NT - 1) / NT : 1;  // 16-byte chunks per plane
-  float4 f[F4 > 0 ? F4 : 1];
+  float4 f[(F4 > 0 && KIND != OK_BF16_MC) ? F4 : 1];
+  bf16x4 hm[KIND == OK_BF16_MC ? F4 : 1];
   bf16x8 h[NP][V8];
 
   RB_DEV void load(const void* base, int64_t ld, int64_t plane, int64_t r0, int64_t k0, int tid) {
@@ -81,6 +93,17 @@ struct TileLoader {
           const int m4 = (b % (ROWS / 4)) * 4, kk = (b / (ROWS / 4)) * 4;
 #pragma unroll
           for (int j = 0; j < 4; ++j) f[4 * i + j] = *(const float4*)(A + (k0 + kk + j) * ld + r0 + m4);
+        }
+      }
+    } else if constexpr (KIND == OK_BF16_MC) {
+      const __bf16* A = (const __bf16*)base;
+#pragma unroll
+      for (int i = 0; i < F4 / 4; ++i) {
+        const int b = tid + NT * i;
+        if (MBLK % NT == 0 || b < MBLK) {
+          const int m4 = (b % (ROWS / 4)) * 4, kk = (b / (ROWS / 4)) * 4;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) hm[4 * i + j] = *(const bf16x4*)(A + (k0 + kk + j) * ld + r0 + m4);
         }
       }
     } else {
@@ -139,6 +162,21 @@ struct TileLoader {
               bf16x4 v = {p0[p], p1[p], p2[p], p3[p]};
               *(bf16x4*)(lds + (p * ROWS + m4 + mm) * PITCH + kk) = v;
             }
+          }
+        }
+      }
+    } else if constexpr (KIND == OK_BF16_MC) {
+      // transpose the 4 x 4 bf16 micro-block: LDS row m gets k = kk..kk+3
+#pragma unroll
+      for (int i = 0; i < F4 / 4; ++i) {
+        const int b = tid + NT * i;
+        if (MBLK % NT == 0 || b < MBLK) {
+          const int m4 = (b % (ROWS / 4)) * 4, kk = (b / (ROWS / 4)) * 4;
+          const bf16x4* hb = &hm[4 * i];
+#pragma unroll
+          for (int mm = 0; mm < 4; ++mm) {
+            bf16x4 v = {hb[0][mm], hb[1][mm], hb[2][mm], hb[3][mm]};
+            *(bf16x4*)(lds + (m4 + mm) * PITCH + kk) = v;
           }
         }
       }
@@ -414,6 +452,22 @@ __global__ __launch_bounds__(256) void k_reduce_partials_f32(GemmArgs g, const f
       const float* b = (const float*)g.B0 + m + n * g.ld01;
       s0 += g.c0 * (double)b[0]; s1 += g.c0 * (double)b[1]; s2 += g.c0 * (double)b[2]; s3 += g.c0 * (double)b[3];
     }
+    if (g.B1) {
+      double b0, b1, b2, b3;
+      if (g.b1_dt == DT_BF16) {
+        const __bf16* b = (const __bf16*)g.B1 + m + n * g.ld01;
+        b0 = (float)b[0]; b1 = (float)b[1]; b2 = (float)b[2]; b3 = (float)b[3];
+      } else {
+        const float* b = (const float*)g.B1 + m + n * g.ld01;
+        b0 = b[0]; b1 = b[1]; b2 = b[2]; b3 = b[3];
+      }
+      s0 += g.c1 * b0; s1 += g.c1 * b1; s2 += g.c1 * b2; s3 += g.c1 * b3;
+    }
+    if (g.c_dt == DT_F64) {
+      double* c = (double*)g.C + m + n * g.ldc;
+      c[0] = s0; c[1] = s1; c[2] = s2; c[3] = s3;
+      return;  // (no estimator on this path)
+    }
     const float4 r = {(float)s0, (float)s1, (float)s2, (float)s3};
     *(float4*)((float*)g.C + m + n * g.ldc) = r;
     if (g.est_red) {
@@ -464,10 +518,10 @@ void launch_ts(const GemmArgs& g, int64_t blocks, hipStream_t s) {
                      dim3(blocks), dim3(64 * WAVES_M * WAVES_N), 0, s, g);
 }
 
-template <int NA, int NB, int PMAX, int AK, int BKD, bool LDB>
+template <int NA, int NB, int PMAX, int AK, int BKD, bool LDB, int WM256, int WN256>
 hipError_t launch_tall(const GemmArgs& g, int bn, int64_t blocks, hipStream_t s) {
   switch (bn) {
-    case 256: launch_ts<256, 2, 4, NA, NB, PMAX, AK, BKD, LDB>(g, blocks, s); break;
+    case 256: launch_ts<256, WM256, WN256, NA, NB, PMAX, AK, BKD, LDB>(g, blocks, s); break;
     case 128: launch_ts<128, 2, 2, NA, NB, PMAX, AK, BKD, LDB>(g, blocks, s); break;
     case 64: launch_ts<64, 2, 2, NA, NB, PMAX, AK, BKD, LDB>(g, blocks, s); break;
     default: launch_ts<32, 4, 1, NA, NB, PMAX, AK, BKD, LDB>(g, blocks, s); break;
@@ -475,7 +529,12 @@ hipError_t launch_tall(const GemmArgs& g, int bn, int64_t blocks, hipStream_t s)
   return hipGetLastError();
 }
 
-int pick_bn(int64_t N) {
+int pick_bn_auto(int64_t N);
+int pick_bn(const GemmArgs& g) {
+  if (g.bn == 256 || g.bn == 128 || g.bn == 64 || g.bn == 32) return (g.N % g.bn == 0) ? g.bn : pick_bn_auto(g.N);
+  return pick_bn_auto(g.N);
+}
+int pick_bn_auto(int64_t N) {
   if (N % 256 == 0) return 256;
   if (N % 128 == 0) return 128;
   if (N % 64 == 0) return 64;
@@ -496,7 +555,7 @@ int64_t gemm_bf16_blocks(const MixedGemm& mg) {
     const int64_t NTT = g.tiles ? g.ntiles : (g.epi == EPI_SYMUPD ? T * (T + 1) / 2 : T * T);
     return (NTT + 7) / 8 * 8;
   }
-  return (g.M / 128) * (g.N / pick_bn(g.N)) * g.splitk;
+  return (g.M / 128) * (g.N / pick_bn(g)) * g.splitk;
 }
 
 hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
@@ -517,10 +576,10 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
     else
 #endif
     if (g.epi == EPI_SYMUPD)
-      hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, false, EPI_SYMUPD, 1, 32>),
+      hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, RB_UPD_LDB, EPI_SYMUPD, 1, 32>),
                          dim3(gemm_bf16_blocks(mg)), dim3(256), 0, s, g);
     else
-      hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, false, EPI_ADDROW, 1, 32>),
+      hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, RB_UPD_LDB, EPI_ADDROW, 1, 32>),
                          dim3(gemm_bf16_blocks(mg)), dim3(256), 0, s, g);
     return hipGetLastError();
   }
@@ -528,17 +587,22 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
   GemmArgs run = g;
   run.epi = EPI_PARTIAL;
   run.C = partial_ws;
-  const int bn = pick_bn(g.N);
+  const int bn = pick_bn(g);
   const int64_t blocks = gemm_bf16_blocks(mg);
   hipError_t e;
-#define RB_TALL(NA_, NB_, PM_, AK_, BK_, LDB_)                                                         \
+#define RB_TALL(NA_, NB_, PM_, AK_, BK_, LDB_, WAVES256_)                                              \
   if (mg.na == NA_ && mg.nb == NB_ && mg.pmax == PM_ && mg.a_kind == AK_ && mg.b_kind == BK_)         \
-    e = launch_tall<NA_, NB_, PM_, AK_, BK_, LDB_>(run, bn, blocks, s);                               \
+    e = launch_tall<NA_, NB_, PM_, AK_, BK_, LDB_, WAVES256_>(run, bn, blocks, s);                    \
   else
-  RB_TALL(3, 1, 2, OK_F32_KC, OK_BF16_KC, RB_TS_LDB_AS)  // A S with an exact bf16 sketch, L S~
-  RB_TALL(2, 2, 1, OK_F32_KC, OK_F32_KC, RB_TS_LDB)      // X Y
-  RB_TALL(3, 2, 2, OK_F32_KC, OK_F32_KC, RB_TS_LDB)      // A S with S = L S~ (FP32)
-  RB_TALL(2, 3, 2, OK_F32_MC, OK_F32_KC, RB_TS_LDB)      // L^T Y
+  RB_TALL(3, 1, 2, OK_F32_KC, OK_BF16_KC, RB_TS_LDB_AS, RB_TS_WAVES256_AS)  // A S, exact bf16 sketch; L S~
+  RB_TALL(2, 2, 1, OK_F32_KC, OK_F32_KC, RB_TS_LDB, RB_TS_WAVES256)        // X Y
+  RB_TALL(3, 2, 2, OK_F32_KC, OK_F32_KC, RB_TS_LDB, RB_TS_WAVES256)        // A S with S = L S~ (FP32)
+  RB_TALL(2, 3, 2, OK_F32_MC, OK_F32_KC, RB_TS_LDB, RB_TS_WAVES256)        // L^T Y
+  // q-sized products: one LDS buffer, so that they share CUs with the n x n products
+  RB_TALL(1, 3, 2, OK_BF16_KC, OK_F32_KC, false, RB_TS_WAVES256)  // G = S^T Y
+  RB_TALL(1, 3, 2, OK_BF16_MC, OK_F32_KC, false, RB_TS_WAVES256)  // U = S G^-1
+  RB_TALL(3, 3, 2, OK_F32_KC, OK_F32_KC, false, RB_TS_WAVES256)   // H = Y^T V
+  RB_TALL(3, 3, 2, OK_F32_MC, OK_F32_KC, false, RB_TS_WAVES256)   // U H
   return hipErrorInvalidValue;
 #undef RB_TALL
   if (e != hipSuccess) return e;
@@ -549,7 +613,8 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
 int64_t reduce_blocks_f32(const GemmArgs& g) { return (g.M + 1023) / 1024 * g.N; }
 
 hipError_t reduce_partials_f32(const GemmArgs& g, const float* P, hipStream_t s) {
-  if (g.M % 4 || g.ldc % 4 || (g.B0 && g.ld01 % 4)) return hipErrorInvalidValue;
+  if (g.M % 4 || g.ldc % 4 || ((g.B0 || g.B1) && g.ld01 % 4) || (g.c_dt == DT_F64 && g.est_red))
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_reduce_partials_f32, dim3((unsigned)((g.M + 1023) / 1024), (unsigned)g.N), dim3(256), 0, s, g,
                      P);
   return hipGetLastError();

@@ -51,6 +51,8 @@ struct GemmArgs {
   // with leading dimension ldc) to est_red[workgroup]; reduce_blocks_f32 gives the count
   const __bf16* est_S = nullptr;
   double* est_red = nullptr;
+  // bf16 tall-skinny products: tile width along N (0: the widest of 256/128/64/32 dividing N)
+  int bn = 0;
 };
 
 // Tile order for an n x n product of T x T tiles: super-tiles of S x S tiles in row-major
@@ -68,9 +70,12 @@ int64_t gemm_f64_blocks(const GemmArgs& g);
 enum OpKind : int {
   OK_F32_KC = 0,    // FP32, contiguous along k, split into bf16 pieces on load
   OK_F32_MC = 1,    // FP32, contiguous along m (or n), split on load
-  OK_BF16_KC = 2    // pre-split bf16 planes, contiguous along k (plane p at base + p*plane)
+  OK_BF16_KC = 2,   // pre-split bf16 planes, contiguous along k (plane p at base + p*plane)
+  OK_BF16_MC = 3    // one bf16 plane, contiguous along m (or n)
 };
 struct MixedGemm {
+  // the products write FP32 unless g.c_dt is set to DT_F64 explicitly (q x q results)
+  MixedGemm() { g.c_dt = DT_F32; }
   GemmArgs g;
   int a_kind = OK_F32_KC, b_kind = OK_F32_KC;
   int na = 2, nb = 2;   // pieces per operand
@@ -79,6 +84,8 @@ struct MixedGemm {
 hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s);
 // Tile edge of the bf16 square products (EPI_SYMUPD / EPI_ADDROW) for order M.
 int bf16_square_tile(int64_t M, int epi);
+// Sum the FP32 split-K partials of a bf16 product (COLSTORE epilogue of g): C = c2 * sum
+// + c0 * B0 (FP32) + c1 * B1 (FP32 or bf16, b1_dt), column-major; C is FP32 or FP64 (c_dt).
 hipError_t reduce_partials_f32(const GemmArgs& g, const float* partial, hipStream_t s);
 int64_t reduce_blocks_f32(const GemmArgs& g);
 int64_t gemm_bf16_blocks(const MixedGemm& mg);
