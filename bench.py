@@ -135,6 +135,70 @@ def timed_steps(Solver, A_dev, q, seed, sketch, variant, precision, warmup, step
     return s, (t1 - t0), rep
 
 
+def serving(args, torch, rbfgs):
+    """C5: a trace of independent inversions to ||I - AX||_F / sqrt(n) <= tol through the
+    server (AdaRBFGS, Gaussian sketch, mixed precision; A_j = M^T M / n + 1e-3 I with n_j
+    log-uniform in [64, 8192], q_j = min(256, n_j / 8)).
+
+    1. closed loop: every job submitted at t = 0; saturation throughput = jobs / makespan;
+    2. open loop: Poisson arrivals at 0.7 x the saturation rate; sojourn = done - arrival,
+       service = done - start on a worker;
+    3. baseline: the same arrivals served one at a time in FP64.
+    The matrices are formed and resident in HBM before any timing.
+    """
+    import numpy as np
+    from workloads import serving_trace, gram_ridge
+    unit = serving_trace(args.serve_jobs, args.seed, rate=1.0)
+    mats = {j["id"]: torch.from_numpy(gram_ridge(j["n"], j["seed"], device="cuda")).cuda() for j in unit}
+    torch.cuda.synchronize()
+    budget = int(args.serve_budget_gb * 2 ** 30)
+
+    def run(arrivals, precision, workers):
+        res = []
+        with rbfgs.Server(budget, workers) as srv:
+            start = time.perf_counter()
+            for j, ta in zip(unit, arrivals):
+                while True:
+                    wait = ta - (time.perf_counter() - start)
+                    if wait <= 0:
+                        break
+                    res += srv.poll(256, wait_ms=max(1, int(min(wait, 0.05) * 1000)))
+                srv.submit(mats[j["id"]], j["q"], j["seed"], args.serve_tol, 20000, tag=j["id"],
+                           variant="adaptive", precision=precision, sketch="gauss")
+            while len(res) < len(unit):
+                res += srv.poll(256, wait_ms=50)
+            makespan = time.perf_counter() - start
+            peak = srv.stats()["peak_running"]
+        return res, makespan, peak
+
+    def summary(res, makespan, peak):
+        soj = np.array([r["t_done"] - r["t_submit"] for r in res])
+        svc = np.array([r["t_done"] - r["t_admit"] for r in res])
+        its = sum(r["iters"] for r in res)
+        conv = sum(1 for r in res if r["status"] == rbfgs.OK)
+        worst = max((r["resid"] for r in res if r["status"] == rbfgs.OK), default=float("nan"))
+        return {"jobs": len(res), "converged": conv, "max_resid": float(worst), "makespan_s": round(makespan, 3),
+                "jobs_per_s": round(len(res) / makespan, 2), "iters_per_s": round(its / makespan, 1),
+                "sojourn_p50_ms": round(1e3 * float(np.percentile(soj, 50)), 2),
+                "sojourn_p99_ms": round(1e3 * float(np.percentile(soj, 99)), 2),
+                "service_p50_ms": round(1e3 * float(np.percentile(svc, 50)), 2),
+                "service_p99_ms": round(1e3 * float(np.percentile(svc, 99)), 2), "peak_running": peak}
+
+    closed = run([0.0] * len(unit), "mixed", args.serve_workers)
+    sat = len(unit) / closed[1]
+    rate = 0.7 * sat
+    arrivals = [j["t_arrive"] / rate for j in unit]
+    open_mixed = run(arrivals, "mixed", args.serve_workers)
+    base = run(arrivals, "fp64", 1) if args.serve_baseline else None
+    out = {"workload": f"{len(unit)} AdaRBFGS jobs (gauss), n log-uniform in [64, 8192], q = min(256, n/8), "
+                       f"tol {args.serve_tol}, budget {args.serve_budget_gb} GiB, {args.serve_workers} workers",
+           "saturation_jobs_per_s": round(sat, 2), "arrival_rate_jobs_per_s": round(rate, 2),
+           "closed_loop": summary(*closed), "mixed": summary(*open_mixed),
+           "fp64_one_at_a_time": summary(*base) if base else None}
+    del mats
+    return out
+
+
 def cpu_baseline(A32, q, seed, sketch, variant, steps):
     """The FP64 oracle on the host: `steps` iterations from X_0 = I (or L_0 = I)."""
     import numpy as np
@@ -170,6 +234,11 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=8)
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--serve-jobs", type=int, default=64, help="serving trace length (0: skip serving)")
+    ap.add_argument("--serve-workers", type=int, default=8)
+    ap.add_argument("--serve-budget-gb", type=float, default=200.0)
+    ap.add_argument("--serve-tol", type=float, default=1e-3)
+    ap.add_argument("--serve-baseline", type=int, default=1, help="also serve the trace one at a time in FP64")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -225,6 +294,9 @@ def main():
     s64.close()
     del A64_dev
 
+    # ---- serving trace (p50 / p99 solve latency)
+    serve = serving(args, torch, rbfgs) if args.serve_jobs > 0 else None
+
     # ---- CPU oracle baseline (bounded sample) and parity of the same steps
     cpu = None
     parity = None
@@ -266,6 +338,7 @@ def main():
         "roofline": roof,
         "products_ms_timed_region": live_ms,
         "phases_ms": {k: round(v["avg_ms"], 4) for k, v in phases.items()},
+        "serving": serve,
         "cpu_baseline": cpu,
         "parity": parity,
         "input_gen_s": round(t_gen, 1),

@@ -183,6 +183,69 @@ rbfgs_status rbfgs_sketch_gauss(uint64_t seed, int64_t k, int64_t n, int32_t q,
 rbfgs_status rbfgs_sketch_coord(uint64_t seed, int64_t k, int64_t n, int32_t q,
                                 int32_t* idx_dev, void* hip_stream);
 
+/* Device bytes a context for `params` holds (plus, for the adaptive method, the
+ * n x n FP64 scratch of its exact residual), computed without allocating.  Used by
+ * the server's admission control.  E_INVALID_ARG for invalid sizes. */
+rbfgs_status rbfgs_footprint(const rbfgs_params* params, int64_t* bytes_out);
+
+/* ---- serving: many inversions (Sec. 10 stopping rule) sharing one GPU ----
+ * A server owns `workers` host threads; each runs one job at a time -- a context
+ * of its own on its own non-blocking stream, driven by rbfgs_invert -- so the
+ * kernels of concurrent jobs overlap on the device.  Admission is first come,
+ * first served: the job at the head of the queue starts when a worker is free and
+ * its footprint (rbfgs_footprint, plus the staging copy of a host A) fits in
+ * `budget_bytes` beside the running jobs.  Times are seconds on a monotonic
+ * clock started at rbfgs_server_create.  The server is thread-safe; calls from
+ * several host threads may interleave. */
+typedef struct rbfgs_server rbfgs_server;
+
+typedef struct {
+  uint64_t tag;      /* the caller's job tag */
+  int32_t status;    /* rbfgs_status of the job (OK: converged to tol) */
+  int64_t iters;     /* iterations run */
+  double resid;      /* last exact ||I - AX||_F / sqrt(n) (NaN if never computed) */
+  double t_submit;   /* submission */
+  double t_admit;    /* start on a worker */
+  double t_done;     /* completion */
+} rbfgs_job_result;
+
+typedef struct {
+  double now;            /* server clock */
+  int64_t queued;        /* submitted, not started */
+  int32_t running;       /* on a worker now */
+  int64_t outstanding;   /* queued + running */
+  int64_t active_bytes;  /* footprints of the running jobs */
+  int64_t peak_bytes;    /* largest active_bytes so far (<= budget) */
+  int32_t peak_running;  /* most jobs running at once so far */
+} rbfgs_server_info;
+
+/* workers in [1, 64], budget_bytes > 0.  E_INVALID_ARG, E_DEVICE. */
+rbfgs_status rbfgs_server_create(int64_t budget_bytes, int32_t workers, rbfgs_server** out);
+
+/* Queue one inversion: A as in rbfgs_create (it must stay valid and unchanged until
+ * the job's result has been polled), iterate with rbfgs_invert(tol, max_iters);
+ * when x_out != NULL copy X_k there at the end (as rbfgs_get_x; also when not
+ * converged).  Returns at once: E_INVALID_ARG for invalid arguments (as
+ * rbfgs_create, plus tol <= 0, max_iters < 0), E_OOM when the job alone exceeds the
+ * budget; every other outcome arrives in the job's result. */
+rbfgs_status rbfgs_server_submit(rbfgs_server* server, const rbfgs_params* params, const void* A,
+                                 int32_t a_dtype, int64_t lda, int32_t a_on_device, double tol,
+                                 int64_t max_iters, void* x_out, int32_t x_dtype, int64_t ldx,
+                                 int32_t x_on_device, uint64_t tag);
+
+/* Move up to max_results finished jobs (in completion order) into results; *n_out
+ * receives the count.  If none is ready and jobs are outstanding, wait up to
+ * wait_ms milliseconds for one. */
+rbfgs_status rbfgs_server_poll(rbfgs_server* server, rbfgs_job_result* results, int32_t max_results,
+                               int32_t* n_out, int32_t wait_ms);
+
+/* Snapshot of the queue and the budget use. */
+rbfgs_status rbfgs_server_stats(rbfgs_server* server, rbfgs_server_info* info);
+
+/* Finish every submitted job, then stop the workers and free the server;
+ * results not yet polled are discarded. */
+void rbfgs_server_destroy(rbfgs_server* server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -99,6 +99,8 @@ struct rbfgs_ctx {
   int2* tiles = nullptr;    // tile order of the n x n update (super-tiles, see make_tile_order)
   int64_t ntiles = 0;
   std::vector<void*> allocs;
+  int64_t bytes = 0;  // device bytes the context holds (allocate() accounts them)
+  bool dry = false;   // allocate() only sums sizes (rbfgs_footprint)
   // per-phase timing with HIP events on the lanes' streams (rbfgs_profile)
   struct ProfRec {
     std::string name;
@@ -127,11 +129,16 @@ struct Fail {
 
 size_t dt_size(int dt) { return dt == DT_F32 ? 4 : (dt == DT_BF16 ? 2 : 8); }
 
+// Zeroed device allocation owned by the context.  In a dry run (footprint) only the
+// size is accounted and a placeholder is returned.
 void* dalloc(rbfgs_ctx* ctx, size_t bytes) {
+  const size_t b = bytes ? bytes : 16;
+  ctx->bytes += (int64_t)((b + 255) / 256 * 256);
+  if (ctx->dry) return (void*)(uintptr_t)256;
   void* p = nullptr;
-  HIPCHK(hipMalloc(&p, bytes ? bytes : 16));
+  HIPCHK(hipMalloc(&p, b));
   ctx->allocs.push_back(p);
-  HIPCHK(hipMemsetAsync(p, 0, bytes ? bytes : 16, ctx->main.s));
+  HIPCHK(hipMemsetAsync(p, 0, b, ctx->main.s));
   return p;
 }
 
@@ -698,6 +705,7 @@ void make_slot(rbfgs_ctx* ctx, Slot& S) {
       if (ctx->mixed) S.planes = (__bf16*)dalloc(ctx, (size_t)2 * 3 * np * qp * sizeof(__bf16));
     }
   }
+  if (ctx->dry) return;
   HIPCHK(hipEventCreateWithFlags(&S.y_ready, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&S.g_ready, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&S.ready, hipEventDisableTiming));
@@ -727,6 +735,68 @@ void release(rbfgs_ctx* ctx) {
   delete ctx;
 }
 
+// Parameters and derived sizes of a context.
+void set_params(rbfgs_ctx* ctx, const rbfgs_params& p) {
+  ctx->p = p;
+  if (ctx->p.check_every == 0) ctx->p.check_every = 16;
+  ctx->n = p.n;
+  ctx->q = p.q;
+  ctx->np = (p.n + 255) / 256 * 256;
+  ctx->qp = ((int64_t)p.q + 31) / 32 * 32;
+  ctx->mixed = p.precision == RBFGS_MIXED;
+  ctx->ada = p.variant == RBFGS_ADAPTIVE;
+  ctx->coord = p.sketch == RBFGS_SKETCH_COORD;
+  ctx->mdt = ctx->mixed ? DT_F32 : DT_F64;
+  ctx->bf16q = RB_BF16_Q && ctx->mixed && !ctx->ada && !ctx->coord && ctx->qp % 128 == 0;
+  ctx->bf16h = ctx->bf16q && 8 * ctx->qp <= ctx->np;
+}
+
+// Every device buffer of the context (accounted only, in a dry run).
+void allocate(rbfgs_ctx* ctx) {
+  const int64_t np = ctx->np, qp = ctx->qp;
+  const size_t es = dt_size(ctx->mdt);
+  const size_t partial = std::max<size_t>((size_t)8 * np * qp * 8, (size_t)128 * qp * qp * sizeof(double));
+  const size_t red = (size_t)std::max<int64_t>(4096, (np / 32) * (np / 32) + 16);
+  make_lane(ctx, ctx->main, partial, red);
+  make_lane(ctx, ctx->side, partial, 4096);
+  make_lane(ctx, ctx->inv, partial, 4096);
+  for (Slot& S : ctx->slot) make_slot(ctx, S);
+  ctx->A = dalloc(ctx, np * np * es);
+  ctx->X = dalloc(ctx, np * np * es);
+  ctx->pos = (int32_t*)dalloc(ctx, np * sizeof(int32_t));
+  if (!ctx->dry) HIPCHK(hipMemsetAsync(ctx->pos, 0xff, np * sizeof(int32_t), ctx->main.s));  // -1
+  ctx->V = dalloc(ctx, np * qp * es);
+  ctx->W = dalloc(ctx, np * qp * es);
+  if (ctx->ada) {
+    ctx->Sa = dalloc(ctx, np * qp * es);
+    ctx->Y = dalloc(ctx, np * qp * es);
+    if (ctx->mixed) ctx->planes = (__bf16*)dalloc(ctx, (size_t)4 * np * qp * sizeof(__bf16));
+  }
+  if (!ctx->ada && ctx->coord) ctx->R = dalloc(ctx, qp * np * es);
+  const size_t qq = (size_t)qp * qp * sizeof(double);
+  ctx->G = (double*)dalloc(ctx, qq);
+  ctx->H = (double*)dalloc(ctx, qq);
+  if (ctx->bf16h) ctx->H32 = (float*)dalloc(ctx, (size_t)qp * qp * sizeof(float));
+  ctx->Ginv = (double*)dalloc(ctx, qq);
+  ctx->Z = (double*)dalloc(ctx, qq);
+  ctx->GH = (double*)dalloc(ctx, qq);
+  ctx->Mq = (double*)dalloc(ctx, qq);
+  ctx->est = (double*)dalloc(ctx, 4 * sizeof(double));
+  ctx->status = (int*)dalloc(ctx, sizeof(int));
+  {  // tile order of the n x n update: lower triangle (fixed) or full square (adaptive)
+    const int epi = ctx->ada ? EPI_ADDROW : EPI_SYMUPD;
+    const int T = (int)(np / (ctx->mixed ? bf16_square_tile(np, epi) : 128));
+    std::vector<int2> order((size_t)make_tile_order(T, RB_SUPER_TILES, !ctx->ada, nullptr));
+    ctx->ntiles = make_tile_order(T, RB_SUPER_TILES, !ctx->ada, order.data());
+    ctx->tiles = (int2*)dalloc(ctx, order.size() * sizeof(int2));
+    if (!ctx->dry) {
+      HIPCHK(hipMemcpyAsync(ctx->tiles, order.data(), order.size() * sizeof(int2), hipMemcpyHostToDevice,
+                            ctx->main.s));
+      HIPCHK(hipStreamSynchronize(ctx->main.s));
+    }
+  }
+}
+
 }  // namespace
 
 extern "C" {
@@ -743,18 +813,7 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
       (p.precision != RBFGS_FP64 && p.precision != RBFGS_MIXED) || p.check_every < 0 || p.n > (1ll << 20))
     return RBFGS_E_INVALID_ARG;
   rbfgs_ctx* ctx = new rbfgs_ctx();
-  ctx->p = p;
-  if (ctx->p.check_every == 0) ctx->p.check_every = 16;
-  ctx->n = p.n;
-  ctx->q = p.q;
-  ctx->np = (p.n + 255) / 256 * 256;
-  ctx->qp = ((int64_t)p.q + 31) / 32 * 32;
-  ctx->mixed = p.precision == RBFGS_MIXED;
-  ctx->ada = p.variant == RBFGS_ADAPTIVE;
-  ctx->coord = p.sketch == RBFGS_SKETCH_COORD;
-  ctx->mdt = ctx->mixed ? DT_F32 : DT_F64;
-  ctx->bf16q = RB_BF16_Q && ctx->mixed && !ctx->ada && !ctx->coord && ctx->qp % 128 == 0;
-  ctx->bf16h = ctx->bf16q && 8 * ctx->qp <= ctx->np;
+  set_params(ctx, p);
   ctx->main.s = (hipStream_t)hip_stream;
   try {
     HIPCHK(hipGetDevice(&ctx->device));
@@ -762,46 +821,8 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
     HIPCHK(hipStreamCreateWithFlags(&ctx->inv.s, hipStreamNonBlocking));   // default priority
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_begin, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_xy, hipEventDisableTiming));
-    const int64_t np = ctx->np, qp = ctx->qp;
-    const size_t es = dt_size(ctx->mdt);
-    const size_t partial = std::max<size_t>((size_t)8 * np * qp * 8, (size_t)128 * qp * qp * sizeof(double));
-    const size_t red = (size_t)std::max<int64_t>(4096, (np / 32) * (np / 32) + 16);
-    make_lane(ctx, ctx->main, partial, red);
-    make_lane(ctx, ctx->side, partial, 4096);
-    make_lane(ctx, ctx->inv, partial, 4096);
-    for (Slot& S : ctx->slot) make_slot(ctx, S);
-    ctx->A = dalloc(ctx, np * np * es);
-    ctx->X = dalloc(ctx, np * np * es);
-    ctx->pos = (int32_t*)dalloc(ctx, np * sizeof(int32_t));
-    HIPCHK(hipMemsetAsync(ctx->pos, 0xff, np * sizeof(int32_t), ctx->main.s));  // -1
-    ctx->V = dalloc(ctx, np * qp * es);
-    ctx->W = dalloc(ctx, np * qp * es);
-    if (ctx->ada) {
-      ctx->Sa = dalloc(ctx, np * qp * es);
-      ctx->Y = dalloc(ctx, np * qp * es);
-      if (ctx->mixed) ctx->planes = (__bf16*)dalloc(ctx, (size_t)4 * np * qp * sizeof(__bf16));
-    }
-    if (!ctx->ada && ctx->coord) ctx->R = dalloc(ctx, qp * np * es);
-    const size_t qq = (size_t)qp * qp * sizeof(double);
-    ctx->G = (double*)dalloc(ctx, qq);
-    ctx->H = (double*)dalloc(ctx, qq);
-    if (ctx->bf16h) ctx->H32 = (float*)dalloc(ctx, (size_t)qp * qp * sizeof(float));
-    ctx->Ginv = (double*)dalloc(ctx, qq);
-    ctx->Z = (double*)dalloc(ctx, qq);
-    ctx->GH = (double*)dalloc(ctx, qq);
-    ctx->Mq = (double*)dalloc(ctx, qq);
-    ctx->est = (double*)dalloc(ctx, 4 * sizeof(double));
-    ctx->status = (int*)dalloc(ctx, sizeof(int));
-    {  // tile order of the n x n update: lower triangle (fixed) or full square (adaptive)
-      const int epi = ctx->ada ? EPI_ADDROW : EPI_SYMUPD;
-      const int T = (int)(np / (ctx->mixed ? bf16_square_tile(np, epi) : 128));
-      std::vector<int2> order((size_t)make_tile_order(T, RB_SUPER_TILES, !ctx->ada, nullptr));
-      ctx->ntiles = make_tile_order(T, RB_SUPER_TILES, !ctx->ada, order.data());
-      ctx->tiles = (int2*)dalloc(ctx, order.size() * sizeof(int2));
-      HIPCHK(hipMemcpyAsync(ctx->tiles, order.data(), order.size() * sizeof(int2), hipMemcpyHostToDevice,
-                            ctx->main.s));
-      HIPCHK(hipStreamSynchronize(ctx->main.s));
-    }
+    allocate(ctx);
+    const int64_t np = ctx->np;
     // copy A (n x n, lda) into the padded np x np buffer, converting its type
     const int sdt = a_dtype == RBFGS_F32 ? DT_F32 : DT_F64;
     const size_t ses = dt_size(sdt);
@@ -876,7 +897,8 @@ rbfgs_status rbfgs_estimate(rbfgs_ctx* ctx, double* est_out) {
   try {
     rbfgs_status st = read_status(ctx);
     if (st != RBFGS_OK) return st;
-    HIPCHK(hipMemcpy(est_out, ctx->est, sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(est_out, ctx->est, sizeof(double), hipMemcpyDeviceToHost, ctx->main.s));
+    HIPCHK(hipStreamSynchronize(ctx->main.s));
   } catch (const Fail& f) {
     return f.st;
   }
@@ -897,7 +919,8 @@ rbfgs_status rbfgs_invert(rbfgs_ctx* ctx, double tol, int64_t max_iters, int64_t
       rbfgs_status st = read_status(ctx);
       if (st != RBFGS_OK) { result = st; break; }
       double est = 0;
-      HIPCHK(hipMemcpy(&est, ctx->est, sizeof(double), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpyAsync(&est, ctx->est, sizeof(double), hipMemcpyDeviceToHost, ctx->main.s));
+      HIPCHK(hipStreamSynchronize(ctx->main.s));
       if (est <= thresh) {
         const double r = exact_residual(ctx);
         resid = r / sqrt((double)ctx->n);
@@ -999,6 +1022,24 @@ rbfgs_status rbfgs_set_state(rbfgs_ctx* ctx, const void* M, int32_t m_dtype, int
 rbfgs_status rbfgs_get_iter(const rbfgs_ctx* ctx, int64_t* k_out) {
   if (!ctx || !k_out) return RBFGS_E_INVALID_ARG;
   *k_out = ctx->k;
+  return RBFGS_OK;
+}
+
+rbfgs_status rbfgs_footprint(const rbfgs_params* params, int64_t* bytes_out) {
+  if (!params || !bytes_out) return RBFGS_E_INVALID_ARG;
+  const rbfgs_params& p = *params;
+  if (p.n < 1 || p.q < 1 || p.q > p.n || p.q > 1024 || p.n > (1ll << 20)) return RBFGS_E_INVALID_ARG;
+  rbfgs_ctx ctx;
+  ctx.dry = true;
+  set_params(&ctx, p);
+  try {
+    allocate(&ctx);
+  } catch (const Fail& f) {
+    return f.st;
+  }
+  int64_t b = ctx.bytes;
+  if (ctx.ada) b += ctx.np * ctx.np * (int64_t)sizeof(double);  // exact residual of L L^T
+  *bytes_out = b;
   return RBFGS_OK;
 }
 

@@ -15,6 +15,8 @@
 // Larger orders recurse on 2 x 2 blocks with FP64 GEMMs.
 #include <math.h>
 
+#include <mutex>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -341,13 +343,13 @@ __global__ void k_zero_pad_sq(double* M, int64_t ld, int q, int qp) {
 
 hipError_t launch_leaf(const double* G, int64_t ldg, int nb, int qv, double* Z, int64_t ldz, double* Ginv,
                        int64_t ldi, int* status, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_chol_leaf, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(leaf_lds_doubles(LEAF_MAX) * sizeof(double)));
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  static std::once_flag once;  // contexts may be driven from several host threads
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(once, [] {
+    attr_err = hipFuncSetAttribute((const void*)k_chol_leaf, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)(leaf_lds_doubles(LEAF_MAX) * sizeof(double)));
+  });
+  if (attr_err != hipSuccess) return attr_err;
   if (nb % CB || nb > LEAF_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_chol_leaf, dim3(1), dim3(LEAF_NT), leaf_lds_doubles(nb) * sizeof(double), s, G, ldg, nb,
                      qv < 0 ? 0 : (qv > nb ? nb : qv), Z, ldz, Ginv, ldi, status);

@@ -2,6 +2,7 @@
 // Gaussian sketches (Box-Muller on Philox4x64-10 words, rounded to bf16 values)
 // and coordinate sketches (Floyd's sampling with Lemire's bounded draws).
 #include <algorithm>
+#include <mutex>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -109,11 +110,12 @@ __global__ __launch_bounds__(256) void k_sketch_coord(uint64_t seed, uint64_t k,
 
 hipError_t sketch_coord(uint64_t seed, int64_t k, int64_t n, int32_t q, int32_t* idx, hipStream_t s) {
   const size_t lds = sizeof(uint32_t) * (size_t)((n + 31) / 32);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipFuncSetAttribute((const void*)k_sketch_coord, hipFuncAttributeMaxDynamicSharedMemorySize, 131072);
-    attr_set = true;
-  }
+  static std::once_flag once;  // contexts may be driven from several host threads
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(once, [] {
+    attr_err = hipFuncSetAttribute((const void*)k_sketch_coord, hipFuncAttributeMaxDynamicSharedMemorySize, 131072);
+  });
+  if (attr_err != hipSuccess) return attr_err;
   hipLaunchKernelGGL(k_sketch_coord, dim3(1), dim3(256), lds, s, seed, (uint64_t)k, n, (int)q, idx);
   return hipGetLastError();
 }

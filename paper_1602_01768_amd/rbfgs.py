@@ -38,6 +38,18 @@ class rbfgs_params(ctypes.Structure):
                 ("precision", ctypes.c_int32), ("check_every", ctypes.c_int32)]
 
 
+class rbfgs_job_result(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("iters", ctypes.c_int64),
+                ("resid", ctypes.c_double), ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class rbfgs_server_info(ctypes.Structure):
+    _fields_ = [("now", ctypes.c_double), ("queued", ctypes.c_int64), ("running", ctypes.c_int32),
+                ("outstanding", ctypes.c_int64), ("active_bytes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64),
+                ("peak_running", ctypes.c_int32)]
+
+
 EXPORTS = {
     "rbfgs_create": (ctypes.c_int, [ctypes.POINTER(rbfgs_params), ctypes.c_void_p, ctypes.c_int32,
                                     ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
@@ -63,6 +75,16 @@ EXPORTS = {
                                           ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "rbfgs_sketch_coord": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "rbfgs_footprint": (ctypes.c_int, [ctypes.POINTER(rbfgs_params), ctypes.POINTER(ctypes.c_int64)]),
+    "rbfgs_server_create": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
+    "rbfgs_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rbfgs_params), ctypes.c_void_p,
+                                           ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_double,
+                                           ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                                           ctypes.c_int32, ctypes.c_uint64]),
+    "rbfgs_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rbfgs_job_result), ctypes.c_int32,
+                                         ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
+    "rbfgs_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rbfgs_server_info)]),
+    "rbfgs_server_destroy": (None, [ctypes.c_void_p]),
 }
 
 _lib = None
@@ -223,6 +245,89 @@ def rbfgs_sketch_coord(seed, k, n, q, stream=None):
     _check(load_library().rbfgs_sketch_coord(int(seed), int(k), int(n), int(q), ctypes.c_void_p(out.data_ptr()),
                                              _stream_handle(stream)))
     return out
+
+
+def _params(n, q, seed, sketch, variant, precision, check_every):
+    return rbfgs_params(n=int(n), q=int(q), seed=int(seed), sketch=SKETCH[sketch], variant=VARIANT[variant],
+                        precision=PRECISION[precision], check_every=int(check_every))
+
+
+def rbfgs_footprint(n, q, sketch="gauss", variant="fixed", precision="fp64"):
+    """Device bytes of a context for these parameters (no allocation, no GPU needed)."""
+    p = _params(n, q, 1, sketch, variant, precision, 16)
+    out = ctypes.c_int64()
+    _check(load_library().rbfgs_footprint(ctypes.byref(p), ctypes.byref(out)))
+    return out.value
+
+
+def rbfgs_server_create(budget_bytes, workers):
+    out = ctypes.c_void_p()
+    _check(load_library().rbfgs_server_create(int(budget_bytes), int(workers), ctypes.byref(out)))
+    return out.value
+
+
+def rbfgs_server_submit(server, A, q, seed, tol, max_iters, tag, sketch="gauss", variant="adaptive",
+                        precision="mixed", check_every=16, x_out=None):
+    """Queue one inversion; A (and x_out) must stay alive until the job's result is polled."""
+    ptr, code, ld, on_dev, _keep = _matrix_arg(A)
+    p = _params(A.shape[0], q, seed, sketch, variant, precision, check_every)
+    xp, xcode, xld, xdev = None, F64, 0, 0
+    if x_out is not None:
+        xp, xcode, xld, xdev, _xkeep = _matrix_arg(x_out)
+    _check(load_library().rbfgs_server_submit(server, ctypes.byref(p), ptr, code, ld, on_dev, float(tol),
+                                              int(max_iters), xp, xcode, xld, xdev, int(tag)))
+
+
+def rbfgs_server_poll(server, max_results=256, wait_ms=0):
+    buf = (rbfgs_job_result * max(1, int(max_results)))()
+    n = ctypes.c_int32()
+    _check(load_library().rbfgs_server_poll(server, buf, int(max_results), ctypes.byref(n), int(wait_ms)))
+    return [dict(tag=r.tag, status=r.status, iters=r.iters, resid=r.resid, t_submit=r.t_submit,
+                 t_admit=r.t_admit, t_done=r.t_done) for r in buf[:n.value]]
+
+
+def rbfgs_server_stats(server):
+    info = rbfgs_server_info()
+    _check(load_library().rbfgs_server_stats(server, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in info._fields_}
+
+
+def rbfgs_server_destroy(server):
+    if server:
+        load_library().rbfgs_server_destroy(server)
+
+
+class Server:
+    """Many inversions sharing the GPU under a device-memory budget (see rbfgs.h)."""
+
+    def __init__(self, budget_bytes, workers=8):
+        self.handle = rbfgs_server_create(budget_bytes, workers)
+        self._keep = {}
+
+    def submit(self, A, q, seed, tol, max_iters, tag, x_out=None, **kw):
+        self._keep[int(tag)] = (A, x_out)
+        rbfgs_server_submit(self.handle, A, q, seed, tol, max_iters, tag, x_out=x_out, **kw)
+
+    def poll(self, max_results=256, wait_ms=0):
+        res = rbfgs_server_poll(self.handle, max_results, wait_ms)
+        for r in res:
+            self._keep.pop(int(r["tag"]), None)
+        return res
+
+    def stats(self):
+        return rbfgs_server_stats(self.handle)
+
+    def close(self):
+        if self.handle:
+            rbfgs_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 class Solver:

@@ -1,0 +1,94 @@
+"""Serving extension: several inversions sharing the GPU through rbfgs_server_*.
+
+Every job's outcome must equal a direct rbfgs_invert of the same problem (the
+path is deterministic, so iterations and residual agree exactly), admission must
+keep the running footprints within the budget, and a job that cannot fit is
+rejected at submission.
+"""
+import numpy as np
+import pytest
+
+from workloads import gram_ridge, spectral_spd
+
+pytestmark = pytest.mark.gpu
+
+JOBS = [  # (n, q, variant, precision, sketch)
+    (64, 8, "adaptive", "mixed", "gauss"),
+    (100, 12, "adaptive", "mixed", "coord"),
+    (300, 20, "fixed", "fp64", "gauss"),
+    (520, 40, "adaptive", "fp64", "gauss"),
+    (257, 32, "adaptive", "mixed", "gauss"),
+    (700, 64, "fixed", "mixed", "coord"),
+]
+TOL = 1e-2
+
+
+def _matrix(j, n):
+    return gram_ridge(n, 10 + j) if j % 2 == 0 else spectral_spd(n, 20 + j, 1.0, 30.0)[0].astype(np.float32)
+
+
+def _direct(lib, A, q, seed, variant, precision, sketch, max_iters):
+    with lib.Solver(A, q, seed, sketch=sketch, variant=variant, precision=precision) as s:
+        ok, iters, resid = s.invert(TOL, max_iters)
+    return ok, iters, resid
+
+
+def _drain(srv, count, timeout_polls=2000):
+    out = []
+    for _ in range(timeout_polls):
+        out += srv.poll(64, wait_ms=50)
+        if len(out) >= count:
+            break
+    return out
+
+
+def test_server_results_match_direct_solves(lib):
+    import torch
+    mats = [_matrix(j, n) for j, (n, *_rest) in enumerate(JOBS)]
+    with lib.Server(budget_bytes=8 << 30, workers=4) as srv:
+        for j, ((n, q, variant, precision, sketch), A) in enumerate(zip(JOBS, mats)):
+            srv.submit(torch.from_numpy(A).cuda(), q, 100 + j, TOL, 3000, tag=j, variant=variant,
+                       precision=precision, sketch=sketch)
+        res = {r["tag"]: r for r in _drain(srv, len(JOBS))}
+        info = srv.stats()
+    assert sorted(res) == list(range(len(JOBS)))
+    assert info["peak_running"] >= 2  # jobs did overlap
+    for j, ((n, q, variant, precision, sketch), A) in enumerate(zip(JOBS, mats)):
+        ok, iters, resid = _direct(lib, A, q, 100 + j, variant, precision, sketch, 3000)
+        r = res[j]
+        assert r["status"] == (lib.OK if ok else lib.E_NOT_CONVERGED), (j, r)
+        assert r["iters"] == iters, (j, r, iters)
+        assert r["resid"] == resid or (np.isnan(r["resid"]) and np.isnan(resid)), (j, r, resid)
+        assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+
+
+def test_server_budget_limits_concurrency_and_returns_x(lib):
+    import torch
+    n, q = 256, 16
+    fp = lib.rbfgs_footprint(n, q, variant="adaptive", precision="mixed")
+    A = torch.from_numpy(gram_ridge(n, 3)).cuda()
+    X = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for _ in range(3)]
+    with lib.Server(budget_bytes=fp + fp // 2, workers=4) as srv:  # room for one job at a time
+        for t in range(3):
+            srv.submit(A, q, 7 + t, TOL, 2000, tag=t, x_out=X[t])
+        res = _drain(srv, 3)
+        info = srv.stats()
+    assert len(res) == 3 and all(r["status"] == lib.OK for r in res)
+    assert info["peak_running"] == 1 and info["peak_bytes"] <= fp + fp // 2
+    for t in range(3):
+        with lib.Solver(A, q, 7 + t, variant="adaptive", precision="mixed") as s:
+            s.invert(TOL, 2000)
+            ref = s.x()
+        assert torch.equal(X[t], ref)
+
+
+def test_server_rejects_job_beyond_budget(lib):
+    import torch
+    n, q = 512, 32
+    fp = lib.rbfgs_footprint(n, q, variant="adaptive", precision="mixed")
+    A = torch.from_numpy(gram_ridge(n, 3)).cuda()
+    with lib.Server(budget_bytes=fp // 2, workers=2) as srv:
+        with pytest.raises(lib.RbfgsError) as e:
+            srv.submit(A, q, 1, TOL, 100, tag=0)
+        assert e.value.status == lib.E_OOM
+        assert srv.stats()["outstanding"] == 0

@@ -22,10 +22,22 @@ def spectral_spd(n, seed, lam_min=1.0, lam_max=1e3):
     return 0.5 * (A + A.T), 0.5 * (Ainv + Ainv.T)
 
 
-def gram_ridge(n, seed, mu=1e-3, dtype=np.float32):
-    """A = M^T M / n + mu I with M a seeded N(0,1) n x n matrix, rounded to `dtype`."""
+def gram_ridge(n, seed, mu=1e-3, dtype=np.float32, device=None):
+    """A = M^T M / n + mu I with M a seeded N(0,1) n x n matrix, rounded to `dtype`.
+
+    M is drawn on the host; the FP64 Gram product runs on `device` (a torch device
+    string) when given, with the same result up to the rounding order."""
     rng = _rng(seed, 2)
     M = rng.standard_normal((n, n), dtype=np.float64)
+    if device is not None:
+        import torch
+        Mt = torch.from_numpy(M).to(device)
+        A = (Mt.T @ Mt) / n
+        A.diagonal().add_(mu)
+        A = 0.5 * (A + A.T)
+        out = A.to(torch.float32 if dtype == np.float32 else torch.float64).cpu().numpy()
+        del Mt, A
+        return out
     A = (M.T @ M) / n
     A[np.diag_indices(n)] += mu
     A = 0.5 * (A + A.T)
