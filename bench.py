@@ -199,6 +199,26 @@ def serving(args, torch, rbfgs):
     return out
 
 
+def time_to_tolerance(A_dev, q, seed, tol, max_iters, torch, rbfgs):
+    """AdaRBFGS (Gaussian sketch) from L_0 = I to ||I - AX||_F / sqrt(n) <= tol, mixed and
+    FP64 on the same A; wall time includes every estimator read and exact residual check."""
+    out = {}
+    for prec in ("mixed", "fp64"):
+        A = A_dev if prec == "mixed" else A_dev.to(torch.float64)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with rbfgs.Solver(A, q, seed, sketch="gauss", variant="adaptive", precision=prec) as s:
+            ok, iters, resid = s.invert(tol, max_iters)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[prec] = {"converged": bool(ok), "iters": iters, "resid": resid, "seconds": round(t, 3)}
+        del A
+    if out["mixed"]["converged"] and out["fp64"]["converged"]:
+        out["fp64_over_mixed"] = round(out["fp64"]["seconds"] / out["mixed"]["seconds"], 2)
+    out["tol"] = tol
+    return out
+
+
 def cpu_baseline(A32, q, seed, sketch, variant, steps):
     """The FP64 oracle on the host: `steps` iterations from X_0 = I (or L_0 = I)."""
     import numpy as np
@@ -234,6 +254,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=8)
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--ttt-iters", type=int, default=4000,
+                    help="iteration cap of the AdaRBFGS time-to-tolerance runs (0: skip them)")
     ap.add_argument("--serve-jobs", type=int, default=64, help="serving trace length (0: skip serving)")
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
@@ -294,6 +316,9 @@ def main():
     s64.close()
     del A64_dev
 
+    # ---- time to tolerance, AdaRBFGS mixed vs FP64
+    ttt = time_to_tolerance(A_dev, q, args.seed, 1e-3, args.ttt_iters, torch, rbfgs) if args.ttt_iters > 0 else None
+
     # ---- serving trace (p50 / p99 solve latency)
     serve = serving(args, torch, rbfgs) if args.serve_jobs > 0 else None
 
@@ -338,6 +363,7 @@ def main():
         "roofline": roof,
         "products_ms_timed_region": live_ms,
         "phases_ms": {k: round(v["avg_ms"], 4) for k, v in phases.items()},
+        "time_to_tolerance_ada": ttt,
         "serving": serve,
         "cpu_baseline": cpu,
         "parity": parity,
