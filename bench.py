@@ -68,8 +68,8 @@ def phase_roofline(name, n, q, variant, sketch, precision="mixed"):
 
 # kernel symbol (as rocprofv3 names it) of each product phase in mixed mode, fixed/Gaussian
 PHASE_KERNEL = {
-    "XY": "k_gemm_bf16<128, 256, 2, 4, 2, 2, 1, 0, 0, false, 0, 1, 32>",
-    "AS": "k_gemm_bf16<128, 256, 2, 4, 3, 1, 2, 0, 2, false, 0, 1, 32>",
+    "XY": "k_gemm_bf16<128, 256, 2, 4, 2, 2, 1, 0, 0, true, 0, 1, 32>",
+    "AS": "k_gemm_bf16<128, 256, 4, 1, 3, 1, 2, 0, 2, false, 0, 1, 32>",
     "update": "k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, 2, 2, false, 2, 1, 32>",
 }
 KERNEL_SOURCES = ["paper_1602_01768_amd/csrc/k_bf16.hip", "paper_1602_01768_amd/csrc/common.hpp",
