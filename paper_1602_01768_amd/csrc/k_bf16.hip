@@ -34,6 +34,12 @@ namespace {
 #ifndef RB_UPD_LDB
 #define RB_UPD_LDB false  // two LDS buffers in the square updates (measured no faster)
 #endif
+#ifndef RB_UPD_KERNEL
+#define RB_UPD_KERNEL 1  // square update: 0 the general mixed GEMM, 1 the LDS-DMA kernel (k_symupd.hip; 2-5% faster)
+#endif
+#ifndef RB_UPD_MIRROR
+#define RB_UPD_MIRROR 1  // mirrored half of the square update: 0 LDS transpose, 1 16-byte stores from registers (10% faster)
+#endif
 #ifndef RB_UPD_TILE
 #define RB_UPD_TILE 128  // square-update tile (128 measured faster than 256)
 #endif
@@ -371,6 +377,43 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArg
   }
 
   // ---------------------------------------------------------------- epilogue
+  if constexpr (EPI == EPI_SYMUPD && RB_UPD_MIRROR == 1) {
+    // X += c2 * acc on the lower tile, one 32 x 32 block at a time, the mirrored
+    // positions written straight from registers: a lane holds column lc of the block
+    // and rows 8g + lr + j (j = 0..3), which is row lc, four consecutive columns, of
+    // the mirrored block -- one 16-byte store per g.  Off-diagonal tiles only; a
+    // diagonal tile masks element by element.
+    const int ld = (int)g.ldc;
+    float* Xd = (float*)g.C + (m0 + wm * WM) * g.ldc + (n0 + wn * WN);
+    float* Xm = (float*)g.C + (n0 + wn * WN) * g.ldc + (m0 + wm * WM);
+    const float c2 = (float)g.c2;
+    const int dofs = (int)((m0 + wm * WM) - (n0 + wn * WN));
+#pragma unroll
+    for (int i = 0; i < NBLK; ++i) {
+      const int a = i / FN, b = i % FN;
+      float nvs[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) nvs[r] = oldv[i & 1][r] + c2 * acc[a][b][r];
+      if (i + 2 < NBLK) load_old(i + 2, oldv[i & 1]);
+      if (!diag) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) Xd[(a * 32 + (r >> 2) * 8 + lr + (r & 3)) * ld + b * 32 + lc] = nvs[r];
+#pragma unroll
+        for (int q4 = 0; q4 < 4; ++q4)
+          *(float4*)(Xm + (b * 32 + lc) * ld + a * 32 + 8 * q4 + lr) =
+              make_float4(nvs[4 * q4], nvs[4 * q4 + 1], nvs[4 * q4 + 2], nvs[4 * q4 + 3]);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int ml = (r >> 2) * 8 + lr + (r & 3);
+          const int d = dofs + a * 32 + ml - b * 32 - lc;  // m - n of this element
+          if (d >= 0) Xd[(a * 32 + ml) * ld + b * 32 + lc] = nvs[r];
+          if (d > 0) Xm[(b * 32 + lc) * ld + a * 32 + ml] = nvs[r];
+        }
+      }
+    }
+    return;
+  }
   if constexpr (EPI == EPI_SYMUPD) {
     // X += c2 * acc on the lower tile, one 32 x 32 block at a time: the old values
     // of the block are loaded together, the new values go to X directly and,
@@ -575,7 +618,9 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
                          dim3(gemm_bf16_blocks(mg)), dim3(512), 0, s, g);
     else
 #endif
-    if (g.epi == EPI_SYMUPD)
+    if (g.epi == EPI_SYMUPD && RB_UPD_KERNEL == 1)
+      return symupd_bf16_dma(g, gemm_bf16_blocks(mg), s);
+    else if (g.epi == EPI_SYMUPD)
       hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, RB_UPD_LDB, EPI_SYMUPD, 1, 32>),
                          dim3(gemm_bf16_blocks(mg)), dim3(256), 0, s, g);
     else

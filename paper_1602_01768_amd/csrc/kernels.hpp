@@ -87,6 +87,9 @@ int bf16_square_tile(int64_t M, int epi);
 // Sum the FP32 split-K partials of a bf16 product (COLSTORE epilogue of g): C = c2 * sum
 // + c0 * B0 (FP32) + c1 * B1 (FP32 or bf16, b1_dt), column-major; C is FP32 or FP64 (c_dt).
 hipError_t reduce_partials_f32(const GemmArgs& g, const float* partial, hipStream_t s);
+// Square symmetric update (EPI_SYMUPD, 2 x 2 bf16 pieces) with operands loaded
+// straight into LDS; blocks as gemm_bf16_blocks gives for 128 x 128 tiles.
+hipError_t symupd_bf16_dma(const GemmArgs& g, int64_t blocks, hipStream_t s);
 int64_t reduce_blocks_f32(const GemmArgs& g);
 int64_t gemm_bf16_blocks(const MixedGemm& mg);
 
