@@ -70,10 +70,10 @@ def phase_roofline(name, n, q, variant, sketch, precision="mixed"):
 PHASE_KERNEL = {
     "XY": "k_gemm_bf16<128, 256, 2, 4, 2, 2, 1, 0, 0, true, 0, 1, 32>",
     "AS": "k_gemm_bf16<128, 256, 4, 1, 3, 1, 2, 0, 2, false, 0, 1, 32>",
-    "update": "k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, 2, 2, false, 2, 1, 32>",
+    "update": "k_symupd_dma<32, 2, 2, 2, 2>",
 }
-KERNEL_SOURCES = ["paper_1602_01768_amd/csrc/k_bf16.hip", "paper_1602_01768_amd/csrc/common.hpp",
-                  "paper_1602_01768_amd/csrc/kernels.hpp"]
+KERNEL_SOURCES = ["paper_1602_01768_amd/csrc/k_bf16.hip", "paper_1602_01768_amd/csrc/k_symupd.hip",
+                  "paper_1602_01768_amd/csrc/common.hpp", "paper_1602_01768_amd/csrc/kernels.hpp"]
 COUNTERS_FILE = "profiles/hbm_counters_c3_fixed_gauss_mixed.txt"
 
 

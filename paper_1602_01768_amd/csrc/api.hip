@@ -24,7 +24,7 @@
 using namespace rb;
 
 #ifndef RB_GATE
-#define RB_GATE 0  // where the fixed method releases the side lane's next products (see main_fixed)
+#define RB_GATE 0  // where the fixed method releases the side and inverse lanes' next work (see enqueue_steps)
 #endif
 #ifndef RB_BF16_Q
 #define RB_BF16_Q 1  // q-sized products of the mixed fixed Gaussian path in split bf16
@@ -414,10 +414,11 @@ void side_inverse(rbfgs_ctx* ctx, Slot& S) {
 // X-dependent part of one fixed-sketch RBFGS iteration, eq. (qunac) as the
 // symmetric rank-2q update X+ = X - (U W'^T + W' U^T), U = S G^-1,
 // W' = V - S/2 - U H/2, V = X Y, H = Y^T V (Y = A S and G = S^T Y from the slot).
-// `ahead` is called once, at the point where the side lanes' work for later iterations
-// is to be released (RB_GATE: 0 after V = X Y, 1 before the update of X).
-template <class F>
-void main_fixed(rbfgs_ctx* ctx, Slot& S, F&& ahead) {
+// `after_xy` is called once V = X Y is enqueued, `ahead` once, at the point where the
+// side lanes' remaining work for later iterations is to be released (before the update
+// of X, or earlier on the paths that have no separate update).
+template <class F, class G>
+void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
   const Lane& L = ctx->main;
   bool fired = false;
   auto release = [&]() {
@@ -435,7 +436,7 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, F&& ahead) {
     nn_times_panel(ctx, L, ctx->X, false, S.Y, mdt, ctx->V, 2, 2, 1, ph.mark(),
                    fused_est ? (const __bf16*)S.Sk : nullptr);
   }
-  if (RB_GATE == 0) release();
+  after_xy();
   {
     Phase ph(ctx, L, "gram_H");
     if (ctx->bf16h) gram_bf16(ctx, L, S.Y, false, (const float*)ctx->V, ctx->H32, DT_F32);
@@ -624,11 +625,28 @@ void enqueue_steps(rbfgs_ctx* ctx, int64_t nsteps) {
       main_adaptive(ctx, S);
     } else {
       HIPCHK(hipStreamWaitEvent(ctx->main.s, S.y_ready, 0));
-      main_fixed(ctx, S, [&]() {
+      // RB_GATE 0: the side lane's products of k+2 and the inverse of k+1 are released
+      // after X Y; 1: both before the update of X; 2: the inverse after X Y, the
+      // products before the update (so that A S does not hold the CUs that the main
+      // lane's q-sized kernels between X Y and the update need)
+      auto release_products = [&]() {
         HIPCHK(hipEventRecord(ctx->ev_xy, ctx->main.s));
         HIPCHK(hipStreamWaitEvent(ctx->side.s, ctx->ev_xy, 0));
-        ahead();
-      });
+        if (i + 2 < nsteps) products(k + 2);
+      };
+      auto release_inverse = [&]() {
+        if (i + 1 < nsteps) inverse(k + 1);
+      };
+      main_fixed(
+          ctx, S,
+          [&]() {
+            if (RB_GATE == 0) release_products();
+            if (RB_GATE != 1) release_inverse();
+          },
+          [&]() {
+            if (RB_GATE != 0) release_products();
+            if (RB_GATE == 1) release_inverse();
+          });
     }
     HIPCHK(hipEventRecord(S.released, ctx->main.s));
     S.released_valid = true;

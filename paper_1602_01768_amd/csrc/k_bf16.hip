@@ -451,16 +451,23 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArg
     return;
   }
   if constexpr (EPI == EPI_PARTIAL) {
-    // column-major partial sums of split kc: P[kc][n * M + m]
+    // column-major partial sums of split kc: P[kc][n * M + m]; a lane holds rows
+    // 8 g + lr + j (j = 0..3) of column lc, one 16-byte store per g.  The lane offsets
+    // are recomputed here from an opaque copy of the lane index, so that the compiler
+    // does not hold these addresses through the k loop.
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    const uint32_t plr = (ln >> 5) * 4, plc = ln & 31;
     float* P = (float*)g.C + (int64_t)kc * g.M * g.N + (n0 + wn * WN) * g.M + (m0 + wm * WM);
-    const int ldp = (int)g.M;
+    const uint32_t ldp = (uint32_t)g.M;
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
       for (int b = 0; b < FN; ++b)
 #pragma unroll
-        for (int r = 0; r < 16; ++r)
-          P[(b * 32 + lc) * ldp + a * 32 + (r >> 2) * 8 + lr + (r & 3)] = acc[a][b][r];
+        for (int q4 = 0; q4 < 4; ++q4)
+          *(float4*)(P + (b * 32 + plc) * ldp + a * 32 + q4 * 8 + plr) =
+              make_float4(acc[a][b][4 * q4], acc[a][b][4 * q4 + 1], acc[a][b][4 * q4 + 2], acc[a][b][4 * q4 + 3]);
   } else if constexpr (EPI == EPI_ADDROW) {
     float* C = (float*)g.C + (m0 + wm * WM) * g.ldc + (n0 + wn * WN);
     const int ld = (int)g.ldc;

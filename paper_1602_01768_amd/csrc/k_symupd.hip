@@ -21,6 +21,27 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+// Measured on the n = 16384, q = 256 update with random operands (same-run
+// comparisons): two stages of 32 columns, two workgroups per CU and 2 x 2 waves of
+// 64 x 64 were fastest; 16-column stages (any depth or occupancy), three or four
+// stages (one workgroup per CU) and 2 x 1 / 1 x 2 wave grids were 10-40% slower.
+#ifndef RB_UPD_BKS
+#define RB_UPD_BKS 32  // columns per stage
+#endif
+#ifndef RB_UPD_NS
+#define RB_UPD_NS 2  // stages in the ring
+#endif
+#ifndef RB_UPD_OCC
+#define RB_UPD_OCC 2  // workgroups per CU the register budget is sized for
+#endif
+#ifndef RB_UPD_SCHED
+#define RB_UPD_SCHED 0  // 1: explicit interleave of the second substep's LDS reads with MFMAs
+#endif
+#ifndef RB_UPD_WAVES
+#define RB_UPD_WAVES 2, 2  // wave grid over the 128 x 128 tile
+#endif
+
+
 namespace rb {
 
 namespace {
@@ -120,7 +141,52 @@ void k_symupd_dma(GemmArgs g) {
 
   // byte offset of this lane's fragment row within a piece, and its chunk swizzle
   const int ra = wm * WM + (lane & 31), rb = wn * WN + (lane & 31);
+  auto frag = [&](const char* S, int s, bf16x8 (&av)[NP][FM], bf16x8 (&bv)[NP][FN]) {
+    const int c = 2 * s + (lane >> 5);
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int a = 0; a < FM; ++a) {
+        const int r = ra + a * 32;
+        av[p][a] = *(const bf16x8*)(S + p * PLB + r * ROWB + ((c ^ ((r / RPB) % CHUNKS)) * 16));
+      }
+#pragma unroll
+    for (int p = 0; p < NP; ++p)
+#pragma unroll
+      for (int b = 0; b < FN; ++b) {
+        const int r = rb + b * 32;
+        bv[p][b] = *(const bf16x8*)(S + OPB + p * PLB + r * ROWB + ((c ^ ((r / RPB) % CHUNKS)) * 16));
+      }
+  };
+  auto mfmas = [&](const bf16x8 (&av)[NP][FM], const bf16x8 (&bv)[NP][FN]) {
+#pragma unroll
+    for (int pp = 0; pp < 3; ++pp)
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[pp == 1 ? 1 : 0][a], bv[pp == 0 ? 1 : 0][b], acc[a][b],
+                                                               0, 0, 0);
+  };
   auto compute = [&](const char* S) {
+    if constexpr (RB_UPD_SCHED == 1 && BKS == 32) {
+      // both substeps' fragments read up front, the second substep's reads placed
+      // between the first substep's MFMAs (one read after each of the first NR MFMAs)
+      constexpr int NR = NP * (FM + FN), NM = 3 * FM * FN;
+      bf16x8 a0[NP][FM], b0[NP][FN], a1[NP][FM], b1[NP][FN];
+      frag(S, 0, a0, b0);
+      frag(S, 1, a1, b1);
+      mfmas(a0, b0);
+      mfmas(a1, b1);
+      __builtin_amdgcn_sched_group_barrier(0x100, NR, 0);
+#pragma unroll
+      for (int j = 0; j < NR; ++j) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+      }
+      __builtin_amdgcn_sched_group_barrier(0x008, 2 * NM - NR, 0);
+      return;
+    }
 #pragma unroll
     for (int s = 0; s < BKS / 16; ++s) {
       const int c = 2 * s + (lane >> 5);
@@ -239,23 +305,6 @@ void k_symupd_dma(GemmArgs g) {
 }
 
 }  // namespace
-
-// Measured on the n = 16384, q = 256 update with random operands (same-run
-// comparisons): two stages of 32 columns, two workgroups per CU and 2 x 2 waves of
-// 64 x 64 were fastest; 16-column stages (any depth or occupancy), three or four
-// stages (one workgroup per CU) and 2 x 1 / 1 x 2 wave grids were 10-40% slower.
-#ifndef RB_UPD_BKS
-#define RB_UPD_BKS 32  // columns per stage
-#endif
-#ifndef RB_UPD_NS
-#define RB_UPD_NS 2  // stages in the ring
-#endif
-#ifndef RB_UPD_OCC
-#define RB_UPD_OCC 2  // workgroups per CU the register budget is sized for
-#endif
-#ifndef RB_UPD_WAVES
-#define RB_UPD_WAVES 2, 2  // wave grid over the 128 x 128 tile
-#endif
 
 hipError_t symupd_bf16_dma(const GemmArgs& g, int64_t blocks, hipStream_t s) {
   if (g.K % (RB_UPD_BKS * 1) || g.M % 128 || g.M != g.N || g.lda % 8 || g.ldb % 8 || g.a_plane % 8 ||
