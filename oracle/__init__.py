@@ -12,10 +12,13 @@ Modules
   sketch   Gaussian and coordinate sketches drawn from that stream.
   rbfgs    fixed-sketch RBFGS (eq. qunac, Sec. 8.7) and AdaRBFGS (Alg. 4 /
            eq. Cholimprov, Sec. 9.3), residuals and the per-step estimator.
+  variants simultaneous randomized Kaczmarz (eq. badbroyadj), AIP (eq. BFGSas)
+           and randomized PSB (eq. Xupdatesym with W = I), and the residual
+           estimator of the row variants.
   theory   closed-form quantities used by the pins: the rate rho of Thm 6.2 /
            eq. rhoequiv, E[Z] for discrete sketches (Prop. 7.1), brute-force
-           projection (eq. NFsym) by a dense KKT solve.
+           projections (eq. NF, eq. NFsym) by a dense KKT solve.
 
 Parity status: every function here is pinned by a `-m "not gpu"` test against
-something other than itself (see tests/test_oracle_pins.py).
+something other than itself (see tests/test_oracle_pins.py, tests/test_oracle_variants.py).
 """

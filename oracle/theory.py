@@ -89,3 +89,35 @@ def projection_kkt(Xk, A, S):
     rhs = np.concatenate([D.T @ H @ xk, b])
     sol = np.linalg.lstsq(K, rhs, rcond=None)[0]
     return (D @ sol[:m]).reshape(n, n, order="F")
+
+
+def projection_kkt_weighted(Xk, A, S, Winv, symmetric):
+    """argmin_X 1/2 ||X - Xk||_{F(W^-1)}^2  s.t.  S^T A X = S^T  (and X = X^T when
+    `symmetric`): eq. (NF) (row variant) or eq. (NFsym), for a general weight.
+
+    ||X||_{F(W^-1)}^2 = Tr(X^T W^-1 X W^-1) = vec(X)^T (W^-1 kron W^-1) vec(X)
+    (column-major vec, W symmetric).  X is parametrised by all n^2 entries, or by
+    its lower triangle when symmetric; the KKT system is solved by least squares
+    (some constraints are redundant under the symmetry constraint).
+    """
+    n, q = S.shape
+    if symmetric:
+        pairs = [(i, j) for j in range(n) for i in range(j, n)]
+        D = np.zeros((n * n, len(pairs)))
+        for t, (i, j) in enumerate(pairs):
+            D[i + j * n, t] = 1.0
+            D[j + i * n, t] = 1.0
+    else:
+        D = np.eye(n * n)
+    H = np.kron(Winv, Winv)
+    C = np.kron(np.eye(n), S.T @ A) @ D
+    b = S.T.reshape(-1, order="F")
+    xk = Xk.reshape(-1, order="F")
+    m = D.shape[1]
+    K = np.zeros((m + C.shape[0], m + C.shape[0]))
+    K[:m, :m] = D.T @ H @ D
+    K[:m, m:] = C.T
+    K[m:, :m] = C
+    rhs = np.concatenate([D.T @ H @ xk, b])
+    sol = np.linalg.lstsq(K, rhs, rcond=None)[0]
+    return (D @ sol[:m]).reshape(n, n, order="F")
