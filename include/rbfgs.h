@@ -14,6 +14,22 @@
  *                   S = L S~ with S~ i.i.d.; L+ = L + S R (C S~^T - R^T S^T A L),
  *                   R = L_G^-T (G = L_G L_G^T), C = L_M^-1 (S~^T S~ = L_M L_M^T).
  *
+ * Other instances of the sketch-and-project family (same sketches and stream):
+ *   RBFGS_PSB       randomized Powell-symmetric-Broyden, Sec. 8.4: Alg. 3 with
+ *                   W = I, read through eq. (Xupdatesym) (the printed eq. (PSB)
+ *                   has garbled transposes): with Y = A S, G = Y^T Y,
+ *                   X+ = X - (X A - I) S G^-1 Y^T + Y G^-1 (Y^T X - S^T)(Y G^-1 Y^T - I).
+ *                   A symmetric (not necessarily definite); X stays symmetric.
+ *   RBFGS_AIP       approximate inverse preconditioning, Sec. 8.6 eq. (BFGSas):
+ *                   Alg. 1 with W = A^-1, X+ = X + S (S^T A S)^-1 S^T (I - A X).
+ *                   A SPD; the iterates are not symmetric.
+ *   RBFGS_KACZMARZ  simultaneous randomized Kaczmarz, Sec. 8.2 eq. (badbroyadj):
+ *                   Alg. 1 with W = I, X+ = X + A^T S (S^T A A^T S)^-1 S^T (I - A X).
+ *                   Any invertible A (row-major, not required to be symmetric).
+ * For PSB, AIP and Kaczmarz a coordinate sketch is applied as the dense 0/1 matrix,
+ * and the estimator of AIP and Kaczmarz is ||S^T (I - A X)||_F^2 scaled as for the
+ * fixed method (it estimates ||I - A X||_F^2).
+ *
  * Sketch distributions (Sec. 10): RBFGS_SKETCH_GAUSS, S~ n x q with i.i.d.
  * N(0,1) entries; RBFGS_SKETCH_COORD, q distinct coordinate vectors drawn
  * uniformly.  Both come from a counter-based stream keyed by (seed, iteration),
@@ -73,7 +89,13 @@ typedef enum {
 } rbfgs_status;
 
 typedef enum { RBFGS_SKETCH_GAUSS = 0, RBFGS_SKETCH_COORD = 1 } rbfgs_sketch;
-typedef enum { RBFGS_FIXED = 0, RBFGS_ADAPTIVE = 1 } rbfgs_variant;
+typedef enum {
+  RBFGS_FIXED = 0,
+  RBFGS_ADAPTIVE = 1,
+  RBFGS_PSB = 2,
+  RBFGS_AIP = 3,
+  RBFGS_KACZMARZ = 4
+} rbfgs_variant;
 typedef enum { RBFGS_FP64 = 0, RBFGS_MIXED = 1 } rbfgs_precision;
 typedef enum { RBFGS_F32 = 0, RBFGS_F64 = 1 } rbfgs_dtype;
 
@@ -91,8 +113,9 @@ typedef struct {
  * (converted to FP32 in mixed mode, FP64 in FP64 mode), set X_0 = I (L_0 = I).
  *   A          n x n matrix, row-major, leading dimension lda >= n, element type
  *              a_dtype; host memory if a_on_device == 0, else device memory.
- *              Must be symmetric (checked exactly on the stored type) and
- *              finite; positive definiteness is detected during iteration.
+ *              Must be symmetric (checked exactly on the stored type; not for
+ *              RBFGS_KACZMARZ) and finite; positive definiteness (where the
+ *              variant needs it) is detected during iteration.
  *   hip_stream hipStream_t to run on (NULL = the default stream).
  *   out        receives the context; set to NULL on failure.
  * Errors: E_INVALID_ARG (sizes, NULL pointers, asymmetric or non-finite A),

@@ -48,7 +48,8 @@ struct Slot {  // sketch-dependent quantities of one iteration
   void* Sk = nullptr;        // Gaussian sketch (S or S~), bf16 in mixed mode, FP64 otherwise
   int32_t* C = nullptr;      // coordinate indices
   void* Y = nullptr;         // fixed: A S
-  double* G = nullptr;       // fixed: S^T A S;  adaptive: S~^T S~
+  double* G = nullptr;       // fixed: S^T A S;  adaptive: S~^T S~;  PSB, Kaczmarz: Y^T Y
+  double* G2 = nullptr;      // PSB: S^T Y
   double* Ginv = nullptr;    // fixed: G^-1
   float* Ginv32 = nullptr;   // fixed, q-sized products in bf16: G^-1 rounded to FP32
   double* Z = nullptr;       // inverse Cholesky factor of G (fixed) or of S~^T S~ (adaptive)
@@ -68,6 +69,11 @@ struct rbfgs_ctx {
   int64_t n = 0, np = 0, qp = 0;
   int q = 0;
   bool mixed = false, ada = false, coord = false;
+  // other instances of the family: PSB (Alg. 3, W = I), AIP and Kaczmarz (Alg. 1 with
+  // W = A^-1 or W = I; "row variants", nonsymmetric iterates); coordinate sketches of
+  // these are used as dense 0/1 matrices (dcoord), `coord` marks the gather paths of
+  // fixed RBFGS and AdaRBFGS only
+  bool psb = false, rowv = false, kacz = false, dcoord = false;
   int mdt = DT_F64;  // element type of A, X/L and the n x q panels
   int device = 0;
   int64_t k = 0;
@@ -344,8 +350,9 @@ void side_products(rbfgs_ctx* ctx, int64_t k, Slot& S) {
   const int mdt = ctx->mdt;
   {
     Phase ph(ctx, L, "sketch");
-    if (ctx->coord) HIPCHK(sketch_coord(ctx->p.seed, k, ctx->n, ctx->q, S.C, L.s));
+    if (ctx->coord || ctx->dcoord) HIPCHK(sketch_coord(ctx->p.seed, k, ctx->n, ctx->q, S.C, L.s));
     else HIPCHK(sketch_gauss(ctx->p.seed, k, ctx->n, ctx->q, S.Sk, sk_dt(ctx), np, L.s));
+    if (ctx->dcoord) HIPCHK(coord_dense(S.C, ctx->q, S.Sk, sk_dt(ctx), np, qp, L.s));
   }
   if (ctx->ada) {
     if (!ctx->coord) {
@@ -358,13 +365,16 @@ void side_products(rbfgs_ctx* ctx, int64_t k, Slot& S) {
     HIPCHK(hipEventRecord(S.y_ready, L.s));
   } else {
     {
+      // Y = A S (Kaczmarz: P = A^T S)
       Phase ph(ctx, L, "AS", true);
-      nn_times_panel(ctx, L, ctx->A, false, S.Sk, sk_dt(ctx), S.Y, 3, 1, 2, ph.mark());  // exact
+      nn_times_panel(ctx, L, ctx->A, ctx->kacz, S.Sk, sk_dt(ctx), S.Y, 3, 1, 2, ph.mark());  // exact
     }
     HIPCHK(hipEventRecord(S.y_ready, L.s));
     Phase ph(ctx, L, "gram_G");
     if (ctx->bf16q) gram_bf16(ctx, L, S.Sk, true, (const float*)S.Y, S.G, DT_F64);
+    else if (ctx->psb || ctx->kacz) gram(ctx, L, S.Y, mdt, S.Y, mdt, S.G);  // S^T A^2 S, S^T A A^T S
     else gram(ctx, L, S.Sk, sk_dt(ctx), S.Y, mdt, S.G);
+    if (ctx->psb) gram(ctx, L, S.Sk, sk_dt(ctx), S.Y, mdt, S.G2);
   }
   HIPCHK(hipEventRecord(S.g_ready, L.s));
 }
@@ -397,6 +407,8 @@ void side_inverse(rbfgs_ctx* ctx, Slot& S) {
       g.epi = EPI_COLSTORE; g.C = U; g.ldc = np; g.c_dt = DT_F32; g.c2 = 1.0; g.bn = 128;
       mg.a_kind = OK_BF16_MC; mg.b_kind = OK_F32_KC; mg.na = 1; mg.nb = 3; mg.pmax = 2;
       bf_gemm(ctx, L, mg, 1);  // k = q is short: no split
+    } else if (ctx->psb || ctx->kacz) {
+      panel_times_small(ctx, L, S.Y, DT_F32, S.Ginv, U, DT_F32, 1.0);  // U = Y G^-1
     } else {
       panel_times_small(ctx, L, S.Sk, DT_BF16, S.Ginv, U, DT_F32, 1.0);
     }
@@ -405,7 +417,8 @@ void side_inverse(rbfgs_ctx* ctx, Slot& S) {
     HIPCHK(pack_split2(U, np, np, qp, S.planes, S.planes + plane, ldp, 2 * qp, L.s));
   } else {
     double* U = (double*)S.U;
-    panel_times_small(ctx, L, S.Sk, DT_F64, S.Ginv, U, DT_F64, 1.0);
+    if (ctx->psb || ctx->kacz) panel_times_small(ctx, L, S.Y, DT_F64, S.Ginv, U, DT_F64, 1.0);  // U = Y G^-1
+    else panel_times_small(ctx, L, S.Sk, DT_F64, S.Ginv, U, DT_F64, 1.0);
     HIPCHK(hipMemcpyAsync(U + 2 * np * qp, U, (size_t)np * qp * sizeof(double), hipMemcpyDeviceToDevice, L.s));
   }
 }
@@ -442,7 +455,7 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
     if (ctx->bf16h) gram_bf16(ctx, L, S.Y, false, (const float*)ctx->V, ctx->H32, DT_F32);
     else gram(ctx, L, S.Y, mdt, ctx->V, mdt, ctx->H);
   }
-  const double scale = ctx->coord ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
+  const double scale = (ctx->coord || ctx->dcoord) ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
   {
     Phase ph(ctx, L, "estimator");
     if (fused_est)
@@ -452,6 +465,9 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
                        ctx->q, scale, L.red, ctx->est, ctx->status, L.s));
   }
   HIPCHK(hipStreamWaitEvent(L.s, S.ready, 0));  // G^-1 and U of this slot
+  // PSB: H' = Y^T V - S^T Y (= R^T Y with R = V - S), and W' = V - S - U H'/2
+  const double cs = ctx->psb ? -1.0 : -0.5;
+  if (ctx->psb) HIPCHK(panel_axpby(ctx->H, DT_F64, 1.0, S.G2, DT_F64, -1.0, ctx->H, DT_F64, qp, qp, qp, L.s));
   if (ctx->coord) {
     // U = E_C G^-1 is not formed: W' = V - E_C/2 - E_C (G^-1 H)/2 and R = G^-1 W'^T;
     // the update touches only rows and columns C.
@@ -485,7 +501,7 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
         mg.a_kind = OK_F32_MC; mg.b_kind = OK_F32_KC; mg.na = 3; mg.nb = 3; mg.pmax = 2;
         bf_gemm(ctx, L, mg, 1);  // k = q is short: no split
       } else {
-        panel_times_small(ctx, L, S.U, DT_F32, ctx->H, W, DT_F32, -0.5, ctx->V, DT_F32, 1.0, S.Sk, DT_BF16, -0.5);
+        panel_times_small(ctx, L, S.U, DT_F32, ctx->H, W, DT_F32, -0.5, ctx->V, DT_F32, 1.0, S.Sk, DT_BF16, cs);
       }
       HIPCHK(pack_split2(W, np, np, qp, S.planes, S.planes + plane, ldp, qp, L.s));
     }
@@ -505,7 +521,7 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
     {
       Phase ph(ctx, L, "panels");
       panel_times_small(ctx, L, PQ, DT_F64, ctx->H, PQ + np * qp, DT_F64, -0.5, ctx->V, DT_F64, 1.0, S.Sk, DT_F64,
-                        -0.5);
+                        cs);
     }
     release();
     Phase ph(ctx, L, "update", true);
@@ -514,6 +530,65 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
     g.A = PQ; g.lda = np; g.a_dt = DT_F64; g.a_kc = false;
     g.B = PQ + np * qp; g.ldb = np; g.b_dt = DT_F64; g.b_kc = false;
     g.epi = EPI_SYMUPD; g.C = ctx->X; g.ldc = np; g.c_dt = DT_F64; g.c2 = -1.0;
+    g.tiles = ctx->tiles; g.ntiles = ctx->ntiles;
+    f64_gemm(ctx, L, g);
+  }
+}
+
+// X-dependent part of one step of a row variant of Alg. 1 (AIP, eq. BFGSas: P = A S,
+// U = S G^-1, G = S^T P; simultaneous randomized Kaczmarz, eq. badbroyadj: P = A^T S,
+// U = P G^-1, G = P^T P; P, G and U from the slot):
+//   C = X^T P,  R = S - C  (R^T = S^T (I - A X), the residual sketch),  X+ = X + U R^T
+// on every tile of X (the iterates are not symmetric).  The estimator is ||R||_F^2.
+template <class F, class G>
+void main_row(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
+  const Lane& L = ctx->main;
+  const int64_t np = ctx->np, qp = ctx->qp;
+  const int mdt = ctx->mdt;
+  GemmArgs shape;
+  shape.M = np; shape.N = qp;
+  const bool fused_est = ctx->mixed && (size_t)reduce_blocks_f32(shape) <= L.red_count;
+  {
+    Phase ph(ctx, L, "XtP", true);
+    nn_times_panel(ctx, L, ctx->X, true, S.Y, mdt, ctx->V, 2, 2, 1, ph.mark(),
+                   fused_est ? (const __bf16*)S.Sk : nullptr);
+  }
+  after_xy();
+  const double scale = ctx->dcoord ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
+  {
+    Phase ph(ctx, L, "estimator");
+    if (fused_est)
+      HIPCHK(reduce_sum_scaled(L.red, reduce_blocks_f32(shape), ctx->est, scale, ctx->status, L.s));
+    else
+      HIPCHK(estimator(S.Sk, sk_dt(ctx), nullptr, ctx->V, mdt, np, ctx->n, ctx->q, scale, L.red, ctx->est,
+                       ctx->status, L.s));
+  }
+  HIPCHK(hipStreamWaitEvent(L.s, S.ready, 0));  // U of this slot
+  ahead();
+  {
+    Phase ph(ctx, L, "panels");
+    HIPCHK(panel_axpby(S.Sk, sk_dt(ctx), 1.0, ctx->V, mdt, -1.0, ctx->W, mdt, np, qp, np, L.s));  // R = S - C
+    if (ctx->mixed)
+      HIPCHK(pack_split2((const float*)ctx->W, np, np, qp, ctx->planes, ctx->planes + np * qp, qp, 0, L.s));
+  }
+  Phase ph(ctx, L, "update", true);  // X += U R^T
+  if (ctx->mixed) {
+    const int64_t ldp = 3 * qp;
+    MixedGemm mg;
+    GemmArgs& g = mg.g;
+    g.M = np; g.N = np; g.K = qp;
+    g.A = S.planes; g.lda = ldp; g.a_plane = np * ldp;
+    g.B = ctx->planes; g.ldb = qp; g.b_plane = np * qp;
+    g.epi = EPI_ADDROW; g.C = ctx->X; g.ldc = np; g.c2 = 1.0;
+    g.tiles = ctx->tiles; g.ntiles = ctx->ntiles;
+    mg.a_kind = OK_BF16_KC; mg.b_kind = OK_BF16_KC; mg.na = 2; mg.nb = 2; mg.pmax = 1;
+    bf_gemm(ctx, L, mg);
+  } else {
+    GemmArgs g;
+    g.M = np; g.N = np; g.K = qp;
+    g.A = S.U; g.lda = np; g.a_dt = DT_F64; g.a_kc = false;
+    g.B = ctx->W; g.ldb = np; g.b_dt = DT_F64; g.b_kc = false;
+    g.epi = EPI_ADDROW; g.C = ctx->X; g.ldc = np; g.c_dt = DT_F64; g.c2 = 1.0;
     g.tiles = ctx->tiles; g.ntiles = ctx->ntiles;
     f64_gemm(ctx, L, g);
   }
@@ -637,16 +712,16 @@ void enqueue_steps(rbfgs_ctx* ctx, int64_t nsteps) {
       auto release_inverse = [&]() {
         if (i + 1 < nsteps) inverse(k + 1);
       };
-      main_fixed(
-          ctx, S,
-          [&]() {
-            if (RB_GATE == 0) release_products();
-            if (RB_GATE != 1) release_inverse();
-          },
-          [&]() {
-            if (RB_GATE != 0) release_products();
-            if (RB_GATE == 1) release_inverse();
-          });
+      auto after_xy = [&]() {
+        if (RB_GATE == 0) release_products();
+        if (RB_GATE != 1) release_inverse();
+      };
+      auto before_update = [&]() {
+        if (RB_GATE != 0) release_products();
+        if (RB_GATE == 1) release_inverse();
+      };
+      if (ctx->rowv) main_row(ctx, S, after_xy, before_update);
+      else main_fixed(ctx, S, after_xy, before_update);
     }
     HIPCHK(hipEventRecord(S.released, ctx->main.s));
     S.released_valid = true;
@@ -687,7 +762,8 @@ double exact_residual(rbfgs_ctx* ctx) {
     HIPCHK(gemm_f64(b, nullptr, L.s));
     g.A = tmp; g.a_dt = DT_F64;
   }
-  g.B = ctx->X; g.ldb = np; g.b_dt = ctx->mdt; g.b_kc = true;  // X symmetric; for L: Bop(k,j) = L[j][k]
+  // X symmetric (fixed, PSB): either orientation; for L: Bop(k,j) = L[j][k]; row variants: Bop(k,j) = X[k][j]
+  g.B = ctx->X; g.ldb = np; g.b_dt = ctx->mdt; g.b_kc = !ctx->rowv;
   g.epi = EPI_RESID; g.red = L.red; g.nvalid = ctx->n;
   const int64_t blocks = gemm_f64_blocks(g);
   HIPCHK(gemm_f64(g, nullptr, L.s));
@@ -713,6 +789,7 @@ void make_slot(rbfgs_ctx* ctx, Slot& S) {
   S.Sk = dalloc(ctx, np * qp * dt_size(sk_dt(ctx)));
   S.C = (int32_t*)dalloc(ctx, qp * sizeof(int32_t));
   S.G = (double*)dalloc(ctx, qq);
+  if (ctx->psb) S.G2 = (double*)dalloc(ctx, qq);
   S.Z = (double*)dalloc(ctx, qq);
   if (!ctx->ada) {
     S.Y = dalloc(ctx, np * qp * es);
@@ -763,9 +840,13 @@ void set_params(rbfgs_ctx* ctx, const rbfgs_params& p) {
   ctx->qp = ((int64_t)p.q + 31) / 32 * 32;
   ctx->mixed = p.precision == RBFGS_MIXED;
   ctx->ada = p.variant == RBFGS_ADAPTIVE;
-  ctx->coord = p.sketch == RBFGS_SKETCH_COORD;
+  ctx->psb = p.variant == RBFGS_PSB;
+  ctx->kacz = p.variant == RBFGS_KACZMARZ;
+  ctx->rowv = ctx->kacz || p.variant == RBFGS_AIP;
+  ctx->dcoord = p.sketch == RBFGS_SKETCH_COORD && (ctx->psb || ctx->rowv);
+  ctx->coord = p.sketch == RBFGS_SKETCH_COORD && !ctx->dcoord;
   ctx->mdt = ctx->mixed ? DT_F32 : DT_F64;
-  ctx->bf16q = RB_BF16_Q && ctx->mixed && !ctx->ada && !ctx->coord && ctx->qp % 128 == 0;
+  ctx->bf16q = RB_BF16_Q && ctx->mixed && p.variant == RBFGS_FIXED && !ctx->coord && ctx->qp % 128 == 0;
   ctx->bf16h = ctx->bf16q && 8 * ctx->qp <= ctx->np;
 }
 
@@ -790,6 +871,7 @@ void allocate(rbfgs_ctx* ctx) {
     ctx->Y = dalloc(ctx, np * qp * es);
     if (ctx->mixed) ctx->planes = (__bf16*)dalloc(ctx, (size_t)4 * np * qp * sizeof(__bf16));
   }
+  if (ctx->rowv && ctx->mixed) ctx->planes = (__bf16*)dalloc(ctx, (size_t)2 * np * qp * sizeof(__bf16));
   if (!ctx->ada && ctx->coord) ctx->R = dalloc(ctx, qp * np * es);
   const size_t qq = (size_t)qp * qp * sizeof(double);
   ctx->G = (double*)dalloc(ctx, qq);
@@ -801,11 +883,12 @@ void allocate(rbfgs_ctx* ctx) {
   ctx->Mq = (double*)dalloc(ctx, qq);
   ctx->est = (double*)dalloc(ctx, 4 * sizeof(double));
   ctx->status = (int*)dalloc(ctx, sizeof(int));
-  {  // tile order of the n x n update: lower triangle (fixed) or full square (adaptive)
-    const int epi = ctx->ada ? EPI_ADDROW : EPI_SYMUPD;
+  {  // tile order of the n x n update: lower triangle (symmetric X) or full square (L, row variants)
+    const bool full = ctx->ada || ctx->rowv;
+    const int epi = full ? EPI_ADDROW : EPI_SYMUPD;
     const int T = (int)(np / (ctx->mixed ? bf16_square_tile(np, epi) : 128));
-    std::vector<int2> order((size_t)make_tile_order(T, RB_SUPER_TILES, !ctx->ada, nullptr));
-    ctx->ntiles = make_tile_order(T, RB_SUPER_TILES, !ctx->ada, order.data());
+    std::vector<int2> order((size_t)make_tile_order(T, RB_SUPER_TILES, !full, nullptr));
+    ctx->ntiles = make_tile_order(T, RB_SUPER_TILES, !full, order.data());
     ctx->tiles = (int2*)dalloc(ctx, order.size() * sizeof(int2));
     if (!ctx->dry) {
       HIPCHK(hipMemcpyAsync(ctx->tiles, order.data(), order.size() * sizeof(int2), hipMemcpyHostToDevice,
@@ -827,7 +910,7 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
   const rbfgs_params& p = *params;
   if (p.n < 1 || p.q < 1 || p.q > p.n || p.q > 1024 || lda < p.n || (a_dtype != RBFGS_F32 && a_dtype != RBFGS_F64) ||
       (p.sketch != RBFGS_SKETCH_GAUSS && p.sketch != RBFGS_SKETCH_COORD) ||
-      (p.variant != RBFGS_FIXED && p.variant != RBFGS_ADAPTIVE) ||
+      (p.variant < RBFGS_FIXED || p.variant > RBFGS_KACZMARZ) ||
       (p.precision != RBFGS_FP64 && p.precision != RBFGS_MIXED) || p.check_every < 0 || p.n > (1ll << 20))
     return RBFGS_E_INVALID_ARG;
   rbfgs_ctx* ctx = new rbfgs_ctx();
@@ -852,14 +935,15 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
       Adev = staging;
     }
     int* flag = ctx->status;
-    HIPCHK(check_sym_finite(Adev, sdt, lda, p.n, flag, ctx->main.s));
+    const bool need_sym = p.variant != RBFGS_KACZMARZ;  // Kaczmarz takes any invertible A
+    HIPCHK(check_sym_finite(Adev, sdt, lda, p.n, flag, ctx->main.s, need_sym));
     HIPCHK(copy_convert(Adev, sdt, lda, ctx->A, ctx->mdt, np, p.n, p.n, ctx->main.s));
     int bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->main.s));
     HIPCHK(hipStreamSynchronize(ctx->main.s));
     if (staging) HIPCHK(hipFree(staging));
     if (!bad && ctx->mixed) {  // the stored FP32 A must also be symmetric and finite
-      HIPCHK(check_sym_finite(ctx->A, DT_F32, np, p.n, flag, ctx->main.s));
+      HIPCHK(check_sym_finite(ctx->A, DT_F32, np, p.n, flag, ctx->main.s, need_sym));
       HIPCHK(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->main.s));
       HIPCHK(hipStreamSynchronize(ctx->main.s));
     }

@@ -650,6 +650,8 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
   RB_TALL(2, 2, 1, OK_F32_KC, OK_F32_KC, RB_TS_LDB, RB_TS_WAVES256)        // X Y
   RB_TALL(3, 2, 2, OK_F32_KC, OK_F32_KC, RB_TS_LDB, RB_TS_WAVES256)        // A S with S = L S~ (FP32)
   RB_TALL(2, 3, 2, OK_F32_MC, OK_F32_KC, RB_TS_LDB, RB_TS_WAVES256)        // L^T Y
+  RB_TALL(2, 2, 1, OK_F32_MC, OK_F32_KC, RB_TS_LDB, RB_TS_WAVES256)        // X^T P (row variants)
+  RB_TALL(3, 1, 2, OK_F32_MC, OK_BF16_KC, RB_TS_LDB_AS, RB_TS_WAVES256_AS)  // A^T S (Kaczmarz)
   // q-sized products: one LDS buffer, so that they share CUs with the n x n products
   RB_TALL(1, 3, 2, OK_BF16_KC, OK_F32_KC, false, RB_TS_WAVES256)  // G = S^T Y
   RB_TALL(1, 3, 2, OK_BF16_MC, OK_F32_KC, false, RB_TS_WAVES256)  // U = S G^-1

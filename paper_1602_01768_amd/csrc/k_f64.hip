@@ -16,6 +16,7 @@ RB_DEV double load_any(const void* p, int dt, int64_t i) {
 }
 RB_DEV void store_any(void* p, int dt, int64_t i, double v) {
   if (dt == DT_F32) ((float*)p)[i] = (float)v;
+  else if (dt == DT_BF16) ((__bf16*)p)[i] = (__bf16)(float)v;
   else ((double*)p)[i] = v;
 }
 RB_DEV double round_to(int dt, double v) { return dt == DT_F32 ? (double)(float)v : v; }
@@ -327,6 +328,8 @@ hipError_t gemm_f64(const GemmArgs& gin, void* partial_ws, hipStream_t s) {
       hipLaunchKernelGGL((k_gemm_f64<128, 128, false, false, EPI_ADDROW>), dim3(blocks), dim3(256), 0, s, run);
     else if (run.epi == EPI_RESID && run.a_kc && run.b_kc)
       hipLaunchKernelGGL((k_gemm_f64<128, 128, true, true, EPI_RESID>), dim3(blocks), dim3(256), 0, s, run);
+    else if (run.epi == EPI_RESID && run.a_kc)  // I - A X for a nonsymmetric X
+      hipLaunchKernelGGL((k_gemm_f64<128, 128, true, false, EPI_RESID>), dim3(blocks), dim3(256), 0, s, run);
     else
       return hipErrorInvalidValue;
   } else if (BM == 128 && BN == 128) e = launch_f64_epi<128, 128>(run, blocks, s);
@@ -530,21 +533,56 @@ hipError_t copy_convert(const void* src, int s_dt, int64_t lds, void* dst, int d
   return hipGetLastError();
 }
 
-__global__ void k_check_sym_finite(const void* A, int dt, int64_t lda, int64_t n, int* flag) {
+__global__ void k_check_sym_finite(const void* A, int dt, int64_t lda, int64_t n, int sym, int* flag) {
   const int64_t total = n * n;
   int bad = 0;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = e / n, j = e % n;
     const double v = load_any(A, dt, i * lda + j);
-    if (!isfinite(v) || v != load_any(A, dt, j * lda + i)) bad = 1;
+    if (!isfinite(v) || (sym && v != load_any(A, dt, j * lda + i))) bad = 1;
   }
   if (bad) atomicOr(flag, 1);
 }
 
-hipError_t check_sym_finite(const void* A, int dt, int64_t lda, int64_t n, int* flag, hipStream_t s) {
+hipError_t check_sym_finite(const void* A, int dt, int64_t lda, int64_t n, int* flag, hipStream_t s, bool sym) {
   const int64_t total = n * n;
   hipLaunchKernelGGL(k_check_sym_finite, dim3((unsigned)std::min<int64_t>(ceil_div(total, 256), 8192)), dim3(256), 0,
-                     s, A, dt, lda, n, flag);
+                     s, A, dt, lda, n, sym ? 1 : 0, flag);
+  return hipGetLastError();
+}
+
+// out = a X + b Y elementwise on column-major rows x cols panels with leading dimension ld.
+__global__ void k_panel_axpby(const void* X, int xdt, double a, const void* Y, int ydt, double b, void* out, int odt,
+                              int64_t rows, int64_t cols, int64_t ld) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t idx = (e / rows) * ld + e % rows;
+    store_any(out, odt, idx, a * load_any(X, xdt, idx) + b * load_any(Y, ydt, idx));
+  }
+}
+
+hipError_t panel_axpby(const void* X, int xdt, double a, const void* Y, int ydt, double b, void* out, int odt,
+                       int64_t rows, int64_t cols, int64_t ld, hipStream_t s) {
+  const int64_t total = rows * cols;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_panel_axpby, dim3((unsigned)std::min<int64_t>(ceil_div(total, 256), 8192)), dim3(256), 0, s, X,
+                     xdt, a, Y, ydt, b, out, odt, rows, cols, ld);
+  return hipGetLastError();
+}
+
+// Dense coordinate sketch: S[i + j*ld] = (j < q && i == C[j]) for i < ld, j < qp.
+__global__ void k_coord_dense(const int32_t* C, int q, void* S, int dt, int64_t ld, int64_t qp) {
+  const int64_t total = ld * qp;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = e / ld, i = e % ld;
+    store_any(S, dt, e, (j < q && i == (int64_t)C[j]) ? 1.0 : 0.0);
+  }
+}
+
+hipError_t coord_dense(const int32_t* C, int q, void* S, int dt, int64_t ld, int64_t qp, hipStream_t s) {
+  const int64_t total = ld * qp;
+  hipLaunchKernelGGL(k_coord_dense, dim3((unsigned)std::min<int64_t>(ceil_div(total, 256), 8192)), dim3(256), 0, s, C,
+                     q, S, dt, ld, qp);
   return hipGetLastError();
 }
 

@@ -144,7 +144,12 @@ hipError_t set_identity(void* X, int dt, int64_t ld, int64_t n, hipStream_t s);
 // Copy (with conversion) an n x n row-major matrix between element types.
 hipError_t copy_convert(const void* src, int s_dt, int64_t lds, void* dst, int d_dt, int64_t ldd,
                         int64_t rows, int64_t cols, hipStream_t s);
-// 1 if any of the n x n entries is non-finite or A[i][j] != A[j][i] (exact), accumulated into *flag.
-hipError_t check_sym_finite(const void* A, int dt, int64_t lda, int64_t n, int* flag, hipStream_t s);
+// 1 if any of the n x n entries is non-finite or (sym) A[i][j] != A[j][i] (exact), accumulated into *flag.
+hipError_t check_sym_finite(const void* A, int dt, int64_t lda, int64_t n, int* flag, hipStream_t s, bool sym = true);
+// out = a X + b Y on column-major rows x cols panels (leading dimension ld), any element types.
+hipError_t panel_axpby(const void* X, int xdt, double a, const void* Y, int ydt, double b, void* out, int odt,
+                       int64_t rows, int64_t cols, int64_t ld, hipStream_t s);
+// Dense ld x qp column-major coordinate sketch from the indices C (q of them): ones at (C_j, j).
+hipError_t coord_dense(const int32_t* C, int q, void* S, int dt, int64_t ld, int64_t qp, hipStream_t s);
 
 }  // namespace rb
