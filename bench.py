@@ -37,8 +37,15 @@ def alg_flops(n, q, variant, sketch):
     fixed/coord: X Y (2 n^2 q) and the row/column update (4 n q), H, G^-1 H, R = G^-1 W'^T
     adaptive/gauss: L S~, A S, L^T Y, rank-q update of L (2 n^2 q each) + 4 panel products (2 n q^2)
     adaptive/coord: A S, L^T Y, update (2 n^2 q each) + 2 panel products
+    psb: as fixed/gauss plus S^T Y (2 n q^2); coordinates applied as dense 0/1 matrices
+    aip, kaczmarz: P = A S (or A^T S), X^T P, rank-q update of all of X (2 n^2 q each),
+                   G and U (2 n q^2 each)
     """
     n2q, nq2 = 2.0 * n * n * q, 2.0 * n * q * q
+    if variant == "psb":
+        return 3 * n2q + 5 * nq2
+    if variant in ("aip", "kaczmarz"):
+        return 3 * n2q + 2 * nq2
     if variant == "fixed":
         return 3 * n2q + 4 * nq2 if sketch == "gauss" else n2q + 2 * nq2 + 4.0 * n * q
     return 4 * n2q + 4 * nq2 if sketch == "gauss" else 3 * n2q + 2 * nq2
@@ -48,21 +55,24 @@ def phase_roofline(name, n, q, variant, sketch, precision="mixed"):
     """(bound, algorithmic bytes per launch, unit) of one n x n product kernel.
 
     Bytes count each operand once at its stored width (4 B in mixed mode, 8 B in FP64):
-      AS, XY, LS, LtY (tall-skinny, M(n x n) * P(n x q)): read M once, read P, write
-                       the n x q result                             -> e n^2 + 2 e n q
-      update (fixed):  read the lower triangle of X, write all of X, read the two
+      AS, XY, LS, LtY, XtP (tall-skinny, M(n x n) * P(n x q)): read M once, read P,
+                       write the n x q result                       -> e n^2 + 2 e n q
+      update (fixed, PSB): read the lower triangle of X, write all of X, read the two
                        n x 2q bf16 hi/lo panel pairs                -> 1.5 e n^2 + 16 n q
-      update (adaptive): read and write L, read the panels          -> 2 e n^2 + 8 n q
+      update (adaptive, AIP, Kaczmarz): read and write L (or X), read the panels
+                                                                    -> 2 e n^2 + 8 n q
     Their intensity (2 n^2 q algorithmic flops over these bytes) is below the bf16
     ridge point (2500 TFLOP/s / 8 TB/s = 312 flop/B) for q <= 256, so the roofline
     that bounds them is HBM bandwidth.
     """
     e = 4.0 if precision == "mixed" else 8.0
     nn, nq = float(n) * n, float(n) * q
-    if name in ("AS", "XY", "LS", "LtY"):
+    if name in ("AS", "XY", "LS", "LtY", "XtP"):
         return "hbm", e * nn + 2 * e * nq, "GB/s"
     if name == "update":
-        return ("hbm", 1.5 * e * nn + 16 * nq, "GB/s") if variant == "fixed" else ("hbm", 2 * e * nn + 8 * nq, "GB/s")
+        if variant in ("fixed", "psb"):
+            return "hbm", 1.5 * e * nn + 16 * nq, "GB/s"
+        return "hbm", 2 * e * nn + 8 * nq, "GB/s"
     return None
 
 
@@ -219,6 +229,60 @@ def time_to_tolerance(A_dev, q, seed, tol, max_iters, torch, rbfgs):
     return out
 
 
+def live_roofline(live, n, q, variant, sketch, traffic=None):
+    """Roofline object of the dominant n x n product kernel (largest total live time)."""
+    products = {k: v for k, v in live.items() if phase_roofline(k, n, q, variant, sketch)}
+    dominant = max(products, key=lambda k: products[k][0], default=None)
+    if not dominant:
+        return None
+    bound, units, unit = phase_roofline(dominant, n, q, variant, sketch)
+    avg_s = products[dominant][0] / products[dominant][1] / 1e3
+    achieved = units / avg_s / 1e9
+    tr = traffic(dominant) if traffic else None
+    return {"bound": bound, "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": unit, "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None if tr is None else round(tr),
+            "launches": products[dominant][1], "avg_ms": round(avg_s * 1e3, 4), "alg_bytes_per_launch": units}
+
+
+def variants_section(A_dev, A32, q, seed, sketch, warmup, steps, torch, rbfgs):
+    """PSB, AIP and simultaneous randomized Kaczmarz on the same matrix (the ridge Hessian
+    is symmetric positive definite, so all three apply): mixed iters/s with the dominant
+    kernel's live roofline, the FP64 oracle timed on one iteration beside it, and the
+    one-iteration parity of the GPU iterate (mixed and FP64) against that oracle step."""
+    import numpy as np
+    from oracle import sketch as sk, variants as V
+    n = A32.shape[0]
+    A64 = np.asarray(A32, dtype=np.float64)
+    S0 = sk.sketch(seed, 0, n, q, "cols" if sketch == "coord" else "gauss")
+    out = {}
+    for v in ("psb", "aip", "kaczmarz"):
+        sv, dtv, live = timed_steps(rbfgs.Solver, A_dev, q, seed, sketch, v, "mixed", warmup, steps, torch,
+                                    events=True)
+        sv.close()
+        ips = steps / dtv
+        t0 = time.perf_counter()
+        Xo = V.STEPS[v](np.eye(n), A64, S0)
+        t_or = time.perf_counter() - t0
+        par = {}
+        for prec in ("mixed", "fp64"):
+            Ause = A_dev if prec == "mixed" else A_dev.to(torch.float64)
+            with rbfgs.Solver(Ause, q, seed, sketch=sketch, variant=v, precision=prec) as s:
+                s.step(1)
+                Xg = s.x().cpu().numpy()
+            par[prec] = float(np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo))
+            del Xg
+        del Xo
+        flops = alg_flops(n, q, v, sketch)
+        out[v] = {"value": round(ips, 3), "unit": "iters/s", "ms_per_step": round(dtv / steps * 1e3, 4),
+                  "steps": steps, "tflops_effective": round(flops * ips / 1e12, 3),
+                  "roofline": live_roofline(live, n, q, v, sketch),
+                  "products_ms_timed_region": {k: round(x[0] / max(x[1], 1), 4) for k, x in live.items()},
+                  "cpu_oracle": {"value": round(1.0 / t_or, 4), "unit": "iters/s",
+                                 "sample": f"1 FP64 oracle iteration from X_0 = I (n={n}, q={q})"},
+                  "parity_1_step_rel_fro_err": par}
+    return out
+
+
 def cpu_baseline(A32, q, seed, sketch, variant, steps):
     """The FP64 oracle on the host: `steps` iterations from X_0 = I (or L_0 = I)."""
     import numpy as np
@@ -254,6 +318,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=8)
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--variant-steps", type=int, default=20,
+                    help="timed iterations of each of PSB, AIP and Kaczmarz (0: skip them)")
     ap.add_argument("--ttt-iters", type=int, default=4000,
                     help="iteration cap of the AdaRBFGS time-to-tolerance runs (0: skip them)")
     ap.add_argument("--serve-jobs", type=int, default=64, help="serving trace length (0: skip serving)")
@@ -287,18 +353,8 @@ def main():
                                     args.warmup, args.steps, torch, events=True)
     ips = args.steps / dt
     flops = alg_flops(n, q, args.variant, args.sketch)
-    products = {k: v for k, v in live.items() if phase_roofline(k, n, q, args.variant, args.sketch)}
-    dominant = max(products, key=lambda k: products[k][0], default=None)
-    roof = None
-    if dominant:
-        bound, units, unit = phase_roofline(dominant, n, q, args.variant, args.sketch)
-        avg_s = products[dominant][0] / products[dominant][1] / 1e3
-        achieved = units / avg_s / 1e9
-        traffic = counter_traffic(dominant) if args.sketch == "gauss" and args.variant == "fixed" else None
-        roof = {"bound": bound, "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": unit, "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if traffic is None else round(traffic),
-                "launches": products[dominant][1], "avg_ms": round(avg_s * 1e3, 4), "alg_bytes_per_launch": units}
+    roof = live_roofline(live, n, q, args.variant, args.sketch,
+                         counter_traffic if args.sketch == "gauss" and args.variant == "fixed" else None)
     live_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in live.items()}
 
     # ---- all phases timed in a separate window (informational)
@@ -315,6 +371,10 @@ def main():
     ips64 = args.fp64_steps / dt64
     s64.close()
     del A64_dev
+
+    # ---- the other instances of the family (PSB, AIP, Kaczmarz) on the same matrix
+    variants = (variants_section(A_dev, A32, q, args.seed, args.sketch, args.warmup, args.variant_steps, torch, rbfgs)
+                if args.variant_steps > 0 else None)
 
     # ---- time to tolerance, AdaRBFGS mixed vs FP64
     ttt = time_to_tolerance(A_dev, q, args.seed, 1e-3, args.ttt_iters, torch, rbfgs) if args.ttt_iters > 0 else None
@@ -363,6 +423,7 @@ def main():
         "roofline": roof,
         "products_ms_timed_region": live_ms,
         "phases_ms": {k: round(v["avg_ms"], 4) for k, v in phases.items()},
+        "variants": variants,
         "time_to_tolerance_ada": ttt,
         "serving": serve,
         "cpu_baseline": cpu,

@@ -85,7 +85,7 @@ struct rbfgs_ctx {
   hipEvent_t ev_xy = nullptr;  // main lane: X Y of the current iteration enqueued before it
   // main-lane buffers
   void* A = nullptr;
-  void* X = nullptr;        // X (fixed) or L (adaptive)
+  void* X = nullptr;        // X (fixed, PSB), L (adaptive), X^T (AIP, Kaczmarz: the products read it k-contiguous)
   int32_t* pos = nullptr;   // inverse map of the coordinate set (-1 elsewhere)
   void* Sa = nullptr;       // adaptive: S = L S~
   void* Y = nullptr;        // adaptive: Y = A S
@@ -539,7 +539,9 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
 // U = S G^-1, G = S^T P; simultaneous randomized Kaczmarz, eq. badbroyadj: P = A^T S,
 // U = P G^-1, G = P^T P; P, G and U from the slot):
 //   C = X^T P,  R = S - C  (R^T = S^T (I - A X), the residual sketch),  X+ = X + U R^T
-// on every tile of X (the iterates are not symmetric).  The estimator is ||R||_F^2.
+// on every tile of X (the iterates are not symmetric).  The context stores Z = X^T, so
+// that C = Z P reads Z k-contiguous like X Y, and the update is Z+ = Z + R U^T.  The
+// estimator is ||R||_F^2.
 template <class F, class G>
 void main_row(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
   const Lane& L = ctx->main;
@@ -550,7 +552,7 @@ void main_row(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
   const bool fused_est = ctx->mixed && (size_t)reduce_blocks_f32(shape) <= L.red_count;
   {
     Phase ph(ctx, L, "XtP", true);
-    nn_times_panel(ctx, L, ctx->X, true, S.Y, mdt, ctx->V, 2, 2, 1, ph.mark(),
+    nn_times_panel(ctx, L, ctx->X, false, S.Y, mdt, ctx->V, 2, 2, 1, ph.mark(),
                    fused_est ? (const __bf16*)S.Sk : nullptr);
   }
   after_xy();
@@ -571,14 +573,14 @@ void main_row(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
     if (ctx->mixed)
       HIPCHK(pack_split2((const float*)ctx->W, np, np, qp, ctx->planes, ctx->planes + np * qp, qp, 0, L.s));
   }
-  Phase ph(ctx, L, "update", true);  // X += U R^T
+  Phase ph(ctx, L, "update", true);  // Z = X^T += R U^T
   if (ctx->mixed) {
     const int64_t ldp = 3 * qp;
     MixedGemm mg;
     GemmArgs& g = mg.g;
     g.M = np; g.N = np; g.K = qp;
-    g.A = S.planes; g.lda = ldp; g.a_plane = np * ldp;
-    g.B = ctx->planes; g.ldb = qp; g.b_plane = np * qp;
+    g.A = ctx->planes; g.lda = qp; g.a_plane = np * qp;
+    g.B = S.planes; g.ldb = ldp; g.b_plane = np * ldp;
     g.epi = EPI_ADDROW; g.C = ctx->X; g.ldc = np; g.c2 = 1.0;
     g.tiles = ctx->tiles; g.ntiles = ctx->ntiles;
     mg.a_kind = OK_BF16_KC; mg.b_kind = OK_BF16_KC; mg.na = 2; mg.nb = 2; mg.pmax = 1;
@@ -586,8 +588,8 @@ void main_row(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
   } else {
     GemmArgs g;
     g.M = np; g.N = np; g.K = qp;
-    g.A = S.U; g.lda = np; g.a_dt = DT_F64; g.a_kc = false;
-    g.B = ctx->W; g.ldb = np; g.b_dt = DT_F64; g.b_kc = false;
+    g.A = ctx->W; g.lda = np; g.a_dt = DT_F64; g.a_kc = false;
+    g.B = S.U; g.ldb = np; g.b_dt = DT_F64; g.b_kc = false;
     g.epi = EPI_ADDROW; g.C = ctx->X; g.ldc = np; g.c_dt = DT_F64; g.c2 = 1.0;
     g.tiles = ctx->tiles; g.ntiles = ctx->ntiles;
     f64_gemm(ctx, L, g);
@@ -762,8 +764,8 @@ double exact_residual(rbfgs_ctx* ctx) {
     HIPCHK(gemm_f64(b, nullptr, L.s));
     g.A = tmp; g.a_dt = DT_F64;
   }
-  // X symmetric (fixed, PSB): either orientation; for L: Bop(k,j) = L[j][k]; row variants: Bop(k,j) = X[k][j]
-  g.B = ctx->X; g.ldb = np; g.b_dt = ctx->mdt; g.b_kc = !ctx->rowv;
+  // Bop(k,j) = M[j][k]: X symmetric (fixed, PSB); L (adaptive, I - (A L) L^T); Z = X^T (row variants)
+  g.B = ctx->X; g.ldb = np; g.b_dt = ctx->mdt; g.b_kc = true;
   g.epi = EPI_RESID; g.red = L.red; g.nvalid = ctx->n;
   const int64_t blocks = gemm_f64_blocks(g);
   HIPCHK(gemm_f64(g, nullptr, L.s));
@@ -1064,6 +1066,14 @@ rbfgs_status rbfgs_get_x(rbfgs_ctx* ctx, void* X, int32_t x_dtype, int64_t ldx, 
   try {
     rbfgs_status st = read_status(ctx);
     if (st != RBFGS_OK) return st;
+    if (ctx->rowv) {  // the context holds X^T
+      void* tmp = nullptr;
+      HIPCHK(hipMalloc(&tmp, (size_t)ctx->np * ctx->np * dt_size(ctx->mdt)));
+      HIPCHK(copy_transpose(ctx->X, ctx->mdt, ctx->np, tmp, ctx->mdt, ctx->np, ctx->np, ctx->np, ctx->main.s));
+      st = copy_out(ctx, tmp, ctx->mdt, ctx->np, X, x_dtype, ldx, on_device);
+      HIPCHK(hipFree(tmp));
+      return st;
+    }
     if (!ctx->ada) return copy_out(ctx, ctx->X, ctx->mdt, ctx->np, X, x_dtype, ldx, on_device);
     const int64_t np = ctx->np;
     void* tmp = nullptr;
@@ -1110,7 +1120,8 @@ rbfgs_status rbfgs_set_state(rbfgs_ctx* ctx, const void* M, int32_t m_dtype, int
       HIPCHK(hipMemcpyAsync(staging, M, (size_t)n * ldm * dt_size(sdt), hipMemcpyHostToDevice, ctx->main.s));
       src = staging;
     }
-    HIPCHK(copy_convert(src, sdt, ldm, ctx->X, ctx->mdt, ctx->np, n, n, ctx->main.s));
+    if (ctx->rowv) HIPCHK(copy_transpose(src, sdt, ldm, ctx->X, ctx->mdt, ctx->np, n, n, ctx->main.s));  // X^T
+    else HIPCHK(copy_convert(src, sdt, ldm, ctx->X, ctx->mdt, ctx->np, n, n, ctx->main.s));
     HIPCHK(hipMemsetAsync(ctx->status, 0, sizeof(int), ctx->main.s));
     HIPCHK(hipStreamSynchronize(ctx->main.s));
     if (staging) HIPCHK(hipFree(staging));
@@ -1141,6 +1152,7 @@ rbfgs_status rbfgs_footprint(const rbfgs_params* params, int64_t* bytes_out) {
   }
   int64_t b = ctx.bytes;
   if (ctx.ada) b += ctx.np * ctx.np * (int64_t)sizeof(double);  // exact residual of L L^T
+  if (ctx.rowv) b += ctx.np * ctx.np * (int64_t)dt_size(ctx.mdt);  // X = Z^T formed for the caller
   *bytes_out = b;
   return RBFGS_OK;
 }

@@ -625,8 +625,7 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
                          dim3(gemm_bf16_blocks(mg)), dim3(512), 0, s, g);
     else
 #endif
-    if (g.epi == EPI_SYMUPD && RB_UPD_KERNEL == 1)
-      return symupd_bf16_dma(g, gemm_bf16_blocks(mg), s);
+    if (RB_UPD_KERNEL == 1) return symupd_bf16_dma(g, gemm_bf16_blocks(mg), s);
     else if (g.epi == EPI_SYMUPD)
       hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, RB_UPD_LDB, EPI_SYMUPD, 1, 32>),
                          dim3(gemm_bf16_blocks(mg)), dim3(256), 0, s, g);

@@ -328,8 +328,6 @@ hipError_t gemm_f64(const GemmArgs& gin, void* partial_ws, hipStream_t s) {
       hipLaunchKernelGGL((k_gemm_f64<128, 128, false, false, EPI_ADDROW>), dim3(blocks), dim3(256), 0, s, run);
     else if (run.epi == EPI_RESID && run.a_kc && run.b_kc)
       hipLaunchKernelGGL((k_gemm_f64<128, 128, true, true, EPI_RESID>), dim3(blocks), dim3(256), 0, s, run);
-    else if (run.epi == EPI_RESID && run.a_kc)  // I - A X for a nonsymmetric X
-      hipLaunchKernelGGL((k_gemm_f64<128, 128, true, false, EPI_RESID>), dim3(blocks), dim3(256), 0, s, run);
     else
       return hipErrorInvalidValue;
   } else if (BM == 128 && BN == 128) e = launch_f64_epi<128, 128>(run, blocks, s);
@@ -567,6 +565,25 @@ hipError_t panel_axpby(const void* X, int xdt, double a, const void* Y, int ydt,
   if (total <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_panel_axpby, dim3((unsigned)std::min<int64_t>(ceil_div(total, 256), 8192)), dim3(256), 0, s, X,
                      xdt, a, Y, ydt, b, out, odt, rows, cols, ld);
+  return hipGetLastError();
+}
+
+// dst[j*ldd + i] = src[i*lds + j] for i < rows, j < cols (with conversion).
+__global__ void k_copy_transpose(const void* src, int s_dt, int64_t lds, void* dst, int d_dt, int64_t ldd,
+                                 int64_t rows, int64_t cols) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / cols, j = e % cols;
+    store_any(dst, d_dt, j * ldd + i, load_any(src, s_dt, i * lds + j));
+  }
+}
+
+hipError_t copy_transpose(const void* src, int s_dt, int64_t lds, void* dst, int d_dt, int64_t ldd, int64_t rows,
+                          int64_t cols, hipStream_t s) {
+  const int64_t total = rows * cols;
+  if (total <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_transpose, dim3((unsigned)std::min<int64_t>(ceil_div(total, 256), 65536)), dim3(256), 0,
+                     s, src, s_dt, lds, dst, d_dt, ldd, rows, cols);
   return hipGetLastError();
 }
 

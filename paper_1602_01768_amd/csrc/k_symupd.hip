@@ -1,6 +1,8 @@
-// Symmetric rank-2q update of the fixed-sketch step on bf16 matrix cores:
-// X += c2 * [U W'] [W' U]^T on the lower 128 x 128 tiles of X, each tile also
-// written to its mirrored position (the symmetric form of the update, Eq. (qunac)).
+// Square updates on bf16 matrix cores.  Symmetric rank-2q update of the fixed-sketch
+// step: X += c2 * [U W'] [W' U]^T on the lower 128 x 128 tiles of X, each tile also
+// written to its mirrored position (the symmetric form of the update, eq. (qunac));
+// FULL: C += c2 * A B^T on every tile (the rank-q updates of AdaRBFGS, eq. (Cholimprov),
+// and of the row variants of Alg. 1).
 //
 // Both operands are pre-split into two bf16 pieces (hi, lo); the product keeps the
 // piece products hi*hi + hi*lo + lo*hi with FP32 accumulation.  Unlike the general
@@ -62,7 +64,7 @@ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) |
 // ... and for "no LDS operation outstanding" (lgkmcnt 0, vmcnt and expcnt at their maxima)
 constexpr int lgkm0_imm() { return 15 | (3 << 14) | (7 << 4); }
 
-template <int BKS, int NS, int OCC, int WAVES_M, int WAVES_N>
+template <int BKS, int NS, int OCC, int WAVES_M, int WAVES_N, bool FULL>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) __attribute__((amdgpu_waves_per_eu(OCC * WAVES_M * WAVES_N / 4, 8)))
 void k_symupd_dma(GemmArgs g) {
   constexpr int BM = 128, NP = 2, NW = WAVES_M * WAVES_N;
@@ -87,17 +89,20 @@ void k_symupd_dma(GemmArgs g) {
 
   // tile of this workgroup: each XCD (blockIdx % 8) takes a contiguous run of the order
   const int64_t T = g.M / BM;
-  const int64_t NTT = g.tiles ? g.ntiles : T * (T + 1) / 2;
+  const int64_t NTT = g.tiles ? g.ntiles : (FULL ? T * T : T * (T + 1) / 2);
   const int64_t per = (NTT + 7) / 8, t = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
   if (t >= NTT) return;
   int64_t mt, nt;
   if (g.tiles) {
     mt = g.tiles[t].x;
     nt = g.tiles[t].y;
+  } else if (FULL) {
+    mt = t / T;
+    nt = t % T;
   } else {
     tri_index(t, mt, nt);
   }
-  const bool diag = mt == nt;
+  const bool diag = !FULL && mt == nt;
   const int64_t m0 = mt * BM, n0 = nt * BM;
 
   // Sources of this wave's D loads per stage: load d covers stage bytes
@@ -288,10 +293,12 @@ void k_symupd_dma(GemmArgs g) {
     if (!diag) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) Xd[(a * 32 + (r >> 2) * 8 + lr + (r & 3)) * ld + b * 32 + lc] = nvs[r];
+      if constexpr (!FULL) {
 #pragma unroll
-      for (int q4 = 0; q4 < 4; ++q4)
-        *(float4*)(Xm + (b * 32 + lc) * ld + a * 32 + 8 * q4 + lr) =
-            make_float4(nvs[4 * q4], nvs[4 * q4 + 1], nvs[4 * q4 + 2], nvs[4 * q4 + 3]);
+        for (int q4 = 0; q4 < 4; ++q4)
+          *(float4*)(Xm + (b * 32 + lc) * ld + a * 32 + 8 * q4 + lr) =
+              make_float4(nvs[4 * q4], nvs[4 * q4 + 1], nvs[4 * q4 + 2], nvs[4 * q4 + 3]);
+      }
     } else {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
@@ -311,8 +318,12 @@ hipError_t symupd_bf16_dma(const GemmArgs& g, int64_t blocks, hipStream_t s) {
       g.b_plane % 8 || g.ldc % 4)
     return hipErrorInvalidValue;
   constexpr int wv[2] = {RB_UPD_WAVES};
-  hipLaunchKernelGGL((k_symupd_dma<RB_UPD_BKS, RB_UPD_NS, RB_UPD_OCC, RB_UPD_WAVES>), dim3((unsigned)blocks),
-                     dim3(64 * wv[0] * wv[1]), 0, s, g);
+  if (g.epi == EPI_ADDROW)
+    hipLaunchKernelGGL((k_symupd_dma<RB_UPD_BKS, RB_UPD_NS, RB_UPD_OCC, RB_UPD_WAVES, true>), dim3((unsigned)blocks),
+                       dim3(64 * wv[0] * wv[1]), 0, s, g);
+  else
+    hipLaunchKernelGGL((k_symupd_dma<RB_UPD_BKS, RB_UPD_NS, RB_UPD_OCC, RB_UPD_WAVES, false>), dim3((unsigned)blocks),
+                       dim3(64 * wv[0] * wv[1]), 0, s, g);
   return hipGetLastError();
 }
 

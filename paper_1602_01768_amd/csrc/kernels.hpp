@@ -87,8 +87,9 @@ int bf16_square_tile(int64_t M, int epi);
 // Sum the FP32 split-K partials of a bf16 product (COLSTORE epilogue of g): C = c2 * sum
 // + c0 * B0 (FP32) + c1 * B1 (FP32 or bf16, b1_dt), column-major; C is FP32 or FP64 (c_dt).
 hipError_t reduce_partials_f32(const GemmArgs& g, const float* partial, hipStream_t s);
-// Square symmetric update (EPI_SYMUPD, 2 x 2 bf16 pieces) with operands loaded
-// straight into LDS; blocks as gemm_bf16_blocks gives for 128 x 128 tiles.
+// Square update with operands loaded straight into LDS, 2 x 2 bf16 pieces: EPI_SYMUPD
+// (lower tiles, mirrored) or EPI_ADDROW (every tile); blocks as gemm_bf16_blocks gives
+// for 128 x 128 tiles.
 hipError_t symupd_bf16_dma(const GemmArgs& g, int64_t blocks, hipStream_t s);
 int64_t reduce_blocks_f32(const GemmArgs& g);
 int64_t gemm_bf16_blocks(const MixedGemm& mg);
@@ -149,6 +150,9 @@ hipError_t check_sym_finite(const void* A, int dt, int64_t lda, int64_t n, int* 
 // out = a X + b Y on column-major rows x cols panels (leading dimension ld), any element types.
 hipError_t panel_axpby(const void* X, int xdt, double a, const void* Y, int ydt, double b, void* out, int odt,
                        int64_t rows, int64_t cols, int64_t ld, hipStream_t s);
+// Transposed copy with conversion: dst[j*ldd + i] = src[i*lds + j], i < rows, j < cols.
+hipError_t copy_transpose(const void* src, int s_dt, int64_t lds, void* dst, int d_dt, int64_t ldd, int64_t rows,
+                          int64_t cols, hipStream_t s);
 // Dense ld x qp column-major coordinate sketch from the indices C (q of them): ones at (C_j, j).
 hipError_t coord_dense(const int32_t* C, int q, void* S, int dt, int64_t ld, int64_t qp, hipStream_t s);
 
