@@ -15,10 +15,13 @@ Modules
   variants simultaneous randomized Kaczmarz (eq. badbroyadj), AIP (eq. BFGSas)
            and randomized PSB (eq. Xupdatesym with W = I), and the residual
            estimator of the row variants.
+  comparison  Newton-Schulz (eq. Newton-Schulz) and MR (eq. MRiter) with the starting
+           points of Sec. 10, and the power-method norm estimate they use.
   theory   closed-form quantities used by the pins: the rate rho of Thm 6.2 /
            eq. rhoequiv, E[Z] for discrete sketches (Prop. 7.1), brute-force
            projections (eq. NF, eq. NFsym) by a dense KKT solve.
 
 Parity status: every function here is pinned by a `-m "not gpu"` test against
-something other than itself (see tests/test_oracle_pins.py, tests/test_oracle_variants.py).
+something other than itself (see tests/test_oracle_pins.py, tests/test_oracle_variants.py,
+tests/test_oracle_comparison.py).
 """
