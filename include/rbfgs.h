@@ -26,6 +26,12 @@
  *   RBFGS_KACZMARZ  simultaneous randomized Kaczmarz, Sec. 8.2 eq. (badbroyadj):
  *                   Alg. 1 with W = I, X+ = X + A^T S (S^T A A^T S)^-1 S^T (I - A X).
  *                   Any invertible A (row-major, not required to be symmetric).
+ * The two comparison methods of Sec. 10 (FP64 only; sketch and q unused):
+ *   RBFGS_NEWTON_SCHULZ  eq. (Newton-Schulz), X+ = 2X - X A X, from X_0 = 0.99 A^T / rho^2(A)
+ *                   with rho(A) ~ ||A||_2 by 100 power-method steps from the all-ones vector;
+ *   RBFGS_MR        eq. (MRiter), X+ = X + alpha X R, R = I - A X,
+ *                   alpha = Tr(R^T A X R) / Tr((A X R)^T A X R), from X_0 = (Tr A / Tr(A A^T)) I.
+ *   Their estimator is the exact ||I - A X_k||_F^2 of the iterate each step starts from.
  * For PSB, AIP and Kaczmarz a coordinate sketch is applied as the dense 0/1 matrix,
  * and the estimator of AIP and Kaczmarz is ||S^T (I - A X)||_F^2 scaled as for the
  * fixed method (it estimates ||I - A X||_F^2).
@@ -94,7 +100,9 @@ typedef enum {
   RBFGS_ADAPTIVE = 1,
   RBFGS_PSB = 2,
   RBFGS_AIP = 3,
-  RBFGS_KACZMARZ = 4
+  RBFGS_KACZMARZ = 4,
+  RBFGS_NEWTON_SCHULZ = 5,
+  RBFGS_MR = 6
 } rbfgs_variant;
 typedef enum { RBFGS_FP64 = 0, RBFGS_MIXED = 1 } rbfgs_precision;
 typedef enum { RBFGS_F32 = 0, RBFGS_F64 = 1 } rbfgs_dtype;

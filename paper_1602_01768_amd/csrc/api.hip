@@ -29,6 +29,9 @@ using namespace rb;
 #ifndef RB_BF16_Q
 #define RB_BF16_Q 1  // q-sized products of the mixed fixed Gaussian path in split bf16
 #endif
+#ifndef RB_POWER_STEPS
+#define RB_POWER_STEPS 100  // power-method steps of the Newton-Schulz starting point
+#endif
 #ifndef RB_SUPER_TILES
 #define RB_SUPER_TILES 4  // super-tile edge of the n x n update order (4 x 4 tiles share panels in L2)
 #endif
@@ -74,6 +77,10 @@ struct rbfgs_ctx {
   // these are used as dense 0/1 matrices (dcoord), `coord` marks the gather paths of
   // fixed RBFGS and AdaRBFGS only
   bool psb = false, rowv = false, kacz = false, dcoord = false;
+  // comparison methods of Sec. 10 (FP64 only): Newton-Schulz and MR, n^3 products per step
+  bool ns = false, mr = false;
+  double *T2 = nullptr, *P2 = nullptr, *Q2 = nullptr;  // n x n FP64 work matrices
+  double* scal = nullptr;                              // device scalars (sigma, ratios)
   int mdt = DT_F64;  // element type of A, X/L and the n x q panels
   int device = 0;
   int64_t k = 0;
@@ -664,12 +671,54 @@ void main_adaptive(rbfgs_ctx* ctx, Slot& S) {
   }
 }
 
+// One step of a comparison method of Sec. 10 on the main lane (FP64, n^3 products):
+//   Newton-Schulz, eq. (Newton-Schulz): T = A X, X+ = 2 X - X T;
+//   MR, eq. (MRiter): R = I - A X, P = X R, Q = A P, X+ = X + (<R, Q> / <Q, Q>) P,
+//   where <R, Q> = Tr(R^T A X R) and <Q, Q> = Tr((A X R)^T A X R).
+// The estimator is the exact ||I - A X_k||_F^2 of the iterate the step starts from.
+void main_comparison(rbfgs_ctx* ctx) {
+  const Lane& L = ctx->main;
+  const int64_t np = ctx->np, n = ctx->n;
+  auto square = [&](const void* Aop, const void* Bop, double* out, const char* name) {
+    Phase ph(ctx, L, name, true);
+    GemmArgs g;
+    g.M = np; g.N = np; g.K = np;
+    g.A = Aop; g.lda = np; g.a_dt = DT_F64; g.a_kc = true;
+    g.B = Bop; g.ldb = np; g.b_dt = DT_F64; g.b_kc = false;
+    g.epi = EPI_ROWSTORE; g.C = out; g.ldc = np; g.c_dt = DT_F64; g.c2 = 1.0;
+    f64_gemm(ctx, L, g);
+  };
+  const int nb = sums_blocks(n);
+  square(ctx->A, ctx->X, ctx->T2, "AX");  // T = A X
+  if (ctx->ns) {
+    HIPCHK(mat_sums(ctx->T2, nullptr, np, n, 0, L.red, L.s));
+    HIPCHK(reduce_sum_scaled(L.red, nb, ctx->est, 1.0, ctx->status, L.s));
+    square(ctx->X, ctx->T2, ctx->P2, "XT");  // X T
+    HIPCHK(panel_axpby(ctx->X, DT_F64, 2.0, ctx->P2, DT_F64, -1.0, ctx->P2, DT_F64, np, np, np, L.s));
+    double* xn = ctx->P2;  // the new iterate; the old buffer is next step's work matrix
+    ctx->P2 = (double*)ctx->X;
+    ctx->X = xn;
+    return;
+  }
+  HIPCHK(mat_sums(ctx->T2, nullptr, np, n, 1, L.red, L.s));  // R = I - A X in place
+  HIPCHK(reduce_sum_scaled(L.red, nb, ctx->est, 1.0, ctx->status, L.s));
+  square(ctx->X, ctx->T2, ctx->P2, "XR");  // P = X R
+  square(ctx->A, ctx->P2, ctx->Q2, "AP");  // Q = A P
+  HIPCHK(mat_sums(ctx->T2, ctx->Q2, np, n, 2, L.red, L.s));
+  HIPCHK(reduce_pairs(L.red, nb, ctx->scal, L.s));
+  HIPCHK(axpy_ratio((double*)ctx->X, ctx->P2, np * np, ctx->scal, L.s));
+}
+
 // Enqueue iterations k .. k+nsteps-1: the side lane runs up to two iterations ahead,
 // the inverse lane one.  For the fixed method the side lane's products of iteration
 // k+2 start once the main lane's X Y of iteration k is done, so that A S shares the
 // GPU with the main lane's small q-sized kernels rather than with X Y.
 void enqueue_steps(rbfgs_ctx* ctx, int64_t nsteps) {
   if (nsteps <= 0) return;
+  if (ctx->ns || ctx->mr) {
+    for (int64_t i = 0; i < nsteps; ++i, ++ctx->k) main_comparison(ctx);
+    return;
+  }
   constexpr int NS = rbfgs_ctx::NSLOT;
   HIPCHK(hipEventRecord(ctx->ev_begin, ctx->main.s));
   HIPCHK(hipStreamWaitEvent(ctx->side.s, ctx->ev_begin, 0));
@@ -845,6 +894,8 @@ void set_params(rbfgs_ctx* ctx, const rbfgs_params& p) {
   ctx->psb = p.variant == RBFGS_PSB;
   ctx->kacz = p.variant == RBFGS_KACZMARZ;
   ctx->rowv = ctx->kacz || p.variant == RBFGS_AIP;
+  ctx->ns = p.variant == RBFGS_NEWTON_SCHULZ;
+  ctx->mr = p.variant == RBFGS_MR;
   ctx->dcoord = p.sketch == RBFGS_SKETCH_COORD && (ctx->psb || ctx->rowv);
   ctx->coord = p.sketch == RBFGS_SKETCH_COORD && !ctx->dcoord;
   ctx->mdt = ctx->mixed ? DT_F32 : DT_F64;
@@ -874,6 +925,12 @@ void allocate(rbfgs_ctx* ctx) {
     if (ctx->mixed) ctx->planes = (__bf16*)dalloc(ctx, (size_t)4 * np * qp * sizeof(__bf16));
   }
   if (ctx->rowv && ctx->mixed) ctx->planes = (__bf16*)dalloc(ctx, (size_t)2 * np * qp * sizeof(__bf16));
+  if (ctx->ns || ctx->mr) {
+    ctx->T2 = (double*)dalloc(ctx, (size_t)np * np * sizeof(double));
+    ctx->P2 = (double*)dalloc(ctx, (size_t)np * np * sizeof(double));
+    if (ctx->mr) ctx->Q2 = (double*)dalloc(ctx, (size_t)np * np * sizeof(double));
+  }
+  ctx->scal = (double*)dalloc(ctx, 8 * sizeof(double));
   if (!ctx->ada && ctx->coord) ctx->R = dalloc(ctx, qp * np * es);
   const size_t qq = (size_t)qp * qp * sizeof(double);
   ctx->G = (double*)dalloc(ctx, qq);
@@ -912,7 +969,8 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
   const rbfgs_params& p = *params;
   if (p.n < 1 || p.q < 1 || p.q > p.n || p.q > 1024 || lda < p.n || (a_dtype != RBFGS_F32 && a_dtype != RBFGS_F64) ||
       (p.sketch != RBFGS_SKETCH_GAUSS && p.sketch != RBFGS_SKETCH_COORD) ||
-      (p.variant < RBFGS_FIXED || p.variant > RBFGS_KACZMARZ) ||
+      (p.variant < RBFGS_FIXED || p.variant > RBFGS_MR) ||
+      ((p.variant == RBFGS_NEWTON_SCHULZ || p.variant == RBFGS_MR) && p.precision != RBFGS_FP64) ||
       (p.precision != RBFGS_FP64 && p.precision != RBFGS_MIXED) || p.check_every < 0 || p.n > (1ll << 20))
     return RBFGS_E_INVALID_ARG;
   rbfgs_ctx* ctx = new rbfgs_ctx();
@@ -953,7 +1011,18 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
       release(ctx);
       return RBFGS_E_INVALID_ARG;
     }
-    HIPCHK(set_identity(ctx->X, ctx->mdt, np, p.n, ctx->main.s));
+    if (ctx->ns) {  // X_0 = 0.99 A^T / rho^2(A), rho by the power method (Sec. 10)
+      double* v = (double*)ctx->T2;
+      HIPCHK(power_norm((const double*)ctx->A, np, p.n, RB_POWER_STEPS, v, v + np, ctx->scal, ctx->main.s));
+      HIPCHK(ns_start((const double*)ctx->A, np, p.n, ctx->scal, (double*)ctx->X, ctx->main.s));
+      HIPCHK(hipMemsetAsync(ctx->T2, 0, (size_t)2 * np * sizeof(double), ctx->main.s));
+    } else if (ctx->mr) {  // X_0 = (Tr A / Tr(A A^T)) I (Sec. 10)
+      HIPCHK(mat_sums((double*)ctx->A, nullptr, np, p.n, 3, ctx->main.red, ctx->main.s));
+      HIPCHK(reduce_pairs(ctx->main.red, sums_blocks(p.n), ctx->scal, ctx->main.s));
+      HIPCHK(scaled_identity((double*)ctx->X, np, p.n, ctx->scal, ctx->main.s));
+    } else {
+      HIPCHK(set_identity(ctx->X, ctx->mdt, np, p.n, ctx->main.s));
+    }
     const double nanv = NAN;
     HIPCHK(hipMemcpyAsync(ctx->est, &nanv, sizeof(double), hipMemcpyHostToDevice, ctx->main.s));
     HIPCHK(hipStreamSynchronize(ctx->main.s));

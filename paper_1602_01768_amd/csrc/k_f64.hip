@@ -587,6 +587,177 @@ hipError_t copy_transpose(const void* src, int s_dt, int64_t lds, void* dst, int
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- comparison methods
+// Newton-Schulz and MR (Sec. 10) on n x n row-major FP64 matrices with leading dimension ld.
+
+// w = A v, one wave per row.
+__global__ __launch_bounds__(256) void k_gemv_f64(const double* A, int64_t ld, int64_t n, const double* v, double* w) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;  // uniform per wave; no barrier in this kernel
+  double s = 0.0;
+  for (int64_t j = lane; j < n; j += 64) s = fma(A[row * ld + j], v[j], s);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) w[row] = s;
+}
+
+// sigma = ||w||_2, v = w / sigma, *sigma_out = sigma (one workgroup, fixed summation order).
+__global__ __launch_bounds__(1024) void k_normalize(const double* w, int64_t n, double* v, double* sigma_out) {
+  __shared__ double sh[1024];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) s = fma(w[i], w[i], s);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 512; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double sig = sqrt(sh[0]);
+  for (int64_t i = threadIdx.x; i < n; i += 1024) v[i] = w[i] / sig;
+  if (threadIdx.x == 0) *sigma_out = sig;
+}
+
+__global__ void k_fill_f64(double* v, int64_t n, double x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) v[i] = x;
+}
+
+// X = 0.99 A^T / sigma^2 on the n x n block (Sec. 10, the Newton-Schulz start).
+__global__ void k_ns_x0(const double* A, int64_t ld, int64_t n, const double* sigma, double* X) {
+  const double s = *sigma;
+  const int64_t total = n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / n, j = e % n;
+    X[i * ld + j] = (0.99 * A[j * ld + i]) / (s * s);
+  }
+}
+
+// Per-block partial sums over the n x n block of row-major matrices:
+//   mode 0: red[b] = sum (delta_ij - T_ij)^2                       (residual of T = A X)
+//   mode 1: T := I - T in place, red[b] = sum of the new T_ij^2    (R = I - A X)
+//   mode 2: red[2b] = sum T_ij Q_ij, red[2b+1] = sum Q_ij^2          (<R, Q>, <Q, Q>)
+//   mode 3: red[2b] = trace T, red[2b+1] = sum T_ij^2                (Tr A, ||A||_F^2)
+__global__ __launch_bounds__(256) void k_sums(double* T, const double* Q, int64_t ld, int64_t n, int mode, double* red) {
+  __shared__ double s0[256], s1[256];
+  double a = 0.0, b = 0.0;
+  const int64_t total = n * n;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / n, j = e % n, idx = i * ld + j;
+    const double t = T[idx];
+    if (mode == 0) {
+      const double d = (i == j ? 1.0 : 0.0) - t;
+      a = fma(d, d, a);
+    } else if (mode == 1) {
+      const double r = (i == j ? 1.0 : 0.0) - t;
+      T[idx] = r;
+      a = fma(r, r, a);
+    } else if (mode == 2) {
+      const double qv = Q[idx];
+      a = fma(t, qv, a);
+      b = fma(qv, qv, b);
+    } else {
+      if (i == j) a += t;
+      b = fma(t, t, b);
+    }
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      s0[threadIdx.x] += s0[threadIdx.x + st];
+      s1[threadIdx.x] += s1[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (mode <= 1) {
+      red[blockIdx.x] = s0[0];
+    } else {
+      red[2 * blockIdx.x] = s0[0];
+      red[2 * blockIdx.x + 1] = s1[0];
+    }
+  }
+}
+
+// out[0], out[1] = sums of the pairs red[2b], red[2b+1] (one workgroup, fixed order).
+__global__ __launch_bounds__(256) void k_reduce_pairs(const double* red, int nb, double* out) {
+  __shared__ double s0[256], s1[256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) {
+    a += red[2 * i];
+    b += red[2 * i + 1];
+  }
+  s0[threadIdx.x] = a;
+  s1[threadIdx.x] = b;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      s0[threadIdx.x] += s0[threadIdx.x + st];
+      s1[threadIdx.x] += s1[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = s0[0];
+    out[1] = s1[0];
+  }
+}
+
+// X += (sc[0] / sc[1]) P on the whole ld x ld buffer (padding is zero in both).
+__global__ void k_axpy_ratio(double* X, const double* P, int64_t total, const double* sc) {
+  const double a = sc[0] / sc[1];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x)
+    X[e] = fma(a, P[e], X[e]);
+}
+
+// X = (sc[0] / sc[1]) I on the n x n block (Sec. 10, the MR start: Tr A / Tr(A A^T)).
+__global__ void k_scaled_identity(double* X, int64_t ld, int64_t n, const double* sc) {
+  const double c = sc[0] / sc[1];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    X[i * ld + i] = c;
+}
+
+int sums_blocks(int64_t n) { return (int)std::min<int64_t>(ceil_div(n * n, 256), 2048); }
+
+hipError_t power_norm(const double* A, int64_t ld, int64_t n, int steps, double* v, double* w, double* sigma,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)std::min<int64_t>(ceil_div(n, 256), 1024)), dim3(256), 0, s, v, n,
+                     1.0 / sqrt((double)n));
+  for (int i = 0; i < steps; ++i) {
+    hipLaunchKernelGGL(k_gemv_f64, dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, s, A, ld, n, (const double*)v, w);
+    hipLaunchKernelGGL(k_normalize, dim3(1), dim3(1024), 0, s, (const double*)w, n, v, sigma);
+  }
+  return hipGetLastError();
+}
+
+hipError_t ns_start(const double* A, int64_t ld, int64_t n, const double* sigma, double* X, hipStream_t s) {
+  hipLaunchKernelGGL(k_ns_x0, dim3((unsigned)std::min<int64_t>(ceil_div(n * n, 256), 8192)), dim3(256), 0, s, A, ld, n,
+                     sigma, X);
+  return hipGetLastError();
+}
+
+hipError_t mat_sums(double* T, const double* Q, int64_t ld, int64_t n, int mode, double* red, hipStream_t s) {
+  hipLaunchKernelGGL(k_sums, dim3((unsigned)sums_blocks(n)), dim3(256), 0, s, T, Q, ld, n, mode, red);
+  return hipGetLastError();
+}
+
+hipError_t reduce_pairs(const double* red, int nb, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_pairs, dim3(1), dim3(256), 0, s, red, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t axpy_ratio(double* X, const double* P, int64_t total, const double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_ratio, dim3((unsigned)std::min<int64_t>(ceil_div(total, 256), 8192)), dim3(256), 0, s, X, P,
+                     total, sc);
+  return hipGetLastError();
+}
+
+hipError_t scaled_identity(double* X, int64_t ld, int64_t n, const double* sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_scaled_identity, dim3((unsigned)std::min<int64_t>(ceil_div(n, 256), 1024)), dim3(256), 0, s, X, ld,
+                     n, sc);
+  return hipGetLastError();
+}
+
 // Dense coordinate sketch: S[i + j*ld] = (j < q && i == C[j]) for i < ld, j < qp.
 __global__ void k_coord_dense(const int32_t* C, int q, void* S, int dt, int64_t ld, int64_t qp) {
   const int64_t total = ld * qp;

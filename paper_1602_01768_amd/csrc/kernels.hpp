@@ -153,6 +153,20 @@ hipError_t panel_axpby(const void* X, int xdt, double a, const void* Y, int ydt,
 // Transposed copy with conversion: dst[j*ldd + i] = src[i*lds + j], i < rows, j < cols.
 hipError_t copy_transpose(const void* src, int s_dt, int64_t lds, void* dst, int d_dt, int64_t ldd, int64_t rows,
                           int64_t cols, hipStream_t s);
+// Comparison methods (Newton-Schulz, MR), n x n row-major FP64 with leading dimension ld.
+// sigma ~ ||A||_2 by `steps` power-method steps from the all-ones vector (v, w: n doubles).
+hipError_t power_norm(const double* A, int64_t ld, int64_t n, int steps, double* v, double* w, double* sigma,
+                      hipStream_t s);
+// X = 0.99 A^T / sigma^2 on the n x n block.
+hipError_t ns_start(const double* A, int64_t ld, int64_t n, const double* sigma, double* X, hipStream_t s);
+// Per-block partial sums (sums_blocks(n) blocks): mode 0 sum (I - T)^2; 1 T := I - T and sum T^2;
+// 2 pairs (sum T Q, sum Q^2); 3 pairs (trace T, sum T^2).
+int sums_blocks(int64_t n);
+hipError_t mat_sums(double* T, const double* Q, int64_t ld, int64_t n, int mode, double* red, hipStream_t s);
+hipError_t reduce_pairs(const double* red, int nb, double* out, hipStream_t s);
+// X += (sc[0] / sc[1]) P over `total` entries; X = (sc[0] / sc[1]) I on the n x n block.
+hipError_t axpy_ratio(double* X, const double* P, int64_t total, const double* sc, hipStream_t s);
+hipError_t scaled_identity(double* X, int64_t ld, int64_t n, const double* sc, hipStream_t s);
 // Dense ld x qp column-major coordinate sketch from the indices C (q of them): ones at (C_j, j).
 hipError_t coord_dense(const int32_t* C, int q, void* S, int dt, int64_t ld, int64_t qp, hipStream_t s);
 
