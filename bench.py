@@ -283,6 +283,67 @@ def variants_section(A_dev, A32, q, seed, sketch, warmup, steps, torch, rbfgs):
     return out
 
 
+def experiment1(sizes, seed, torch, rbfgs):
+    """Sec. 10, Experiment 1, on synthetic matrices: A = M^T M with M uniform on [0, 1)
+    (a matrix built from rand; formed in FP64 on the GPU), q = floor(sqrt(n)).  Each method
+    runs from its own starting point (AdaRBFGS: X_0 = I; Newton-Schulz: 0.99 A^T / rho^2(A);
+    MR: the projected identity) until ||I - A X_k||_F / ||I - A X_0||_F < 1e-2.  The time
+    includes creating the context and computing X_0 (as the paper's does), not the
+    matrix; ||I - A X_0||_F is taken beforehand in an untimed context.  Newton-Schulz and
+    MR are FP64 only; AdaRBFGS runs in both precisions.  The FP64 oracle's per-iteration
+    time at the smallest n is reported beside."""
+    import numpy as np
+    from oracle import comparison as Cm, rbfgs as R, sketch as sk
+    out = {}
+    runs = [("adarbfgs_gauss", "adaptive", "gauss", "fp64"), ("adarbfgs_gauss_mixed", "adaptive", "gauss", "mixed"),
+            ("adarbfgs_cols", "adaptive", "coord", "fp64"), ("newton_schulz", "newton_schulz", "gauss", "fp64"),
+            ("mr", "mr", "gauss", "fp64")]
+    for n in sizes:
+        g = torch.Generator(device="cuda").manual_seed(seed + n)
+        M = torch.rand((n, n), generator=g, device="cuda", dtype=torch.float64)
+        A64 = M.T @ M
+        del M
+        A32 = A64.to(torch.float32)
+        A64 = A32.to(torch.float64)  # both precisions invert the same (FP32-representable) matrix
+        torch.cuda.synchronize()
+        q = int(math.isqrt(n))
+        row = {"q": q}
+        for name, variant, sketch, prec in runs:
+            Ause = A32 if prec == "mixed" else A64
+            cap = 20000 if variant == "adaptive" else 300
+            with rbfgs.Solver(Ause, q, seed, sketch=sketch, variant=variant, precision=prec) as s0:
+                r0 = s0.residual()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            with rbfgs.Solver(Ause, q, seed, sketch=sketch, variant=variant, precision=prec,
+                              check_every=4 if variant == "adaptive" else 1) as s:
+                ok, iters, resid = s.invert(tol=1e-2 * r0 / math.sqrt(n), max_iters=cap)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            row[name] = {"seconds": round(t, 4), "iters": int(iters), "reached": bool(ok),
+                         "rel_err": round(resid * math.sqrt(n) / r0, 5)}
+        out[str(n)] = row
+        del A32, A64
+    # the oracle's time per iteration at the smallest n (FP64, host cores)
+    n = sizes[0]
+    g = torch.Generator(device="cuda").manual_seed(seed + n)
+    M = torch.rand((n, n), generator=g, device="cuda", dtype=torch.float64)
+    A = (M.T @ M).to(torch.float32).to(torch.float64).cpu().numpy()
+    q = int(math.isqrt(n))
+    per = {}
+    t0 = time.perf_counter()
+    L = np.eye(n)
+    for k in range(3):
+        L = R.ada_step(L, A, sk.sketch(seed, k, n, q, "gauss"))
+    per["adarbfgs_gauss"] = round((time.perf_counter() - t0) / 3, 5)
+    for meth in ("newton_schulz", "mr"):
+        t0 = time.perf_counter()
+        Cm.run(meth, A, 3)
+        per[meth] = round((time.perf_counter() - t0) / 3, 5)
+    out["cpu_oracle_s_per_iter"] = {"n": n, "s_per_iter": per, "kind": "oracle"}
+    return out
+
+
 def cpu_baseline(A32, q, seed, sketch, variant, steps):
     """The FP64 oracle on the host: `steps` iterations from X_0 = I (or L_0 = I)."""
     import numpy as np
@@ -318,6 +379,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=8)
     ap.add_argument("--profile-steps", type=int, default=10)
     ap.add_argument("--cpu-steps", type=int, default=4, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--exp1-sizes", default="1000,2000,5000",
+                    help="sizes of the Experiment-1 comparison (AdaRBFGS vs Newton-Schulz vs MR; empty: skip)")
     ap.add_argument("--variant-steps", type=int, default=20,
                     help="timed iterations of each of PSB, AIP and Kaczmarz (0: skip them)")
     ap.add_argument("--ttt-iters", type=int, default=4000,
@@ -376,6 +439,10 @@ def main():
     variants = (variants_section(A_dev, A32, q, args.seed, args.sketch, args.warmup, args.variant_steps, torch, rbfgs)
                 if args.variant_steps > 0 else None)
 
+    # ---- Experiment 1 of Sec. 10: AdaRBFGS against Newton-Schulz and MR
+    sizes = [int(x) for x in args.exp1_sizes.split(",") if x.strip()]
+    exp1 = experiment1(sizes, args.seed, torch, rbfgs) if sizes else None
+
     # ---- time to tolerance, AdaRBFGS mixed vs FP64
     ttt = time_to_tolerance(A_dev, q, args.seed, 1e-3, args.ttt_iters, torch, rbfgs) if args.ttt_iters > 0 else None
 
@@ -424,6 +491,7 @@ def main():
         "products_ms_timed_region": live_ms,
         "phases_ms": {k: round(v["avg_ms"], 4) for k, v in phases.items()},
         "variants": variants,
+        "experiment1": exp1,
         "time_to_tolerance_ada": ttt,
         "serving": serve,
         "cpu_baseline": cpu,

@@ -673,7 +673,7 @@ void main_adaptive(rbfgs_ctx* ctx, Slot& S) {
 
 // One step of a comparison method of Sec. 10 on the main lane (FP64, n^3 products):
 //   Newton-Schulz, eq. (Newton-Schulz): T = A X, X+ = 2 X - X T;
-//   MR, eq. (MRiter): R = I - A X, P = X R, Q = A P, X+ = X + (<R, Q> / <Q, Q>) P,
+//   MR, eq. (MRiter): R = I - A X, P = X R, Q = (A X) R = R - R R, X+ = X + (<R, Q> / <Q, Q>) P,
 //   where <R, Q> = Tr(R^T A X R) and <Q, Q> = Tr((A X R)^T A X R).
 // The estimator is the exact ||I - A X_k||_F^2 of the iterate the step starts from.
 void main_comparison(rbfgs_ctx* ctx) {
@@ -703,7 +703,11 @@ void main_comparison(rbfgs_ctx* ctx) {
   HIPCHK(mat_sums(ctx->T2, nullptr, np, n, 1, L.red, L.s));  // R = I - A X in place
   HIPCHK(reduce_sum_scaled(L.red, nb, ctx->est, 1.0, ctx->status, L.s));
   square(ctx->X, ctx->T2, ctx->P2, "XR");  // P = X R
-  square(ctx->A, ctx->P2, ctx->Q2, "AP");  // Q = A P
+  // Q = A X R taken as (A X) R = (I - R) R = R - R R: for ill-conditioned A the product
+  // A (X R) carries errors of order ||A|| ||X|| eps that spoil alpha (on the rand-based
+  // matrices of Sec. 10 MR then diverges), while (A X) R is as accurate as R itself
+  square(ctx->T2, ctx->T2, ctx->Q2, "RR");
+  HIPCHK(panel_axpby(ctx->T2, DT_F64, 1.0, ctx->Q2, DT_F64, -1.0, ctx->Q2, DT_F64, np, np, np, L.s));
   HIPCHK(mat_sums(ctx->T2, ctx->Q2, np, n, 2, L.red, L.s));
   HIPCHK(reduce_pairs(L.red, nb, ctx->scal, L.s));
   HIPCHK(axpy_ratio((double*)ctx->X, ctx->P2, np * np, ctx->scal, L.s));
@@ -813,8 +817,10 @@ double exact_residual(rbfgs_ctx* ctx) {
     HIPCHK(gemm_f64(b, nullptr, L.s));
     g.A = tmp; g.a_dt = DT_F64;
   }
-  // Bop(k,j) = M[j][k]: X symmetric (fixed, PSB); L (adaptive, I - (A L) L^T); Z = X^T (row variants)
-  g.B = ctx->X; g.ldb = np; g.b_dt = ctx->mdt; g.b_kc = true;
+  // Bop(k,j) = M[j][k]: X symmetric (fixed, PSB); L (adaptive, I - (A L) L^T); Z = X^T (row variants).
+  // Newton-Schulz and MR: Bop(k,j) = X[k][j] (their iterates are symmetric only in exact
+  // arithmetic, and on ill-conditioned A the rounding asymmetry grows)
+  g.B = ctx->X; g.ldb = np; g.b_dt = ctx->mdt; g.b_kc = !(ctx->ns || ctx->mr);
   g.epi = EPI_RESID; g.red = L.red; g.nvalid = ctx->n;
   const int64_t blocks = gemm_f64_blocks(g);
   HIPCHK(gemm_f64(g, nullptr, L.s));

@@ -328,6 +328,8 @@ hipError_t gemm_f64(const GemmArgs& gin, void* partial_ws, hipStream_t s) {
       hipLaunchKernelGGL((k_gemm_f64<128, 128, false, false, EPI_ADDROW>), dim3(blocks), dim3(256), 0, s, run);
     else if (run.epi == EPI_RESID && run.a_kc && run.b_kc)
       hipLaunchKernelGGL((k_gemm_f64<128, 128, true, true, EPI_RESID>), dim3(blocks), dim3(256), 0, s, run);
+    else if (run.epi == EPI_RESID && run.a_kc)  // I - A X for an X that is not symmetric
+      hipLaunchKernelGGL((k_gemm_f64<128, 128, true, false, EPI_RESID>), dim3(blocks), dim3(256), 0, s, run);
     else
       return hipErrorInvalidValue;
   } else if (BM == 128 && BN == 128) e = launch_f64_epi<128, 128>(run, blocks, s);
