@@ -120,9 +120,49 @@ def counter_traffic(phase):
     return (float(r["fetch_kib"]) * float(kv["fetch_factor"]) + float(r["write_kib"]) * float(kv["write_factor"])) * 1024.0
 
 
-def make_A(n, seed, device):
-    from workloads import ridge_hessian
-    return ridge_hessian(n, seed, m=2 * n, lam=1e-2, device=device)
+def make_A(n, seed, torch, rbfgs, cpu_n=4096):
+    """The C3 ridge Hessian A = B^T B / m + 1e-2 I (m = 2n), formed by the library's
+    ridge-Hessian step (eq. ridgeMatrix, FP64 MFMA) from the seeded FP32 data matrix.
+    Returns A on the device (FP32), on the host, and the step's timing, its FP64-MFMA
+    roofline, a sampled check of 64 entries against FP64 dot products of B's columns,
+    and the oracle timed on an n = cpu_n, m = 2 cpu_n sample."""
+    import numpy as np
+    from oracle import ridge
+    from workloads import ridge_data
+    m = 2 * n
+    t0 = time.perf_counter()
+    B = ridge_data(n, seed, m=m)
+    t_data = time.perf_counter() - t0
+    Bd = torch.from_numpy(B).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    A_dev = rbfgs.rbfgs_ridge_hessian(Bd, 1.0 / m, 1e-2, dtype=rbfgs.F32)
+    torch.cuda.synchronize()
+    t_form = time.perf_counter() - t0
+    del Bd
+    A32 = A_dev.cpu().numpy()
+    rng = np.random.default_rng(seed)
+    idx = rng.integers(0, n, size=(64, 2))
+    idx[:8, 1] = idx[:8, 0]  # some diagonal entries
+    err = 0.0
+    for i, j in idx:
+        ref = float(B[:, i].astype(np.float64) @ B[:, j].astype(np.float64)) / m + (1e-2 if i == j else 0.0)
+        err = max(err, abs(float(A32[i, j]) - ref) / abs(ref))
+    flops = float(n) * (n + 1) * m  # lower triangle with the diagonal, 2 flops per multiply-add
+    Bs = B[: 2 * min(cpu_n, n), : min(cpu_n, n)]
+    t0 = time.perf_counter()
+    ridge.ridge_hessian(Bs, 1.0 / Bs.shape[0], 1e-2)
+    t_cpu = time.perf_counter() - t0
+    fl_cpu = float(Bs.shape[1]) ** 2 * Bs.shape[0] * 2
+    info = {"seconds": round(t_form, 4), "data_gen_s": round(t_data, 2),
+            "tflops": round(flops / t_form / 1e12, 2),
+            "roofline": {"bound": "mfma", "achieved": round(flops / t_form / 1e12, 2), "peak": FP64_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(flops / t_form / 1e12 / FP64_PEAK_TFLOPS, 4),
+                         "traffic": None, "alg_flops": flops},
+            "sampled_parity_max_rel_err": err,
+            "cpu_oracle": {"value": round(fl_cpu / t_cpu / 1e12, 4), "unit": "TFLOP/s", "seconds": round(t_cpu, 3),
+                           "sample": f"numpy FP64 B^T B/m + lam I at n={Bs.shape[1]}, m={Bs.shape[0]}"}}
+    return A_dev, A32, info
 
 
 def timed_steps(Solver, A_dev, q, seed, sketch, variant, precision, warmup, steps, torch, events=False):
@@ -405,9 +445,8 @@ def main():
     dev = "cuda"
     n, q = args.n, args.q
     t_gen = time.perf_counter()
-    A32 = make_A(n, args.seed, dev)
+    A_dev, A32, ridge_info = make_A(n, args.seed, torch, rbfgs)
     t_gen = time.perf_counter() - t_gen
-    A_dev = torch.from_numpy(A32).to(dev)
     A64_dev = A_dev.to(torch.float64)
     torch.cuda.synchronize()
 
@@ -490,6 +529,7 @@ def main():
         "roofline": roof,
         "products_ms_timed_region": live_ms,
         "phases_ms": {k: round(v["avg_ms"], 4) for k, v in phases.items()},
+        "ridge_hessian": ridge_info,
         "variants": variants,
         "experiment1": exp1,
         "time_to_tolerance_ada": ttt,

@@ -209,6 +209,21 @@ rbfgs_status rbfgs_profile_report(rbfgs_ctx* ctx, char* buf, int64_t buflen);
  *                       float (dtype F32) or double (F64); values are bfloat16.
  *   rbfgs_sketch_coord: q sorted distinct int32 indices in [0, n).
  * Asynchronous; E_INVALID_ARG for bad sizes/pointers. */
+/* Ridge-regression Hessian, eq. (ridgeMatrix): A = scale * B^T B + lambda I for an
+ * m x n data matrix B (the benchmark's workload takes scale = 1/m), in FP64 on the
+ * GPU (FP64 MFMA, the symmetric product on lower tiles mirrored, so A is exactly
+ * symmetric), then rounded to a_dtype.
+ *   B   m x n row-major, leading dimension ldb >= n, element type b_dtype; host or
+ *       device memory (b_on_device).
+ *   A   n x n row-major output, leading dimension lda >= n, element type a_dtype;
+ *       host or device memory (a_on_device).
+ * Allocates and frees its own FP64 work buffers (about 8 (m n + n^2) bytes after
+ * padding); synchronises the stream before returning.
+ * Errors: E_INVALID_ARG (sizes, pointers, non-finite scale or lambda), E_OOM, E_DEVICE. */
+rbfgs_status rbfgs_ridge_hessian(const void* B, int32_t b_dtype, int64_t m, int64_t n, int64_t ldb,
+                                 int32_t b_on_device, double scale, double lambda, void* A, int32_t a_dtype,
+                                 int64_t lda, int32_t a_on_device, void* hip_stream);
+
 rbfgs_status rbfgs_sketch_gauss(uint64_t seed, int64_t k, int64_t n, int32_t q,
                                 void* S_dev, int32_t dtype, void* hip_stream);
 rbfgs_status rbfgs_sketch_coord(uint64_t seed, int64_t k, int64_t n, int32_t q,

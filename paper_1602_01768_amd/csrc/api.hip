@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <string>
 #include <vector>
@@ -1278,6 +1279,63 @@ rbfgs_status rbfgs_sketch_gauss(uint64_t seed, int64_t k, int64_t n, int32_t q, 
   if (!S_dev || n < 1 || q < 1 || k < 0 || (dtype != RBFGS_F32 && dtype != RBFGS_F64)) return RBFGS_E_INVALID_ARG;
   hipError_t e = sketch_gauss(seed, k, n, q, S_dev, dtype == RBFGS_F32 ? DT_F32 : DT_F64, n, (hipStream_t)hip_stream);
   return e == hipSuccess ? RBFGS_OK : RBFGS_E_DEVICE;
+}
+
+// Ridge Hessian scale * B^T B + lambda I (eq. ridgeMatrix) in FP64: B copied into a
+// zero-padded FP64 buffer (rows to a multiple of 16, columns to a multiple of 128), the
+// output initialised to lambda I and updated by the FP64-MFMA symmetric product on its
+// lower tiles (mirrored), then the n x n block converted into the caller's buffer.
+rbfgs_status rbfgs_ridge_hessian(const void* B, int32_t b_dtype, int64_t m, int64_t n, int64_t ldb,
+                                 int32_t b_on_device, double scale, double lambda, void* A, int32_t a_dtype,
+                                 int64_t lda, int32_t a_on_device, void* hip_stream) {
+  if (!B || !A || m < 1 || n < 1 || n > (1ll << 20) || m > (1ll << 24) || ldb < n || lda < n ||
+      (b_dtype != RBFGS_F32 && b_dtype != RBFGS_F64) || (a_dtype != RBFGS_F32 && a_dtype != RBFGS_F64) ||
+      !std::isfinite(scale) || !std::isfinite(lambda))
+    return RBFGS_E_INVALID_ARG;
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int64_t np = (n + 127) / 128 * 128, mp = (m + 15) / 16 * 16;
+  const int sdt = b_dtype == RBFGS_F32 ? DT_F32 : DT_F64, ddt = a_dtype == RBFGS_F32 ? DT_F32 : DT_F64;
+  void *Bh = nullptr, *Bp = nullptr, *Ap = nullptr, *Ah = nullptr;
+  double* sc = nullptr;
+  rbfgs_status st = RBFGS_OK;
+  auto chk = [&](hipError_t e) {
+    if (e != hipSuccess && st == RBFGS_OK) st = e == hipErrorOutOfMemory ? RBFGS_E_OOM : RBFGS_E_DEVICE;
+    return e == hipSuccess;
+  };
+  const double host_sc[2] = {lambda, 1.0};
+  do {
+    const void* Bsrc = B;
+    if (!b_on_device) {
+      if (!chk(hipMalloc(&Bh, (size_t)m * ldb * dt_size(sdt)))) break;
+      if (!chk(hipMemcpyAsync(Bh, B, (size_t)m * ldb * dt_size(sdt), hipMemcpyHostToDevice, s))) break;
+      Bsrc = Bh;
+    }
+    if (!chk(hipMalloc(&Bp, (size_t)mp * np * sizeof(double)))) break;
+    if (!chk(hipMalloc(&Ap, (size_t)np * np * sizeof(double)))) break;
+    if (!chk(hipMalloc((void**)&sc, 2 * sizeof(double)))) break;
+    if (!chk(hipMemsetAsync(Bp, 0, (size_t)mp * np * sizeof(double), s))) break;
+    if (!chk(hipMemsetAsync(Ap, 0, (size_t)np * np * sizeof(double), s))) break;
+    if (!chk(hipMemcpyAsync(sc, host_sc, sizeof(host_sc), hipMemcpyHostToDevice, s))) break;
+    if (!chk(copy_convert(Bsrc, sdt, ldb, Bp, DT_F64, np, m, n, s))) break;
+    if (!chk(scaled_identity((double*)Ap, np, n, sc, s))) break;  // lambda I
+    GemmArgs g;
+    g.M = np; g.N = np; g.K = mp;
+    g.A = Bp; g.lda = np; g.a_dt = DT_F64; g.a_kc = false;  // Aop(i, k) = B[k][i]
+    g.B = Bp; g.ldb = np; g.b_dt = DT_F64; g.b_kc = false;  // Bop(k, j) = B[k][j]
+    g.epi = EPI_SYMUPD; g.C = Ap; g.ldc = np; g.c_dt = DT_F64; g.c2 = scale;
+    if (!chk(gemm_f64(g, nullptr, s))) break;
+    if (a_on_device) {
+      if (!chk(copy_convert(Ap, DT_F64, np, A, ddt, lda, n, n, s))) break;
+    } else {
+      if (!chk(hipMalloc(&Ah, (size_t)n * lda * dt_size(ddt)))) break;
+      if (!chk(copy_convert(Ap, DT_F64, np, Ah, ddt, lda, n, n, s))) break;
+      if (!chk(hipMemcpyAsync(A, Ah, (size_t)n * lda * dt_size(ddt), hipMemcpyDeviceToHost, s))) break;
+    }
+  } while (false);
+  (void)hipStreamSynchronize(s);  // the temporaries are in use until the stream drains
+  for (void* p : {Bh, Bp, Ap, Ah, (void*)sc})
+    if (p) (void)hipFree(p);
+  return st;
 }
 
 rbfgs_status rbfgs_sketch_coord(uint64_t seed, int64_t k, int64_t n, int32_t q, int32_t* idx_dev, void* hip_stream) {

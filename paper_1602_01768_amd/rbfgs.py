@@ -72,6 +72,10 @@ EXPORTS = {
     "rbfgs_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "rbfgs_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "rbfgs_profile_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]),
+    "rbfgs_ridge_hessian": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                            ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                            ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                            ctypes.c_void_p]),
     "rbfgs_sketch_gauss": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                           ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "rbfgs_sketch_coord": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
@@ -230,6 +234,34 @@ def rbfgs_profile_report(ctx):
     buf = ctypes.create_string_buffer(1 << 16)
     _check(load_library().rbfgs_profile_report(ctx, buf, len(buf)), ctx)
     return {k: (v[0], v[1]) for k, v in json.loads(buf.value.decode()).items()}
+
+
+def rbfgs_ridge_hessian(B, scale, lam, dtype=F32, stream=None):
+    """scale * B^T B + lam I (eq. ridgeMatrix) for an m x n B (numpy or torch, FP32/FP64,
+    host or device); returns the n x n result as a CUDA tensor of `dtype`."""
+    import torch
+    on_dev = isinstance(B, torch.Tensor) and B.is_cuda
+    if isinstance(B, torch.Tensor):
+        Bt = B.contiguous()
+        b_dt = F32 if Bt.dtype == torch.float32 else F64
+        if Bt.dtype not in (torch.float32, torch.float64):
+            raise TypeError("B must be float32 or float64")
+        ptr = Bt.data_ptr()
+        keep = Bt
+    else:
+        import numpy as np
+        keep = np.ascontiguousarray(B)
+        if keep.dtype not in (np.float32, np.float64):
+            keep = keep.astype(np.float64)
+        b_dt = F32 if keep.dtype == np.float32 else F64
+        ptr = keep.ctypes.data
+    m, n = keep.shape
+    out = torch.empty((n, n), dtype=torch.float32 if dtype == F32 else torch.float64, device="cuda")
+    _check(load_library().rbfgs_ridge_hessian(ctypes.c_void_p(ptr), b_dt, m, n, n, 1 if on_dev else 0, float(scale),
+                                              float(lam), ctypes.c_void_p(out.data_ptr()), dtype, n, 1,
+                                              _stream_handle(stream)))
+    del keep
+    return out
 
 
 def rbfgs_sketch_gauss(seed, k, n, q, dtype=F64, stream=None):

@@ -20,9 +20,9 @@ available here, so the families below stand in for them with the same structure:
                    diagonal matrix; exact inverse by the same construction.
   serving_trace    Poisson arrivals of jobs with log-uniform n.
 """
-from .matrices import (spectral_spd, gram_ridge, ridge_hessian, householder_spd,
+from .matrices import (spectral_spd, gram_ridge, ridge_hessian, ridge_data, householder_spd,
                        householder_factors, householder_entries, serving_trace,
                        CONFIGS)
 
-__all__ = ["spectral_spd", "gram_ridge", "ridge_hessian", "householder_spd",
+__all__ = ["spectral_spd", "gram_ridge", "ridge_hessian", "ridge_data", "householder_spd",
            "householder_factors", "householder_entries", "serving_trace", "CONFIGS"]

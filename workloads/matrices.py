@@ -44,9 +44,21 @@ def gram_ridge(n, seed, mu=1e-3, dtype=np.float32, device=None):
     return A.astype(dtype)
 
 
+def ridge_data(n, seed, m=None, scale_lo=1e-2, scale_hi=1e2):
+    """The m x n FP32 data matrix B = N(0,1) times diag(d), d log-uniform in
+    [scale_lo, scale_hi] (heterogeneous feature scales), of the ridge workload."""
+    if m is None:
+        m = 2 * n
+    rng = _rng(seed, 3)
+    d = np.exp(rng.uniform(math.log(scale_lo), math.log(scale_hi), n))
+    B = rng.standard_normal((m, n), dtype=np.float32)
+    B *= d.astype(np.float32)[None, :]
+    return B
+
+
 def ridge_hessian(n, seed, m=None, lam=1e-2, scale_lo=1e-2, scale_hi=1e2,
                   dtype=np.float32, device=None):
-    """A = B^T B / m + lam I, B = N(0,1) m x n times diag(d), d log-uniform.
+    """A = B^T B / m + lam I with B from `ridge_data`.
 
     B is drawn on the host (seeded numpy stream, FP32 normal draws promoted to
     FP64).  The Gram product is formed in FP64, on `device` (a torch device
@@ -55,10 +67,7 @@ def ridge_hessian(n, seed, m=None, lam=1e-2, scale_lo=1e-2, scale_hi=1e2,
     """
     if m is None:
         m = 2 * n
-    rng = _rng(seed, 3)
-    d = np.exp(rng.uniform(math.log(scale_lo), math.log(scale_hi), n))
-    B = rng.standard_normal((m, n), dtype=np.float32)
-    B *= d.astype(np.float32)[None, :]
+    B = ridge_data(n, seed, m, scale_lo, scale_hi)
     if device is not None:
         import torch
         Bt = torch.from_numpy(B).to(device=device, dtype=torch.float64)
