@@ -249,9 +249,53 @@ def serving(args, torch, rbfgs):
     return out
 
 
-def time_to_tolerance(A_dev, q, seed, tol, max_iters, torch, rbfgs):
+def pcg_section(s, A_dev, A32, seed, torch, tol=1e-8, cap=20000, cpu_n=4096, cpu_iters=40):
+    """A x = b by CG and by CG preconditioned with the AdaRBFGS iterate X = L L^T of the
+    open context s: iterations, wall time, the true residual ||b - A x|| / ||b|| (FP64),
+    and each iteration's HBM roofline -- the algorithmic bytes are the matrices it reads
+    (A; with the preconditioner also L and L^T: 3 n^2 entries), the FP64 vectors ignored.
+    The oracle's PCG is timed beside it on the leading cpu_n x cpu_n block of A."""
+    import numpy as np
+    from oracle import pcg as P
+    n = A_dev.shape[0]
+    b = torch.from_numpy(np.random.default_rng(seed + 7).standard_normal(n)).cuda()
+    A64 = A_dev.to(torch.float64)
+    out = {"tol": tol}
+    for name, pre in (("cg", False), ("pcg_X", True)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x, ok, k, rel = s.pcg(b, precond=pre, tol=tol, max_iters=cap)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        true_rel = float(torch.linalg.vector_norm(b - A64 @ x) / torch.linalg.vector_norm(b))
+        per_it = t / max(k, 1)
+        bytes_it = float(n) * n * A_dev.element_size() * (3 if pre else 1)
+        gbs = bytes_it / per_it / 1e9
+        out[name] = {"converged": bool(ok), "iters": k, "relres": rel, "true_relres": true_rel,
+                     "seconds": round(t, 4), "ms_per_iter": round(per_it * 1e3, 4),
+                     "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                                  "alg_bytes_per_iter": bytes_it}}
+    del A64
+    if out["cg"]["converged"] and out["pcg_X"]["converged"]:
+        out["cg_over_pcg_seconds"] = round(out["cg"]["seconds"] / out["pcg_X"]["seconds"], 2)
+    m = min(cpu_n, n)
+    Ac = np.asarray(A32[:m, :m], np.float64)
+    rng = np.random.default_rng(seed)
+    Mc = rng.standard_normal((m, m)) / m
+    Mc = Mc @ Mc.T + np.eye(m)  # an SPD stand-in: the oracle's cost does not depend on M's values
+    t0 = time.perf_counter()
+    P.pcg(Ac, rng.standard_normal(m), M=Mc, iters=cpu_iters)
+    t_cpu = time.perf_counter() - t0
+    out["cpu_oracle"] = {"ms_per_iter": round(t_cpu / cpu_iters * 1e3, 3), "kind": "oracle",
+                         "sample": f"{cpu_iters} oracle PCG iterations (dense M) at n={m}"}
+    return out
+
+
+def time_to_tolerance(A_dev, A32, q, seed, tol, max_iters, torch, rbfgs, pcg=True):
     """AdaRBFGS (Gaussian sketch) from L_0 = I to ||I - AX||_F / sqrt(n) <= tol, mixed and
-    FP64 on the same A; wall time includes every estimator read and exact residual check."""
+    FP64 on the same A; wall time includes every estimator read and exact residual check.
+    The mixed run's X then preconditions CG on the same A."""
     out = {}
     for prec in ("mixed", "fp64"):
         A = A_dev if prec == "mixed" else A_dev.to(torch.float64)
@@ -259,8 +303,10 @@ def time_to_tolerance(A_dev, q, seed, tol, max_iters, torch, rbfgs):
         t0 = time.perf_counter()
         with rbfgs.Solver(A, q, seed, sketch="gauss", variant="adaptive", precision=prec) as s:
             ok, iters, resid = s.invert(tol, max_iters)
-        torch.cuda.synchronize()
-        t = time.perf_counter() - t0
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            if prec == "mixed" and pcg:
+                out["pcg"] = pcg_section(s, A_dev, A32, seed, torch)
         out[prec] = {"converged": bool(ok), "iters": iters, "resid": resid, "seconds": round(t, 3)}
         del A
     if out["mixed"]["converged"] and out["fp64"]["converged"]:
@@ -482,8 +528,9 @@ def main():
     sizes = [int(x) for x in args.exp1_sizes.split(",") if x.strip()]
     exp1 = experiment1(sizes, args.seed, torch, rbfgs) if sizes else None
 
-    # ---- time to tolerance, AdaRBFGS mixed vs FP64
-    ttt = time_to_tolerance(A_dev, q, args.seed, 1e-3, args.ttt_iters, torch, rbfgs) if args.ttt_iters > 0 else None
+    # ---- time to tolerance, AdaRBFGS mixed vs FP64; its X as a CG preconditioner
+    ttt = (time_to_tolerance(A_dev, A32, q, args.seed, 1e-3, args.ttt_iters, torch, rbfgs)
+           if args.ttt_iters > 0 else None)
 
     # ---- serving trace (p50 / p99 solve latency)
     serve = serving(args, torch, rbfgs) if args.serve_jobs > 0 else None

@@ -209,6 +209,21 @@ rbfgs_status rbfgs_profile_report(rbfgs_ctx* ctx, char* buf, int64_t buflen);
  *                       float (dtype F32) or double (F64); values are bfloat16.
  *   rbfgs_sketch_coord: q sorted distinct int32 indices in [0, n).
  * Asynchronous; E_INVALID_ARG for bad sizes/pointers. */
+/* Solve A x = b by conjugate gradients preconditioned with the context's current
+ * approximate inverse -- the use of X ~ A^-1 that motivates the method (Sec. 1):
+ * textbook PCG (Hestenes & Stiefel; Saad, Alg. 9.1) from x_0 = 0 with z = M r,
+ * M = X_k (fixed RBFGS) or L_k L_k^T applied as L (L^T r) (AdaRBFGS) when precond = 1,
+ * M = I (plain CG) when precond = 0.  FP64 vectors; A and X as the context stores them.
+ * Stops when ||r_k|| <= tol ||b|| (tested every 8 iterations) or after max_iters.
+ *   b, x   n-vectors of b_dtype / x_dtype (F32 or F64), host or device memory.
+ *   iters_out, relres_out: iterations run and the last ||r_k|| / ||b|| (may be NULL).
+ * Needs an SPD A (not PSB, Kaczmarz) and, with precond = 1, a fixed or adaptive context.
+ * Allocates O(n) work memory of its own; synchronises.  Returns OK, E_NOT_CONVERGED,
+ * E_NONFINITE, E_INVALID_ARG or a device error. */
+rbfgs_status rbfgs_pcg(rbfgs_ctx* ctx, const void* b, int32_t b_dtype, int32_t b_on_device, void* x, int32_t x_dtype,
+                       int32_t x_on_device, int32_t precond, double tol, int64_t max_iters, int64_t* iters_out,
+                       double* relres_out);
+
 /* Ridge-regression Hessian, eq. (ridgeMatrix): A = scale * B^T B + lambda I for an
  * m x n data matrix B (the benchmark's workload takes scale = 1/m), in FP64 on the
  * GPU (FP64 MFMA, the symmetric product on lower tiles mirrored, so A is exactly

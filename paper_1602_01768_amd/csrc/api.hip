@@ -1281,6 +1281,112 @@ rbfgs_status rbfgs_sketch_gauss(uint64_t seed, int64_t k, int64_t n, int32_t q, 
   return e == hipSuccess ? RBFGS_OK : RBFGS_E_DEVICE;
 }
 
+rbfgs_status rbfgs_pcg(rbfgs_ctx* ctx, const void* b, int32_t b_dtype, int32_t b_on_device, void* x, int32_t x_dtype,
+                       int32_t x_on_device, int32_t precond, double tol, int64_t max_iters, int64_t* iters_out,
+                       double* relres_out) {
+  if (!ctx || !b || !x || (b_dtype != RBFGS_F32 && b_dtype != RBFGS_F64) || (x_dtype != RBFGS_F32 && x_dtype != RBFGS_F64) ||
+      (precond != 0 && precond != 1) || !(tol > 0) || max_iters < 0)
+    return RBFGS_E_INVALID_ARG;
+  // A must be SPD; with the preconditioner, X must be too (fixed RBFGS, AdaRBFGS)
+  if (ctx->kacz || ctx->psb || (precond == 1 && !(ctx->p.variant == RBFGS_FIXED || ctx->ada)))
+    return RBFGS_E_INVALID_ARG;
+  if (iters_out) *iters_out = 0;
+  if (relres_out) *relres_out = NAN;
+  void* work = nullptr;
+  void* staging = nullptr;
+  try {
+    rbfgs_status st = read_status(ctx);
+    if (st != RBFGS_OK) return st;
+    const int64_t n = ctx->n, np = ctx->np;
+    hipStream_t s = ctx->main.s;
+    const int mdt = ctx->mdt;
+    HIPCHK(hipMalloc(&work, (size_t)(7 + GEMV_T_CHUNKS) * n * sizeof(double) + 8 * sizeof(double)));
+    double* xv = (double*)work;
+    double *r = xv + n, *z = r + n, *p = z + n, *Ap = p + n, *t = Ap + n, *part = t + 2 * n;
+    double* sc = part + (size_t)GEMV_T_CHUNKS * n;  // [p.Ap, r.r, r.z (two slots)]
+    const int sdt = b_dtype == RBFGS_F32 ? DT_F32 : DT_F64;
+    const void* bsrc = b;
+    if (!b_on_device) {
+      HIPCHK(hipMalloc(&staging, (size_t)n * dt_size(sdt)));
+      HIPCHK(hipMemcpyAsync(staging, b, (size_t)n * dt_size(sdt), hipMemcpyHostToDevice, s));
+      bsrc = staging;
+    }
+    HIPCHK(copy_convert(bsrc, sdt, n, r, DT_F64, n, 1, n, s));  // r_0 = b (x_0 = 0)
+    HIPCHK(hipMemsetAsync(xv, 0, (size_t)n * sizeof(double), s));
+    auto apply_m = [&](const double* in, double* out) {
+      if (precond == 0) {
+        HIPCHK(hipMemcpyAsync(out, in, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      } else if (ctx->ada) {  // X = L L^T: out = L (L^T in)
+        HIPCHK(gemv(ctx->X, mdt, np, n, true, in, t, part, s));
+        HIPCHK(gemv(ctx->X, mdt, np, n, false, t, out, part, s));
+      } else {
+        HIPCHK(gemv(ctx->X, mdt, np, n, false, in, out, part, s));
+      }
+    };
+    double host[2] = {0, 0};
+    HIPCHK(dot(r, r, n, sc + 1, s));
+    HIPCHK(hipMemcpyAsync(host, sc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double nb = std::sqrt(host[0]);
+    double rel = nb > 0 ? 1.0 : 0.0;
+    int64_t k = 0;
+    bool done = !(nb > 0) || rel <= tol;
+    if (!std::isfinite(nb)) {
+      HIPCHK(hipFree(work));
+      if (staging) HIPCHK(hipFree(staging));
+      return RBFGS_E_INVALID_ARG;
+    }
+    if (!done) {
+      apply_m(r, z);
+      HIPCHK(hipMemcpyAsync(p, z, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(dot(r, z, n, sc + 2, s));
+    }
+    while (!done && k < max_iters) {
+      const int cur = 2 + (int)(k & 1), nxt = 2 + (int)((k + 1) & 1);
+      HIPCHK(gemv(ctx->A, mdt, np, n, false, p, Ap, part, s));
+      HIPCHK(dot(p, Ap, n, sc, s));
+      HIPCHK(cg_xr(xv, r, p, Ap, n, sc, cur, 0, s));
+      apply_m(r, z);
+      HIPCHK(dot(r, z, n, sc + nxt, s));
+      HIPCHK(cg_p(p, z, n, sc, nxt, cur, s));
+      ++k;
+      if (k % 8 == 0 || k == max_iters) {  // the stopping test reads ||r|| every 8 iterations
+        HIPCHK(dot(r, r, n, sc + 1, s));
+        HIPCHK(hipMemcpyAsync(host, sc + 1, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        rel = std::sqrt(host[0]) / nb;
+        if (!std::isfinite(rel)) {
+          HIPCHK(hipFree(work));
+          if (staging) HIPCHK(hipFree(staging));
+          return fail(ctx, RBFGS_E_NONFINITE, "non-finite residual in PCG");
+        }
+        done = rel <= tol;
+      }
+    }
+    // x out (converted), on the host or the device
+    const int ddt = x_dtype == RBFGS_F32 ? DT_F32 : DT_F64;
+    if (x_on_device) {
+      HIPCHK(copy_convert(xv, DT_F64, n, x, ddt, n, 1, n, s));
+    } else {
+      HIPCHK(copy_convert(xv, DT_F64, n, t, ddt, n, 1, n, s));  // t is free now
+      HIPCHK(hipMemcpyAsync(x, t, (size_t)n * dt_size(ddt), hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipFree(work));
+    work = nullptr;
+    if (staging) HIPCHK(hipFree(staging));
+    staging = nullptr;
+    if (iters_out) *iters_out = k;
+    if (relres_out) *relres_out = rel;
+    return done ? RBFGS_OK : RBFGS_E_NOT_CONVERGED;
+  } catch (const Fail& f) {
+    (void)hipStreamSynchronize(ctx->main.s);
+    if (work) (void)hipFree(work);
+    if (staging) (void)hipFree(staging);
+    return f.st;
+  }
+}
+
 // Ridge Hessian scale * B^T B + lambda I (eq. ridgeMatrix) in FP64: B copied into a
 // zero-padded FP64 buffer (rows to a multiple of 16, columns to a multiple of 128), the
 // output initialised to lambda I and updated by the FP64-MFMA symmetric product on its

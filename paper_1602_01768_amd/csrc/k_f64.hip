@@ -760,6 +760,129 @@ hipError_t scaled_identity(double* X, int64_t ld, int64_t n, const double* sc, h
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- conjugate gradients
+// y = M v for an n x n row-major M (FP32 or FP64, ld a multiple of 4), FP64 vectors; one
+// wave per row, 16-byte loads.
+template <class T>
+__global__ __launch_bounds__(256) void k_gemv_rows(const T* M, int64_t ld, int64_t n, const double* v, double* y) {
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;  // uniform per wave; no barrier in this kernel
+  const T* Mr = M + row * ld;
+  double s = 0.0;
+  const int64_t n4 = n / 4 * 4;
+  for (int64_t j = 4 * lane; j < n4; j += 256) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 a = *(const float4*)(Mr + j);
+      s = fma((double)a.x, v[j], s);
+      s = fma((double)a.y, v[j + 1], s);
+      s = fma((double)a.z, v[j + 2], s);
+      s = fma((double)a.w, v[j + 3], s);
+    } else {
+      const double2 a = *(const double2*)(Mr + j), b = *(const double2*)(Mr + j + 2);
+      s = fma(a.x, v[j], s);
+      s = fma(a.y, v[j + 1], s);
+      s = fma(b.x, v[j + 2], s);
+      s = fma(b.y, v[j + 3], s);
+    }
+  }
+  for (int64_t j = n4 + lane; j < n; j += 64) s = fma((double)Mr[j], v[j], s);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) y[row] = s;
+}
+
+// Partial sums of y = M^T v: chunk c of the rows, column j -> part[c * n + j].
+template <class T>
+__global__ __launch_bounds__(256) void k_gemv_cols_part(const T* M, int64_t ld, int64_t n, const double* v, int64_t rows_per,
+                                                        double* part) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per, r1 = r0 + rows_per < n ? r0 + rows_per : n;
+  double s = 0.0;
+  for (int64_t i = r0; i < r1; ++i) s = fma((double)M[i * ld + j], v[i], s);
+  part[(int64_t)blockIdx.y * n + j] = s;
+}
+
+__global__ void k_sum_chunks(const double* part, int64_t n, int chunks, double* y) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * n + j];
+    y[j] = s;
+  }
+}
+
+// out[0] = a . b (one workgroup, fixed order).
+__global__ __launch_bounds__(1024) void k_dot(const double* a, const double* b, int64_t n, double* out) {
+  __shared__ double sh[1024];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 1024) s = fma(a[i], b[i], s);
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 512; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0];
+}
+
+// alpha = sc[num] / sc[den]; x += alpha p; r -= alpha Ap.
+__global__ void k_cg_xr(double* x, double* r, const double* p, const double* Ap, int64_t n, const double* sc, int num,
+                        int den) {
+  const double a = sc[num] / sc[den];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] = fma(a, p[i], x[i]);
+    r[i] = fma(-a, Ap[i], r[i]);
+  }
+}
+
+// beta = sc[num] / sc[den]; p = z + beta p.
+__global__ void k_cg_p(double* p, const double* z, int64_t n, const double* sc, int num, int den) {
+  const double bt = sc[num] / sc[den];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = fma(bt, p[i], z[i]);
+}
+
+hipError_t gemv(const void* M, int dt, int64_t ld, int64_t n, bool transpose, const double* v, double* y,
+                double* part, hipStream_t s) {
+  if (ld % 4) return hipErrorInvalidValue;
+  if (!transpose) {
+    if (dt == DT_F32)
+      hipLaunchKernelGGL(k_gemv_rows<float>, dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, s, (const float*)M, ld, n, v, y);
+    else
+      hipLaunchKernelGGL(k_gemv_rows<double>, dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, s, (const double*)M, ld, n, v,
+                         y);
+    return hipGetLastError();
+  }
+  const int chunks = GEMV_T_CHUNKS;
+  const int64_t rows_per = ceil_div(n, chunks);
+  const dim3 grid((unsigned)ceil_div(n, 256), (unsigned)chunks);
+  if (dt == DT_F32)
+    hipLaunchKernelGGL(k_gemv_cols_part<float>, grid, dim3(256), 0, s, (const float*)M, ld, n, v, rows_per, part);
+  else
+    hipLaunchKernelGGL(k_gemv_cols_part<double>, grid, dim3(256), 0, s, (const double*)M, ld, n, v, rows_per, part);
+  hipLaunchKernelGGL(k_sum_chunks, dim3((unsigned)std::min<int64_t>(ceil_div(n, 256), 1024)), dim3(256), 0, s,
+                     (const double*)part, n, chunks, y);
+  return hipGetLastError();
+}
+
+hipError_t dot(const double* a, const double* b, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot, dim3(1), dim3(1024), 0, s, a, b, n, out);
+  return hipGetLastError();
+}
+
+hipError_t cg_xr(double* x, double* r, const double* p, const double* Ap, int64_t n, const double* sc, int num, int den,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_xr, dim3((unsigned)std::min<int64_t>(ceil_div(n, 256), 1024)), dim3(256), 0, s, x, r, p, Ap,
+                     n, sc, num, den);
+  return hipGetLastError();
+}
+
+hipError_t cg_p(double* p, const double* z, int64_t n, const double* sc, int num, int den, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_p, dim3((unsigned)std::min<int64_t>(ceil_div(n, 256), 1024)), dim3(256), 0, s, p, z, n, sc,
+                     num, den);
+  return hipGetLastError();
+}
+
 // Dense coordinate sketch: S[i + j*ld] = (j < q && i == C[j]) for i < ld, j < qp.
 __global__ void k_coord_dense(const int32_t* C, int q, void* S, int dt, int64_t ld, int64_t qp) {
   const int64_t total = ld * qp;

@@ -167,6 +167,16 @@ hipError_t reduce_pairs(const double* red, int nb, double* out, hipStream_t s);
 // X += (sc[0] / sc[1]) P over `total` entries; X = (sc[0] / sc[1]) I on the n x n block.
 hipError_t axpy_ratio(double* X, const double* P, int64_t total, const double* sc, hipStream_t s);
 hipError_t scaled_identity(double* X, int64_t ld, int64_t n, const double* sc, hipStream_t s);
+// Conjugate gradients: y = M v (transpose: M^T v) for an n x n row-major M (FP32/FP64,
+// ld % 4 == 0), FP64 vectors; `part` holds GEMV_T_CHUNKS * n doubles for the transpose.
+constexpr int GEMV_T_CHUNKS = 32;
+hipError_t gemv(const void* M, int dt, int64_t ld, int64_t n, bool transpose, const double* v, double* y,
+                double* part, hipStream_t s);
+hipError_t dot(const double* a, const double* b, int64_t n, double* out, hipStream_t s);
+// x += (sc[num]/sc[den]) p, r -= (sc[num]/sc[den]) Ap;  p = z + (sc[num]/sc[den]) p.
+hipError_t cg_xr(double* x, double* r, const double* p, const double* Ap, int64_t n, const double* sc, int num, int den,
+                 hipStream_t s);
+hipError_t cg_p(double* p, const double* z, int64_t n, const double* sc, int num, int den, hipStream_t s);
 // Dense ld x qp column-major coordinate sketch from the indices C (q of them): ones at (C_j, j).
 hipError_t coord_dense(const int32_t* C, int q, void* S, int dt, int64_t ld, int64_t qp, hipStream_t s);
 

@@ -72,6 +72,9 @@ EXPORTS = {
     "rbfgs_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "rbfgs_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "rbfgs_profile_report": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.c_int64]),
+    "rbfgs_pcg": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                  ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int64,
+                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     "rbfgs_ridge_hessian": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
                                             ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                             ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
@@ -236,6 +239,25 @@ def rbfgs_profile_report(ctx):
     return {k: (v[0], v[1]) for k, v in json.loads(buf.value.decode()).items()}
 
 
+def rbfgs_pcg(ctx, b, precond=True, tol=1e-8, max_iters=10000):
+    """Solve A x = b by CG preconditioned with the context's X (or plain CG); b a CUDA
+    tensor or numpy vector.  Returns (x as an FP64 CUDA tensor, converged, iters, relres)."""
+    import torch
+    if isinstance(b, torch.Tensor):
+        bt = b.to(device="cuda", dtype=torch.float64).contiguous()
+    else:
+        import numpy as np
+        bt = torch.from_numpy(np.ascontiguousarray(b, dtype=np.float64)).cuda()
+    x = torch.empty_like(bt)
+    it = ctypes.c_int64(0)
+    rel = ctypes.c_double(0.0)
+    st = load_library().rbfgs_pcg(ctx, ctypes.c_void_p(bt.data_ptr()), F64, 1, ctypes.c_void_p(x.data_ptr()), F64, 1,
+                                  1 if precond else 0, float(tol), int(max_iters), ctypes.byref(it), ctypes.byref(rel))
+    if st not in (OK, E_NOT_CONVERGED):
+        _check(st, ctx)
+    return x, st == OK, it.value, rel.value
+
+
 def rbfgs_ridge_hessian(B, scale, lam, dtype=F32, stream=None):
     """scale * B^T B + lam I (eq. ridgeMatrix) for an m x n B (numpy or torch, FP32/FP64,
     host or device); returns the n x n result as a CUDA tensor of `dtype`."""
@@ -383,6 +405,10 @@ class Solver:
     def invert(self, tol=1e-3, max_iters=20000):
         """(converged, iterations, ||I - AX||_F / sqrt(n))"""
         return rbfgs_invert(self.ctx, tol, max_iters)
+
+    def pcg(self, b, precond=True, tol=1e-8, max_iters=10000):
+        """Solve A x = b by CG preconditioned with the current X: (x, converged, iters, relres)."""
+        return rbfgs_pcg(self.ctx, b, precond, tol, max_iters)
 
     def residual(self):
         return rbfgs_residual(self.ctx)
