@@ -19,6 +19,9 @@ Modules
            points of Sec. 10, and the power-method norm estimate they use.
   ridge    the ridge-regression Hessian scale B^T B + lam I (eq. ridgeMatrix).
   pcg      preconditioned CG for A x = b with X ~ A^-1 as the preconditioner.
+  partition  partition sampling with the probabilities of eq. (ihsih0) for fixed
+           RBFGS and AdaRBFGS (Sec. 9.3), the draw from the stream, and the
+           Horvitz-Thompson residual estimator.
   theory   closed-form quantities used by the pins: the rate rho of Thm 6.2 /
            eq. rhoequiv, E[Z] for discrete sketches (Prop. 7.1), brute-force
            projections (eq. NF, eq. NFsym) by a dense KKT solve.
@@ -26,5 +29,5 @@ Modules
 Parity status: every function here is pinned by a `-m "not gpu"` test against
 something other than itself (see tests/test_oracle_pins.py, tests/test_oracle_variants.py,
 tests/test_oracle_comparison.py, tests/test_oracle_ridge.py,
-tests/test_oracle_pcg.py).
+tests/test_oracle_pcg.py, tests/test_oracle_partition.py).
 """
