@@ -46,6 +46,16 @@
  *          significant bits (bfloat16 values) nearest-even;
  *   coord: Floyd's algorithm with Lemire's bounded draws on the word stream,
  *          indices sorted ascending.
+ * RBFGS_SKETCH_PARTITION (fixed RBFGS and AdaRBFGS; q must divide n): S~ = I_{:C_i} for
+ * the block C_i = [iq, (i+1)q) of a partition of [n], drawn with the probabilities of
+ * eq. (ihsih0), p_i = Tr(S_i^T A S_i) / Tr(S^T A S) -- the complete discrete sampling
+ * that the convergence results of Sec. 7.3 and Sec. 9.3 assume.  Fixed RBFGS: S_i =
+ * I_{:C_i}, weights the diagonal of A.  AdaRBFGS: S_i = L_k I_{:C_i}, weights the
+ * diagonal of L_k^T A L_k, kept on the device in O(nq) per step through
+ * L+^T A L+ = L^T A L - K K^T + S~ (S~^T S~)^-1 S~^T, K = L^T A S R, and recomputed
+ * (n^3 flops) by rbfgs_set_state.  Draw: word 0 of block 0 of the kind-3 stream gives
+ * u = ((x>>11)+0.5) 2^-53; the first block whose running weight sum exceeds u times the
+ * total is taken.  The estimator carries the factor 1/p_i (unbiased, Horvitz-Thompson).
  *
  * Starting point: X_0 = I, L_0 = I (the experiments' choice, Sec. 10).
  *
@@ -94,7 +104,7 @@ typedef enum {
   RBFGS_E_DEVICE = 6         /* a HIP runtime call failed */
 } rbfgs_status;
 
-typedef enum { RBFGS_SKETCH_GAUSS = 0, RBFGS_SKETCH_COORD = 1 } rbfgs_sketch;
+typedef enum { RBFGS_SKETCH_GAUSS = 0, RBFGS_SKETCH_COORD = 1, RBFGS_SKETCH_PARTITION = 2 } rbfgs_sketch;
 typedef enum {
   RBFGS_FIXED = 0,
   RBFGS_ADAPTIVE = 1,
@@ -178,6 +188,11 @@ rbfgs_status rbfgs_get_l(rbfgs_ctx* ctx, void* L, int32_t l_dtype, int64_t ldl,
 rbfgs_status rbfgs_set_state(rbfgs_ctx* ctx, const void* M, int32_t m_dtype, int64_t ldm,
                              int32_t on_device, int64_t k);
 
+/* Partition sampling: copy the n per-coordinate FP64 weights (the diagonal of A for
+ * fixed RBFGS, of L_k^T A L_k for AdaRBFGS) to host memory; synchronises.
+ * E_INVALID_ARG unless the context samples partitions. */
+rbfgs_status rbfgs_get_weights(rbfgs_ctx* ctx, double* out);
+
 /* Iterations performed so far (k of X_k). */
 rbfgs_status rbfgs_get_iter(const rbfgs_ctx* ctx, int64_t* k_out);
 
@@ -203,12 +218,6 @@ const char* rbfgs_last_error(const rbfgs_ctx* ctx);
 rbfgs_status rbfgs_profile(rbfgs_ctx* ctx, int32_t enable);
 rbfgs_status rbfgs_profile_report(rbfgs_ctx* ctx, char* buf, int64_t buflen);
 
-/* ---- sketch stream (Sec. 10 sketch distributions), for testing and reuse ----
- * Write the iteration-k sketch of the stream (seed) to device memory on `hip_stream`.
- *   rbfgs_sketch_gauss: S n x q column-major (entry (i,j) at S[j*n + i]) as
- *                       float (dtype F32) or double (F64); values are bfloat16.
- *   rbfgs_sketch_coord: q sorted distinct int32 indices in [0, n).
- * Asynchronous; E_INVALID_ARG for bad sizes/pointers. */
 /* Solve A x = b by conjugate gradients preconditioned with the context's current
  * approximate inverse -- the use of X ~ A^-1 that motivates the method (Sec. 1):
  * textbook PCG (Hestenes & Stiefel; Saad, Alg. 9.1) from x_0 = 0 with z = M r,
@@ -239,10 +248,26 @@ rbfgs_status rbfgs_ridge_hessian(const void* B, int32_t b_dtype, int64_t m, int6
                                  int32_t b_on_device, double scale, double lambda, void* A, int32_t a_dtype,
                                  int64_t lda, int32_t a_on_device, void* hip_stream);
 
+/* ---- sketch stream (Sec. 10 sketch distributions), for testing and reuse ----
+ * Write the iteration-k sketch of the stream (seed) to device memory on `hip_stream`.
+ *   rbfgs_sketch_gauss: S n x q column-major (entry (i,j) at S[j*n + i]) as
+ *                       float (dtype F32) or double (F64); values are bfloat16.
+ *   rbfgs_sketch_coord: q sorted distinct int32 indices in [0, n).
+ * Asynchronous; E_INVALID_ARG for bad sizes/pointers. */
 rbfgs_status rbfgs_sketch_gauss(uint64_t seed, int64_t k, int64_t n, int32_t q,
                                 void* S_dev, int32_t dtype, void* hip_stream);
 rbfgs_status rbfgs_sketch_coord(uint64_t seed, int64_t k, int64_t n, int32_t q,
                                 int32_t* idx_dev, void* hip_stream);
+
+/* Partition draw of iteration k (RBFGS_SKETCH_PARTITION): block i of the partition of
+ * [0, n) into consecutive blocks C_i = [iq, (i+1)q) with probability w_i / sum_j w_j,
+ * w_i = max(0, sum_{c in C_i} t[c]) (eq. ihsih0 when t is the diagonal of A, or of
+ * L^T A L).  t_dev: n FP64 weights on the device.  Writes idx_dev[0..q) = C_i and, when
+ * ht_dev is not NULL, ht_dev[0] = 1/p_i.  A weight total that is not finite and positive
+ * draws block 0 (with ht 1).  Asynchronous on hip_stream; E_INVALID_ARG unless q
+ * divides n (1 <= q <= n <= 2^20) and the pointers are set. */
+rbfgs_status rbfgs_sample_partition(const double* t_dev, int64_t n, int32_t q, uint64_t seed, int64_t k,
+                                    int32_t* idx_dev, double* ht_dev, void* hip_stream);
 
 /* Device bytes a context for `params` holds (plus, for the adaptive method, the
  * n x n FP64 scratch of its exact residual), computed without allocating.  Used by

@@ -59,6 +59,7 @@ struct Slot {  // sketch-dependent quantities of one iteration
   double* Z = nullptr;       // inverse Cholesky factor of G (fixed) or of S~^T S~ (adaptive)
   void* U = nullptr;         // fixed: U = S G^-1 (mixed: FP32 n x q; FP64: panels [U | W' | U])
   __bf16* planes = nullptr;  // mixed fixed: bf16 hi/lo planes of [U | W' | U], row-major
+  double* ht = nullptr;      // partition sampling: 1/p_i of the drawn block (Horvitz-Thompson)
   hipEvent_t y_ready = nullptr;   // side lane: sketch and Y = A S written (fixed sketch)
   hipEvent_t g_ready = nullptr;   // side lane: G (or S~^T S~) written
   hipEvent_t ready = nullptr;     // inverse lane: slot complete
@@ -78,6 +79,11 @@ struct rbfgs_ctx {
   // these are used as dense 0/1 matrices (dcoord), `coord` marks the gather paths of
   // fixed RBFGS and AdaRBFGS only
   bool psb = false, rowv = false, kacz = false, dcoord = false;
+  // partition sampling (fixed RBFGS, AdaRBFGS): the coordinate block C_i = [iq, (i+1)q) is
+  // drawn with p_i proportional to Tr(S_i^T A S_i) (eq. ihsih0); tw holds the per-coordinate
+  // weights, A_jj for the fixed method and (L^T A L)_jj for AdaRBFGS (updated every step)
+  bool part = false;
+  double* tw = nullptr;
   // comparison methods of Sec. 10 (FP64 only): Newton-Schulz and MR, n^3 products per step
   bool ns = false, mr = false;
   double *T2 = nullptr, *P2 = nullptr, *Q2 = nullptr;  // n x n FP64 work matrices
@@ -358,7 +364,11 @@ void side_products(rbfgs_ctx* ctx, int64_t k, Slot& S) {
   const int mdt = ctx->mdt;
   {
     Phase ph(ctx, L, "sketch");
-    if (ctx->coord || ctx->dcoord) HIPCHK(sketch_coord(ctx->p.seed, k, ctx->n, ctx->q, S.C, L.s));
+    if (ctx->part) {
+      // fixed: static weights, drawn ahead; AdaRBFGS draws on the main lane (its weights
+      // depend on the previous step)
+      if (!ctx->ada) HIPCHK(sample_partition(ctx->tw, ctx->n, ctx->q, ctx->p.seed, k, S.C, S.ht, ctx->status, L.s));
+    } else if (ctx->coord || ctx->dcoord) HIPCHK(sketch_coord(ctx->p.seed, k, ctx->n, ctx->q, S.C, L.s));
     else HIPCHK(sketch_gauss(ctx->p.seed, k, ctx->n, ctx->q, S.Sk, sk_dt(ctx), np, L.s));
     if (ctx->dcoord) HIPCHK(coord_dense(S.C, ctx->q, S.Sk, sk_dt(ctx), np, qp, L.s));
   }
@@ -463,14 +473,15 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
     if (ctx->bf16h) gram_bf16(ctx, L, S.Y, false, (const float*)ctx->V, ctx->H32, DT_F32);
     else gram(ctx, L, S.Y, mdt, ctx->V, mdt, ctx->H);
   }
-  const double scale = (ctx->coord || ctx->dcoord) ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
+  // partition: the Horvitz-Thompson factor 1/p_i of the drawn block, read on the device
+  const double scale = ctx->part ? 1.0 : (ctx->coord || ctx->dcoord) ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
   {
     Phase ph(ctx, L, "estimator");
     if (fused_est)
       HIPCHK(reduce_sum_scaled(L.red, reduce_blocks_f32(shape), ctx->est, scale, ctx->status, L.s));
     else
       HIPCHK(estimator(ctx->coord ? nullptr : S.Sk, sk_dt(ctx), ctx->coord ? S.C : nullptr, ctx->V, mdt, np, ctx->n,
-                       ctx->q, scale, L.red, ctx->est, ctx->status, L.s));
+                       ctx->q, scale, L.red, ctx->est, ctx->status, L.s, ctx->part ? S.ht : nullptr));
   }
   HIPCHK(hipStreamWaitEvent(L.s, S.ready, 0));  // G^-1 and U of this slot
   // PSB: H' = Y^T V - S^T Y (= R^T Y with R = V - S), and W' = V - S - U H'/2
@@ -608,10 +619,14 @@ void main_row(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
 // C = L_M^-1 (L_M^-1 from the slot):
 //   S = L S~,  Y = A S,  G = S^T Y = L_G L_G^T,  T^T = L^T Y,
 //   Q^T = S~ (L_M^-T L_G^-1) - T^T G^-1,  L+ = L + S Q.
-void main_adaptive(rbfgs_ctx* ctx, Slot& S) {
+void main_adaptive(rbfgs_ctx* ctx, Slot& S, int64_t k) {
   const Lane& L = ctx->main;
   const int64_t np = ctx->np, qp = ctx->qp;
   const int mdt = ctx->mdt;
+  if (ctx->part) {  // block drawn by the weights (L_k^T A L_k)_jj of eq. ihsih0
+    Phase ph(ctx, L, "sample");
+    HIPCHK(sample_partition(ctx->tw, ctx->n, ctx->q, ctx->p.seed, k, S.C, S.ht, ctx->status, L.s));
+  }
   if (ctx->coord) {
     Phase ph(ctx, L, "gather");
     HIPCHK(gather_cols_gen(ctx->X, mdt, np, S.C, ctx->q, np, ctx->Sa, mdt, np, L.s));
@@ -632,12 +647,13 @@ void main_adaptive(rbfgs_ctx* ctx, Slot& S) {
     Phase ph(ctx, L, "LtY", true);
     nn_times_panel(ctx, L, ctx->X, true, ctx->Y, mdt, ctx->V, 2, 3, 2, ph.mark());  // T^T = L^T Y
   }
-  const double scale = ctx->coord ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
+  const double scale = ctx->part ? 1.0 : ctx->coord ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
   {
     Phase ph(ctx, L, "panels");
     HIPCHK(estimator(ctx->coord ? nullptr : S.Sk, sk_dt(ctx), ctx->coord ? S.C : nullptr, ctx->V, mdt, np, ctx->n,
-                     ctx->q, scale, L.red, ctx->est, ctx->status, L.s));
+                     ctx->q, scale, L.red, ctx->est, ctx->status, L.s, ctx->part ? S.ht : nullptr));
     panel_times_small(ctx, L, ctx->V, mdt, ctx->Ginv, ctx->W, mdt, -1.0);  // Q^T = -T^T G^-1
+    if (ctx->part) HIPCHK(part_weights(ctx->V, ctx->W, mdt, np, ctx->n, ctx->q, S.C, ctx->tw, L.s));  // (L+^T A L+)_jj
     if (ctx->coord) {
       HIPCHK(coord_add_rows(ctx->W, mdt, np, S.C, ctx->q, ctx->Z, qp, L.s));  // + E_C L_G^-1
     } else {
@@ -669,6 +685,20 @@ void main_adaptive(rbfgs_ctx* ctx, Slot& S) {
     g.epi = EPI_ADDROW; g.C = ctx->X; g.ldc = np; g.c_dt = DT_F64; g.c2 = 1.0;
     g.tiles = ctx->tiles; g.ntiles = ctx->ntiles;
     f64_gemm(ctx, L, g);
+  }
+}
+
+// Partition weights (L^T A L)_jj of AdaRBFGS for an L the caller set: block by block,
+// P = L I_{:C} (gathered), Q = A P (the step's product), t_C = column dots of P and Q;
+// n^3 flops in all, once per rbfgs_set_state.  Uses slot 0's index buffer.
+void refresh_part_weights(rbfgs_ctx* ctx) {
+  const Lane& L = ctx->main;
+  int32_t* C = ctx->slot[0].C;
+  for (int64_t b = 0; b < ctx->n / ctx->q; ++b) {
+    HIPCHK(fill_block(C, b * ctx->q, ctx->q, L.s));
+    HIPCHK(gather_cols_gen(ctx->X, ctx->mdt, ctx->np, C, ctx->q, ctx->np, ctx->Sa, ctx->mdt, ctx->np, L.s));
+    nn_times_panel(ctx, L, ctx->A, false, ctx->Sa, ctx->mdt, ctx->Y, 3, 2, 2);
+    HIPCHK(col_dots(ctx->Sa, ctx->Y, ctx->mdt, ctx->np, ctx->n, ctx->q, C, ctx->tw, L.s));
   }
 }
 
@@ -753,7 +783,7 @@ void enqueue_steps(rbfgs_ctx* ctx, int64_t nsteps) {
     if (ctx->ada) {
       ahead();
       HIPCHK(hipStreamWaitEvent(ctx->main.s, S.ready, 0));
-      main_adaptive(ctx, S);
+      main_adaptive(ctx, S, k);
     } else {
       HIPCHK(hipStreamWaitEvent(ctx->main.s, S.y_ready, 0));
       // RB_GATE 0: the side lane's products of k+2 and the inverse of k+1 are released
@@ -849,6 +879,7 @@ void make_slot(rbfgs_ctx* ctx, Slot& S) {
   S.G = (double*)dalloc(ctx, qq);
   if (ctx->psb) S.G2 = (double*)dalloc(ctx, qq);
   S.Z = (double*)dalloc(ctx, qq);
+  if (ctx->part) S.ht = (double*)dalloc(ctx, sizeof(double));
   if (!ctx->ada) {
     S.Y = dalloc(ctx, np * qp * es);
     S.Ginv = (double*)dalloc(ctx, qq);
@@ -903,8 +934,9 @@ void set_params(rbfgs_ctx* ctx, const rbfgs_params& p) {
   ctx->rowv = ctx->kacz || p.variant == RBFGS_AIP;
   ctx->ns = p.variant == RBFGS_NEWTON_SCHULZ;
   ctx->mr = p.variant == RBFGS_MR;
+  ctx->part = p.sketch == RBFGS_SKETCH_PARTITION;
   ctx->dcoord = p.sketch == RBFGS_SKETCH_COORD && (ctx->psb || ctx->rowv);
-  ctx->coord = p.sketch == RBFGS_SKETCH_COORD && !ctx->dcoord;
+  ctx->coord = (p.sketch == RBFGS_SKETCH_COORD && !ctx->dcoord) || ctx->part;
   ctx->mdt = ctx->mixed ? DT_F32 : DT_F64;
   ctx->bf16q = RB_BF16_Q && ctx->mixed && p.variant == RBFGS_FIXED && !ctx->coord && ctx->qp % 128 == 0;
   ctx->bf16h = ctx->bf16q && 8 * ctx->qp <= ctx->np;
@@ -938,6 +970,7 @@ void allocate(rbfgs_ctx* ctx) {
     if (ctx->mr) ctx->Q2 = (double*)dalloc(ctx, (size_t)np * np * sizeof(double));
   }
   ctx->scal = (double*)dalloc(ctx, 8 * sizeof(double));
+  if (ctx->part) ctx->tw = (double*)dalloc(ctx, np * sizeof(double));
   if (!ctx->ada && ctx->coord) ctx->R = dalloc(ctx, qp * np * es);
   const size_t qq = (size_t)qp * qp * sizeof(double);
   ctx->G = (double*)dalloc(ctx, qq);
@@ -975,7 +1008,9 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
   if (!params || !A) return RBFGS_E_INVALID_ARG;
   const rbfgs_params& p = *params;
   if (p.n < 1 || p.q < 1 || p.q > p.n || p.q > 1024 || lda < p.n || (a_dtype != RBFGS_F32 && a_dtype != RBFGS_F64) ||
-      (p.sketch != RBFGS_SKETCH_GAUSS && p.sketch != RBFGS_SKETCH_COORD) ||
+      (p.sketch != RBFGS_SKETCH_GAUSS && p.sketch != RBFGS_SKETCH_COORD && p.sketch != RBFGS_SKETCH_PARTITION) ||
+      (p.sketch == RBFGS_SKETCH_PARTITION &&
+       ((p.variant != RBFGS_FIXED && p.variant != RBFGS_ADAPTIVE) || p.n % p.q != 0)) ||
       (p.variant < RBFGS_FIXED || p.variant > RBFGS_MR) ||
       ((p.variant == RBFGS_NEWTON_SCHULZ || p.variant == RBFGS_MR) && p.precision != RBFGS_FP64) ||
       (p.precision != RBFGS_FP64 && p.precision != RBFGS_MIXED) || p.check_every < 0 || p.n > (1ll << 20))
@@ -1030,6 +1065,7 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
     } else {
       HIPCHK(set_identity(ctx->X, ctx->mdt, np, p.n, ctx->main.s));
     }
+    if (ctx->part) HIPCHK(diag_weights(ctx->A, ctx->mdt, np, p.n, ctx->tw, ctx->main.s));  // L_0 = I
     const double nanv = NAN;
     HIPCHK(hipMemcpyAsync(ctx->est, &nanv, sizeof(double), hipMemcpyHostToDevice, ctx->main.s));
     HIPCHK(hipStreamSynchronize(ctx->main.s));
@@ -1089,24 +1125,32 @@ rbfgs_status rbfgs_invert(rbfgs_ctx* ctx, double tol, int64_t max_iters, int64_t
   if (!ctx || !(tol > 0) || max_iters < 0) return RBFGS_E_INVALID_ARG;
   int64_t done = 0;
   double resid = NAN;
-  double thresh = tol * tol * (double)ctx->n;  // estimator target for ||I - XA||_F^2
+  const double target = tol * tol * (double)ctx->n;  // estimator target for ||I - XA||_F^2
+  double thresh = target;
   rbfgs_status result = RBFGS_E_NOT_CONVERGED;
   try {
     while (done < max_iters) {
       const int64_t m = std::min<int64_t>(ctx->p.check_every, max_iters - done);
+      // the trigger is the mean of the window's m estimates (each unbiased; a single one
+      // can be ~0, e.g. a partition block drawn again right after it was projected)
+      HIPCHK(hipMemsetAsync(ctx->est + 2, 0, sizeof(double), ctx->main.s));
       enqueue_steps(ctx, m);
       done += m;
       rbfgs_status st = read_status(ctx);
       if (st != RBFGS_OK) { result = st; break; }
       double est = 0;
-      HIPCHK(hipMemcpyAsync(&est, ctx->est, sizeof(double), hipMemcpyDeviceToHost, ctx->main.s));
+      HIPCHK(hipMemcpyAsync(&est, ctx->est + 2, sizeof(double), hipMemcpyDeviceToHost, ctx->main.s));
       HIPCHK(hipStreamSynchronize(ctx->main.s));
+      est /= (double)m;
       if (est <= thresh) {
         const double r = exact_residual(ctx);
         resid = r / sqrt((double)ctx->n);
         if (resid <= tol) { result = RBFGS_OK; break; }
-        // the estimate runs below the exact value: scale the trigger by the observed ratio
-        if (r > 0 && est > 0) thresh = std::min(thresh, tol * tol * (double)ctx->n * est / (r * r));
+        // the estimate runs below the exact value: scale the trigger by the observed ratio,
+        // at most down to 1% of the target (so that estimates at the rounding floor still
+        // trigger a check)
+        if (r > 0 && est > 0)
+          thresh = std::min(thresh, std::max(0.01 * target, target * est / (r * r)));
       }
     }
   } catch (const Fail& f) {
@@ -1199,6 +1243,7 @@ rbfgs_status rbfgs_set_state(rbfgs_ctx* ctx, const void* M, int32_t m_dtype, int
     if (ctx->rowv) HIPCHK(copy_transpose(src, sdt, ldm, ctx->X, ctx->mdt, ctx->np, n, n, ctx->main.s));  // X^T
     else HIPCHK(copy_convert(src, sdt, ldm, ctx->X, ctx->mdt, ctx->np, n, n, ctx->main.s));
     HIPCHK(hipMemsetAsync(ctx->status, 0, sizeof(int), ctx->main.s));
+    if (ctx->part && ctx->ada) refresh_part_weights(ctx);
     HIPCHK(hipStreamSynchronize(ctx->main.s));
     if (staging) HIPCHK(hipFree(staging));
     ctx->k = k;
@@ -1206,6 +1251,27 @@ rbfgs_status rbfgs_set_state(rbfgs_ctx* ctx, const void* M, int32_t m_dtype, int
     return f.st;
   }
   return RBFGS_OK;
+}
+
+rbfgs_status rbfgs_get_weights(rbfgs_ctx* ctx, double* out) {
+  if (!ctx || !out || !ctx->part) return RBFGS_E_INVALID_ARG;
+  try {
+    rbfgs_status st = read_status(ctx);
+    if (st != RBFGS_OK) return st;
+    HIPCHK(hipMemcpyAsync(out, ctx->tw, (size_t)ctx->n * sizeof(double), hipMemcpyDeviceToHost, ctx->main.s));
+    HIPCHK(hipStreamSynchronize(ctx->main.s));
+  } catch (const Fail& f) {
+    return f.st;
+  }
+  return RBFGS_OK;
+}
+
+rbfgs_status rbfgs_sample_partition(const double* t_dev, int64_t n, int32_t q, uint64_t seed, int64_t k,
+                                    int32_t* idx_dev, double* ht_dev, void* hip_stream) {
+  if (!t_dev || !idx_dev || n < 1 || q < 1 || q > n || n % q != 0 || k < 0 || n > (1ll << 20))
+    return RBFGS_E_INVALID_ARG;
+  hipError_t e = sample_partition(t_dev, n, q, seed, k, idx_dev, ht_dev, nullptr, (hipStream_t)hip_stream);
+  return e == hipSuccess ? RBFGS_OK : RBFGS_E_DEVICE;
 }
 
 rbfgs_status rbfgs_get_iter(const rbfgs_ctx* ctx, int64_t* k_out) {

@@ -36,7 +36,7 @@ RB_DEV u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
   return {c0, c1, c2, c3};
 }
 
-enum : uint64_t { KIND_GAUSS = 1, KIND_COORD = 2 };
+enum : uint64_t { KIND_GAUSS = 1, KIND_COORD = 2, KIND_PART = 3 };
 
 // (x >> 11) + 0.5 scaled by 2^-53: a double strictly inside (0, 1).
 RB_DEV double u53(uint64_t x) { return ((double)(x >> 11) + 0.5) * 0x1p-53; }

@@ -403,33 +403,40 @@ __global__ void k_est_partial(const void* Sk, int sk_dt, const int32_t* C, const
   if (threadIdx.x == 0) red[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = t;
 }
 
-__global__ void k_reduce_sum(const double* in, int64_t count, double* out, double scale, int* status) {
+// *out = scale * dscale * sum; with win, the value is also added to out[2] (the sum of
+// the estimates since the host last cleared it).
+__global__ void k_reduce_sum(const double* in, int64_t count, double* out, double scale, int* status,
+                             const double* dscale, int win) {
   __shared__ double sh[4];
   double s = 0;
   for (int64_t e = threadIdx.x; e < count; e += 256) s += in[e];
   const double t = block_sum_256(s, sh);
   if (threadIdx.x == 0) {
-    *out = t * scale;
+    const double v = t * scale * (dscale ? *dscale : 1.0);
+    *out = v;
+    if (win) out[2] += v;
     if (status && !isfinite(t)) atomicCAS(status, 0, 4);
   }
 }
 
 hipError_t reduce_sum(const double* in, int64_t count, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, in, count, out, 1.0, (int*)nullptr);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, in, count, out, 1.0, (int*)nullptr,
+                     (const double*)nullptr, 0);
   return hipGetLastError();
 }
 
 hipError_t estimator(const void* Sk, int sk_dt, const int32_t* C, const void* V, int v_dt, int64_t ld, int64_t n,
-                     int q, double scale, double* red, double* est, int* status, hipStream_t s) {
+                     int q, double scale, double* red, double* est, int* status, hipStream_t s, const double* dscale) {
   const dim3 grid((unsigned)((n + 255) / 256), (unsigned)((q + 15) / 16));
   hipLaunchKernelGGL(k_est_partial, grid, dim3(256), 0, s, Sk, sk_dt, C, V, v_dt, ld, n, q, red);
-  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, red, (int64_t)grid.x * grid.y, est, scale, status);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, red, (int64_t)grid.x * grid.y, est, scale, status,
+                     dscale, 1);
   return hipGetLastError();
 }
 
 hipError_t reduce_sum_scaled(const double* in, int64_t count, double* out, double scale, int* status,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, in, count, out, scale, status);
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, s, in, count, out, scale, status, (const double*)nullptr, 1);
   return hipGetLastError();
 }
 
@@ -896,6 +903,66 @@ hipError_t coord_dense(const int32_t* C, int q, void* S, int dt, int64_t ld, int
   const int64_t total = ld * qp;
   hipLaunchKernelGGL(k_coord_dense, dim3((unsigned)std::min<int64_t>(ceil_div(total, 256), 8192)), dim3(256), 0, s, C,
                      q, S, dt, ld, qp);
+  return hipGetLastError();
+}
+
+
+// ---------------------------------------------------------------- partition weights
+// t_j = A_jj in FP64 for j < n (the weights of fixed RBFGS, and of AdaRBFGS at L = I).
+__global__ void k_diag_weights(const void* A, int dt, int64_t ld, int64_t n, double* t) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < n) t[j] = load_any(A, dt, j * ld + j);
+}
+
+hipError_t diag_weights(const void* A, int dt, int64_t ld, int64_t n, double* t, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, A, dt, ld, n, t);
+  return hipGetLastError();
+}
+
+// AdaRBFGS weight update t_j = (L^T A L)_jj from one step's panels (n x q column-major,
+// leading dimension ld): with V = L^T Y and W = -L^T Y G^-1, sum_c V_jc W_jc = -||K_j||^2
+// for K = L^T Y L_G^-T, and L+^T A L+ = L^T A L - K K^T + S~ (S~^T S~)^-1 S~^T, whose last
+// term is the identity on the drawn block [C[0], C[0] + q) for a coordinate block.
+__global__ void k_part_weights(const void* V, const void* W, int dt, int64_t ld, int64_t n, int q, const int32_t* C,
+                               double* t) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double acc = 0.0;
+  for (int c = 0; c < q; ++c) acc += load_any(V, dt, j + c * ld) * load_any(W, dt, j + c * ld);
+  const int64_t c0 = C[0];
+  t[j] += acc + ((j >= c0 && j < c0 + q) ? 1.0 : 0.0);
+}
+
+hipError_t part_weights(const void* V, const void* W, int dt, int64_t ld, int64_t n, int q, const int32_t* C, double* t,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(k_part_weights, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, V, W, dt, ld, n, q, C, t);
+  return hipGetLastError();
+}
+
+// t[C[c]] = sum_r P_rc Q_rc for the first q columns of two n x q column-major panels (one
+// workgroup per column): the diagonal of L^T A L block by block, with P = L I_{:C}, Q = A P.
+__global__ void k_col_dots(const void* P, const void* Q, int dt, int64_t ld, int64_t n, const int32_t* C, double* t) {
+  __shared__ double sh[4];
+  const int c = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t r = threadIdx.x; r < n; r += 256) acc += load_any(P, dt, r + c * ld) * load_any(Q, dt, r + c * ld);
+  const double v = block_sum_256(acc, sh);
+  if (threadIdx.x == 0) t[C[c]] = v;
+}
+
+hipError_t col_dots(const void* P, const void* Q, int dt, int64_t ld, int64_t n, int q, const int32_t* C, double* t,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(k_col_dots, dim3((unsigned)q), dim3(256), 0, s, P, Q, dt, ld, n, C, t);
+  return hipGetLastError();
+}
+
+// idx[c] = start + c, c < q.
+__global__ void k_fill_block(int32_t* idx, int64_t start, int q) {
+  for (int c = threadIdx.x; c < q; c += blockDim.x) idx[c] = (int32_t)(start + c);
+}
+
+hipError_t fill_block(int32_t* idx, int64_t start, int q, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_block, dim3(1), dim3(256), 0, s, idx, start, q);
   return hipGetLastError();
 }
 

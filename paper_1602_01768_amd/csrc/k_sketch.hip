@@ -120,4 +120,97 @@ hipError_t sketch_coord(uint64_t seed, int64_t k, int64_t n, int32_t q, int32_t*
   return hipGetLastError();
 }
 
+
+// Partition sampling (the probabilities of eq. ihsih0 over consecutive blocks
+// C_i = [i q, (i+1) q), q dividing n): block weight w_i = max(0, sum_{j in C_i} t_j),
+// summed in index order; block i is the first whose running weight sum exceeds u times
+// the total, u = ((x >> 11) + 0.5) 2^-53 from word 0 of block 0 of iteration k's stream
+// (kind 3).  One workgroup: each thread sums a contiguous run of blocks, thread 0 scans
+// the run totals in order, and the thread whose run holds the crossing scans it again
+// from the running sum before it (if rounding leaves no crossing, the last block with
+// positive weight is drawn).  Writes idx[0..q) = C_i and ht = total / w_i, the
+// Horvitz-Thompson factor 1/p_i.  A total that is not finite and positive sets status 4
+// and draws block 0.
+__global__ __launch_bounds__(256) void k_sample_partition(const double* t, int64_t n, int q, uint64_t seed, uint64_t k,
+                                                          int32_t* idx, double* ht, int* status) {
+  __shared__ double run[256];
+  __shared__ double sh_thr, sh_before, sh_total;
+  __shared__ int sh_owner;
+  __shared__ int64_t sh_pick;
+  const int64_t r = n / q;
+  const int64_t per = (r + 255) / 256;
+  const int64_t b0 = min<int64_t>(r, (int64_t)threadIdx.x * per), b1 = min<int64_t>(r, b0 + per);
+  auto weight = [&](int64_t b) {
+    double w = 0.0;
+    for (int64_t j = b * q; j < (b + 1) * q; ++j) w += t[j];
+    return w > 0.0 ? w : 0.0;
+  };
+  double mine = 0.0;
+  for (int64_t b = b0; b < b1; ++b) mine += weight(b);
+  run[threadIdx.x] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double total = 0.0;
+    for (int i = 0; i < 256; ++i) total += run[i];
+    const u64x4 w = philox4x64_10(0, k, KIND_PART, 0, seed, 0);
+    const double u = ((double)(w.x >> 11) + 0.5) * 0x1.0p-53;
+    const double thr = u * total;
+    int owner = -1, last = -1;
+    double c = 0.0, before = 0.0, before_last = 0.0;
+    for (int i = 0; i < 256; ++i) {
+      if (!(run[i] > 0.0)) continue;
+      if (c + run[i] > thr) {
+        owner = i;
+        before = c;
+        break;
+      }
+      last = i;
+      before_last = c;
+      c += run[i];
+    }
+    if (owner < 0) {
+      owner = last;
+      before = before_last;
+    }
+    if (!(total > 0.0) || !isfinite(total)) {
+      owner = -1;
+      if (status) atomicCAS(status, 0, 4);
+    }
+    sh_owner = owner;
+    sh_thr = thr;
+    sh_before = before;
+    sh_total = total;
+    sh_pick = 0;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x == sh_owner) {
+    double c = sh_before;
+    int64_t pick = -1, last = b0;
+    for (int64_t b = b0; b < b1; ++b) {
+      const double w = weight(b);
+      if (!(w > 0.0)) continue;
+      last = b;
+      c += w;
+      if (c > sh_thr) {
+        pick = b;
+        break;
+      }
+    }
+    pick = pick >= 0 ? pick : last;
+    sh_pick = pick;
+    if (ht) ht[0] = sh_total / weight(pick);
+  } else if (threadIdx.x == 0 && sh_owner < 0 && ht) {
+    ht[0] = 1.0;
+  }
+  __syncthreads();
+  const int64_t pick = sh_pick;
+  for (int c = threadIdx.x; c < q; c += blockDim.x) idx[c] = (int32_t)(pick * q + c);
+}
+
+hipError_t sample_partition(const double* t, int64_t n, int32_t q, uint64_t seed, int64_t k, int32_t* idx, double* ht,
+                            int* status, hipStream_t s) {
+  hipLaunchKernelGGL(k_sample_partition, dim3(1), dim3(256), 0, s, t, n, (int)q, seed, (uint64_t)k, idx, ht, status);
+  return hipGetLastError();
+}
+
 }  // namespace rb

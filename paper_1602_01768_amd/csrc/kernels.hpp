@@ -121,13 +121,15 @@ hipError_t gather_cols_sym(const void* A, int a_dt, int64_t lda, const int32_t* 
 hipError_t gather_cols_gen(const void* L, int l_dt, int64_t ldl, const int32_t* C, int q,
                            int64_t np, void* S, int s_dt, int64_t lds, hipStream_t s);
 // sum (Sk - V)^2 over the n x q block, Sk dense (sk_dt) or coordinate (C != null).
-// Writes est = sum * scale to *est, sets *status = 4 when not finite.
+// Writes est = sum * scale (* dscale[0] when given) to est[0] and adds it to est[2] (the
+// window sum the stopping test reads); sets *status = 4 when not finite.
 hipError_t estimator(const void* Sk, int sk_dt, const int32_t* C, const void* V, int v_dt,
                      int64_t ld, int64_t n, int q, double scale, double* red, double* est,
-                     int* status, hipStream_t s);
+                     int* status, hipStream_t s, const double* dscale = nullptr);
 // Deterministic sum of `count` doubles into *out (single workgroup).
 hipError_t reduce_sum(const double* in, int64_t count, double* out, hipStream_t s);
-// *out = scale * sum of `count` doubles; *status = 4 when the sum is not finite.
+// out[0] = scale * sum of `count` doubles, also added to out[2] (an estimate's window sum);
+// *status = 4 when the sum is not finite.
 hipError_t reduce_sum_scaled(const double* in, int64_t count, double* out, double scale, int* status,
                              hipStream_t s);
 // rows C_a of W' (col-major, ld): W'[C_a + b*ld] -= 0.5*(a==b) + 0.5*GH[a*ldgh + b]
@@ -179,5 +181,22 @@ hipError_t cg_xr(double* x, double* r, const double* p, const double* Ap, int64_
 hipError_t cg_p(double* p, const double* z, int64_t n, const double* sc, int num, int den, hipStream_t s);
 // Dense ld x qp column-major coordinate sketch from the indices C (q of them): ones at (C_j, j).
 hipError_t coord_dense(const int32_t* C, int q, void* S, int dt, int64_t ld, int64_t qp, hipStream_t s);
+
+
+// ---- partition sampling (eq. ihsih0 over consecutive blocks of q; q divides n)
+// Draw block i of [0, n/q) with probability w_i / sum w, w_i = max(0, sum_{j in C_i} t_j),
+// from word 0 of iteration k's stream (kind 3); idx[0..q) = C_i; ht = 1/p_i (optional).
+hipError_t sample_partition(const double* t, int64_t n, int32_t q, uint64_t seed, int64_t k, int32_t* idx, double* ht,
+                            int* status, hipStream_t s);
+// t_j = A_jj (FP64), j < n.
+hipError_t diag_weights(const void* A, int dt, int64_t ld, int64_t n, double* t, hipStream_t s);
+// t_j += sum_c V_jc W_jc + [C[0] <= j < C[0] + q]  (AdaRBFGS: V = L^T Y, W = -L^T Y G^-1).
+hipError_t part_weights(const void* V, const void* W, int dt, int64_t ld, int64_t n, int q, const int32_t* C, double* t,
+                        hipStream_t s);
+// t[C[c]] = sum_r P_rc Q_rc, c < q (column-major n x q panels).
+hipError_t col_dots(const void* P, const void* Q, int dt, int64_t ld, int64_t n, int q, const int32_t* C, double* t,
+                    hipStream_t s);
+// idx[c] = start + c, c < q.
+hipError_t fill_block(int32_t* idx, int64_t start, int q, hipStream_t s);
 
 }  // namespace rb

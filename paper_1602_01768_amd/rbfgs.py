@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "librbfgs.so")
 OK, E_INVALID_ARG, E_OOM, E_NOT_SPD, E_NONFINITE, E_NOT_CONVERGED, E_DEVICE = range(7)
 STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_OOM", 3: "E_NOT_SPD", 4: "E_NONFINITE",
                 5: "E_NOT_CONVERGED", 6: "E_DEVICE"}
-SKETCH = {"gauss": 0, "coord": 1, "cols": 1}
+SKETCH = {"gauss": 0, "coord": 1, "cols": 1, "partition": 2}
 VARIANT = {"fixed": 0, "adaptive": 1, "ada": 1, "psb": 2, "aip": 3, "kaczmarz": 4, "newton_schulz": 5,
            "mr": 6}
 PRECISION = {"fp64": 0, "mixed": 1}
@@ -83,6 +83,9 @@ EXPORTS = {
                                           ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "rbfgs_sketch_coord": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                           ctypes.c_void_p, ctypes.c_void_p]),
+    "rbfgs_sample_partition": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64,
+                                              ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "rbfgs_get_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "rbfgs_footprint": (ctypes.c_int, [ctypes.POINTER(rbfgs_params), ctypes.POINTER(ctypes.c_int64)]),
     "rbfgs_server_create": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]),
     "rbfgs_server_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rbfgs_params), ctypes.c_void_p,
@@ -302,6 +305,26 @@ def rbfgs_sketch_coord(seed, k, n, q, stream=None):
     return out
 
 
+def rbfgs_sample_partition(t, q, seed, k, stream=None):
+    """Partition draw of iteration k from the FP64 weights t (a CUDA tensor of n):
+    returns (the q indices of the drawn block as an int32 CUDA tensor, 1/p_i)."""
+    import torch
+    tt = t.to(device="cuda", dtype=torch.float64).contiguous()
+    idx = torch.zeros(q, dtype=torch.int32, device="cuda")
+    ht = torch.zeros(1, dtype=torch.float64, device="cuda")
+    _check(load_library().rbfgs_sample_partition(ctypes.c_void_p(tt.data_ptr()), int(tt.numel()), int(q), int(seed),
+                                                 int(k), ctypes.c_void_p(idx.data_ptr()),
+                                                 ctypes.c_void_p(ht.data_ptr()), _stream_handle(stream)))
+    return idx, ht
+
+
+def rbfgs_get_weights(ctx, n):
+    """The n per-coordinate partition weights of the context (numpy FP64)."""
+    out = np.empty(int(n), dtype=np.float64)
+    _check(load_library().rbfgs_get_weights(ctx, out.ctypes.data_as(ctypes.c_void_p)), ctx)
+    return out
+
+
 def _params(n, q, seed, sketch, variant, precision, check_every):
     return rbfgs_params(n=int(n), q=int(q), seed=int(seed), sketch=SKETCH[sketch], variant=VARIANT[variant],
                         precision=PRECISION[precision], check_every=int(check_every))
@@ -412,6 +435,10 @@ class Solver:
 
     def residual(self):
         return rbfgs_residual(self.ctx)
+
+    def weights(self):
+        """Partition weights: the diagonal of A (fixed) or of L_k^T A L_k (AdaRBFGS)."""
+        return rbfgs_get_weights(self.ctx, self.n)
 
     def estimate(self):
         return rbfgs_estimate(self.ctx)
