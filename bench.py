@@ -315,6 +315,55 @@ def time_to_tolerance(A_dev, A32, q, seed, tol, max_iters, torch, rbfgs, pcg=Tru
     return out
 
 
+def sampling_section(A_dev, A32, q, seed, torch, rbfgs, tol=1e-3, cap=4000, steps=20, cpu_n=2048):
+    """AdaRBFGS (mixed) on the same matrix with three sketch distributions: Gaussian,
+    uniform coordinates, and the partition of Sec. 9.3 drawn with the probabilities of
+    eq. ihsih0 (q divides n): iters/s over `steps` timed iterations, the phases of the
+    partition run (the draw and the O(nq) weight update, with the weight kernel's HBM
+    roofline: it reads the two n x q FP32 panels and reads and writes the n FP64
+    weights), and the time to ||I - AX||_F / sqrt(n) <= tol from L_0 = I.  The oracle's
+    partition AdaRBFGS iteration (its weights from the definition, n^3 per iteration) is
+    timed at n = cpu_n."""
+    import numpy as np
+    from oracle import partition as Pt
+    n = A_dev.shape[0]
+    out = {"tol": tol}
+    for sk in ("gauss", "coord", "partition"):
+        row = {}
+        s, dt, _ = timed_steps(rbfgs.Solver, A_dev, q, seed, sk, "adaptive", "mixed", 3, steps, torch)
+        row["iters_per_s"] = round(steps / dt, 2)
+        if sk == "partition":
+            s.profile(1)
+            s.step(10)
+            rep = s.profile_report()
+            s.profile(0)
+            ph = {k: v[0] / max(v[1], 1) for k, v in rep.items()}
+            row["phases_ms"] = {k: round(v, 4) for k, v in ph.items()}
+            if ph.get("weights"):
+                nbytes = 2.0 * n * q * 4 + 16.0 * n
+                gbs = nbytes / (ph["weights"] * 1e-3) / 1e9
+                row["weights_roofline"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                                           "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                                           "alg_bytes_per_launch": nbytes}
+        s.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with rbfgs.Solver(A_dev, q, seed, sketch=sk, variant="adaptive", precision="mixed") as s2:
+            ok, iters, resid = s2.invert(tol, cap)
+        torch.cuda.synchronize()
+        row.update({"converged": bool(ok), "iters": iters, "resid": resid,
+                    "seconds": round(time.perf_counter() - t0, 3)})
+        out[sk] = row
+    m = max(q, min(cpu_n, n) // q * q)
+    Ac = np.asarray(A32[:m, :m], np.float64)
+    t0 = time.perf_counter()
+    Pt.run_ada(Ac, q, seed, 2)
+    t_cpu = (time.perf_counter() - t0) / 2
+    out["cpu_oracle"] = {"value": round(1.0 / t_cpu, 3), "unit": "iters/s", "kind": "oracle",
+                         "sample": f"2 oracle partition AdaRBFGS iterations at n={m}, q={q} (leading block of A)"}
+    return out
+
+
 def live_roofline(live, n, q, variant, sketch, traffic=None):
     """Roofline object of the dominant n x n product kernel (largest total live time)."""
     products = {k: v for k, v in live.items() if phase_roofline(k, n, q, variant, sketch)}
@@ -471,6 +520,8 @@ def main():
                     help="timed iterations of each of PSB, AIP and Kaczmarz (0: skip them)")
     ap.add_argument("--ttt-iters", type=int, default=4000,
                     help="iteration cap of the AdaRBFGS time-to-tolerance runs (0: skip them)")
+    ap.add_argument("--sampling-iters", type=int, default=4000,
+                    help="iteration cap of the AdaRBFGS sketch-distribution comparison (0: skip it)")
     ap.add_argument("--serve-jobs", type=int, default=64, help="serving trace length (0: skip serving)")
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
@@ -532,6 +583,10 @@ def main():
     ttt = (time_to_tolerance(A_dev, A32, q, args.seed, 1e-3, args.ttt_iters, torch, rbfgs)
            if args.ttt_iters > 0 else None)
 
+    # ---- sketch distributions for AdaRBFGS: Gaussian, uniform coordinates, partition (eq. ihsih0)
+    sampling = (sampling_section(A_dev, A32, q, args.seed, torch, rbfgs, cap=args.sampling_iters)
+                if args.sampling_iters > 0 and n % q == 0 else None)
+
     # ---- serving trace (p50 / p99 solve latency)
     serve = serving(args, torch, rbfgs) if args.serve_jobs > 0 else None
 
@@ -580,6 +635,7 @@ def main():
         "variants": variants,
         "experiment1": exp1,
         "time_to_tolerance_ada": ttt,
+        "sampling_ada": sampling,
         "serving": serve,
         "cpu_baseline": cpu,
         "parity": parity,

@@ -153,10 +153,14 @@ rbfgs_status rbfgs_step(rbfgs_ctx* ctx, int64_t nsteps);
 rbfgs_status rbfgs_sync(rbfgs_ctx* ctx);
 
 /* Iterate until ||I - A X_k||_F / sqrt(n) <= tol or max_iters total iterations
- * (Sec. 10 stops on a residual threshold).  Every check_every iterations the
- * per-step unbiased estimate of ||I - X A||_F^2 (from S - X A S, no extra
- * products; for the adaptive method it estimates ||I - L^T A L||_F^2) is read;
- * when it falls below (tol^2 n) the exact FP64 residual is computed and decides.
+ * (Sec. 10 stops on a residual threshold).  Every check_every iterations the mean
+ * of the window's per-step unbiased estimates of ||I - X A||_F^2 (from S - X A S, no
+ * extra products; for the adaptive method they estimate ||I - L^T A L||_F^2) is read;
+ * when it falls below the trigger (tol^2 n, lowered by the ratio estimate / exact
+ * residual^2 observed at each failed check) the exact FP64 residual is computed and
+ * decides.  A check is also forced after max(64 check_every, iterations so far)
+ * iterations without one (coordinate and partition sketches, whose estimates are
+ * heavy-tailed: max(16 check_every, half the iterations so far)).
  * iters_out: iterations performed by this call; resid_out: last exact
  * ||I - AX||_F / sqrt(n) (NaN if never computed).  Either may be NULL.
  * Returns OK on convergence, E_NOT_CONVERGED at max_iters, or a device error. */
@@ -208,8 +212,8 @@ const char* rbfgs_last_error(const rbfgs_ctx* ctx);
  * recorded on the stream each phase runs on, and clear the accumulated totals.
  * enable = 0 off, 1 every phase, 2 only the n x n products (AS, XY, LS, LtY,
  * update: the fewest events, for timing inside a measured run); other values
- * E_INVALID_ARG.  Phases: sketch, sketch_gram, gather, AS, LS, gram_G, chol_inv,
- * panel_U, XY, LtY, gram_H, estimator, panels, coord_update, update; a split-K
+ * E_INVALID_ARG.  Phases: sketch, sample, sketch_gram, gather, AS, LS, gram_G, chol_inv,
+ * panel_U, XY, LtY, gram_H, estimator, panels (containing weights), coord_update, update; a split-K
  * product also reports its reduction kernel as "<phase>.reduce", so that the
  * phase itself times the product kernel alone.
  * rbfgs_profile_report: synchronise and write a JSON object

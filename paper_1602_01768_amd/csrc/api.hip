@@ -653,7 +653,10 @@ void main_adaptive(rbfgs_ctx* ctx, Slot& S, int64_t k) {
     HIPCHK(estimator(ctx->coord ? nullptr : S.Sk, sk_dt(ctx), ctx->coord ? S.C : nullptr, ctx->V, mdt, np, ctx->n,
                      ctx->q, scale, L.red, ctx->est, ctx->status, L.s, ctx->part ? S.ht : nullptr));
     panel_times_small(ctx, L, ctx->V, mdt, ctx->Ginv, ctx->W, mdt, -1.0);  // Q^T = -T^T G^-1
-    if (ctx->part) HIPCHK(part_weights(ctx->V, ctx->W, mdt, np, ctx->n, ctx->q, S.C, ctx->tw, L.s));  // (L+^T A L+)_jj
+    if (ctx->part) {  // (L+^T A L+)_jj
+      Phase pw(ctx, L, "weights");
+      HIPCHK(part_weights(ctx->V, ctx->W, mdt, np, ctx->n, ctx->q, S.C, ctx->tw, L.s));
+    }
     if (ctx->coord) {
       HIPCHK(coord_add_rows(ctx->W, mdt, np, S.C, ctx->q, ctx->Z, qp, L.s));  // + E_C L_G^-1
     } else {
@@ -1127,6 +1130,13 @@ rbfgs_status rbfgs_invert(rbfgs_ctx* ctx, double tol, int64_t max_iters, int64_t
   double resid = NAN;
   const double target = tol * tol * (double)ctx->n;  // estimator target for ||I - XA||_F^2
   double thresh = target;
+  // a check is also forced after a gap without one, so that a trigger lowered by an
+  // unluckily small estimate cannot lock out the test: max(64 windows, iterations so far)
+  // for Gaussian sketches; max(16 windows, half the iterations so far) for coordinate and
+  // partition sketches, whose estimates are heavy-tailed when the residual sits in few
+  // columns (a typical window mean is then far below the true mean)
+  const int64_t force_base = (ctx->coord || ctx->dcoord ? 16 : 64) * (int64_t)ctx->p.check_every;
+  int64_t next_force = force_base;
   rbfgs_status result = RBFGS_E_NOT_CONVERGED;
   try {
     while (done < max_iters) {
@@ -1142,15 +1152,14 @@ rbfgs_status rbfgs_invert(rbfgs_ctx* ctx, double tol, int64_t max_iters, int64_t
       HIPCHK(hipMemcpyAsync(&est, ctx->est + 2, sizeof(double), hipMemcpyDeviceToHost, ctx->main.s));
       HIPCHK(hipStreamSynchronize(ctx->main.s));
       est /= (double)m;
-      if (est <= thresh) {
+      if (est <= thresh || done >= next_force) {
         const double r = exact_residual(ctx);
         resid = r / sqrt((double)ctx->n);
         if (resid <= tol) { result = RBFGS_OK; break; }
-        // the estimate runs below the exact value: scale the trigger by the observed ratio,
-        // at most down to 1% of the target (so that estimates at the rounding floor still
-        // trigger a check)
-        if (r > 0 && est > 0)
-          thresh = std::min(thresh, std::max(0.01 * target, target * est / (r * r)));
+        // the estimate runs below the exact value: scale the trigger by the ratio observed
+        // at this check (the latest, not the smallest: the ratio drifts as X converges)
+        if (r > 0 && est > 0) thresh = std::min(target, target * est / (r * r));
+        next_force = done + std::max<int64_t>(force_base, ctx->coord || ctx->dcoord ? done / 2 : done);
       }
     }
   } catch (const Fail& f) {

@@ -122,87 +122,127 @@ hipError_t sketch_coord(uint64_t seed, int64_t k, int64_t n, int32_t q, int32_t*
 
 
 // Partition sampling (the probabilities of eq. ihsih0 over consecutive blocks
-// C_i = [i q, (i+1) q), q dividing n): block weight w_i = max(0, sum_{j in C_i} t_j),
-// summed in index order; block i is the first whose running weight sum exceeds u times
-// the total, u = ((x >> 11) + 0.5) 2^-53 from word 0 of block 0 of iteration k's stream
-// (kind 3).  One workgroup: each thread sums a contiguous run of blocks, thread 0 scans
-// the run totals in order, and the thread whose run holds the crossing scans it again
-// from the running sum before it (if rounding leaves no crossing, the last block with
-// positive weight is drawn).  Writes idx[0..q) = C_i and ht = total / w_i, the
-// Horvitz-Thompson factor 1/p_i.  A total that is not finite and positive sets status 4
-// and draws block 0.
+// C_i = [i q, (i+1) q), q dividing n): block weight w_i = max(0, sum_{j in C_i} t_j);
+// block i is the first whose running weight sum exceeds u times the total,
+// u = ((x >> 11) + 0.5) 2^-53 from word 0 of block 0 of iteration k's stream (kind 3);
+// if rounding leaves no crossing, the last block with positive weight is drawn.  Writes
+// idx[0..q) = C_i and ht = total / w_i, the Horvitz-Thompson factor 1/p_i.  A total that
+// is not finite and positive sets status 4 and draws block 0.  One workgroup, two forms:
+//  * q >= 64 and at most SAMPLE_LDS blocks: one wave per block (lanes stride the block,
+//    a fixed shuffle tree adds them) into LDS, then thread 0 scans the block weights;
+//  * otherwise each thread sums a contiguous run of whole blocks, thread 0 scans the run
+//    totals, and the thread whose run holds the crossing scans it again.
+constexpr int SAMPLE_LDS = 4096;
+
 __global__ __launch_bounds__(256) void k_sample_partition(const double* t, int64_t n, int q, uint64_t seed, uint64_t k,
                                                           int32_t* idx, double* ht, int* status) {
+  __shared__ double wl[SAMPLE_LDS];
   __shared__ double run[256];
   __shared__ double sh_thr, sh_before, sh_total;
   __shared__ int sh_owner;
   __shared__ int64_t sh_pick;
   const int64_t r = n / q;
-  const int64_t per = (r + 255) / 256;
-  const int64_t b0 = min<int64_t>(r, (int64_t)threadIdx.x * per), b1 = min<int64_t>(r, b0 + per);
   auto weight = [&](int64_t b) {
     double w = 0.0;
     for (int64_t j = b * q; j < (b + 1) * q; ++j) w += t[j];
     return w > 0.0 ? w : 0.0;
   };
-  double mine = 0.0;
-  for (int64_t b = b0; b < b1; ++b) mine += weight(b);
-  run[threadIdx.x] = mine;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double total = 0.0;
-    for (int i = 0; i < 256; ++i) total += run[i];
-    const u64x4 w = philox4x64_10(0, k, KIND_PART, 0, seed, 0);
-    const double u = ((double)(w.x >> 11) + 0.5) * 0x1.0p-53;
-    const double thr = u * total;
-    int owner = -1, last = -1;
-    double c = 0.0, before = 0.0, before_last = 0.0;
-    for (int i = 0; i < 256; ++i) {
-      if (!(run[i] > 0.0)) continue;
-      if (c + run[i] > thr) {
-        owner = i;
-        before = c;
-        break;
+  const u64x4 words = philox4x64_10(0, k, KIND_PART, 0, seed, 0);
+  const double u = ((double)(words.x >> 11) + 0.5) * 0x1.0p-53;
+  if (q >= 64 && r <= SAMPLE_LDS) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int64_t b = wave; b < r; b += 4) {
+      double v = 0.0;
+      for (int j = lane; j < q; j += 64) v += t[b * q + j];
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      if (lane == 0) wl[b] = v > 0.0 ? v : 0.0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double total = 0.0;
+      for (int64_t b = 0; b < r; ++b) total += wl[b];
+      const double thr = u * total;
+      int64_t pick = -1, last = 0;
+      double c = 0.0;
+      for (int64_t b = 0; b < r; ++b) {
+        if (!(wl[b] > 0.0)) continue;
+        last = b;
+        c += wl[b];
+        if (c > thr) {
+          pick = b;
+          break;
+        }
       }
-      last = i;
-      before_last = c;
-      c += run[i];
-    }
-    if (owner < 0) {
-      owner = last;
-      before = before_last;
-    }
-    if (!(total > 0.0) || !isfinite(total)) {
-      owner = -1;
-      if (status) atomicCAS(status, 0, 4);
-    }
-    sh_owner = owner;
-    sh_thr = thr;
-    sh_before = before;
-    sh_total = total;
-    sh_pick = 0;
-  }
-  __syncthreads();
-  if ((int)threadIdx.x == sh_owner) {
-    double c = sh_before;
-    int64_t pick = -1, last = b0;
-    for (int64_t b = b0; b < b1; ++b) {
-      const double w = weight(b);
-      if (!(w > 0.0)) continue;
-      last = b;
-      c += w;
-      if (c > sh_thr) {
-        pick = b;
-        break;
+      if (pick < 0) pick = last;
+      const bool ok = total > 0.0 && isfinite(total);
+      if (!ok) {
+        pick = 0;
+        if (status) atomicCAS(status, 0, 4);
       }
+      sh_pick = pick;
+      if (ht) ht[0] = ok ? total / wl[pick] : 1.0;
     }
-    pick = pick >= 0 ? pick : last;
-    sh_pick = pick;
-    if (ht) ht[0] = sh_total / weight(pick);
-  } else if (threadIdx.x == 0 && sh_owner < 0 && ht) {
-    ht[0] = 1.0;
+    __syncthreads();
+  } else {
+    const int64_t per = (r + 255) / 256;
+    const int64_t b0 = min<int64_t>(r, (int64_t)threadIdx.x * per), b1 = min<int64_t>(r, b0 + per);
+    double mine = 0.0;
+    for (int64_t b = b0; b < b1; ++b) mine += weight(b);
+    run[threadIdx.x] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double total = 0.0;
+      for (int i = 0; i < 256; ++i) total += run[i];
+      const double thr = u * total;
+      int owner = -1, last = -1;
+      double c = 0.0, before = 0.0, before_last = 0.0;
+      for (int i = 0; i < 256; ++i) {
+        if (!(run[i] > 0.0)) continue;
+        if (c + run[i] > thr) {
+          owner = i;
+          before = c;
+          break;
+        }
+        last = i;
+        before_last = c;
+        c += run[i];
+      }
+      if (owner < 0) {
+        owner = last;
+        before = before_last;
+      }
+      if (!(total > 0.0) || !isfinite(total)) {
+        owner = -1;
+        if (status) atomicCAS(status, 0, 4);
+      }
+      sh_owner = owner;
+      sh_thr = thr;
+      sh_before = before;
+      sh_total = total;
+      sh_pick = 0;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x == sh_owner) {
+      double c = sh_before;
+      int64_t pick = -1, last = b0;
+      for (int64_t b = b0; b < b1; ++b) {
+        const double w = weight(b);
+        if (!(w > 0.0)) continue;
+        last = b;
+        c += w;
+        if (c > sh_thr) {
+          pick = b;
+          break;
+        }
+      }
+      pick = pick >= 0 ? pick : last;
+      sh_pick = pick;
+      if (ht) ht[0] = sh_total / weight(pick);
+    } else if (threadIdx.x == 0 && sh_owner < 0 && ht) {
+      ht[0] = 1.0;
+    }
+    __syncthreads();
   }
-  __syncthreads();
   const int64_t pick = sh_pick;
   for (int c = threadIdx.x; c < q; c += blockDim.x) idx[c] = (int32_t)(pick * q + c);
 }
