@@ -20,8 +20,9 @@ Modules
   ridge    the ridge-regression Hessian scale B^T B + lam I (eq. ridgeMatrix).
   pcg      preconditioned CG for A x = b with X ~ A^-1 as the preconditioner.
   partition  partition sampling with the probabilities of eq. (ihsih0) for fixed
-           RBFGS and AdaRBFGS (Sec. 9.3), the draw from the stream, and the
-           Horvitz-Thompson residual estimator.
+           RBFGS and AdaRBFGS (Sec. 9.3), the draw from the stream, the
+           Horvitz-Thompson residual estimator, and Kaczmarz with the importance
+           probabilities of eq. (discoptprob) taking X_k as the proxy for A^-1.
   theory   closed-form quantities used by the pins: the rate rho of Thm 6.2 /
            eq. rhoequiv, E[Z] for discrete sketches (Prop. 7.1), brute-force
            projections (eq. NF, eq. NFsym) by a dense KKT solve.

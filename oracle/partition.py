@@ -111,3 +111,46 @@ def estimator_ada(L, A, C, p):
     n = A.shape[0]
     S = coord_matrix(C, n)
     return float(np.sum((S - L.T @ (A @ (L @ S))) ** 2)) / p
+
+
+# ---------------------------------------------------------------- importance (eq. discoptprob)
+# Simultaneous randomized Kaczmarz (Alg. 1 with W = I, eq. badbroyadj) over the same
+# partition, S = I_{:C_i}, with the probabilities that minimise the bound gamma(p) of
+# eq. (98h9s8h8s): p_i proportional to ||W^1/2 A^-1 Sbar_i S_i^T A W^-1/2||_F with W = I and
+# Sbar_i = S_i (the partition's S is the identity), and the iterate X_k in place of the
+# unknown A^-1 (the heuristic of Sec. 7.2): p_i proportional to ||X_k I_{:C_i} I_{C_i:} A||_F,
+# recomputed at every iteration (for q = 1 the paper's example ||X_k e_i|| ||e_i^T A||).
+
+def block_weights_importance(X, A, q):
+    """||X I_{:C_i} I_{C_i:} A||_F for every block (eq. discoptprob with A^-1 -> X)."""
+    X = np.asarray(X, dtype=np.float64)
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    out = []
+    for C in blocks(n, q):
+        E = coord_matrix(C, n)
+        out.append(np.linalg.norm(X @ E @ E.T @ A))
+    return np.array(out)
+
+
+def run_kaczmarz_importance(A, q, seed, iters, X0=None, record=None):
+    """Kaczmarz steps (eq. badbroyadj) with S = I_{:C_i}, i drawn by the weights of X_k."""
+    from . import variants as _v
+    A = np.asarray(A, dtype=np.float64)
+    n = A.shape[0]
+    parts = blocks(n, q)
+    X = np.eye(n) if X0 is None else np.array(X0, dtype=np.float64)
+    for k in range(iters):
+        i = draw(block_weights_importance(X, A, q), uniform(seed, k))
+        X = _v.kaczmarz_step(X, A, coord_matrix(parts[i], n))
+        if record is not None:
+            record(k, X, i)
+    return X
+
+
+def estimator_rows(X, A, C, p):
+    """||I_{C:} (I - A X)||_F^2 / p_C, unbiased for ||I - A X||_F^2 (the rows of the
+    blocks cover every row once)."""
+    n = A.shape[0]
+    S = coord_matrix(C, n)
+    return float(np.sum((S.T - S.T @ A @ X) ** 2)) / p

@@ -154,3 +154,69 @@ def test_converges(which):
         L = Pt.run_ada(A, q, 1, 60)
         X = L @ L.T
     assert np.linalg.norm(X - Ainv) <= 1e-6 * np.linalg.norm(Ainv)
+
+
+# ---------------------------------------------------------------- importance (eq. discoptprob)
+def kaczmarz_Z(A, S):
+    """Z = A^T S (S^T A A^T S)^-1 S^T A, Alg. 1 with W = I."""
+    P = A.T @ S
+    return P @ np.linalg.solve(P.T @ P, P.T)
+
+
+def gamma(A, outs, p):
+    """gamma(p) = 1 - 1 / Tr(E[Z_p]^-1) (eq. 98h9s8h8s with W = I)."""
+    EZ = sum(pi * kaczmarz_Z(A, S) for pi, S in zip(p, outs))
+    return 1.0 - 1.0 / np.trace(np.linalg.inv(EZ))
+
+
+def general_matrix(n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((n, n)) / np.sqrt(n) + 2.0 * np.eye(n) + np.diag(np.linspace(0.0, 3.0, n))
+
+
+@pytest.mark.parametrize("q", [1, 2, 3])
+def test_importance_with_exact_inverse_is_optimal(q):
+    """With X = A^-1 the weights are those of eq. (discoptprob): gamma at them equals the
+    closed form 1 - (sum_i w_i)^-2 of eq. (discoptrate) and is below gamma at every other p
+    tried (uniform, the squared weights, random points of the simplex)."""
+    n = 6
+    A = general_matrix(n, q)
+    Ainv = np.linalg.inv(A)
+    outs = [coord_matrix(C, n) for C in Pt.blocks(n, q)]
+    w = Pt.block_weights_importance(Ainv, A, q)
+    p = Pt.probabilities(w)
+    g = gamma(A, outs, p)
+    assert abs(g - (1.0 - w.sum() ** -2)) <= 1e-12
+    rng = np.random.default_rng(0)
+    others = [np.full(len(outs), 1.0 / len(outs)), Pt.probabilities(w ** 2)]
+    others += list(rng.dirichlet(np.ones(len(outs)), size=20))
+    for po in others:
+        assert gamma(A, outs, po) >= g - 1e-12
+
+
+def test_importance_single_coordinates_is_product_of_norms():
+    """q = 1: ||X e_i e_i^T A||_F = ||X e_i|| ||e_i^T A|| (the example of Sec. 7.2)."""
+    n = 7
+    A = general_matrix(n, 3)
+    X = np.random.default_rng(4).standard_normal((n, n))
+    w = Pt.block_weights_importance(X, A, 1)
+    ref = np.linalg.norm(X, axis=0) * np.linalg.norm(A, axis=1)
+    assert np.allclose(w, ref, rtol=1e-13)
+
+
+def test_importance_estimator_mean_is_residual():
+    n, q = 12, 3
+    A = general_matrix(n, 5)
+    X = Pt.run_kaczmarz_importance(A, q, 2, 5)
+    p = Pt.probabilities(Pt.block_weights_importance(X, A, q))
+    est = [Pt.estimator_rows(X, A, C, pi) for C, pi in zip(Pt.blocks(n, q), p)]
+    ref = np.linalg.norm(np.eye(n) - A @ X) ** 2
+    assert abs(float(np.dot(p, est)) - ref) <= 1e-12 * ref
+
+
+def test_importance_kaczmarz_converges():
+    """Not guaranteed by the theory (Sec. 7.2); on this well-conditioned matrix it converges."""
+    n, q = 24, 4
+    A = general_matrix(n, 6)
+    X = Pt.run_kaczmarz_importance(A, q, 1, 1500)
+    assert np.linalg.norm(np.eye(n) - A @ X) <= 1e-8 * np.sqrt(n)
