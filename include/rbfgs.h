@@ -56,6 +56,13 @@
  * (n^3 flops) by rbfgs_set_state.  Draw: word 0 of block 0 of the kind-3 stream gives
  * u = ((x>>11)+0.5) 2^-53; the first block whose running weight sum exceeds u times the
  * total is taken.  The estimator carries the factor 1/p_i (unbiased, Horvitz-Thompson).
+ * RBFGS_SKETCH_IMPORTANCE (Kaczmarz only; q must divide n): the same partition and draw,
+ * with the probabilities of eq. (discoptprob) for W = I, S = I, taking the iterate X_k in
+ * place of the unknown A^-1 (the heuristic of Sec. 7.2, not covered by the convergence
+ * theory): p_i proportional to ||X_k I_{:C_i} I_{C_i:} A||_F = <(X_k^T X_k)_{C_i C_i},
+ * (A A^T)_{C_i C_i}>^(1/2), recomputed from X_k at every iteration (r = n/q FP64 Gram
+ * products of q rows, 2 n^2 q flops per step; the blocks of A A^T once at creation).  The
+ * draw needs X_k, so the iteration's lanes run one step at a time (no look-ahead).
  *
  * Starting point: X_0 = I, L_0 = I (the experiments' choice, Sec. 10).
  *
@@ -104,7 +111,12 @@ typedef enum {
   RBFGS_E_DEVICE = 6         /* a HIP runtime call failed */
 } rbfgs_status;
 
-typedef enum { RBFGS_SKETCH_GAUSS = 0, RBFGS_SKETCH_COORD = 1, RBFGS_SKETCH_PARTITION = 2 } rbfgs_sketch;
+typedef enum {
+  RBFGS_SKETCH_GAUSS = 0,
+  RBFGS_SKETCH_COORD = 1,
+  RBFGS_SKETCH_PARTITION = 2,
+  RBFGS_SKETCH_IMPORTANCE = 3
+} rbfgs_sketch;
 typedef enum {
   RBFGS_FIXED = 0,
   RBFGS_ADAPTIVE = 1,
@@ -193,8 +205,9 @@ rbfgs_status rbfgs_set_state(rbfgs_ctx* ctx, const void* M, int32_t m_dtype, int
                              int32_t on_device, int64_t k);
 
 /* Partition sampling: copy the n per-coordinate FP64 weights (the diagonal of A for
- * fixed RBFGS, of L_k^T A L_k for AdaRBFGS) to host memory; synchronises.
- * E_INVALID_ARG unless the context samples partitions. */
+ * fixed RBFGS, of L_k^T A L_k for AdaRBFGS; for importance sampling the weight of each
+ * block on its first coordinate, zeros elsewhere, as of the last draw) to host memory;
+ * synchronises.  E_INVALID_ARG unless the context samples partitions. */
 rbfgs_status rbfgs_get_weights(rbfgs_ctx* ctx, double* out);
 
 /* Iterations performed so far (k of X_k). */
@@ -212,7 +225,7 @@ const char* rbfgs_last_error(const rbfgs_ctx* ctx);
  * recorded on the stream each phase runs on, and clear the accumulated totals.
  * enable = 0 off, 1 every phase, 2 only the n x n products (AS, XY, LS, LtY,
  * update: the fewest events, for timing inside a measured run); other values
- * E_INVALID_ARG.  Phases: sketch, sample, sketch_gram, gather, AS, LS, gram_G, chol_inv,
+ * E_INVALID_ARG.  Phases: sketch, sample, importance, sketch_gram, gather, AS, LS, gram_G, chol_inv,
  * panel_U, XY, LtY, gram_H, estimator, panels (containing weights), coord_update, update; a split-K
  * product also reports its reduction kernel as "<phase>.reduce", so that the
  * phase itself times the product kernel alone.

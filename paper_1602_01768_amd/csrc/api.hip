@@ -84,6 +84,13 @@ struct rbfgs_ctx {
   // weights, A_jj for the fixed method and (L^T A L)_jj for AdaRBFGS (updated every step)
   bool part = false;
   double* tw = nullptr;
+  // importance sampling for Kaczmarz (eq. discoptprob with W = I and X_k in place of A^-1):
+  // block i of the same partition with p_i proportional to ||X_k I_{:C_i} I_{C_i:} A||_F =
+  // <(Z Z^T)_{C_i C_i}, (A A^T)_{C_i C_i}>^(1/2), recomputed from Z = X_k^T at every step;
+  // BA holds the r blocks (A A^T)_{C_i C_i}, BZ one block of Z Z^T, Pz q rows as a panel
+  bool imp = false;
+  double *BA = nullptr, *BZ = nullptr;
+  void* Pz = nullptr;
   // comparison methods of Sec. 10 (FP64 only): Newton-Schulz and MR, n^3 products per step
   bool ns = false, mr = false;
   double *T2 = nullptr, *P2 = nullptr, *Q2 = nullptr;  // n x n FP64 work matrices
@@ -354,6 +361,29 @@ void small_small(rbfgs_ctx* ctx, const Lane& L, const double* A, bool at, const 
 
 int sk_dt(const rbfgs_ctx* ctx) { return ctx->mixed ? DT_BF16 : DT_F64; }
 
+// (M M^T)_{CC} for the q rows C = [bq, (b+1)q) of the row-major np x np matrix M (A, or
+// Z = X^T for the row variants): the rows, contiguous in memory, are the first q columns of
+// the column-major panel Pz (its other columns are zero), and out (qp x qp) = Pz^T Pz.
+void row_block_gram(rbfgs_ctx* ctx, const Lane& L, const void* M, int64_t b, double* out) {
+  const size_t es = dt_size(ctx->mdt);
+  HIPCHK(hipMemcpyAsync(ctx->Pz, (const char*)M + (size_t)b * ctx->q * ctx->np * es, (size_t)ctx->q * ctx->np * es,
+                        hipMemcpyDeviceToDevice, L.s));
+  gram(ctx, L, ctx->Pz, ctx->mdt, ctx->Pz, ctx->mdt, out);
+}
+
+// Kaczmarz with importance sampling: the weights ||X_k I_{:C_i} I_{C_i:} A||_F of every block
+// from the current Z = X_k^T, then the draw of iteration k into the slot (main lane).
+void importance_draw(rbfgs_ctx* ctx, Slot& S, int64_t k) {
+  const Lane& L = ctx->main;
+  const int64_t qp = ctx->qp;
+  Phase ph(ctx, L, "importance");
+  for (int64_t b = 0; b < ctx->n / ctx->q; ++b) {
+    row_block_gram(ctx, L, ctx->X, b, ctx->BZ);
+    HIPCHK(block_dot(ctx->BZ, ctx->BA + b * qp * qp, qp, ctx->q, ctx->tw + b * ctx->q, L.s));
+  }
+  HIPCHK(sample_partition(ctx->tw, ctx->n, ctx->q, ctx->p.seed, k, S.C, S.ht, ctx->status, L.s));
+}
+
 // ---------------------------------------------------------------- side lanes
 // Sketch-dependent products of iteration k into slot S (side lane): the sketch, and
 // for the fixed method Y = A S (or the gathered columns) and G = S^T Y; for the
@@ -364,7 +394,9 @@ void side_products(rbfgs_ctx* ctx, int64_t k, Slot& S) {
   const int mdt = ctx->mdt;
   {
     Phase ph(ctx, L, "sketch");
-    if (ctx->part) {
+    if (ctx->imp) {
+      // drawn on the main lane (the weights depend on X_k)
+    } else if (ctx->part) {
       // fixed: static weights, drawn ahead; AdaRBFGS draws on the main lane (its weights
       // depend on the previous step)
       if (!ctx->ada) HIPCHK(sample_partition(ctx->tw, ctx->n, ctx->q, ctx->p.seed, k, S.C, S.ht, ctx->status, L.s));
@@ -568,21 +600,22 @@ void main_row(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
   const int mdt = ctx->mdt;
   GemmArgs shape;
   shape.M = np; shape.N = qp;
-  const bool fused_est = ctx->mixed && (size_t)reduce_blocks_f32(shape) <= L.red_count;
+  const bool fused_est = ctx->mixed && !ctx->imp && (size_t)reduce_blocks_f32(shape) <= L.red_count;
   {
     Phase ph(ctx, L, "XtP", true);
     nn_times_panel(ctx, L, ctx->X, false, S.Y, mdt, ctx->V, 2, 2, 1, ph.mark(),
                    fused_est ? (const __bf16*)S.Sk : nullptr);
   }
   after_xy();
-  const double scale = ctx->dcoord ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
+  // importance sampling: the Horvitz-Thompson factor 1/p_i of the drawn block
+  const double scale = ctx->imp ? 1.0 : ctx->dcoord ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
   {
     Phase ph(ctx, L, "estimator");
     if (fused_est)
       HIPCHK(reduce_sum_scaled(L.red, reduce_blocks_f32(shape), ctx->est, scale, ctx->status, L.s));
     else
       HIPCHK(estimator(S.Sk, sk_dt(ctx), nullptr, ctx->V, mdt, np, ctx->n, ctx->q, scale, L.red, ctx->est,
-                       ctx->status, L.s));
+                       ctx->status, L.s, ctx->imp ? S.ht : nullptr));
   }
   HIPCHK(hipStreamWaitEvent(L.s, S.ready, 0));  // U of this slot
   ahead();
@@ -758,6 +791,25 @@ void enqueue_steps(rbfgs_ctx* ctx, int64_t nsteps) {
     return;
   }
   constexpr int NS = rbfgs_ctx::NSLOT;
+  if (ctx->imp) {  // each draw depends on X_k: no look-ahead, the lanes run one step at a time
+    for (int64_t i = 0; i < nsteps; ++i) {
+      const int64_t k = ctx->k;
+      Slot& S = ctx->slot[k % NS];
+      importance_draw(ctx, S, k);
+      HIPCHK(hipEventRecord(ctx->ev_begin, ctx->main.s));
+      HIPCHK(hipStreamWaitEvent(ctx->side.s, ctx->ev_begin, 0));
+      side_products(ctx, k, S);
+      HIPCHK(hipStreamWaitEvent(ctx->inv.s, S.g_ready, 0));
+      side_inverse(ctx, S);
+      HIPCHK(hipEventRecord(S.ready, ctx->inv.s));
+      HIPCHK(hipStreamWaitEvent(ctx->main.s, S.y_ready, 0));
+      main_row(ctx, S, [] {}, [] {});
+      HIPCHK(hipEventRecord(S.released, ctx->main.s));
+      S.released_valid = true;
+      ++ctx->k;
+    }
+    return;
+  }
   HIPCHK(hipEventRecord(ctx->ev_begin, ctx->main.s));
   HIPCHK(hipStreamWaitEvent(ctx->side.s, ctx->ev_begin, 0));
   HIPCHK(hipStreamWaitEvent(ctx->inv.s, ctx->ev_begin, 0));
@@ -882,7 +934,7 @@ void make_slot(rbfgs_ctx* ctx, Slot& S) {
   S.G = (double*)dalloc(ctx, qq);
   if (ctx->psb) S.G2 = (double*)dalloc(ctx, qq);
   S.Z = (double*)dalloc(ctx, qq);
-  if (ctx->part) S.ht = (double*)dalloc(ctx, sizeof(double));
+  if (ctx->part || ctx->imp) S.ht = (double*)dalloc(ctx, sizeof(double));
   if (!ctx->ada) {
     S.Y = dalloc(ctx, np * qp * es);
     S.Ginv = (double*)dalloc(ctx, qq);
@@ -938,7 +990,8 @@ void set_params(rbfgs_ctx* ctx, const rbfgs_params& p) {
   ctx->ns = p.variant == RBFGS_NEWTON_SCHULZ;
   ctx->mr = p.variant == RBFGS_MR;
   ctx->part = p.sketch == RBFGS_SKETCH_PARTITION;
-  ctx->dcoord = p.sketch == RBFGS_SKETCH_COORD && (ctx->psb || ctx->rowv);
+  ctx->imp = p.sketch == RBFGS_SKETCH_IMPORTANCE;
+  ctx->dcoord = (p.sketch == RBFGS_SKETCH_COORD && (ctx->psb || ctx->rowv)) || ctx->imp;
   ctx->coord = (p.sketch == RBFGS_SKETCH_COORD && !ctx->dcoord) || ctx->part;
   ctx->mdt = ctx->mixed ? DT_F32 : DT_F64;
   ctx->bf16q = RB_BF16_Q && ctx->mixed && p.variant == RBFGS_FIXED && !ctx->coord && ctx->qp % 128 == 0;
@@ -973,7 +1026,13 @@ void allocate(rbfgs_ctx* ctx) {
     if (ctx->mr) ctx->Q2 = (double*)dalloc(ctx, (size_t)np * np * sizeof(double));
   }
   ctx->scal = (double*)dalloc(ctx, 8 * sizeof(double));
-  if (ctx->part) ctx->tw = (double*)dalloc(ctx, np * sizeof(double));
+  if (ctx->part || ctx->imp) ctx->tw = (double*)dalloc(ctx, np * sizeof(double));
+  if (ctx->imp) {
+    ctx->BA = (double*)dalloc(ctx, (size_t)(ctx->n / ctx->q) * qp * qp * sizeof(double));
+    ctx->BZ = (double*)dalloc(ctx, (size_t)qp * qp * sizeof(double));
+    ctx->Pz = dalloc(ctx, np * qp * es);
+    if (!ctx->dry) HIPCHK(hipMemsetAsync(ctx->Pz, 0, np * qp * es, ctx->main.s));  // pad columns stay 0
+  }
   if (!ctx->ada && ctx->coord) ctx->R = dalloc(ctx, qp * np * es);
   const size_t qq = (size_t)qp * qp * sizeof(double);
   ctx->G = (double*)dalloc(ctx, qq);
@@ -1011,9 +1070,10 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
   if (!params || !A) return RBFGS_E_INVALID_ARG;
   const rbfgs_params& p = *params;
   if (p.n < 1 || p.q < 1 || p.q > p.n || p.q > 1024 || lda < p.n || (a_dtype != RBFGS_F32 && a_dtype != RBFGS_F64) ||
-      (p.sketch != RBFGS_SKETCH_GAUSS && p.sketch != RBFGS_SKETCH_COORD && p.sketch != RBFGS_SKETCH_PARTITION) ||
+      (p.sketch < RBFGS_SKETCH_GAUSS || p.sketch > RBFGS_SKETCH_IMPORTANCE) ||
       (p.sketch == RBFGS_SKETCH_PARTITION &&
        ((p.variant != RBFGS_FIXED && p.variant != RBFGS_ADAPTIVE) || p.n % p.q != 0)) ||
+      (p.sketch == RBFGS_SKETCH_IMPORTANCE && (p.variant != RBFGS_KACZMARZ || p.n % p.q != 0)) ||
       (p.variant < RBFGS_FIXED || p.variant > RBFGS_MR) ||
       ((p.variant == RBFGS_NEWTON_SCHULZ || p.variant == RBFGS_MR) && p.precision != RBFGS_FP64) ||
       (p.precision != RBFGS_FP64 && p.precision != RBFGS_MIXED) || p.check_every < 0 || p.n > (1ll << 20))
@@ -1069,6 +1129,9 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
       HIPCHK(set_identity(ctx->X, ctx->mdt, np, p.n, ctx->main.s));
     }
     if (ctx->part) HIPCHK(diag_weights(ctx->A, ctx->mdt, np, p.n, ctx->tw, ctx->main.s));  // L_0 = I
+    if (ctx->imp)  // (A A^T)_{C_i C_i} of every block, once
+      for (int64_t b = 0; b < p.n / p.q; ++b)
+        row_block_gram(ctx, ctx->main, ctx->A, b, ctx->BA + b * ctx->qp * ctx->qp);
     const double nanv = NAN;
     HIPCHK(hipMemcpyAsync(ctx->est, &nanv, sizeof(double), hipMemcpyHostToDevice, ctx->main.s));
     HIPCHK(hipStreamSynchronize(ctx->main.s));
@@ -1263,7 +1326,7 @@ rbfgs_status rbfgs_set_state(rbfgs_ctx* ctx, const void* M, int32_t m_dtype, int
 }
 
 rbfgs_status rbfgs_get_weights(rbfgs_ctx* ctx, double* out) {
-  if (!ctx || !out || !ctx->part) return RBFGS_E_INVALID_ARG;
+  if (!ctx || !out || !(ctx->part || ctx->imp)) return RBFGS_E_INVALID_ARG;
   try {
     rbfgs_status st = read_status(ctx);
     if (st != RBFGS_OK) return st;

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "librbfgs.so")
 OK, E_INVALID_ARG, E_OOM, E_NOT_SPD, E_NONFINITE, E_NOT_CONVERGED, E_DEVICE = range(7)
 STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_OOM", 3: "E_NOT_SPD", 4: "E_NONFINITE",
                 5: "E_NOT_CONVERGED", 6: "E_DEVICE"}
-SKETCH = {"gauss": 0, "coord": 1, "cols": 1, "partition": 2}
+SKETCH = {"gauss": 0, "coord": 1, "cols": 1, "partition": 2, "importance": 3}
 VARIANT = {"fixed": 0, "adaptive": 1, "ada": 1, "psb": 2, "aip": 3, "kaczmarz": 4, "newton_schulz": 5,
            "mr": 6}
 PRECISION = {"fp64": 0, "mixed": 1}

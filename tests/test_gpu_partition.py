@@ -158,3 +158,78 @@ def test_rejected_uses(lib):
     with lib.Solver(A, 8, 1) as s:
         with pytest.raises(lib.RbfgsError):
             s.weights()
+
+
+# ---------------------------------------------------------------- importance (eq. discoptprob)
+def general_matrix(n, seed, dtype=np.float64):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n)) / math.sqrt(n) + 2.5 * np.eye(n)
+    return np.ascontiguousarray(A.astype(dtype))
+
+
+@pytest.mark.parametrize("n,q,steps", [(96, 12, 30), (256, 32, 20), (64, 1, 40)])
+def test_importance_fp64_parity(lib, n, q, steps):
+    A = general_matrix(n, n + q)
+    rec = {}
+    Xo = Pt.run_kaczmarz_importance(A, q, 7, steps, record=lambda k, X, i: rec.update({k: X}))
+    with lib.Solver(A, q, 7, sketch="importance", variant="kaczmarz") as s:
+        s.step(steps)
+        X = s.x().cpu().numpy()
+        t = s.weights()
+    assert rel(X, Xo) <= FP64_TOL
+    Xprev = rec[steps - 2] if steps > 1 else np.eye(n)  # the last draw used X_{steps-1}
+    w = Pt.block_weights_importance(Xprev, A, q)
+    assert np.abs(t[::q] - w).max() <= FP64_TOL * w.max()
+    assert not np.any(t.reshape(-1, q)[:, 1:])
+
+
+def test_importance_mixed_parity(lib):
+    n, q, steps = 520, 40, 30
+    A = general_matrix(n, 3, np.float32)
+    with lib.Solver(A, q, 2, sketch="importance", variant="kaczmarz", precision="mixed") as s:
+        s.step(steps)
+        X = s.x().cpu().numpy()
+    Xo = Pt.run_kaczmarz_importance(np.asarray(A, np.float64), q, 2, steps)
+    assert rel(X, Xo) <= MIXED_TOL
+
+
+def test_importance_estimator_matches_oracle(lib):
+    n, q, steps = 120, 12, 6
+    A = general_matrix(n, 5)
+    rec = {}
+    Pt.run_kaczmarz_importance(A, q, 9, steps - 1, record=lambda k, X, i: rec.update(X=X))
+    X = rec["X"]
+    w = Pt.block_weights_importance(X, A, q)
+    i = Pt.draw(w, Pt.uniform(9, steps - 1))
+    ref = Pt.estimator_rows(X, A, Pt.blocks(n, q)[i], w[i] / w.sum())
+    with lib.Solver(A, q, 9, sketch="importance", variant="kaczmarz") as s:
+        s.step(steps)
+        est = s.estimate()
+    assert abs(est - ref) <= 1e-9 * ref
+
+
+def test_importance_invert_and_resume(lib):
+    n, q = 96, 12
+    A = general_matrix(n, 6)
+    with lib.Solver(A, q, 1, sketch="importance", variant="kaczmarz", check_every=4) as s:
+        ok, iters, resid = s.invert(tol=1e-8, max_iters=20000)
+        assert ok and resid <= 1e-8
+    with lib.Solver(A, q, 1, sketch="importance", variant="kaczmarz") as s:
+        s.step(5)
+        X5 = s.x().cpu().numpy()
+        s.step(5)
+        X10 = s.x().cpu().numpy()
+    with lib.Solver(A, q, 1, sketch="importance", variant="kaczmarz") as r:
+        r.set_state(X5, 5)
+        r.step(5)
+        assert rel(r.x().cpu().numpy(), X10) <= FP64_TOL
+
+
+def test_importance_rejected_uses(lib):
+    A = general_matrix(64, 1)
+    As, _ = spectral_spd(64, 1)
+    for variant in ("fixed", "adaptive", "psb", "aip"):
+        with pytest.raises(lib.RbfgsError):
+            lib.Solver(As, 8, 1, sketch="importance", variant=variant)
+    with pytest.raises(lib.RbfgsError):
+        lib.Solver(A, 6, 1, sketch="importance", variant="kaczmarz")
