@@ -364,6 +364,49 @@ def sampling_section(A_dev, A32, q, seed, torch, rbfgs, tol=1e-3, cap=4000, step
     return out
 
 
+def importance_section(A_dev, A32, q, seed, torch, rbfgs, steps=10, iters=100, cpu_n=1024):
+    """Simultaneous randomized Kaczmarz (W = I) on the same matrix with uniform coordinate
+    blocks and with the importance probabilities of eq. discoptprob taking X_k in place of
+    A^-1 (mixed): iters/s over `steps` timed iterations, the exact ||I - AX||_F / sqrt(n)
+    after `iters` iterations from X_0 = I, and for the importance run the phase that forms
+    the weights (r FP64 Grams of q rows of X^T, 2 n^2 q flops) against the FP64 MFMA peak.
+    The oracle's importance iteration (weights from the definition) is timed at n = cpu_n."""
+    import numpy as np
+    from oracle import partition as Pt
+    n = A_dev.shape[0]
+    out = {"iters": iters}
+    for sk in ("coord", "importance"):
+        row = {}
+        s, dt, _ = timed_steps(rbfgs.Solver, A_dev, q, seed, sk, "kaczmarz", "mixed", 2, steps, torch)
+        row["iters_per_s"] = round(steps / dt, 2)
+        if sk == "importance":
+            s.profile(1)
+            s.step(3)
+            rep = s.profile_report()
+            s.profile(0)
+            ph = {k: v[0] / max(v[1], 1) for k, v in rep.items()}
+            row["phases_ms"] = {k: round(v, 4) for k, v in ph.items()}
+            if ph.get("importance"):
+                flops = 2.0 * n * n * q
+                tf = flops / (ph["importance"] * 1e-3) / 1e12
+                row["weights_roofline"] = {"bound": "mfma", "achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS,
+                                           "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4),
+                                           "traffic": None, "alg_flops": flops}
+        s.close()
+        with rbfgs.Solver(A_dev, q, seed, sketch=sk, variant="kaczmarz", precision="mixed") as s2:
+            s2.step(iters)
+            row["resid_after"] = s2.residual() / math.sqrt(n)
+        out[sk] = row
+    m = max(q, min(cpu_n, n) // q * q)
+    Ac = np.asarray(A32[:m, :m], np.float64)
+    t0 = time.perf_counter()
+    Pt.run_kaczmarz_importance(Ac, q, seed, 2)
+    t_cpu = (time.perf_counter() - t0) / 2
+    out["cpu_oracle"] = {"value": round(1.0 / t_cpu, 3), "unit": "iters/s", "kind": "oracle",
+                         "sample": f"2 oracle importance Kaczmarz iterations at n={m}, q={q} (leading block of A)"}
+    return out
+
+
 def live_roofline(live, n, q, variant, sketch, traffic=None):
     """Roofline object of the dominant n x n product kernel (largest total live time)."""
     products = {k: v for k, v in live.items() if phase_roofline(k, n, q, variant, sketch)}
@@ -522,6 +565,8 @@ def main():
                     help="iteration cap of the AdaRBFGS time-to-tolerance runs (0: skip them)")
     ap.add_argument("--sampling-iters", type=int, default=4000,
                     help="iteration cap of the AdaRBFGS sketch-distribution comparison (0: skip it)")
+    ap.add_argument("--importance-iters", type=int, default=100,
+                    help="Kaczmarz iterations of the importance-sampling comparison (0: skip it)")
     ap.add_argument("--serve-jobs", type=int, default=64, help="serving trace length (0: skip serving)")
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
@@ -587,6 +632,10 @@ def main():
     sampling = (sampling_section(A_dev, A32, q, args.seed, torch, rbfgs, cap=args.sampling_iters)
                 if args.sampling_iters > 0 and n % q == 0 else None)
 
+    # ---- Kaczmarz with importance probabilities (eq. discoptprob, X_k as the proxy)
+    importance = (importance_section(A_dev, A32, q, args.seed, torch, rbfgs, iters=args.importance_iters)
+                  if args.importance_iters > 0 and n % q == 0 else None)
+
     # ---- serving trace (p50 / p99 solve latency)
     serve = serving(args, torch, rbfgs) if args.serve_jobs > 0 else None
 
@@ -636,6 +685,7 @@ def main():
         "experiment1": exp1,
         "time_to_tolerance_ada": ttt,
         "sampling_ada": sampling,
+        "importance_kaczmarz": importance,
         "serving": serve,
         "cpu_baseline": cpu,
         "parity": parity,
