@@ -83,6 +83,30 @@ def estimator(X, A, S, kind):
     return r2 / q if kind == "gauss" else r2 * n / q
 
 
+def first_step_entries(A, S, rows, cols, block=4096):
+    """Entries (rows[t], cols[t]) of X_1 = eq. (qunac) applied to X_0 = I, for n too large to
+    form n x n matrices.  With P = S G^-1 S^T, X_1 = P + (I - P A)(I - A P), and with Y = A S:
+        X_1[i, j] = delta_ij + S_i G^-1 S_j^T - S_i G^-1 Y_j^T - Y_i G^-1 S_j^T
+                    + S_i G^-1 (Y^T Y) G^-1 S_j^T,
+    where S_i is row i of S.  A is promoted to FP64 in blocks of `block` rows to form Y."""
+    n = A.shape[0]
+    S = np.asarray(S, dtype=np.float64)
+    Y = np.empty_like(S)
+    for r0 in range(0, n, block):
+        r1 = min(n, r0 + block)
+        Y[r0:r1] = np.asarray(A[r0:r1], dtype=np.float64) @ S
+    G = S.T @ Y
+    Lg = chol_lower(G)
+    Gi = sla.cho_solve((Lg, True), np.eye(G.shape[0]))
+    rows = np.asarray(rows)
+    cols = np.asarray(cols)
+    Si, Sj, Yi, Yj = S[rows], S[cols], Y[rows], Y[cols]
+    SiG, YiG = Si @ Gi, Yi @ Gi
+    K = Gi @ (Y.T @ Y) @ Gi
+    return ((rows == cols).astype(np.float64) + np.einsum("tk,tk->t", SiG, Sj) - np.einsum("tk,tk->t", SiG, Yj)
+            - np.einsum("tk,tk->t", YiG, Sj) + np.einsum("tk,tk->t", Si @ K, Sj))
+
+
 # ------------------------------------------------------------------- AdaRBFGS
 def ada_step(L, A, St):
     """One AdaRBFGS factor update, eq. (Cholimprov), Cholesky square roots."""

@@ -353,3 +353,17 @@ def test_fixed_rbfgs_converges_to_closed_form_inverse():
     e0 = np.linalg.norm(np.eye(n) - Ainv)
     X = R.run_fixed(A, q, 1, "gauss", 150)
     assert np.linalg.norm(X - Ainv) < 1e-2 * e0
+
+
+def test_first_step_entries_match_dense_step():
+    """The entry formula for X_1 from X_0 = I equals the dense step of eq. (qunac)."""
+    from oracle import rbfgs as R, sketch as sk
+    n, q = 40, 7
+    A, _ = spectral_spd(n, 3, 1.0, 50.0)
+    S = sk.gaussian_sketch(5, 0, n, q)
+    X1 = R.fixed_step_literal(np.eye(n), A, S)
+    rows, cols = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    got = R.first_step_entries(A.astype(np.float32), S, rows.ravel(), cols.ravel(), block=16)
+    ref = R.fixed_step_literal(np.eye(n), A.astype(np.float32).astype(np.float64), S)
+    assert np.abs(got - ref.ravel()).max() <= 1e-12 * np.abs(ref).max()
+    assert np.abs(R.first_step_entries(A, S, rows.ravel(), cols.ravel()) - X1.ravel()).max() <= 1e-12 * np.abs(X1).max()
