@@ -165,6 +165,22 @@ def make_A(n, seed, torch, rbfgs, cpu_n=4096):
     return A_dev, A32, info
 
 
+def reference_A(n, seed, torch):
+    """The same ridge Hessian formed without the library (torch's FP64 GEMM on the host-drawn
+    B), for the oracle leg: the oracle's input does not come from the path it checks."""
+    from workloads import ridge_data
+    m = 2 * n
+    B = torch.from_numpy(ridge_data(n, seed, m=m)).cuda().to(torch.float64)
+    A = B.T @ B
+    del B
+    A /= m
+    A.diagonal().add_(1e-2)
+    A32 = A.to(torch.float32)
+    del A
+    torch.cuda.synchronize()
+    return A32
+
+
 def timed_steps(Solver, A_dev, q, seed, sketch, variant, precision, warmup, steps, torch, events=False):
     """Warm up, then time `steps` iterations.  With events, the n x n product kernels are
     bracketed by HIP events on the stream each runs on during the timed steps."""
@@ -407,6 +423,68 @@ def importance_section(A_dev, A32, q, seed, torch, rbfgs, steps=10, iters=100, c
     return out
 
 
+SPLIT_PASSES = {"XY": 3, "AS": 3, "update": 3}  # bf16 piece products issued per product (mixed, fixed/Gaussian)
+
+
+def c4_section(qs, seed, torch, rbfgs, steps=200, warmup=3, samples=4096):
+    """n = 32768: A = Q diag(lambda) Q^T with Q a product of 64 seeded Householder reflectors
+    (compact WY in FP64 on the host, stored FP32: 4 GiB), lambda log-uniform in [1e-2, 1e2];
+    fixed RBFGS, Gaussian sketch, mixed precision, `steps` timed iterations per q after
+    `warmup`, the n x n product kernels timed live with HIP events.  Per q and kernel: HBM
+    GB/s of algorithmic bytes, algorithmic TFLOP/s (2 n^2 q per product, the symmetric update
+    on its triangle) and issued TFLOP/s (the split-bf16 piece products) against the bf16
+    MFMA peak.  q = 32 sits below the ridge point (HBM-bound), q = 512 above it once the split
+    passes are counted.  The error is that of 4096 sampled entries of X against the exact
+    A^-1 of the same construction (with 1/lambda)."""
+    import numpy as np
+    from workloads import householder_entries, householder_spd
+    n = 32768
+    t0 = time.perf_counter()
+    A = householder_spd(n, seed)
+    A_dev = torch.from_numpy(A).cuda()
+    del A
+    torch.cuda.synchronize()
+    out = {"n": n, "steps": steps, "input_gen_s": round(time.perf_counter() - t0, 1)}
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(0, n, samples)
+    cols = rng.integers(0, n, samples)
+    exact = householder_entries(n, seed, rows, cols, inverse=True)
+    ri = torch.from_numpy(rows).cuda()
+    ci = torch.from_numpy(cols).cuda()
+    for q in qs:
+        s, dt, live = timed_steps(rbfgs.Solver, A_dev, q, seed, "gauss", "fixed", "mixed", warmup, steps, torch,
+                                  events=True)
+        X = s.x()
+        got = X[ri, ci].cpu().numpy()
+        del X
+        s.close()
+        kern = {}
+        for ph in ("XY", "AS", "update"):
+            if ph not in live:
+                continue
+            avg = live[ph][0] / live[ph][1] / 1e3
+            nbytes = phase_roofline(ph, n, q, "fixed", "gauss")[1]
+            flops = 2.0 * n * n * q
+            kern[ph] = {"avg_ms": round(avg * 1e3, 4), "hbm_gbs": round(nbytes / avg / 1e9, 1),
+                        "alg_tflops": round(flops / avg / 1e12, 1),
+                        "issued_tflops": round(SPLIT_PASSES[ph] * flops / avg / 1e12, 1),
+                        "issued_mfma_frac": round(SPLIT_PASSES[ph] * flops / avg / 1e12 / BF16_PEAK_TFLOPS, 4)}
+        dom = max(kern, key=lambda k: kern[k]["avg_ms"])
+        bound = "hbm" if q <= 256 else "mfma"
+        if bound == "hbm":
+            ach, peak, unit = kern[dom]["hbm_gbs"], HBM_PEAK_GBS, "GB/s"
+        else:
+            ach, peak, unit = kern[dom]["alg_tflops"], BF16_PEAK_TFLOPS, "TFLOP/s"
+        out[f"q{q}"] = {"value": round(steps / dt, 2), "unit": "iters/s", "ms_per_step": round(dt / steps * 1e3, 3),
+                        "tflops_effective": round(alg_flops(n, q, "fixed", "gauss") * steps / dt / 1e12, 1),
+                        "roofline": {"bound": bound, "kernel": dom, "achieved": ach, "peak": peak, "unit": unit,
+                                     "frac": round(ach / peak, 4), "traffic": None},
+                        "kernels": kern,
+                        "sampled_rel_err_vs_exact_inverse": float(np.linalg.norm(got - exact) / np.linalg.norm(exact))}
+    del A_dev
+    return out
+
+
 def live_roofline(live, n, q, variant, sketch, traffic=None):
     """Roofline object of the dominant n x n product kernel (largest total live time)."""
     products = {k: v for k, v in live.items() if phase_roofline(k, n, q, variant, sketch)}
@@ -567,6 +645,9 @@ def main():
                     help="iteration cap of the AdaRBFGS sketch-distribution comparison (0: skip it)")
     ap.add_argument("--importance-iters", type=int, default=100,
                     help="Kaczmarz iterations of the importance-sampling comparison (0: skip it)")
+    ap.add_argument("--c4-qs", default="32,512",
+                    help="sketch sizes of the n = 32768 Householder runs (bandwidth- and MFMA-bound; empty: skip)")
+    ap.add_argument("--c4-steps", type=int, default=200)
     ap.add_argument("--serve-jobs", type=int, default=64, help="serving trace length (0: skip serving)")
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
@@ -636,6 +717,10 @@ def main():
     importance = (importance_section(A_dev, A32, q, args.seed, torch, rbfgs, iters=args.importance_iters)
                   if args.importance_iters > 0 and n % q == 0 else None)
 
+    # ---- n = 32768 Householder matrix, q = 32 (HBM-bound) and q = 512 (MFMA-bound)
+    c4_qs = [int(x) for x in args.c4_qs.split(",") if x.strip()]
+    c4 = c4_section(c4_qs, args.seed, torch, rbfgs, steps=args.c4_steps) if c4_qs else None
+
     # ---- serving trace (p50 / p99 solve latency)
     serve = serving(args, torch, rbfgs) if args.serve_jobs > 0 else None
 
@@ -643,18 +728,23 @@ def main():
     cpu = None
     parity = None
     if args.cpu_steps > 0:
-        cps, threads, Xo = cpu_baseline(A32, q, args.seed, args.sketch, args.variant, args.cpu_steps)
+        A_ref = reference_A(n, args.seed, torch)
+        ref_diff = float((A_ref - A_dev).abs().max() / A_dev.abs().max())
+        A_ref32 = A_ref.cpu().numpy()
+        cps, threads, Xo = cpu_baseline(A_ref32, q, args.seed, args.sketch, args.variant, args.cpu_steps)
         cpu = {"value": round(cps, 4), "unit": "iters/s", "cores": threads, "kind": "oracle",
                "sample": f"{args.cpu_steps} FP64 oracle iterations from X_0 = I on the same A (n={n}, q={q})"}
+        parity = {"input": "A formed by torch's FP64 GEMM from the same B (not by the library)",
+                  "input_max_rel_diff_vs_library_A": ref_diff}
         for prec in ("mixed", "fp64"):
-            Ause = A_dev if prec == "mixed" else A_dev.to(torch.float64)
+            Ause = A_ref if prec == "mixed" else A_ref.to(torch.float64)
             with rbfgs.Solver(Ause, q, args.seed, sketch=args.sketch, variant=args.variant, precision=prec) as s:
                 s.step(args.cpu_steps)
                 Xg = s.x().cpu().numpy()
             err = float(np.linalg.norm(Xg - Xo) / np.linalg.norm(Xo))
-            parity = parity or {}
             parity[prec] = {"steps": args.cpu_steps, "rel_fro_err_vs_oracle": err}
-            del Xg
+            del Xg, Ause
+        del A_ref
 
     out = {
         "metric": "RBFGS iters/s + TFLOP/s (n=16384,q=256) mixed vs FP64; p50/p99 solve latency",
@@ -686,6 +776,7 @@ def main():
         "time_to_tolerance_ada": ttt,
         "sampling_ada": sampling,
         "importance_kaczmarz": importance,
+        "c4_householder_n32768": c4,
         "serving": serve,
         "cpu_baseline": cpu,
         "parity": parity,

@@ -1,0 +1,61 @@
+"""Parity at the full sizes the benchmark runs, in its launch configuration (mixed precision,
+fixed RBFGS, Gaussian sketch), on outputs the oracle computes one by one: sampled entries of
+the first step's X_1 from X_0 = I (eq. qunac) at n = 32768 with q = 32 (bandwidth-bound
+update) and q = 512 (MFMA-bound), A the Householder matrix built on the host; and the large
+sketch sizes q = 512 and q = 1000 (q_p = 1024) at small n against the full oracle."""
+import numpy as np
+import pytest
+
+from oracle import rbfgs as R, sketch as sk
+from workloads import householder_spd, spectral_spd
+
+pytestmark = pytest.mark.gpu
+
+MIXED_TOL = 1e-4
+FP64_TOL = 1e-10
+N_C4 = 32768
+
+
+@pytest.fixture(scope="module")
+def c4_matrix():
+    return householder_spd(N_C4, 2016)
+
+
+@pytest.mark.timeout(300)  # builds the 4 GiB matrix on the host first
+@pytest.mark.parametrize("q", [32, 512])
+def test_c4_first_step_sampled(lib, c4_matrix, q):
+    import torch
+    n, seed = N_C4, 2016
+    A = c4_matrix
+    rng = np.random.default_rng(q)
+    rows = np.concatenate([rng.integers(0, n, 1500), rng.integers(0, n, 500)])
+    cols = np.concatenate([rng.integers(0, n, 1500), rows[1500:]])  # 500 diagonal entries
+    print(f"c4 first step n={n} q={q}", flush=True)
+    with lib.Solver(torch.from_numpy(A).cuda(), q, seed, precision="mixed") as s:
+        s.step(1)
+        X = s.x()
+        got = X[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()].cpu().numpy()
+        del X
+    ref = R.first_step_entries(A, sk.gaussian_sketch(seed, 0, n, q), rows, cols)
+    assert np.linalg.norm(got - ref) <= MIXED_TOL * np.linalg.norm(ref)
+
+
+NEAR_SQUARE = pytest.mark.xfail(
+    reason="q = 1000 of n = 1100: one step nearly inverts A and G = S^T A S has condition "
+           "~kappa(A) kappa(S)^2 with a nearly square Gaussian S, so the split-bf16 q-sized products "
+           "(q_p a multiple of 128) exceed the 1e-4 mixed bar (2e-4 measured); the bar's workloads "
+           "have q/n <= 1/64, and FP64 at this shape meets 1e-10", strict=False)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+@pytest.mark.parametrize("n,q,steps", [(1536, 512, 3), (1100, 1000, 2)])
+def test_large_q_parity(lib, precision, tol, n, q, steps, request):
+    """q_p = 512 and 1024 code paths (kappa(A) = 100)."""
+    if precision == "mixed" and q == 1000:
+        request.applymarker(NEAR_SQUARE)
+    A = spectral_spd(n, 5, 1.0, 100.0)[0].astype(np.float32)
+    with lib.Solver(A, q, 3, precision=precision) as s:
+        s.step(steps)
+        X = s.x().cpu().numpy()
+    Xo = R.run_fixed(np.asarray(A, np.float64), q, 3, "gauss", steps)
+    assert np.linalg.norm(X - Xo) <= tol * np.linalg.norm(Xo)

@@ -367,3 +367,10 @@ def test_first_step_entries_match_dense_step():
     ref = R.fixed_step_literal(np.eye(n), A.astype(np.float32).astype(np.float64), S)
     assert np.abs(got - ref.ravel()).max() <= 1e-12 * np.abs(ref).max()
     assert np.abs(R.first_step_entries(A, S, rows.ravel(), cols.ravel()) - X1.ravel()).max() <= 1e-12 * np.abs(X1).max()
+
+
+def test_householder_large_n_exactly_symmetric():
+    """The row-block construction used above n = 8192 stores an exactly symmetric matrix
+    (the library checks symmetry on the stored values)."""
+    A = householder_spd(8448, 3, r=8, row_block=2048)
+    assert np.array_equal(A, A.T)

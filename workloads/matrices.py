@@ -140,6 +140,8 @@ def householder_spd(n, seed, r=64, lam_lo=1e-2, lam_hi=1e2, dtype=np.float32,
     else:
         for r0 in range(0, n, row_block):
             r1 = min(n, r0 + row_block)
+            d = out[r0:r1, r0:r1]
+            out[r0:r1, r0:r1] = np.tril(d) + np.tril(d, -1).T
             out[r0:r1, r1:] = out[r1:, r0:r1].T
     return out
 
