@@ -170,9 +170,13 @@ rbfgs_status rbfgs_sync(rbfgs_ctx* ctx);
  * extra products; for the adaptive method they estimate ||I - L^T A L||_F^2) is read;
  * when it falls below the trigger (tol^2 n, lowered by the ratio estimate / exact
  * residual^2 observed at each failed check) the exact FP64 residual is computed and
- * decides.  A check is also forced after max(64 check_every, iterations so far)
- * iterations without one (coordinate and partition sketches, whose estimates are
- * heavy-tailed: max(16 check_every, half the iterations so far)).
+ * decides.  For AdaRBFGS, whose free estimate measures ||I - L^T A L||_F^2 (a lower
+ * bound of ||I - A X||_F^2), the trigger is instead an unbiased FP64 estimate of
+ * ||I - A X||_F^2 from 64 Gaussian probe vectors (6 n^2 64 flops), taken only when the
+ * window mean is below tol^2 n.  A check is also forced after max(64 check_every,
+ * iterations so far) iterations without one (AdaRBFGS: 256 check_every; coordinate and
+ * partition sketches of the fixed method, whose estimates are heavy-tailed: max(16
+ * check_every, half the iterations so far)).
  * iters_out: iterations performed by this call; resid_out: last exact
  * ||I - AX||_F / sqrt(n) (NaN if never computed).  Either may be NULL.
  * Returns OK on convergence, E_NOT_CONVERGED at max_iters, or a device error. */

@@ -39,6 +39,8 @@ using namespace rb;
 
 namespace {
 
+constexpr int PROBES = 64;  // Gaussian probe vectors of the AdaRBFGS stopping test (relative std <= 18%)
+
 struct Lane {  // one stream with its own split-K, reduction and Cholesky workspaces
   hipStream_t s = nullptr;
   void* partial = nullptr;
@@ -104,6 +106,7 @@ struct rbfgs_ctx {
   Slot slot[NSLOT];
   hipEvent_t ev_begin = nullptr;
   hipEvent_t ev_xy = nullptr;  // main lane: X Y of the current iteration enqueued before it
+  hipEvent_t ev_g = nullptr, ev_chol = nullptr;  // adaptive: G formed (main), its inverse done (inverse lane)
   // main-lane buffers
   void* A = nullptr;
   void* X = nullptr;        // X (fixed, PSB), L (adaptive), X^T (AIP, Kaczmarz: the products read it k-contiguous)
@@ -121,7 +124,10 @@ struct rbfgs_ctx {
   // when q <= n/8 (for larger q/n on ill-conditioned A their FP32 accumulation measurably
   // raised the error against the oracle, so they stay FP64 there)
   bool bf16q = false, bf16h = false;
+  // est[0] the last step's estimate, est[1] scratch of the exact residual, est[2] the
+  // window sum of the estimates, est[4] the probe estimate of AdaRBFGS (est[6] its scratch)
   double* est = nullptr;
+  double* prb = nullptr;  // adaptive: Gaussian probes and two work panels, FP64 np x PROBES each
   int* status = nullptr;
   int2* tiles = nullptr;    // tile order of the n x n update (super-tiles, see make_tile_order)
   int64_t ntiles = 0;
@@ -672,14 +678,20 @@ void main_adaptive(rbfgs_ctx* ctx, Slot& S, int64_t k) {
     nn_times_panel(ctx, L, ctx->A, false, ctx->Sa, mdt, ctx->Y, 3, 2, 2, ph.mark());
   }
   { Phase ph(ctx, L, "gram_G"); gram(ctx, L, ctx->Sa, mdt, ctx->Y, mdt, ctx->G); }
+  // the q x q inverse (a latency-bound chain of small kernels) runs on the inverse lane while
+  // the main lane forms T^T = L^T Y, which does not need it
+  HIPCHK(hipEventRecord(ctx->ev_g, L.s));
+  HIPCHK(hipStreamWaitEvent(ctx->inv.s, ctx->ev_g, 0));
   {
-    Phase ph(ctx, L, "chol_inv");
-    HIPCHK(chol_inv(ctx->G, qp, ctx->q, ctx->Z, ctx->Ginv, qp, L.cwork, ctx->status, L.s));
+    Phase ph(ctx, ctx->inv, "chol_inv");
+    HIPCHK(chol_inv(ctx->G, qp, ctx->q, ctx->Z, ctx->Ginv, qp, ctx->inv.cwork, ctx->status, ctx->inv.s));
   }
+  HIPCHK(hipEventRecord(ctx->ev_chol, ctx->inv.s));
   {
     Phase ph(ctx, L, "LtY", true);
     nn_times_panel(ctx, L, ctx->X, true, ctx->Y, mdt, ctx->V, 2, 3, 2, ph.mark());  // T^T = L^T Y
   }
+  HIPCHK(hipStreamWaitEvent(L.s, ctx->ev_chol, 0));
   const double scale = ctx->part ? 1.0 : ctx->coord ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
   {
     Phase ph(ctx, L, "panels");
@@ -887,6 +899,36 @@ rbfgs_status read_status(rbfgs_ctx* ctx) {
   return RBFGS_OK;
 }
 
+// AdaRBFGS: unbiased estimate of ||I - A X||_F^2, X = L L^T, from PROBES Gaussian probe
+// vectors g (E ||(I - A X) g||^2 = ||I - A X||_F^2), in FP64 on the stored A and L:
+// W1 = L^T G, W2 = L W1, W1 = A W2, est = ||G - W1||_F^2 / PROBES (6 n^2 PROBES flops).  The
+// probes come from the sketch stream at iteration 2^62 + w, outside the method's own range.
+double probe_residual(rbfgs_ctx* ctx, uint64_t w) {
+  const Lane& L = ctx->main;
+  const int64_t np = ctx->np;
+  double* G = ctx->prb;
+  double* W1 = G + np * PROBES;
+  double* W2 = W1 + np * PROBES;
+  HIPCHK(sketch_gauss(ctx->p.seed, (int64_t)((1ull << 62) + w), ctx->n, PROBES, G, DT_F64, np, L.s));
+  auto prod = [&](const void* M, bool transpose, const double* in, double* out) {
+    GemmArgs g;
+    g.M = np; g.N = PROBES; g.K = np;
+    g.A = M; g.lda = np; g.a_dt = ctx->mdt; g.a_kc = !transpose;
+    g.B = in; g.ldb = np; g.b_dt = DT_F64; g.b_kc = true;
+    g.epi = EPI_COLSTORE; g.C = out; g.ldc = np; g.c_dt = DT_F64; g.c2 = 1.0;
+    f64_gemm(ctx, L, g);
+  };
+  prod(ctx->X, true, G, W1);
+  prod(ctx->X, false, W1, W2);
+  prod(ctx->A, false, W2, W1);
+  HIPCHK(estimator(G, DT_F64, nullptr, W1, DT_F64, np, ctx->n, PROBES, 1.0 / PROBES, L.red, ctx->est + 4, ctx->status,
+                   L.s));
+  double v = 0;
+  HIPCHK(hipMemcpyAsync(&v, ctx->est + 4, sizeof(double), hipMemcpyDeviceToHost, L.s));
+  HIPCHK(hipStreamSynchronize(L.s));
+  return v;
+}
+
 double exact_residual(rbfgs_ctx* ctx) {
   const int64_t np = ctx->np;
   const Lane& L = ctx->main;
@@ -968,6 +1010,8 @@ void release(rbfgs_ctx* ctx) {
   }
   if (ctx->ev_begin) (void)hipEventDestroy(ctx->ev_begin);
   if (ctx->ev_xy) (void)hipEventDestroy(ctx->ev_xy);
+  if (ctx->ev_g) (void)hipEventDestroy(ctx->ev_g);
+  if (ctx->ev_chol) (void)hipEventDestroy(ctx->ev_chol);
   for (void* p : ctx->allocs) (void)hipFree(p);
   if (ctx->side.s) (void)hipStreamDestroy(ctx->side.s);
   if (ctx->inv.s) (void)hipStreamDestroy(ctx->inv.s);
@@ -1042,7 +1086,8 @@ void allocate(rbfgs_ctx* ctx) {
   ctx->Z = (double*)dalloc(ctx, qq);
   ctx->GH = (double*)dalloc(ctx, qq);
   ctx->Mq = (double*)dalloc(ctx, qq);
-  ctx->est = (double*)dalloc(ctx, 4 * sizeof(double));
+  ctx->est = (double*)dalloc(ctx, 8 * sizeof(double));
+  if (ctx->ada) ctx->prb = (double*)dalloc(ctx, (size_t)3 * np * PROBES * sizeof(double));
   ctx->status = (int*)dalloc(ctx, sizeof(int));
   {  // tile order of the n x n update: lower triangle (symmetric X) or full square (L, row variants)
     const bool full = ctx->ada || ctx->rowv;
@@ -1087,6 +1132,8 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
     HIPCHK(hipStreamCreateWithFlags(&ctx->inv.s, hipStreamNonBlocking));   // default priority
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_begin, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_xy, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_g, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ctx->ev_chol, hipEventDisableTiming));
     allocate(ctx);
     const int64_t np = ctx->np;
     // copy A (n x n, lda) into the padded np x np buffer, converting its type
@@ -1198,7 +1245,8 @@ rbfgs_status rbfgs_invert(rbfgs_ctx* ctx, double tol, int64_t max_iters, int64_t
   // for Gaussian sketches; max(16 windows, half the iterations so far) for coordinate and
   // partition sketches, whose estimates are heavy-tailed when the residual sits in few
   // columns (a typical window mean is then far below the true mean)
-  const int64_t force_base = (ctx->coord || ctx->dcoord ? 16 : 64) * (int64_t)ctx->p.check_every;
+  // (AdaRBFGS, triggered by an unbiased estimate of the decided quantity: 256 windows)
+  const int64_t force_base = (ctx->ada ? 256 : ctx->coord || ctx->dcoord ? 16 : 64) * (int64_t)ctx->p.check_every;
   int64_t next_force = force_base;
   rbfgs_status result = RBFGS_E_NOT_CONVERGED;
   try {
@@ -1215,6 +1263,20 @@ rbfgs_status rbfgs_invert(rbfgs_ctx* ctx, double tol, int64_t max_iters, int64_t
       HIPCHK(hipMemcpyAsync(&est, ctx->est + 2, sizeof(double), hipMemcpyDeviceToHost, ctx->main.s));
       HIPCHK(hipStreamSynchronize(ctx->main.s));
       est /= (double)m;
+      if (ctx->ada) {
+        // the free estimate measures ||I - L^T A L||_F^2 <= ||I - A X||_F^2: only below the
+        // target is the unbiased probe estimate of ||I - A X||_F^2 taken, and only below the
+        // target again is the exact residual computed
+        bool check = done >= next_force;
+        if (!check && est <= target) check = probe_residual(ctx, (uint64_t)ctx->k) <= target;
+        if (check) {
+          const double r = exact_residual(ctx);
+          resid = r / sqrt((double)ctx->n);
+          if (resid <= tol) { result = RBFGS_OK; break; }
+          next_force = done + std::max<int64_t>(force_base, done);
+        }
+        continue;
+      }
       if (est <= thresh || done >= next_force) {
         const double r = exact_residual(ctx);
         resid = r / sqrt((double)ctx->n);
