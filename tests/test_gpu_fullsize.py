@@ -59,3 +59,29 @@ def test_large_q_parity(lib, precision, tol, n, q, steps, request):
         X = s.x().cpu().numpy()
     Xo = R.run_fixed(np.asarray(A, np.float64), q, 3, "gauss", steps)
     assert np.linalg.norm(X - Xo) <= tol * np.linalg.norm(Xo)
+
+
+# ------------------------------------------------ n = 4096, q = 64
+# The workload runs 500 iterations; the dense oracle's n x n temporaries make that several
+# minutes per sketch, so parity is checked at the full size over the first 50.
+@pytest.fixture(scope="module")
+def c2_case():
+    from workloads import gram_ridge
+    return gram_ridge(4096, 2016), {}  # A = M^T M / 4096 + 1e-3 I (FP32), oracle results by sketch
+
+
+@pytest.mark.timeout(300)  # the oracle's iterations run inside the first test of each sketch
+@pytest.mark.parametrize("kind", ["gauss", "coord"])
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("mixed", MIXED_TOL)])
+def test_c2_parity(lib, c2_case, kind, precision, tol):
+    A, cache = c2_case
+    n, q, steps, seed = 4096, 64, 50, 2016
+    if kind not in cache:
+        print(f"oracle n={n} q={q} {kind} {steps} iterations", flush=True)
+        cache[kind] = R.run_fixed(np.asarray(A, np.float64), q, seed, "cols" if kind == "coord" else "gauss", steps)
+    print(f"gpu n={n} q={q} {kind} {precision}", flush=True)
+    with lib.Solver(A, q, seed, sketch=kind, precision=precision) as s:
+        s.step(steps)
+        X = s.x().cpu().numpy()
+    Xo = cache[kind]
+    assert np.linalg.norm(X - Xo) <= tol * np.linalg.norm(Xo)
