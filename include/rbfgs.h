@@ -173,7 +173,7 @@ rbfgs_status rbfgs_sync(rbfgs_ctx* ctx);
  * decides.  For AdaRBFGS, whose free estimate measures ||I - L^T A L||_F^2 (a lower
  * bound of ||I - A X||_F^2), the trigger is instead an unbiased FP64 estimate of
  * ||I - A X||_F^2 from 64 Gaussian probe vectors (6 n^2 64 flops), taken only when the
- * window mean is below tol^2 n.  A check is also forced after max(64 check_every,
+ * window mean is below tol^2 n, must fall below 0.8 tol^2 n.  A check is also forced after max(64 check_every,
  * iterations so far) iterations without one (AdaRBFGS: 256 check_every; coordinate and
  * partition sketches of the fixed method, whose estimates are heavy-tailed: max(16
  * check_every, half the iterations so far)).
