@@ -856,7 +856,11 @@ void enqueue_steps(rbfgs_ctx* ctx, int64_t nsteps) {
       // RB_GATE 0: the side lane's products of k+2 and the inverse of k+1 are released
       // after X Y; 1: both before the update of X; 2: the inverse after X Y, the
       // products before the update (so that A S does not hold the CUs that the main
-      // lane's q-sized kernels between X Y and the update need)
+      // lane's q-sized kernels between X Y and the update need); 3: the products at the
+      // start of the iteration (A S of k+2 beside X Y of k), the inverse after X Y.
+      // Measured at n = 16384, q = 256: 3 lets the q-sized kernels run alone (0.30 -> 0.08 ms)
+      // but X Y beside A S takes 0.90 ms instead of 0.53 (the pair moves no more bytes per
+      // second than either alone), 1.79 ms per step against 1.76 for 0
       auto release_products = [&]() {
         HIPCHK(hipEventRecord(ctx->ev_xy, ctx->main.s));
         HIPCHK(hipStreamWaitEvent(ctx->side.s, ctx->ev_xy, 0));
@@ -870,9 +874,10 @@ void enqueue_steps(rbfgs_ctx* ctx, int64_t nsteps) {
         if (RB_GATE != 1) release_inverse();
       };
       auto before_update = [&]() {
-        if (RB_GATE != 0) release_products();
+        if (RB_GATE == 1 || RB_GATE == 2) release_products();
         if (RB_GATE == 1) release_inverse();
       };
+      if (RB_GATE == 3) release_products();
       if (ctx->rowv) main_row(ctx, S, after_xy, before_update);
       else main_fixed(ctx, S, after_xy, before_update);
     }
