@@ -591,6 +591,15 @@ def experiment1(sizes, seed, torch, rbfgs):
             t = time.perf_counter() - t0
             row[name] = {"seconds": round(t, 4), "iters": int(iters), "reached": bool(ok),
                          "rel_err": round(resid * math.sqrt(n) / r0, 5)}
+        # the comparison methods' iterations against the FP64 MFMA roofline: Newton-Schulz
+        # forms A X and X (A X) (4 n^3 flops), MR A X, X R and R R (6 n^3)
+        for meth, nprod in (("newton_schulz", 2), ("mr", 3)):
+            s, dt, _ = timed_steps(rbfgs.Solver, A64, q, seed, "gauss", meth, "fp64", 1, 5, torch)
+            s.close()
+            tf = 2.0 * nprod * float(n) ** 3 * 5 / dt / 1e12
+            row[meth]["iter_ms"] = round(dt / 5 * 1e3, 3)
+            row[meth]["roofline"] = {"bound": "mfma", "achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS,
+                                     "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4), "traffic": None}
         out[str(n)] = row
         del A32, A64
     # the oracle's time per iteration at the smallest n (FP64, host cores)
