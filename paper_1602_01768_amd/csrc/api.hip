@@ -247,9 +247,16 @@ void prof_flush(rbfgs_ctx* ctx) {
 
 // Split-K factor: enough workgroups to fill the chip (>= 1024) with K chunks of at
 // least min_chunk; at most max_split partial buffers.
+#ifndef RB_SPLIT_TARGET
+// split-K grows until tiles x splits reaches this many workgroups.  At n = 16384, q = 256
+// (128 row tiles): 1024 (split 8) 565 iterations/s, 512 (split 4) 558, 256 (split 2) 573, the
+// last by running A S longer, beside the update; 1024 is kept
+#define RB_SPLIT_TARGET 1024
+#endif
 int pick_split(int64_t tiles, int64_t K, int kmul, int max_split = 8, int64_t min_chunk = 256) {
   int s = 1;
-  while (s < max_split && tiles * s < 1024 && K % ((int64_t)kmul * s * 2) == 0 && K / (s * 2) >= min_chunk) s *= 2;
+  while (s < max_split && tiles * s < RB_SPLIT_TARGET && K % ((int64_t)kmul * s * 2) == 0 && K / (s * 2) >= min_chunk)
+    s *= 2;
   return s;
 }
 
