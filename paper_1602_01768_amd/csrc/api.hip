@@ -1546,8 +1546,8 @@ rbfgs_status rbfgs_pcg(rbfgs_ctx* ctx, const void* b, int32_t b_dtype, int32_t b
     int64_t k = 0;
     bool done = !(nb > 0) || rel <= tol;
     if (!std::isfinite(nb)) {
-      HIPCHK(hipFree(work));
-      if (staging) HIPCHK(hipFree(staging));
+      (void)hipFree(work);
+      if (staging) (void)hipFree(staging);
       return RBFGS_E_INVALID_ARG;
     }
     if (!done) {
@@ -1570,8 +1570,8 @@ rbfgs_status rbfgs_pcg(rbfgs_ctx* ctx, const void* b, int32_t b_dtype, int32_t b
         HIPCHK(hipStreamSynchronize(s));
         rel = std::sqrt(host[0]) / nb;
         if (!std::isfinite(rel)) {
-          HIPCHK(hipFree(work));
-          if (staging) HIPCHK(hipFree(staging));
+          (void)hipFree(work);
+          if (staging) (void)hipFree(staging);
           return fail(ctx, RBFGS_E_NONFINITE, "non-finite residual in PCG");
         }
         done = rel <= tol;
@@ -1586,10 +1586,12 @@ rbfgs_status rbfgs_pcg(rbfgs_ctx* ctx, const void* b, int32_t b_dtype, int32_t b
       HIPCHK(hipMemcpyAsync(x, t, (size_t)n * dt_size(ddt), hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipFree(work));
+    void* w = work;
     work = nullptr;
-    if (staging) HIPCHK(hipFree(staging));
+    HIPCHK(hipFree(w));
+    void* st_buf = staging;
     staging = nullptr;
+    if (st_buf) HIPCHK(hipFree(st_buf));
     if (iters_out) *iters_out = k;
     if (relres_out) *relres_out = rel;
     return done ? RBFGS_OK : RBFGS_E_NOT_CONVERGED;
