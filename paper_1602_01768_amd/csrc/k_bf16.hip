@@ -64,8 +64,25 @@ RB_DEV void tri_index32(int64_t t, int64_t& ti, int64_t& tj) {
   tj = t - i * (i + 1) / 2;
 }
 
+#ifndef RB_TS_NT
+#define RB_TS_NT 0  // 1: the n x n operand of the tall products is read with non-temporal loads (measured within noise)
+#endif
+
+// FP32 float4 load, non-temporal (streamed past the caches) when STREAM.
+template <bool STREAM>
+RB_DEV float4 load_f4(const float* p) {
+  if constexpr (STREAM) {
+    typedef float f32x4v __attribute__((ext_vector_type(4)));
+    const f32x4v v = __builtin_nontemporal_load((const f32x4v*)p);
+    return make_float4(v.x, v.y, v.z, v.w);
+  } else {
+    return *(const float4*)p;
+  }
+}
+
 // Loader for one operand tile of ROWS (m or n) x BK into LDS planes [NP][ROWS][PITCH].
-template <int ROWS, int NP, int KIND, int NT, int BK>
+// STREAM: FP32 loads are non-temporal (an operand read once per launch).
+template <int ROWS, int NP, int KIND, int NT, int BK, bool STREAM = false>
 struct TileLoader {
   static constexpr int PITCH = BK + 8;
   // registers held between the global load and the LDS store
@@ -87,7 +104,7 @@ struct TileLoader {
       for (int i = 0; i < F4; ++i) {
         const int e = tid + NT * i;
         const int row = e / (BK / 4), c4 = (e % (BK / 4)) * 4;
-        f[i] = *(const float4*)(A + (r0 + row) * ld + k0 + c4);
+        f[i] = load_f4<STREAM>(A + (r0 + row) * ld + k0 + c4);
       }
     } else if constexpr (KIND == OK_F32_MC) {
       // micro-block b: columns m4..m4+3 (contiguous in memory) of rows kk..kk+3
@@ -98,7 +115,7 @@ struct TileLoader {
         if (MBLK % NT == 0 || b < MBLK) {
           const int m4 = (b % (ROWS / 4)) * 4, kk = (b / (ROWS / 4)) * 4;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) f[4 * i + j] = *(const float4*)(A + (k0 + kk + j) * ld + r0 + m4);
+          for (int j = 0; j < 4; ++j) f[4 * i + j] = load_f4<STREAM>(A + (k0 + kk + j) * ld + r0 + m4);
         }
       }
     } else if constexpr (KIND == OK_BF16_MC) {
@@ -326,7 +343,9 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArg
     if (NBLK > 1) load_old(1, oldv[1]);
   }
 
-  TileLoader<BM, NA, AK, NT, BK> la0;
+  // tall products (n x n times n x q): the n x n operand is read once, the panel by every row tile
+  constexpr bool STREAM_A = RB_TS_NT && (EPI == EPI_COLSTORE || EPI == EPI_PARTIAL);
+  TileLoader<BM, NA, AK, NT, BK, STREAM_A> la0;
   TileLoader<BN, NB, BKD, NT, BK> lb0;
   la0.load(g.A, g.lda, g.a_plane, m0, kbeg, tid);
   lb0.load(g.B, g.ldb, g.b_plane, n0, kbeg, tid);
@@ -364,7 +383,7 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArg
     for (int64_t k0 = kbeg; k0 < kend; k0 += BK) k_tile(la0, lb0, k0);
   } else {
     // two register stages in flight: tiles k0 and k0 + BK
-    TileLoader<BM, NA, AK, NT, BK> la1;
+    TileLoader<BM, NA, AK, NT, BK, STREAM_A> la1;
     TileLoader<BN, NB, BKD, NT, BK> lb1;
     if (kbeg + BK < kend) {
       la1.load(g.A, g.lda, g.a_plane, m0, kbeg + BK, tid);
