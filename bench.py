@@ -80,7 +80,7 @@ def phase_roofline(name, n, q, variant, sketch, precision="mixed"):
 PHASE_KERNEL = {
     "XY": "k_gemm_bf16<128, 256, 2, 4, 2, 2, 1, 0, 0, true, 0, 1, 32>",
     "AS": "k_gemm_bf16<128, 256, 4, 1, 3, 1, 2, 0, 2, false, 0, 1, 32>",
-    "update": "k_symupd_dma<32, 2, 2, 2, 2, false>",
+    "update": "k_symupd_dma<32, 2, 2, 2, 2, false, 1>",
 }
 KERNEL_SOURCES = ["paper_1602_01768_amd/csrc/k_bf16.hip", "paper_1602_01768_amd/csrc/k_symupd.hip",
                   "paper_1602_01768_amd/csrc/common.hpp", "paper_1602_01768_amd/csrc/kernels.hpp"]

@@ -28,11 +28,16 @@
 // 64 x 64 were fastest; 16-column stages (any depth or occupancy), three or four
 // stages (one workgroup per CU) and 2 x 1 / 1 x 2 wave grids were 10-40% slower.
 #ifndef RB_UPD_NT
-// epilogue accesses of X: 0 ordinary, 1 non-temporal loads and stores, 2 stores only.  X is
-// read and written once per launch while the bf16 panels are re-read by every tile; streaming X
-// past the caches keeps more of the panels in L2 (n = 16384, q = 256: 0.717 -> 0.671 ms with 1,
-// 0.690 ms with 2)
+// epilogue accesses of X: 0 ordinary, 1 non-temporal loads and stores, 2 stores only, used when
+// the panels are at least RB_UPD_NT_MINQ columns wide.  X is read and written once per launch
+// while the bf16 panels are re-read by every tile; streaming X past the caches keeps more of the
+// panels in L2 (n = 16384, q = 256: 0.717 -> 0.671 ms with 1, 0.690 ms with 2; n = 32768,
+// q = 512: 4.50 -> 4.29 ms).  With narrow panels the kernel only streams X, and there the
+// non-temporal accesses cost write bandwidth (n = 32768, q = 32: 1.58 -> 2.20 ms).
 #define RB_UPD_NT 1
+#endif
+#ifndef RB_UPD_NT_MINQ
+#define RB_UPD_NT_MINQ 128
 #endif
 #ifndef RB_UPD_BKS
 #define RB_UPD_BKS 32  // columns per stage
@@ -71,7 +76,7 @@ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) |
 // ... and for "no LDS operation outstanding" (lgkmcnt 0, vmcnt and expcnt at their maxima)
 constexpr int lgkm0_imm() { return 15 | (3 << 14) | (7 << 4); }
 
-template <int BKS, int NS, int OCC, int WAVES_M, int WAVES_N, bool FULL>
+template <int BKS, int NS, int OCC, int WAVES_M, int WAVES_N, bool FULL, int NTX>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) __attribute__((amdgpu_waves_per_eu(OCC * WAVES_M * WAVES_N / 4, 8)))
 void k_symupd_dma(GemmArgs g) {
   constexpr int BM = 128, NP = 2, NW = WAVES_M * WAVES_N;
@@ -242,7 +247,7 @@ void k_symupd_dma(GemmArgs g) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       const float* src = Xd + (a * 32 + (r >> 2) * 8 + lr + (r & 3)) * ld + b * 32 + lc;
-      if constexpr (RB_UPD_NT == 1) o[r] = __builtin_nontemporal_load(src);
+      if constexpr (NTX == 1) o[r] = __builtin_nontemporal_load(src);
       else o[r] = *src;
     }
   };
@@ -305,7 +310,7 @@ void k_symupd_dma(GemmArgs g) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         float* dst = Xd + (a * 32 + (r >> 2) * 8 + lr + (r & 3)) * ld + b * 32 + lc;
-        if constexpr (RB_UPD_NT != 0) __builtin_nontemporal_store(nvs[r], dst);
+        if constexpr (NTX != 0) __builtin_nontemporal_store(nvs[r], dst);
         else *dst = nvs[r];
       }
       if constexpr (!FULL) {
@@ -314,7 +319,7 @@ void k_symupd_dma(GemmArgs g) {
           typedef float f32x4v __attribute__((ext_vector_type(4)));
           f32x4v* dst = (f32x4v*)(Xm + (b * 32 + lc) * ld + a * 32 + 8 * q4 + lr);
           const f32x4v v = {nvs[4 * q4], nvs[4 * q4 + 1], nvs[4 * q4 + 2], nvs[4 * q4 + 3]};
-          if constexpr (RB_UPD_NT != 0) __builtin_nontemporal_store(v, dst);
+          if constexpr (NTX != 0) __builtin_nontemporal_store(v, dst);
           else *dst = v;
         }
       }
@@ -337,12 +342,19 @@ hipError_t symupd_bf16_dma(const GemmArgs& g, int64_t blocks, hipStream_t s) {
       g.b_plane % 8 || g.ldc % 4)
     return hipErrorInvalidValue;
   constexpr int wv[2] = {RB_UPD_WAVES};
-  if (g.epi == EPI_ADDROW)
-    hipLaunchKernelGGL((k_symupd_dma<RB_UPD_BKS, RB_UPD_NS, RB_UPD_OCC, RB_UPD_WAVES, true>), dim3((unsigned)blocks),
-                       dim3(64 * wv[0] * wv[1]), 0, s, g);
+  const dim3 grid((unsigned)blocks), block(64 * wv[0] * wv[1]);
+  const bool full = g.epi == EPI_ADDROW;
+  const bool nt = RB_UPD_NT != 0 && (full ? g.K : g.K / 2) >= RB_UPD_NT_MINQ;  // panel width q
+  if (full && nt)
+    hipLaunchKernelGGL((k_symupd_dma<RB_UPD_BKS, RB_UPD_NS, RB_UPD_OCC, RB_UPD_WAVES, true, RB_UPD_NT>), grid, block, 0,
+                       s, g);
+  else if (full)
+    hipLaunchKernelGGL((k_symupd_dma<RB_UPD_BKS, RB_UPD_NS, RB_UPD_OCC, RB_UPD_WAVES, true, 0>), grid, block, 0, s, g);
+  else if (nt)
+    hipLaunchKernelGGL((k_symupd_dma<RB_UPD_BKS, RB_UPD_NS, RB_UPD_OCC, RB_UPD_WAVES, false, RB_UPD_NT>), grid, block, 0,
+                       s, g);
   else
-    hipLaunchKernelGGL((k_symupd_dma<RB_UPD_BKS, RB_UPD_NS, RB_UPD_OCC, RB_UPD_WAVES, false>), dim3((unsigned)blocks),
-                       dim3(64 * wv[0] * wv[1]), 0, s, g);
+    hipLaunchKernelGGL((k_symupd_dma<RB_UPD_BKS, RB_UPD_NS, RB_UPD_OCC, RB_UPD_WAVES, false, 0>), grid, block, 0, s, g);
   return hipGetLastError();
 }
 
