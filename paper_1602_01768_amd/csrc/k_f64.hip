@@ -44,6 +44,9 @@ RB_DEV double block_sum_256(double v, double* sh) {
 }
 
 // ------------------------------------------------------------------ GEMM
+#ifndef GEMV_RPW
+#define GEMV_RPW 2  // rows per wave of the row product y = M v (CG); 1, 2, 4, 8 measured: 2 fastest
+#endif
 // 256 threads, 4 waves as 2 x 2; wave tile (BM/2) x (BN/2) of 16 x 16 MFMA blocks
 // (v_mfma_f64_16x16x4f64: lane l holds A(l%16, l/16), B(l/16, l%16) and the
 // output column l%16, rows l/16 + 4r).  BK = 16 staged through LDS with a
@@ -768,34 +771,53 @@ hipError_t scaled_identity(double* X, int64_t ld, int64_t n, const double* sc, h
 }
 
 // ---------------------------------------------------------------- conjugate gradients
-// y = M v for an n x n row-major M (FP32 or FP64, ld a multiple of 4), FP64 vectors; one
-// wave per row, 16-byte loads.
+// y = M v for an n x n row-major M (FP32 or FP64, ld a multiple of 4), FP64 vectors; GEMV_RPW
+// rows per wave, 16-byte loads of M.
 template <class T>
 __global__ __launch_bounds__(256) void k_gemv_rows(const T* M, int64_t ld, int64_t n, const double* v, double* y) {
-  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  // GEMV_RPW consecutive rows per wave: each v[j..j+3] (8-byte aligned, loaded as scalars)
+  // serves all of them, and the rows' sums are independent FMA chains
+  constexpr int RPW = GEMV_RPW;
+  const int64_t row0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW;
   const int lane = threadIdx.x & 63;
-  if (row >= n) return;  // uniform per wave; no barrier in this kernel
-  const T* Mr = M + row * ld;
-  double s = 0.0;
+  if (row0 >= n) return;  // uniform per wave; no barrier in this kernel
+  const int nr = (int)min<int64_t>(RPW, n - row0);
+  double s[RPW];
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) s[r] = 0.0;
   const int64_t n4 = n / 4 * 4;
   for (int64_t j = 4 * lane; j < n4; j += 256) {
-    if constexpr (sizeof(T) == 4) {
-      const float4 a = *(const float4*)(Mr + j);
-      s = fma((double)a.x, v[j], s);
-      s = fma((double)a.y, v[j + 1], s);
-      s = fma((double)a.z, v[j + 2], s);
-      s = fma((double)a.w, v[j + 3], s);
-    } else {
-      const double2 a = *(const double2*)(Mr + j), b = *(const double2*)(Mr + j + 2);
-      s = fma(a.x, v[j], s);
-      s = fma(a.y, v[j + 1], s);
-      s = fma(b.x, v[j + 2], s);
-      s = fma(b.y, v[j + 3], s);
+    const double v0 = v[j], v1 = v[j + 1], v2 = v[j + 2], v3 = v[j + 3];
+#pragma unroll
+    for (int r = 0; r < RPW; ++r) {
+      if (r < nr) {
+        const T* Mr = M + (row0 + r) * ld;
+        if constexpr (sizeof(T) == 4) {
+          const float4 a = *(const float4*)(Mr + j);
+          s[r] = fma((double)a.x, v0, s[r]);
+          s[r] = fma((double)a.y, v1, s[r]);
+          s[r] = fma((double)a.z, v2, s[r]);
+          s[r] = fma((double)a.w, v3, s[r]);
+        } else {
+          const double2 a = *(const double2*)(Mr + j), b = *(const double2*)(Mr + j + 2);
+          s[r] = fma(a.x, v0, s[r]);
+          s[r] = fma(a.y, v1, s[r]);
+          s[r] = fma(b.x, v2, s[r]);
+          s[r] = fma(b.y, v3, s[r]);
+        }
+      }
     }
   }
-  for (int64_t j = n4 + lane; j < n; j += 64) s = fma((double)Mr[j], v[j], s);
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-  if (lane == 0) y[row] = s;
+#pragma unroll
+  for (int r = 0; r < RPW; ++r) {
+    if (r < nr) {
+      const T* Mr = M + (row0 + r) * ld;
+      for (int64_t j = n4 + lane; j < n; j += 64) s[r] = fma((double)Mr[j], v[j], s[r]);
+    }
+    double t = s[r];
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if (lane == 0 && r < nr) y[row0 + r] = t;
+  }
 }
 
 // Partial sums of y = M^T v: chunk c of the rows, column j -> part[c * n + j].
@@ -854,10 +876,11 @@ hipError_t gemv(const void* M, int dt, int64_t ld, int64_t n, bool transpose, co
   if (ld % 4) return hipErrorInvalidValue;
   if (!transpose) {
     if (dt == DT_F32)
-      hipLaunchKernelGGL(k_gemv_rows<float>, dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, s, (const float*)M, ld, n, v, y);
+      hipLaunchKernelGGL(k_gemv_rows<float>, dim3((unsigned)ceil_div(n, 4 * GEMV_RPW)), dim3(256), 0, s, (const float*)M,
+                         ld, n, v, y);
     else
-      hipLaunchKernelGGL(k_gemv_rows<double>, dim3((unsigned)ceil_div(n, 4)), dim3(256), 0, s, (const double*)M, ld, n, v,
-                         y);
+      hipLaunchKernelGGL(k_gemv_rows<double>, dim3((unsigned)ceil_div(n, 4 * GEMV_RPW)), dim3(256), 0, s,
+                         (const double*)M, ld, n, v, y);
     return hipGetLastError();
   }
   const int chunks = GEMV_T_CHUNKS;
