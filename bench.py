@@ -398,7 +398,8 @@ def importance_section(A_dev, A32, q, seed, torch, rbfgs, steps=10, iters=100, c
     blocks and with the importance probabilities of eq. discoptprob taking X_k in place of
     A^-1 (mixed): iters/s over `steps` timed iterations, the exact ||I - AX||_F / sqrt(n)
     after `iters` iterations from X_0 = I, and for the importance run the phase that forms
-    the weights (r FP64 Grams of q rows of X^T, 2 n^2 q flops) against the FP64 MFMA peak.
+    the weights against the FP64 MFMA peak: r symmetric q x q Grams of q rows of X^T, whose
+    q (q + 1) / 2 distinct entries take 2 n flops each, n^2 (q + 1) flops in all.
     The oracle's importance iteration (weights from the definition) is timed at n = cpu_n."""
     import numpy as np
     from oracle import partition as Pt
@@ -416,7 +417,7 @@ def importance_section(A_dev, A32, q, seed, torch, rbfgs, steps=10, iters=100, c
             ph = {k: v[0] / max(v[1], 1) for k, v in rep.items()}
             row["phases_ms"] = {k: round(v, 4) for k, v in ph.items()}
             if ph.get("importance"):
-                flops = 2.0 * n * n * q
+                flops = float(n) * n * (q + 1)
                 tf = flops / (ph["importance"] * 1e-3) / 1e12
                 row["weights_roofline"] = {"bound": "mfma", "achieved": round(tf, 2), "peak": FP64_PEAK_TFLOPS,
                                            "unit": "TFLOP/s", "frac": round(tf / FP64_PEAK_TFLOPS, 4),

@@ -20,6 +20,7 @@
 
 #include "../../include/rbfgs.h"
 #include "common.hpp"
+#include "importance.hpp"
 #include "kernels.hpp"
 
 using namespace rb;
@@ -89,9 +90,11 @@ struct rbfgs_ctx {
   // importance sampling for Kaczmarz (eq. discoptprob with W = I and X_k in place of A^-1):
   // block i of the same partition with p_i proportional to ||X_k I_{:C_i} I_{C_i:} A||_F =
   // <(Z Z^T)_{C_i C_i}, (A A^T)_{C_i C_i}>^(1/2), recomputed from Z = X_k^T at every step;
-  // BA holds the r blocks (A A^T)_{C_i C_i}, BZ one block of Z Z^T, Pz q rows as a panel
+  // BA holds the r blocks (A A^T)_{C_i C_i}, Pz q rows as a panel (to form BA), ipart the
+  // partial sums of the batched weight kernel
   bool imp = false;
-  double *BA = nullptr, *BZ = nullptr;
+  double *BA = nullptr, *ipart = nullptr;
+  int64_t ipart_cap = 0;
   void* Pz = nullptr;
   // comparison methods of Sec. 10 (FP64 only): Newton-Schulz and MR, n^3 products per step
   bool ns = false, mr = false;
@@ -385,15 +388,13 @@ void row_block_gram(rbfgs_ctx* ctx, const Lane& L, const void* M, int64_t b, dou
 }
 
 // Kaczmarz with importance sampling: the weights ||X_k I_{:C_i} I_{C_i:} A||_F of every block
-// from the current Z = X_k^T, then the draw of iteration k into the slot (main lane).
+// from the current Z = X_k^T (one batched launch over all blocks), then the draw of
+// iteration k into the slot (main lane).
 void importance_draw(rbfgs_ctx* ctx, Slot& S, int64_t k) {
   const Lane& L = ctx->main;
-  const int64_t qp = ctx->qp;
   Phase ph(ctx, L, "importance");
-  for (int64_t b = 0; b < ctx->n / ctx->q; ++b) {
-    row_block_gram(ctx, L, ctx->X, b, ctx->BZ);
-    HIPCHK(block_dot(ctx->BZ, ctx->BA + b * qp * qp, qp, ctx->q, ctx->tw + b * ctx->q, L.s));
-  }
+  HIPCHK(block_gram_weights(ctx->X, ctx->mdt, ctx->np, ctx->n, (int)ctx->q, ctx->BA, ctx->qp, ctx->ipart,
+                            ctx->ipart_cap, ctx->tw, L.s));
   HIPCHK(sample_partition(ctx->tw, ctx->n, ctx->q, ctx->p.seed, k, S.C, S.ht, ctx->status, L.s));
 }
 
@@ -1085,7 +1086,8 @@ void allocate(rbfgs_ctx* ctx) {
   if (ctx->part || ctx->imp) ctx->tw = (double*)dalloc(ctx, np * sizeof(double));
   if (ctx->imp) {
     ctx->BA = (double*)dalloc(ctx, (size_t)(ctx->n / ctx->q) * qp * qp * sizeof(double));
-    ctx->BZ = (double*)dalloc(ctx, (size_t)qp * qp * sizeof(double));
+    ctx->ipart_cap = block_weights_workspace(ctx->n, (int)ctx->q);
+    ctx->ipart = (double*)dalloc(ctx, (size_t)ctx->ipart_cap * sizeof(double));
     ctx->Pz = dalloc(ctx, np * qp * es);
     if (!ctx->dry) HIPCHK(hipMemsetAsync(ctx->Pz, 0, np * qp * es, ctx->main.s));  // pad columns stay 0
   }

@@ -437,7 +437,8 @@ class Solver:
         return rbfgs_residual(self.ctx)
 
     def weights(self):
-        """Partition weights: the diagonal of A (fixed) or of L_k^T A L_k (AdaRBFGS)."""
+        """Partition weights: the diagonal of A (fixed) or of L_k^T A L_k (AdaRBFGS); with
+        importance sampling each block's weight of the last draw on its first coordinate."""
         return rbfgs_get_weights(self.ctx, self.n)
 
     def estimate(self):

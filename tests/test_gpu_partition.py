@@ -183,6 +183,26 @@ def test_importance_fp64_parity(lib, n, q, steps):
     assert not np.any(t.reshape(-1, q)[:, 1:])
 
 
+@pytest.mark.parametrize("n,q,precision", [(1200, 100, "fp64"), (1088, 64, "mixed"), (1000, 20, "fp64"),
+                                           (1024, 256, "mixed")])
+def test_importance_weights_span_tiles(lib, n, q, precision):
+    """The block weights at sizes whose Grams span several tiles (q = 100, 256), several
+    chunks of the n-long sums with a ragged last chunk, and the narrow-tile form (q = 20):
+    weights of a seeded non-symmetric X_k set by rbfgs_set_state against the oracle's
+    ||X_k I_{:C_i} I_{C_i:} A||_F on the same (stored-precision) X_k and A."""
+    dt = np.float64 if precision == "fp64" else np.float32
+    A = general_matrix(n, n + q, dt)
+    X0 = np.eye(n) + np.random.default_rng(n).standard_normal((n, n)) / (4 * math.sqrt(n))
+    X0 = X0.astype(dt).astype(np.float64)
+    with lib.Solver(A, q, 3, sketch="importance", variant="kaczmarz", precision=precision) as s:
+        s.set_state(X0, 5)
+        s.step(1)
+        t = s.weights()
+    w = Pt.block_weights_importance(X0, np.asarray(A, np.float64), q)
+    assert np.abs(t[::q] - w).max() <= FP64_TOL * w.max()
+    assert not np.any(t.reshape(-1, q)[:, 1:])
+
+
 def test_importance_mixed_parity(lib):
     n, q, steps = 520, 40, 30
     A = general_matrix(n, 3, np.float32)
