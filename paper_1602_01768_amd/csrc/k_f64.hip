@@ -998,25 +998,4 @@ hipError_t fill_block(int32_t* idx, int64_t start, int q, hipStream_t s) {
   return hipGetLastError();
 }
 
-
-// t[0] = sqrt(max(0, sum_{a,b<q} P[a + b ld] Q[a + b ld])) and t[1..q) = 0 (one workgroup):
-// the importance weight <(Z Z^T)_CC, (A A^T)_CC>^(1/2) = ||X_{:C} A_{C:}||_F of one block,
-// placed on the block's first coordinate so that the partition draw sums it as the block's.
-__global__ void k_block_dot(const double* P, const double* Q, int64_t ld, int q, double* t) {
-  __shared__ double sh[4];
-  double acc = 0.0;
-  for (int64_t e = threadIdx.x; e < (int64_t)q * q; e += 256) {
-    const int64_t a = e % q, b = e / q;
-    acc += P[a + b * ld] * Q[a + b * ld];
-  }
-  const double v = block_sum_256(acc, sh);
-  if (threadIdx.x == 0) t[0] = v > 0.0 ? sqrt(v) : 0.0;
-  for (int c = 1 + threadIdx.x; c < q; c += 256) t[c] = 0.0;
-}
-
-hipError_t block_dot(const double* P, const double* Q, int64_t ld, int q, double* t, hipStream_t s) {
-  hipLaunchKernelGGL(k_block_dot, dim3(1), dim3(256), 0, s, P, Q, ld, q, t);
-  return hipGetLastError();
-}
-
 }  // namespace rb

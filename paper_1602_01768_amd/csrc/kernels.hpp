@@ -199,7 +199,4 @@ hipError_t col_dots(const void* P, const void* Q, int dt, int64_t ld, int64_t n,
 // idx[c] = start + c, c < q.
 hipError_t fill_block(int32_t* idx, int64_t start, int q, hipStream_t s);
 
-// t[0] = sqrt(max(0, <P, Q>)) over the leading q x q of two qp x qp blocks (ld), t[1..q) = 0.
-hipError_t block_dot(const double* P, const double* Q, int64_t ld, int q, double* t, hipStream_t s);
-
 }  // namespace rb
