@@ -184,9 +184,9 @@ def test_importance_fp64_parity(lib, n, q, steps):
 
 
 @pytest.mark.parametrize("n,q,precision", [(1200, 100, "fp64"), (1088, 64, "mixed"), (1000, 20, "fp64"),
-                                           (1024, 256, "mixed")])
+                                           (1200, 200, "fp64"), (600, 300, "mixed"), (1024, 256, "mixed")])
 def test_importance_weights_span_tiles(lib, n, q, precision):
-    """The block weights at sizes whose Grams span several tiles (q = 100, 256), several
+    """The block weights at sizes whose Grams span several tiles (q = 100, 200, 256, 300), several
     chunks of the n-long sums with a ragged last chunk, and the narrow-tile form (q = 20):
     weights of a seeded non-symmetric X_k set by rbfgs_set_state against the oracle's
     ||X_k I_{:C_i} I_{C_i:} A||_F on the same (stored-precision) X_k and A."""
