@@ -60,9 +60,10 @@
  * with the probabilities of eq. (discoptprob) for W = I, S = I, taking the iterate X_k in
  * place of the unknown A^-1 (the heuristic of Sec. 7.2, not covered by the convergence
  * theory): p_i proportional to ||X_k I_{:C_i} I_{C_i:} A||_F = <(X_k^T X_k)_{C_i C_i},
- * (A A^T)_{C_i C_i}>^(1/2), recomputed from X_k at every iteration (r = n/q FP64 Gram
- * products of q rows, 2 n^2 q flops per step; the blocks of A A^T once at creation).  The
- * draw needs X_k, so the iteration's lanes run one step at a time (no look-ahead).
+ * (A A^T)_{C_i C_i}>^(1/2), recomputed from X_k at every iteration in FP64 (one launch over
+ * all r = n/q blocks: the distinct entries of their symmetric q x q Grams of q rows, n^2 (q+1)
+ * flops per step; the blocks of A A^T once at creation).  The draw needs X_k, so the
+ * iteration's lanes run one step at a time (no look-ahead).
  *
  * Starting point: X_0 = I, L_0 = I (the experiments' choice, Sec. 10).
  *
