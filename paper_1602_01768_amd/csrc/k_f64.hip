@@ -44,6 +44,9 @@ RB_DEV double block_sum_256(double v, double* sh) {
 }
 
 // ------------------------------------------------------------------ GEMM
+#ifndef GEMV_T_COLS
+#define GEMV_T_COLS 2  // columns per thread of the transposed product y = M^T v (CG); 1, 2, 4 measured: 2
+#endif
 #ifndef GEMV_RPW
 #define GEMV_RPW 2  // rows per wave of the row product y = M v (CG); 1, 2, 4, 8 measured: 2 fastest
 #endif
@@ -820,16 +823,53 @@ __global__ __launch_bounds__(256) void k_gemv_rows(const T* M, int64_t ld, int64
   }
 }
 
-// Partial sums of y = M^T v: chunk c of the rows, column j -> part[c * n + j].
+// Partial sums of y = M^T v: chunk c of the rows, columns j .. j + GEMV_T_COLS - 1 of thread
+// t (j = GEMV_T_COLS t; vector loads, ld and j multiples of 4 / GEMV_T_COLS) -> part[c * n + j];
+// each column's sum runs over the chunk's rows in order.
 template <class T>
 __global__ __launch_bounds__(256) void k_gemv_cols_part(const T* M, int64_t ld, int64_t n, const double* v, int64_t rows_per,
                                                         double* part) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  constexpr int W = GEMV_T_COLS;
+  const int64_t j = ((int64_t)blockIdx.x * 256 + threadIdx.x) * W;
   if (j >= n) return;
   const int64_t r0 = (int64_t)blockIdx.y * rows_per, r1 = r0 + rows_per < n ? r0 + rows_per : n;
-  double s = 0.0;
-  for (int64_t i = r0; i < r1; ++i) s = fma((double)M[i * ld + j], v[i], s);
-  part[(int64_t)blockIdx.y * n + j] = s;
+  double s[W];
+#pragma unroll
+  for (int c = 0; c < W; ++c) s[c] = 0.0;
+  if (j + W <= n) {
+#pragma unroll 4
+    for (int64_t i = r0; i < r1; ++i) {
+      const double vi = v[i];
+      const T* Mi = M + i * ld + j;
+      if constexpr (sizeof(T) == 4 && W == 4) {
+        const float4 a = *(const float4*)Mi;
+        s[0] = fma((double)a.x, vi, s[0]);
+        s[1] = fma((double)a.y, vi, s[1]);
+        s[2] = fma((double)a.z, vi, s[2]);
+        s[3] = fma((double)a.w, vi, s[3]);
+      } else if constexpr (sizeof(T) == 4 && W == 2) {
+        const float2 a = *(const float2*)Mi;
+        s[0] = fma((double)a.x, vi, s[0]);
+        s[1] = fma((double)a.y, vi, s[1]);
+      } else if constexpr (sizeof(T) == 8 && W % 2 == 0) {
+#pragma unroll
+        for (int c = 0; c < W; c += 2) {
+          const double2 a = *(const double2*)(Mi + c);
+          s[c] = fma(a.x, vi, s[c]);
+          s[c + 1] = fma(a.y, vi, s[c + 1]);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < W; ++c) s[c] = fma((double)Mi[c], vi, s[c]);
+      }
+    }
+  } else {
+    for (int64_t i = r0; i < r1; ++i)
+      for (int c = 0; c < W && j + c < n; ++c) s[c] = fma((double)M[i * ld + j + c], v[i], s[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < W; ++c)
+    if (j + c < n) part[(int64_t)blockIdx.y * n + j + c] = s[c];
 }
 
 __global__ void k_sum_chunks(const double* part, int64_t n, int chunks, double* y) {
@@ -885,7 +925,7 @@ hipError_t gemv(const void* M, int dt, int64_t ld, int64_t n, bool transpose, co
   }
   const int chunks = GEMV_T_CHUNKS;
   const int64_t rows_per = ceil_div(n, chunks);
-  const dim3 grid((unsigned)ceil_div(n, 256), (unsigned)chunks);
+  const dim3 grid((unsigned)ceil_div(n, 256 * GEMV_T_COLS), (unsigned)chunks);
   if (dt == DT_F32)
     hipLaunchKernelGGL(k_gemv_cols_part<float>, grid, dim3(256), 0, s, (const float*)M, ld, n, v, rows_per, part);
   else
