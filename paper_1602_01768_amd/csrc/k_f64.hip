@@ -986,28 +986,42 @@ hipError_t diag_weights(const void* A, int dt, int64_t ld, int64_t n, double* t,
 // leading dimension ld): with V = L^T Y and W = -L^T Y G^-1, sum_c V_jc W_jc = -||K_j||^2
 // for K = L^T Y L_G^-T, and L+^T A L+ = L^T A L - K K^T + S~ (S~^T S~)^-1 S~^T, whose last
 // term is the identity on the drawn block [C[0], C[0] + q) for a coordinate block.
-__global__ __launch_bounds__(256) void k_part_weights(const void* V, const void* W, int dt, int64_t ld, int64_t n,
-                                                      int q, const int32_t* C, double* t) {
-  // 64 rows per workgroup; wave g sums columns g, g + 4, ... of its lane's row, and the
-  // four partial sums are added in a fixed order (deterministic)
-  __shared__ double part[4][64];
+template <class T>
+__global__ __launch_bounds__(1024) void k_part_weights(const T* V, const T* W, int64_t ld, int64_t n, int q,
+                                                       const int32_t* C, double* t) {
+  // 64 rows per workgroup; wave g (of 16) sums columns g, g + 16, ... of its lane's row in two
+  // chains, and the 16 partial sums are added in a fixed order (deterministic)
+  __shared__ double part[16][64];
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int64_t j = (int64_t)blockIdx.x * 64 + lane;
-  double acc = 0.0;
-  if (j < n)
-    for (int c = g; c < q; c += 4) acc += load_any(V, dt, j + c * ld) * load_any(W, dt, j + c * ld);
-  part[g][lane] = acc;
+  double a0 = 0.0, a1 = 0.0;
+  if (j < n) {
+    int c = g;
+    for (; c + 16 < q; c += 32) {
+      a0 += (double)V[j + c * ld] * (double)W[j + c * ld];
+      a1 += (double)V[j + (c + 16) * ld] * (double)W[j + (c + 16) * ld];
+    }
+    if (c < q) a0 += (double)V[j + c * ld] * (double)W[j + c * ld];
+  }
+  part[g][lane] = a0 + a1;
   __syncthreads();
   if (g == 0 && j < n) {
+    double sum = 0.0;
+    for (int w = 0; w < 16; ++w) sum += part[w][lane];
     const int64_t c0 = C[0];
-    t[j] += ((part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane])) +
-            ((j >= c0 && j < c0 + q) ? 1.0 : 0.0);
+    t[j] += sum + ((j >= c0 && j < c0 + q) ? 1.0 : 0.0);
   }
 }
 
 hipError_t part_weights(const void* V, const void* W, int dt, int64_t ld, int64_t n, int q, const int32_t* C, double* t,
                         hipStream_t s) {
-  hipLaunchKernelGGL(k_part_weights, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, V, W, dt, ld, n, q, C, t);
+  const dim3 grid((unsigned)((n + 63) / 64)), blk(1024);
+  if (dt == DT_F32)
+    hipLaunchKernelGGL(k_part_weights<float>, grid, blk, 0, s, (const float*)V, (const float*)W, ld, n, q, C, t);
+  else if (dt == DT_F64)
+    hipLaunchKernelGGL(k_part_weights<double>, grid, blk, 0, s, (const double*)V, (const double*)W, ld, n, q, C, t);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
