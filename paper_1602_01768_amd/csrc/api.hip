@@ -25,18 +25,8 @@
 
 using namespace rb;
 
-#ifndef RB_GATE
-#define RB_GATE 0  // where the fixed method releases the side and inverse lanes' next work (see enqueue_steps)
-#endif
-#ifndef RB_BF16_Q
-#define RB_BF16_Q 1  // q-sized products of the mixed fixed Gaussian path in split bf16
-#endif
-#ifndef RB_POWER_STEPS
-#define RB_POWER_STEPS 100  // power-method steps of the Newton-Schulz starting point
-#endif
-#ifndef RB_SUPER_TILES
-#define RB_SUPER_TILES 4  // super-tile edge of the n x n update order (4 x 4 tiles share panels in L2)
-#endif
+constexpr int POWER_STEPS = 100;  // power-method steps of the Newton-Schulz starting point
+constexpr int SUPER_TILES = 4;    // super-tile edge of the n x n update order (4 x 4 tiles share panels in L2)
 
 namespace {
 
@@ -132,6 +122,12 @@ struct rbfgs_ctx {
   double* est = nullptr;
   double* prb = nullptr;  // adaptive: Gaussian probes and two work panels, FP64 np x PROBES each
   int* status = nullptr;
+  // n x n scratch allocated once: AdaRBFGS forms A L (exact residual) or L L^T (rbfgs_get_x)
+  // in FP64 there; the row variants transpose their stored X^T into it (rbfgs_get_x)
+  void* sq = nullptr;
+  // staging for host transfers of n x n matrices, taken in row chunks
+  void* stage = nullptr;
+  size_t stage_bytes = 0;
   int2* tiles = nullptr;    // tile order of the n x n update (super-tiles, see make_tile_order)
   int64_t ntiles = 0;
   std::vector<void*> allocs;
@@ -250,15 +246,13 @@ void prof_flush(rbfgs_ctx* ctx) {
 
 // Split-K factor: enough workgroups to fill the chip (>= 1024) with K chunks of at
 // least min_chunk; at most max_split partial buffers.
-#ifndef RB_SPLIT_TARGET
 // split-K grows until tiles x splits reaches this many workgroups.  At n = 16384, q = 256
 // (128 row tiles): 1024 (split 8) 565 iterations/s, 512 (split 4) 558, 256 (split 2) 573, the
 // last by running A S longer, beside the update; 1024 is kept
-#define RB_SPLIT_TARGET 1024
-#endif
+constexpr int64_t SPLIT_TARGET = 1024;
 int pick_split(int64_t tiles, int64_t K, int kmul, int max_split = 8, int64_t min_chunk = 256) {
   int s = 1;
-  while (s < max_split && tiles * s < RB_SPLIT_TARGET && K % ((int64_t)kmul * s * 2) == 0 && K / (s * 2) >= min_chunk)
+  while (s < max_split && tiles * s < SPLIT_TARGET && K % ((int64_t)kmul * s * 2) == 0 && K / (s * 2) >= min_chunk)
     s *= 2;
   return s;
 }
@@ -861,31 +855,19 @@ void enqueue_steps(rbfgs_ctx* ctx, int64_t nsteps) {
       main_adaptive(ctx, S, k);
     } else {
       HIPCHK(hipStreamWaitEvent(ctx->main.s, S.y_ready, 0));
-      // RB_GATE 0: the side lane's products of k+2 and the inverse of k+1 are released
-      // after X Y; 1: both before the update of X; 2: the inverse after X Y, the
-      // products before the update (so that A S does not hold the CUs that the main
-      // lane's q-sized kernels between X Y and the update need); 3: the products at the
-      // start of the iteration (A S of k+2 beside X Y of k), the inverse after X Y.
-      // Measured at n = 16384, q = 256: 3 lets the q-sized kernels run alone (0.30 -> 0.08 ms)
-      // but X Y beside A S takes 0.90 ms instead of 0.53 (the pair moves no more bytes per
-      // second than either alone), 1.79 ms per step against 1.76 for 0
-      auto release_products = [&]() {
+      // The side lane's products of k+2 and the inverse of k+1 are released after X Y, so
+      // that A S runs beside the q-sized kernels and the update rather than beside X Y.
+      // Measured at n = 16384, q = 256: releasing A S at the start of the iteration lets the
+      // q-sized kernels run alone (0.30 -> 0.08 ms) but X Y beside A S takes 0.90 ms instead
+      // of 0.53 (the pair moves no more bytes per second than either alone): 1.79 ms per step
+      // against 1.76; releasing both only before the update was no faster.
+      auto after_xy = [&]() {
         HIPCHK(hipEventRecord(ctx->ev_xy, ctx->main.s));
         HIPCHK(hipStreamWaitEvent(ctx->side.s, ctx->ev_xy, 0));
         if (i + 2 < nsteps) products(k + 2);
-      };
-      auto release_inverse = [&]() {
         if (i + 1 < nsteps) inverse(k + 1);
       };
-      auto after_xy = [&]() {
-        if (RB_GATE == 0) release_products();
-        if (RB_GATE != 1) release_inverse();
-      };
-      auto before_update = [&]() {
-        if (RB_GATE == 1 || RB_GATE == 2) release_products();
-        if (RB_GATE == 1) release_inverse();
-      };
-      if (RB_GATE == 3) release_products();
+      auto before_update = [&]() {};
       if (ctx->rowv) main_row(ctx, S, after_xy, before_update);
       else main_fixed(ctx, S, after_xy, before_update);
     }
@@ -945,18 +927,16 @@ double probe_residual(rbfgs_ctx* ctx, uint64_t w) {
 double exact_residual(rbfgs_ctx* ctx) {
   const int64_t np = ctx->np;
   const Lane& L = ctx->main;
-  void* tmp = nullptr;
   GemmArgs g;
   g.M = np; g.N = np; g.K = np;
   g.A = ctx->A; g.lda = np; g.a_dt = ctx->mdt; g.a_kc = true;
   if (ctx->ada) {
-    // B = A L (FP64), then I - B L^T
-    HIPCHK(hipMalloc(&tmp, (size_t)np * np * sizeof(double)));
+    // B = A L (FP64, in the context's n x n scratch), then I - B L^T
     GemmArgs b = g;
     b.B = ctx->X; b.ldb = np; b.b_dt = ctx->mdt; b.b_kc = false;
-    b.epi = EPI_ROWSTORE; b.C = tmp; b.ldc = np; b.c_dt = DT_F64; b.c2 = 1.0;
+    b.epi = EPI_ROWSTORE; b.C = ctx->sq; b.ldc = np; b.c_dt = DT_F64; b.c2 = 1.0;
     HIPCHK(gemm_f64(b, nullptr, L.s));
-    g.A = tmp; g.a_dt = DT_F64;
+    g.A = ctx->sq; g.a_dt = DT_F64;
   }
   // Bop(k,j) = M[j][k]: X symmetric (fixed, PSB); L (adaptive, I - (A L) L^T); Z = X^T (row variants).
   // Newton-Schulz and MR: Bop(k,j) = X[k][j] (their iterates are symmetric only in exact
@@ -969,7 +949,6 @@ double exact_residual(rbfgs_ctx* ctx) {
   double r2 = 0;
   HIPCHK(hipMemcpyAsync(&r2, ctx->est + 1, sizeof(double), hipMemcpyDeviceToHost, L.s));
   HIPCHK(hipStreamSynchronize(L.s));
-  if (tmp) HIPCHK(hipFree(tmp));
   return sqrt(r2);
 }
 
@@ -1051,7 +1030,7 @@ void set_params(rbfgs_ctx* ctx, const rbfgs_params& p) {
   ctx->dcoord = (p.sketch == RBFGS_SKETCH_COORD && (ctx->psb || ctx->rowv)) || ctx->imp;
   ctx->coord = (p.sketch == RBFGS_SKETCH_COORD && !ctx->dcoord) || ctx->part;
   ctx->mdt = ctx->mixed ? DT_F32 : DT_F64;
-  ctx->bf16q = RB_BF16_Q && ctx->mixed && p.variant == RBFGS_FIXED && !ctx->coord && ctx->qp % 128 == 0;
+  ctx->bf16q = ctx->mixed && p.variant == RBFGS_FIXED && !ctx->coord && ctx->qp % 128 == 0;
   ctx->bf16h = ctx->bf16q && 8 * ctx->qp <= ctx->np;
 }
 
@@ -1103,12 +1082,16 @@ void allocate(rbfgs_ctx* ctx) {
   ctx->est = (double*)dalloc(ctx, 8 * sizeof(double));
   if (ctx->ada) ctx->prb = (double*)dalloc(ctx, (size_t)3 * np * PROBES * sizeof(double));
   ctx->status = (int*)dalloc(ctx, sizeof(int));
+  if (ctx->ada) ctx->sq = dalloc(ctx, (size_t)np * np * sizeof(double));
+  else if (ctx->rowv) ctx->sq = dalloc(ctx, (size_t)np * np * es);
+  ctx->stage_bytes = std::min<size_t>((size_t)np * np * sizeof(double), (size_t)32 << 20);
+  ctx->stage = dalloc(ctx, ctx->stage_bytes);
   {  // tile order of the n x n update: lower triangle (symmetric X) or full square (L, row variants)
     const bool full = ctx->ada || ctx->rowv;
     const int epi = full ? EPI_ADDROW : EPI_SYMUPD;
     const int T = (int)(np / (ctx->mixed ? bf16_square_tile(np, epi) : 128));
-    std::vector<int2> order((size_t)make_tile_order(T, RB_SUPER_TILES, !full, nullptr));
-    ctx->ntiles = make_tile_order(T, RB_SUPER_TILES, !full, order.data());
+    std::vector<int2> order((size_t)make_tile_order(T, SUPER_TILES, !full, nullptr));
+    ctx->ntiles = make_tile_order(T, SUPER_TILES, !full, order.data());
     ctx->tiles = (int2*)dalloc(ctx, order.size() * sizeof(int2));
     if (!ctx->dry) {
       HIPCHK(hipMemcpyAsync(ctx->tiles, order.data(), order.size() * sizeof(int2), hipMemcpyHostToDevice,
@@ -1150,36 +1133,37 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_chol, hipEventDisableTiming));
     allocate(ctx);
     const int64_t np = ctx->np;
-    // copy A (n x n, lda) into the padded np x np buffer, converting its type
+    // copy A (n x n, lda) into the padded np x np buffer, converting its type (a host A
+    // in row chunks through the staging buffer), then check the stored matrix
     const int sdt = a_dtype == RBFGS_F32 ? DT_F32 : DT_F64;
     const size_t ses = dt_size(sdt);
-    const void* Adev = A;
-    void* staging = nullptr;
-    if (!a_on_device) {
-      HIPCHK(hipMalloc(&staging, (size_t)p.n * lda * ses));
-      HIPCHK(hipMemcpyAsync(staging, A, (size_t)p.n * lda * ses, hipMemcpyHostToDevice, ctx->main.s));
-      Adev = staging;
+    if (a_on_device) {
+      HIPCHK(copy_convert(A, sdt, lda, ctx->A, ctx->mdt, np, p.n, p.n, ctx->main.s));
+    } else {
+      const size_t row = (size_t)p.n * ses;
+      const int64_t chunk = std::max<int64_t>(1, (int64_t)(ctx->stage_bytes / row));
+      for (int64_t r0 = 0; r0 < p.n; r0 += chunk) {
+        const int64_t rows = std::min(chunk, p.n - r0);
+        HIPCHK(hipMemcpy2DAsync(ctx->stage, row, (const char*)A + (size_t)r0 * lda * ses, (size_t)lda * ses, row,
+                                (size_t)rows, hipMemcpyHostToDevice, ctx->main.s));
+        HIPCHK(copy_convert(ctx->stage, sdt, p.n, (char*)ctx->A + (size_t)r0 * np * dt_size(ctx->mdt), ctx->mdt, np,
+                            rows, p.n, ctx->main.s));
+        HIPCHK(hipStreamSynchronize(ctx->main.s));
+      }
     }
     int* flag = ctx->status;
     const bool need_sym = p.variant != RBFGS_KACZMARZ;  // Kaczmarz takes any invertible A
-    HIPCHK(check_sym_finite(Adev, sdt, lda, p.n, flag, ctx->main.s, need_sym));
-    HIPCHK(copy_convert(Adev, sdt, lda, ctx->A, ctx->mdt, np, p.n, p.n, ctx->main.s));
+    HIPCHK(check_sym_finite(ctx->A, ctx->mdt, np, p.n, flag, ctx->main.s, need_sym));
     int bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->main.s));
     HIPCHK(hipStreamSynchronize(ctx->main.s));
-    if (staging) HIPCHK(hipFree(staging));
-    if (!bad && ctx->mixed) {  // the stored FP32 A must also be symmetric and finite
-      HIPCHK(check_sym_finite(ctx->A, DT_F32, np, p.n, flag, ctx->main.s, need_sym));
-      HIPCHK(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, ctx->main.s));
-      HIPCHK(hipStreamSynchronize(ctx->main.s));
-    }
     if (bad) {
       release(ctx);
       return RBFGS_E_INVALID_ARG;
     }
     if (ctx->ns) {  // X_0 = 0.99 A^T / rho^2(A), rho by the power method (Sec. 10)
       double* v = (double*)ctx->T2;
-      HIPCHK(power_norm((const double*)ctx->A, np, p.n, RB_POWER_STEPS, v, v + np, ctx->scal, ctx->main.s));
+      HIPCHK(power_norm((const double*)ctx->A, np, p.n, POWER_STEPS, v, v + np, ctx->scal, ctx->main.s));
       HIPCHK(ns_start((const double*)ctx->A, np, p.n, ctx->scal, (double*)ctx->X, ctx->main.s));
       HIPCHK(hipMemsetAsync(ctx->T2, 0, (size_t)2 * np * sizeof(double), ctx->main.s));
     } else if (ctx->mr) {  // X_0 = (Tr A / Tr(A A^T)) I (Sec. 10)
@@ -1312,6 +1296,8 @@ rbfgs_status rbfgs_invert(rbfgs_ctx* ctx, double tol, int64_t max_iters, int64_t
   return result;
 }
 
+// n x n block of src (element type src_dt, leading dimension lds) to the caller's dst,
+// converted to d_dtype; a host dst is filled in row chunks through the context's staging.
 static rbfgs_status copy_out(rbfgs_ctx* ctx, const void* src, int src_dt, int64_t lds, void* dst, int32_t d_dtype,
                              int64_t ldd, int32_t on_device) {
   const int ddt = d_dtype == RBFGS_F32 ? DT_F32 : DT_F64;
@@ -1322,12 +1308,16 @@ static rbfgs_status copy_out(rbfgs_ctx* ctx, const void* src, int src_dt, int64_
     HIPCHK(hipStreamSynchronize(s));
     return RBFGS_OK;
   }
-  void* tmp = nullptr;
-  HIPCHK(hipMalloc(&tmp, (size_t)n * ldd * dt_size(ddt)));
-  HIPCHK(copy_convert(src, src_dt, lds, tmp, ddt, ldd, n, n, s));
-  HIPCHK(hipMemcpyAsync(dst, tmp, (size_t)n * ldd * dt_size(ddt), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
-  HIPCHK(hipFree(tmp));
+  const size_t row = (size_t)n * dt_size(ddt);
+  const int64_t chunk = std::max<int64_t>(1, (int64_t)(ctx->stage_bytes / row));
+  for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+    const int64_t rows = std::min(chunk, n - r0);
+    HIPCHK(copy_convert((const char*)src + (size_t)r0 * lds * dt_size(src_dt), src_dt, lds, ctx->stage, ddt, n, rows,
+                        n, s));
+    HIPCHK(hipMemcpy2DAsync((char*)dst + (size_t)r0 * ldd * dt_size(ddt), (size_t)ldd * dt_size(ddt), ctx->stage, row,
+                            row, (size_t)rows, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
   return RBFGS_OK;
 }
 
@@ -1337,26 +1327,18 @@ rbfgs_status rbfgs_get_x(rbfgs_ctx* ctx, void* X, int32_t x_dtype, int64_t ldx, 
     rbfgs_status st = read_status(ctx);
     if (st != RBFGS_OK) return st;
     if (ctx->rowv) {  // the context holds X^T
-      void* tmp = nullptr;
-      HIPCHK(hipMalloc(&tmp, (size_t)ctx->np * ctx->np * dt_size(ctx->mdt)));
-      HIPCHK(copy_transpose(ctx->X, ctx->mdt, ctx->np, tmp, ctx->mdt, ctx->np, ctx->np, ctx->np, ctx->main.s));
-      st = copy_out(ctx, tmp, ctx->mdt, ctx->np, X, x_dtype, ldx, on_device);
-      HIPCHK(hipFree(tmp));
-      return st;
+      HIPCHK(copy_transpose(ctx->X, ctx->mdt, ctx->np, ctx->sq, ctx->mdt, ctx->np, ctx->np, ctx->np, ctx->main.s));
+      return copy_out(ctx, ctx->sq, ctx->mdt, ctx->np, X, x_dtype, ldx, on_device);
     }
     if (!ctx->ada) return copy_out(ctx, ctx->X, ctx->mdt, ctx->np, X, x_dtype, ldx, on_device);
     const int64_t np = ctx->np;
-    void* tmp = nullptr;
-    HIPCHK(hipMalloc(&tmp, (size_t)np * np * sizeof(double)));
     GemmArgs g;
     g.M = np; g.N = np; g.K = np;
     g.A = ctx->X; g.lda = np; g.a_dt = ctx->mdt; g.a_kc = true;
     g.B = ctx->X; g.ldb = np; g.b_dt = ctx->mdt; g.b_kc = true;  // Bop(k,j) = L[j][k]
-    g.epi = EPI_ROWSTORE; g.C = tmp; g.ldc = np; g.c_dt = DT_F64; g.c2 = 1.0;
+    g.epi = EPI_ROWSTORE; g.C = ctx->sq; g.ldc = np; g.c_dt = DT_F64; g.c2 = 1.0;
     HIPCHK(gemm_f64(g, nullptr, ctx->main.s));
-    st = copy_out(ctx, tmp, DT_F64, np, X, x_dtype, ldx, on_device);
-    HIPCHK(hipFree(tmp));
-    return st;
+    return copy_out(ctx, ctx->sq, DT_F64, np, X, x_dtype, ldx, on_device);
   } catch (const Fail& f) {
     return f.st;
   }
@@ -1381,21 +1363,31 @@ rbfgs_status rbfgs_set_state(rbfgs_ctx* ctx, const void* M, int32_t m_dtype, int
   try {
     const int sdt = m_dtype == RBFGS_F32 ? DT_F32 : DT_F64;
     const int64_t n = ctx->n;
-    const void* src = M;
-    void* staging = nullptr;
     HIPCHK(hipStreamSynchronize(ctx->side.s));
     HIPCHK(hipStreamSynchronize(ctx->inv.s));
-    if (!on_device) {
-      HIPCHK(hipMalloc(&staging, (size_t)n * ldm * dt_size(sdt)));
-      HIPCHK(hipMemcpyAsync(staging, M, (size_t)n * ldm * dt_size(sdt), hipMemcpyHostToDevice, ctx->main.s));
-      src = staging;
+    if (on_device) {
+      if (ctx->rowv) HIPCHK(copy_transpose(M, sdt, ldm, ctx->X, ctx->mdt, ctx->np, n, n, ctx->main.s));  // X^T
+      else HIPCHK(copy_convert(M, sdt, ldm, ctx->X, ctx->mdt, ctx->np, n, n, ctx->main.s));
+    } else {
+      // row chunks through the staging buffer
+      const size_t row = (size_t)n * dt_size(sdt);
+      const int64_t chunk = std::max<int64_t>(1, (int64_t)(ctx->stage_bytes / row));
+      for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+        const int64_t rows = std::min(chunk, n - r0);
+        HIPCHK(hipMemcpy2DAsync(ctx->stage, row, (const char*)M + (size_t)r0 * ldm * dt_size(sdt),
+                                (size_t)ldm * dt_size(sdt), row, (size_t)rows, hipMemcpyHostToDevice, ctx->main.s));
+        if (ctx->rowv)  // rows r0.. of M are columns r0.. of the stored X^T
+          HIPCHK(copy_transpose(ctx->stage, sdt, n, (char*)ctx->X + (size_t)r0 * dt_size(ctx->mdt), ctx->mdt, ctx->np,
+                                rows, n, ctx->main.s));
+        else
+          HIPCHK(copy_convert(ctx->stage, sdt, n, (char*)ctx->X + (size_t)r0 * ctx->np * dt_size(ctx->mdt), ctx->mdt,
+                              ctx->np, rows, n, ctx->main.s));
+        HIPCHK(hipStreamSynchronize(ctx->main.s));
+      }
     }
-    if (ctx->rowv) HIPCHK(copy_transpose(src, sdt, ldm, ctx->X, ctx->mdt, ctx->np, n, n, ctx->main.s));  // X^T
-    else HIPCHK(copy_convert(src, sdt, ldm, ctx->X, ctx->mdt, ctx->np, n, n, ctx->main.s));
     HIPCHK(hipMemsetAsync(ctx->status, 0, sizeof(int), ctx->main.s));
     if (ctx->part && ctx->ada) refresh_part_weights(ctx);
     HIPCHK(hipStreamSynchronize(ctx->main.s));
-    if (staging) HIPCHK(hipFree(staging));
     ctx->k = k;
   } catch (const Fail& f) {
     return f.st;
@@ -1442,10 +1434,7 @@ rbfgs_status rbfgs_footprint(const rbfgs_params* params, int64_t* bytes_out) {
   } catch (const Fail& f) {
     return f.st;
   }
-  int64_t b = ctx.bytes;
-  if (ctx.ada) b += ctx.np * ctx.np * (int64_t)sizeof(double);  // exact residual of L L^T
-  if (ctx.rowv) b += ctx.np * ctx.np * (int64_t)dt_size(ctx.mdt);  // X = Z^T formed for the caller
-  *bytes_out = b;
+  *bytes_out = ctx.bytes;
   return RBFGS_OK;
 }
 

@@ -13,36 +13,14 @@ namespace rb {
 
 namespace {
 
-#ifndef RB_TS_BK
-#define RB_TS_BK 32  // k depth of one LDS stage for the tall-skinny products
-#endif
-#ifndef RB_TS_PF
-#define RB_TS_PF 1  // register prefetch depth of the tall-skinny products (1 measured faster than 2)
-#endif
-#ifndef RB_TS_LDB
-#define RB_TS_LDB 1  // two LDS buffers in the tall-skinny products
-#endif
-#ifndef RB_TS_LDB_AS
-#define RB_TS_LDB_AS 0  // ... and in the product with an exact bf16 sketch (A S, L S~); 0 measured faster
-#endif
-#ifndef RB_TS_WAVES256
-#define RB_TS_WAVES256 2, 4  // wave grid (along m, along n) of the 128 x 256 tall-skinny tile
-#endif
-#ifndef RB_TS_WAVES256_AS
-#define RB_TS_WAVES256_AS 4, 1  // ... for the product with an exact bf16 sketch (measured fastest)
-#endif
-#ifndef RB_UPD_LDB
-#define RB_UPD_LDB false  // two LDS buffers in the square updates (measured no faster)
-#endif
-#ifndef RB_UPD_KERNEL
-#define RB_UPD_KERNEL 1  // square update: 0 the general mixed GEMM, 1 the LDS-DMA kernel (k_symupd.hip; 2-5% faster)
-#endif
-#ifndef RB_UPD_MIRROR
-#define RB_UPD_MIRROR 1  // mirrored half of the square update: 0 LDS transpose, 1 16-byte stores from registers (10% faster)
-#endif
-#ifndef RB_UPD_TILE
-#define RB_UPD_TILE 128  // square-update tile (128 measured faster than 256)
-#endif
+// Tall-skinny products: 32-deep k stages; two LDS buffers except for the product with an
+// exact bf16 sketch (A S, L S~), where one buffer measured faster; wave grids of the
+// 128 x 256 tile 2 x 4 (4 x 1 for the exact-sketch product, measured fastest).
+constexpr int TS_BK = 32;
+constexpr bool TS_LDB = true;
+constexpr bool TS_LDB_AS = false;
+#define RB_TS_WAVES256 2, 4
+#define RB_TS_WAVES256_AS 4, 1
 // LDS rows hold BK + 8 bf16 (16-byte aligned, rows 8 apart land on distinct banks)
 
 template <int NP>
@@ -56,33 +34,8 @@ RB_DEV void split_n(float x, __bf16 (&o)[NP]) {
   }
 }
 
-RB_DEV void tri_index32(int64_t t, int64_t& ti, int64_t& tj) {
-  int64_t i = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
-  while (i * (i + 1) / 2 > t) --i;
-  while ((i + 1) * (i + 2) / 2 <= t) ++i;
-  ti = i;
-  tj = t - i * (i + 1) / 2;
-}
-
-#ifndef RB_TS_NT
-#define RB_TS_NT 0  // 1: the n x n operand of the tall products is read with non-temporal loads (measured within noise)
-#endif
-
-// FP32 float4 load, non-temporal (streamed past the caches) when STREAM.
-template <bool STREAM>
-RB_DEV float4 load_f4(const float* p) {
-  if constexpr (STREAM) {
-    typedef float f32x4v __attribute__((ext_vector_type(4)));
-    const f32x4v v = __builtin_nontemporal_load((const f32x4v*)p);
-    return make_float4(v.x, v.y, v.z, v.w);
-  } else {
-    return *(const float4*)p;
-  }
-}
-
 // Loader for one operand tile of ROWS (m or n) x BK into LDS planes [NP][ROWS][PITCH].
-// STREAM: FP32 loads are non-temporal (an operand read once per launch).
-template <int ROWS, int NP, int KIND, int NT, int BK, bool STREAM = false>
+template <int ROWS, int NP, int KIND, int NT, int BK>
 struct TileLoader {
   static constexpr int PITCH = BK + 8;
   // registers held between the global load and the LDS store
@@ -104,7 +57,7 @@ struct TileLoader {
       for (int i = 0; i < F4; ++i) {
         const int e = tid + NT * i;
         const int row = e / (BK / 4), c4 = (e % (BK / 4)) * 4;
-        f[i] = load_f4<STREAM>(A + (r0 + row) * ld + k0 + c4);
+        f[i] = *(const float4*)(A + (r0 + row) * ld + k0 + c4);
       }
     } else if constexpr (KIND == OK_F32_MC) {
       // micro-block b: columns m4..m4+3 (contiguous in memory) of rows kk..kk+3
@@ -115,7 +68,7 @@ struct TileLoader {
         if (MBLK % NT == 0 || b < MBLK) {
           const int m4 = (b % (ROWS / 4)) * 4, kk = (b / (ROWS / 4)) * 4;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) f[4 * i + j] = load_f4<STREAM>(A + (k0 + kk + j) * ld + r0 + m4);
+          for (int j = 0; j < 4; ++j) f[4 * i + j] = *(const float4*)(A + (k0 + kk + j) * ld + r0 + m4);
         }
       }
     } else if constexpr (KIND == OK_BF16_MC) {
@@ -218,55 +171,30 @@ struct TileLoader {
   }
 };
 
+// Tall-skinny product, split-K: FP32 partial sums of K chunk kc of output tile (mt, nt).
 // NT = 64 * WAVES_M * WAVES_N threads; wave tile WM x WN of 32 x 32 blocks.
 // v_mfma_f32_32x32x16_bf16: lane l holds A(l%32, 8*(l/32) .. +7), B(8*(l/32) .. +7, l%32);
 // output column l%32, rows 8*(r/4) + 4*(l/32) + r%4 for r = 0..15.
 // LDB: two LDS buffers (one barrier per k tile, the next tile staged during the MFMAs);
-// launch bounds ask for two waves per SIMD (<= 256 VGPRs).
-template <int BM, int BN, int WAVES_M, int WAVES_N, int NA, int NB, int PMAX, int AK, int BKD, bool LDB, int EPI,
-          int PF, int BK>
+// otherwise one buffer with the next tile's global loads in flight during the MFMAs.
+// Launch bounds ask for two waves per SIMD (<= 256 VGPRs).
+template <int BM, int BN, int WAVES_M, int WAVES_N, int NA, int NB, int PMAX, int AK, int BKD, bool LDB, int BK>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArgs g) {
   constexpr int NT = 64 * WAVES_M * WAVES_N;
   constexpr int PITCH = BK + 8;
   constexpr int WM = BM / WAVES_M, WN = BN / WAVES_N;
   constexpr int FM = WM / 32, FN = WN / 32;
-  constexpr int LOOP_E = (NA * BM + NB * BN) * PITCH;                 // bf16 elements of one buffer
-  constexpr int EPI_E = 2 * WAVES_M * WAVES_N * 32 * 33;  // per-wave 32 x 33 float transpose buffers
-  constexpr int SM = (LDB ? 2 : 1) * LOOP_E > EPI_E ? (LDB ? 2 : 1) * LOOP_E : EPI_E;
-  __shared__ __attribute__((aligned(16))) __bf16 smem[SM];
+  constexpr int LOOP_E = (NA * BM + NB * BN) * PITCH;  // bf16 elements of one buffer
+  __shared__ __attribute__((aligned(16))) __bf16 smem[(LDB ? 2 : 1) * LOOP_E];
   __bf16* As = smem;
   __bf16* Bs = smem + NA * BM * PITCH;
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
   const int64_t MT = g.M / BM;
-  int64_t mt, nt;
-  int kc = 0;
-  bool diag = false;
   const int64_t bid = blockIdx.x;
-  if constexpr (EPI == EPI_SYMUPD || EPI == EPI_ADDROW) {
-    // square products: each XCD (blockIdx % 8) takes a contiguous run of the tile
-    // order, so the workgroups resident on it share their panel blocks in its L2
-    const int64_t T = g.M / BM;
-    const int64_t NTT = g.tiles ? g.ntiles : (EPI == EPI_SYMUPD ? T * (T + 1) / 2 : T * T);
-    const int64_t per = (NTT + 7) / 8, t = (bid % 8) * per + bid / 8;
-    if (t >= NTT) return;
-    if (g.tiles) {
-      mt = g.tiles[t].x;
-      nt = g.tiles[t].y;
-    } else if (EPI == EPI_SYMUPD) {
-      tri_index32(t, mt, nt);
-    } else {
-      mt = t / T;
-      nt = t % T;
-    }
-    diag = (EPI == EPI_SYMUPD) && (mt == nt);
-  } else {
-    kc = (int)(bid % g.splitk);
-    const int64_t r = bid / g.splitk;
-    mt = r % MT;
-    nt = r / MT;
-  }
+  const int kc = (int)(bid % g.splitk);
+  const int64_t mt = (bid / g.splitk) % MT, nt = (bid / g.splitk) / MT;
   const int64_t kchunk = g.K / g.splitk;
   const int64_t kbeg = kc * kchunk, kend = kbeg + kchunk;
   const int64_t m0 = mt * BM, n0 = nt * BN;
@@ -278,8 +206,6 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArg
     for (int b = 0; b < FN; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-
-  const int lr = (lane >> 5) * 4, lc = lane & 31;  // MFMA output row group and column of this lane
 
   // MFMAs of one 16-wide k sub-step s of the tile held in LDS at (As_, Bs_); piece
   // products ordered smallest first.
@@ -310,55 +236,19 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArg
       }
   };
 
-  // Single LDS buffer: stage the registers of tile k0 into LDS, start the global loads
-  // of tile k0 + PF*BK into the same registers, then run the MFMAs on LDS.
-  auto k_tile = [&](auto& la, auto& lb, int64_t k0) {
-    __syncthreads();
+  TileLoader<BM, NA, AK, NT, BK> la;
+  TileLoader<BN, NB, BKD, NT, BK> lb;
+  la.load(g.A, g.lda, g.a_plane, m0, kbeg, tid);
+  lb.load(g.B, g.ldb, g.b_plane, n0, kbeg, tid);
+  if constexpr (LDB) {
+    // While the MFMAs of tile t run on buffer t&1, tile t+1 (already in registers) is
+    // split into the other buffer and the global loads of tile t+2 start.  Buffer
+    // (t+1)&1 was last read in iteration t-1, which the barrier closing it has finished.
     la.store(As, tid);
     lb.store(Bs, tid);
-    __syncthreads();
-    if (k0 + PF * BK < kend) {
-      la.load(g.A, g.lda, g.a_plane, m0, k0 + PF * BK, tid);
-      lb.load(g.B, g.ldb, g.b_plane, n0, k0 + PF * BK, tid);
-    }
-#pragma unroll
-    for (int s = 0; s < BK / 16; ++s) substep(As, Bs, s);
-  };
-
-  // square products: the old values of this wave's 32 x 32 output blocks are read two
-  // blocks ahead (the first two before the k loop), so their HBM latency hides behind
-  // the MFMAs and the stores of the blocks before them
-  constexpr bool RMW = (EPI == EPI_SYMUPD || EPI == EPI_ADDROW);
-  constexpr int NBLK = FM * FN;
-  float oldv[RMW ? 2 : 1][16];
-  const float* Cw = (const float*)g.C + (m0 + wm * WM) * g.ldc + (n0 + wn * WN);
-  auto load_old = [&](int i, float (&o)[16]) {
-    const int a = i / FN, b = i % FN;
-    const int ld = (int)g.ldc;
-#pragma unroll
-    for (int r = 0; r < 16; ++r) o[r] = Cw[(a * 32 + (r >> 2) * 8 + lr + (r & 3)) * ld + b * 32 + lc];
-  };
-  if constexpr (RMW) {
-    load_old(0, oldv[0]);
-    if (NBLK > 1) load_old(1, oldv[1]);
-  }
-
-  // tall products (n x n times n x q): the n x n operand is read once, the panel by every row tile
-  constexpr bool STREAM_A = RB_TS_NT && (EPI == EPI_COLSTORE || EPI == EPI_PARTIAL);
-  TileLoader<BM, NA, AK, NT, BK, STREAM_A> la0;
-  TileLoader<BN, NB, BKD, NT, BK> lb0;
-  la0.load(g.A, g.lda, g.a_plane, m0, kbeg, tid);
-  lb0.load(g.B, g.ldb, g.b_plane, n0, kbeg, tid);
-  if constexpr (LDB) {
-    // Two LDS buffers, one barrier per tile: while the MFMAs of tile t run on buffer
-    // t&1, tile t+1 (already in registers) is split into the other buffer and the
-    // global loads of tile t+2 start.  Buffer (t+1)&1 was last read in iteration t-1,
-    // which the barrier closing that iteration has finished.
-    la0.store(As, tid);
-    lb0.store(Bs, tid);
     if (kbeg + BK < kend) {
-      la0.load(g.A, g.lda, g.a_plane, m0, kbeg + BK, tid);
-      lb0.load(g.B, g.ldb, g.b_plane, n0, kbeg + BK, tid);
+      la.load(g.A, g.lda, g.a_plane, m0, kbeg + BK, tid);
+      lb.load(g.B, g.ldb, g.b_plane, n0, kbeg + BK, tid);
     }
     __syncthreads();
     int cur = 0;
@@ -367,11 +257,11 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArg
       const __bf16* Bc = Bs + cur * LOOP_E;
       substep(Ac, Bc, 0);
       if (k0 + BK < kend) {
-        la0.store(As + (cur ^ 1) * LOOP_E, tid);
-        lb0.store(Bs + (cur ^ 1) * LOOP_E, tid);
+        la.store(As + (cur ^ 1) * LOOP_E, tid);
+        lb.store(Bs + (cur ^ 1) * LOOP_E, tid);
         if (k0 + 2 * BK < kend) {
-          la0.load(g.A, g.lda, g.a_plane, m0, k0 + 2 * BK, tid);
-          lb0.load(g.B, g.ldb, g.b_plane, n0, k0 + 2 * BK, tid);
+          la.load(g.A, g.lda, g.a_plane, m0, k0 + 2 * BK, tid);
+          lb.load(g.B, g.ldb, g.b_plane, n0, k0 + 2 * BK, tid);
         }
       }
 #pragma unroll
@@ -379,129 +269,40 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArg
       __syncthreads();
       cur ^= 1;
     }
-  } else if constexpr (PF == 1) {
-    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) k_tile(la0, lb0, k0);
   } else {
-    // two register stages in flight: tiles k0 and k0 + BK
-    TileLoader<BM, NA, AK, NT, BK, STREAM_A> la1;
-    TileLoader<BN, NB, BKD, NT, BK> lb1;
-    if (kbeg + BK < kend) {
-      la1.load(g.A, g.lda, g.a_plane, m0, kbeg + BK, tid);
-      lb1.load(g.B, g.ldb, g.b_plane, n0, kbeg + BK, tid);
-    }
-    for (int64_t k0 = kbeg; k0 < kend; k0 += 2 * BK) {
-      k_tile(la0, lb0, k0);
-      if (k0 + BK < kend) k_tile(la1, lb1, k0 + BK);
+    // one buffer: stage the registers of tile k0 into LDS, start the global loads of
+    // tile k0 + BK into the same registers, then run the MFMAs on LDS
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+      __syncthreads();
+      la.store(As, tid);
+      lb.store(Bs, tid);
+      __syncthreads();
+      if (k0 + BK < kend) {
+        la.load(g.A, g.lda, g.a_plane, m0, k0 + BK, tid);
+        lb.load(g.B, g.ldb, g.b_plane, n0, k0 + BK, tid);
+      }
+#pragma unroll
+      for (int s = 0; s < BK / 16; ++s) substep(As, Bs, s);
     }
   }
 
-  // ---------------------------------------------------------------- epilogue
-  if constexpr (EPI == EPI_SYMUPD && RB_UPD_MIRROR == 1) {
-    // X += c2 * acc on the lower tile, one 32 x 32 block at a time, the mirrored
-    // positions written straight from registers: a lane holds column lc of the block
-    // and rows 8g + lr + j (j = 0..3), which is row lc, four consecutive columns, of
-    // the mirrored block -- one 16-byte store per g.  Off-diagonal tiles only; a
-    // diagonal tile masks element by element.
-    const int ld = (int)g.ldc;
-    float* Xd = (float*)g.C + (m0 + wm * WM) * g.ldc + (n0 + wn * WN);
-    float* Xm = (float*)g.C + (n0 + wn * WN) * g.ldc + (m0 + wm * WM);
-    const float c2 = (float)g.c2;
-    const int dofs = (int)((m0 + wm * WM) - (n0 + wn * WN));
+  // column-major partial sums of split kc: P[kc][n * M + m]; a lane holds rows
+  // 8 g + lr + j (j = 0..3) of column lc, one 16-byte store per g.  The lane offsets
+  // are recomputed here from an opaque copy of the lane index, so that the compiler
+  // does not hold these addresses through the k loop.
+  int ln = lane;
+  asm volatile("" : "+v"(ln));
+  const uint32_t plr = (ln >> 5) * 4, plc = ln & 31;
+  float* P = (float*)g.C + (int64_t)kc * g.M * g.N + (n0 + wn * WN) * g.M + (m0 + wm * WM);
+  const uint32_t ldp = (uint32_t)g.M;
 #pragma unroll
-    for (int i = 0; i < NBLK; ++i) {
-      const int a = i / FN, b = i % FN;
-      float nvs[16];
+  for (int a = 0; a < FM; ++a)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) nvs[r] = oldv[i & 1][r] + c2 * acc[a][b][r];
-      if (i + 2 < NBLK) load_old(i + 2, oldv[i & 1]);
-      if (!diag) {
+    for (int b = 0; b < FN; ++b)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) Xd[(a * 32 + (r >> 2) * 8 + lr + (r & 3)) * ld + b * 32 + lc] = nvs[r];
-#pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4)
-          *(float4*)(Xm + (b * 32 + lc) * ld + a * 32 + 8 * q4 + lr) =
-              make_float4(nvs[4 * q4], nvs[4 * q4 + 1], nvs[4 * q4 + 2], nvs[4 * q4 + 3]);
-      } else {
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int ml = (r >> 2) * 8 + lr + (r & 3);
-          const int d = dofs + a * 32 + ml - b * 32 - lc;  // m - n of this element
-          if (d >= 0) Xd[(a * 32 + ml) * ld + b * 32 + lc] = nvs[r];
-          if (d > 0) Xm[(b * 32 + lc) * ld + a * 32 + ml] = nvs[r];
-        }
-      }
-    }
-    return;
-  }
-  if constexpr (EPI == EPI_SYMUPD) {
-    // X += c2 * acc on the lower tile, one 32 x 32 block at a time: the old values
-    // of the block are loaded together, the new values go to X directly and,
-    // through a per-wave LDS transpose, to the mirrored positions as 128-byte rows.
-    __syncthreads();  // LDS is free once every wave left the k loop
-    float* R = (float*)smem + wave * 32 * 33;
-    const int ld = (int)g.ldc;
-    float* Xd = (float*)g.C + (m0 + wm * WM) * g.ldc + (n0 + wn * WN);  // this wave's block origin
-    float* Xm = (float*)g.C + (n0 + wn * WN) * g.ldc + (m0 + wm * WM);  // mirrored origin
-    const float c2 = (float)g.c2;
-    const int dofs = (int)((m0 + wm * WM) - (n0 + wn * WN));           // m - n at the wave origin
-#pragma unroll
-    for (int i = 0; i < NBLK; ++i) {
-      const int a = i / FN, b = i % FN;
-      float nvs[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) nvs[r] = oldv[i & 1][r] + c2 * acc[a][b][r];
-      if (i + 2 < NBLK) load_old(i + 2, oldv[i & 1]);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int ml = (r >> 2) * 8 + lr + (r & 3);
-        const float nv = nvs[r];
-        // element (m, n): m - n = dofs + a*32 + ml - b*32 - lc
-        if (!diag || dofs + a * 32 + ml - b * 32 - lc >= 0) Xd[(a * 32 + ml) * ld + b * 32 + lc] = nv;
-        R[lc * 33 + ml] = nv;
-      }
-      __syncthreads();
-      if (lane < 32) {
-#pragma unroll 8
-        for (int c = 0; c < 32; ++c)
-          if (!diag || dofs + a * 32 + lane - b * 32 - c > 0) Xm[(b * 32 + c) * ld + a * 32 + lane] = R[c * 33 + lane];
-      }
-      __syncthreads();
-    }
-    return;
-  }
-  if constexpr (EPI == EPI_PARTIAL) {
-    // column-major partial sums of split kc: P[kc][n * M + m]; a lane holds rows
-    // 8 g + lr + j (j = 0..3) of column lc, one 16-byte store per g.  The lane offsets
-    // are recomputed here from an opaque copy of the lane index, so that the compiler
-    // does not hold these addresses through the k loop.
-    int ln = lane;
-    asm volatile("" : "+v"(ln));
-    const uint32_t plr = (ln >> 5) * 4, plc = ln & 31;
-    float* P = (float*)g.C + (int64_t)kc * g.M * g.N + (n0 + wn * WN) * g.M + (m0 + wm * WM);
-    const uint32_t ldp = (uint32_t)g.M;
-#pragma unroll
-    for (int a = 0; a < FM; ++a)
-#pragma unroll
-      for (int b = 0; b < FN; ++b)
-#pragma unroll
-        for (int q4 = 0; q4 < 4; ++q4)
-          *(float4*)(P + (b * 32 + plc) * ldp + a * 32 + q4 * 8 + plr) =
-              make_float4(acc[a][b][4 * q4], acc[a][b][4 * q4 + 1], acc[a][b][4 * q4 + 2], acc[a][b][4 * q4 + 3]);
-  } else if constexpr (EPI == EPI_ADDROW) {
-    float* C = (float*)g.C + (m0 + wm * WM) * g.ldc + (n0 + wn * WN);
-    const int ld = (int)g.ldc;
-    const float c2 = (float)g.c2;
-#pragma unroll
-    for (int i = 0; i < NBLK; ++i) {
-      const int a = i / FN, b = i % FN;
-      float nvs[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) nvs[r] = oldv[i & 1][r] + c2 * acc[a][b][r];
-      if (i + 2 < NBLK) load_old(i + 2, oldv[i & 1]);
-#pragma unroll
-      for (int r = 0; r < 16; ++r) C[(a * 32 + (r >> 2) * 8 + lr + (r & 3)) * ld + b * 32 + lc] = nvs[r];
-    }
-  }
+      for (int q4 = 0; q4 < 4; ++q4)
+        *(float4*)(P + (b * 32 + plc) * ldp + a * 32 + q4 * 8 + plr) =
+            make_float4(acc[a][b][4 * q4], acc[a][b][4 * q4 + 1], acc[a][b][4 * q4 + 2], acc[a][b][4 * q4 + 3]);
 }
 
 // C[m + n*ldc] = c2 * sum_k P[k][n*M + m] (+ c0 * B0[m + n*ld01]); grid (M / 1024, N),
@@ -582,8 +383,8 @@ __global__ void k_pack_split2(const float* in, int64_t ld_in, int64_t rows, int6
 template <int BN, int WAVES_M, int WAVES_N, int NA, int NB, int PMAX, int AK, int BKD, bool LDB>
 void launch_ts(const GemmArgs& g, int64_t blocks, hipStream_t s) {
   // two LDS buffers when asked for and they fit in the 160 KiB of LDS
-  constexpr bool ldb = LDB && 2 * (NA * 128 + NB * BN) * (RB_TS_BK + 8) * 2 <= 160 * 1024;
-  hipLaunchKernelGGL((k_gemm_bf16<128, BN, WAVES_M, WAVES_N, NA, NB, PMAX, AK, BKD, ldb, EPI_PARTIAL, RB_TS_PF, RB_TS_BK>),
+  constexpr bool ldb = LDB && 2 * (NA * 128 + NB * BN) * (TS_BK + 8) * 2 <= 160 * 1024;
+  hipLaunchKernelGGL((k_gemm_bf16<128, BN, WAVES_M, WAVES_N, NA, NB, PMAX, AK, BKD, ldb, TS_BK>),
                      dim3(blocks), dim3(64 * WAVES_M * WAVES_N), 0, s, g);
 }
 
@@ -612,15 +413,12 @@ int pick_bn_auto(int64_t N) {
 
 }  // namespace
 
-// Square-update tile: 256 x 256 with 8 waves when the order allows it.
-static int sq_tile(int64_t M) { return (RB_UPD_TILE == 256 && M % 256 == 0) ? 256 : 128; }
-
-int bf16_square_tile(int64_t M, int epi) { return epi == EPI_SYMUPD ? sq_tile(M) : 128; }
+int bf16_square_tile(int64_t, int) { return 128; }
 
 int64_t gemm_bf16_blocks(const MixedGemm& mg) {
   const GemmArgs& g = mg.g;
   if (g.epi == EPI_SYMUPD || g.epi == EPI_ADDROW) {
-    const int64_t T = g.M / (g.epi == EPI_SYMUPD ? sq_tile(g.M) : 128);
+    const int64_t T = g.M / 128;
     const int64_t NTT = g.tiles ? g.ntiles : (g.epi == EPI_SYMUPD ? T * (T + 1) / 2 : T * T);
     return (NTT + 7) / 8 * 8;
   }
@@ -631,28 +429,14 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
   const GemmArgs& g = mg.g;
   if (g.M <= 0 || g.N <= 0 || g.K <= 0) return hipSuccess;
   if (g.M % 128 || g.N % 32 || g.splitk < 1) return hipErrorInvalidValue;
-  const int64_t bk = (g.epi == EPI_SYMUPD || g.epi == EPI_ADDROW) ? 32 : RB_TS_BK;
-  if (g.K % (bk * g.splitk)) return hipErrorInvalidValue;
   if (g.epi == EPI_SYMUPD || g.epi == EPI_ADDROW) {
-    if (g.N % 128 || mg.a_kind != OK_BF16_KC || mg.b_kind != OK_BF16_KC || mg.na != 2 || mg.nb != 2 ||
+    // square updates: operands pre-split into 2 bf16 planes, loaded straight into LDS
+    if (g.N % 128 || g.K % 32 || mg.a_kind != OK_BF16_KC || mg.b_kind != OK_BF16_KC || mg.na != 2 || mg.nb != 2 ||
         mg.pmax != 1 || g.splitk != 1)
       return hipErrorInvalidValue;
-    if (g.epi == EPI_SYMUPD && g.M != g.N) return hipErrorInvalidValue;
-#if RB_UPD_TILE == 256
-    if (g.epi == EPI_SYMUPD && sq_tile(g.M) == 256)
-      hipLaunchKernelGGL((k_gemm_bf16<256, 256, 2, 4, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, false, EPI_SYMUPD, 1, 32>),
-                         dim3(gemm_bf16_blocks(mg)), dim3(512), 0, s, g);
-    else
-#endif
-    if (RB_UPD_KERNEL == 1) return symupd_bf16_dma(g, gemm_bf16_blocks(mg), s);
-    else if (g.epi == EPI_SYMUPD)
-      hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, RB_UPD_LDB, EPI_SYMUPD, 1, 32>),
-                         dim3(gemm_bf16_blocks(mg)), dim3(256), 0, s, g);
-    else
-      hipLaunchKernelGGL((k_gemm_bf16<128, 128, 2, 2, 2, 2, 1, OK_BF16_KC, OK_BF16_KC, RB_UPD_LDB, EPI_ADDROW, 1, 32>),
-                         dim3(gemm_bf16_blocks(mg)), dim3(256), 0, s, g);
-    return hipGetLastError();
+    return symupd_bf16_dma(g, gemm_bf16_blocks(mg), s);
   }
+  if (g.K % (TS_BK * g.splitk)) return hipErrorInvalidValue;
   if (g.epi != EPI_COLSTORE || !partial_ws) return hipErrorInvalidValue;
   GemmArgs run = g;
   run.epi = EPI_PARTIAL;
@@ -664,12 +448,12 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
   if (mg.na == NA_ && mg.nb == NB_ && mg.pmax == PM_ && mg.a_kind == AK_ && mg.b_kind == BK_)         \
     e = launch_tall<NA_, NB_, PM_, AK_, BK_, LDB_, WAVES256_>(run, bn, blocks, s);                    \
   else
-  RB_TALL(3, 1, 2, OK_F32_KC, OK_BF16_KC, RB_TS_LDB_AS, RB_TS_WAVES256_AS)  // A S, exact bf16 sketch; L S~
-  RB_TALL(2, 2, 1, OK_F32_KC, OK_F32_KC, RB_TS_LDB, RB_TS_WAVES256)        // X Y
-  RB_TALL(3, 2, 2, OK_F32_KC, OK_F32_KC, RB_TS_LDB, RB_TS_WAVES256)        // A S with S = L S~ (FP32)
-  RB_TALL(2, 3, 2, OK_F32_MC, OK_F32_KC, RB_TS_LDB, RB_TS_WAVES256)        // L^T Y
-  RB_TALL(2, 2, 1, OK_F32_MC, OK_F32_KC, RB_TS_LDB, RB_TS_WAVES256)        // X^T P (row variants)
-  RB_TALL(3, 1, 2, OK_F32_MC, OK_BF16_KC, RB_TS_LDB_AS, RB_TS_WAVES256_AS)  // A^T S (Kaczmarz)
+  RB_TALL(3, 1, 2, OK_F32_KC, OK_BF16_KC, TS_LDB_AS, RB_TS_WAVES256_AS)  // A S, exact bf16 sketch; L S~
+  RB_TALL(2, 2, 1, OK_F32_KC, OK_F32_KC, TS_LDB, RB_TS_WAVES256)        // X Y
+  RB_TALL(3, 2, 2, OK_F32_KC, OK_F32_KC, TS_LDB, RB_TS_WAVES256)        // A S with S = L S~ (FP32)
+  RB_TALL(2, 3, 2, OK_F32_MC, OK_F32_KC, TS_LDB, RB_TS_WAVES256)        // L^T Y
+  RB_TALL(2, 2, 1, OK_F32_MC, OK_F32_KC, TS_LDB, RB_TS_WAVES256)        // X^T P (row variants)
+  RB_TALL(3, 1, 2, OK_F32_MC, OK_BF16_KC, TS_LDB_AS, RB_TS_WAVES256_AS)  // A^T S (Kaczmarz)
   // q-sized products: one LDS buffer, so that they share CUs with the n x n products
   RB_TALL(1, 3, 2, OK_BF16_KC, OK_F32_KC, false, RB_TS_WAVES256)  // G = S^T Y
   RB_TALL(1, 3, 2, OK_BF16_MC, OK_F32_KC, false, RB_TS_WAVES256)  // U = S G^-1

@@ -23,38 +23,22 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
-// Measured on the n = 16384, q = 256 update with random operands (same-run
-// comparisons): two stages of 32 columns, two workgroups per CU and 2 x 2 waves of
-// 64 x 64 were fastest; 16-column stages (any depth or occupancy), three or four
-// stages (one workgroup per CU) and 2 x 1 / 1 x 2 wave grids were 10-40% slower.
-#ifndef RB_UPD_NT
-// epilogue accesses of X: 0 ordinary, 1 non-temporal loads and stores, 2 stores only, used when
-// the panels are at least RB_UPD_NT_MINQ columns wide.  X is read and written once per launch
-// while the bf16 panels are re-read by every tile; streaming X past the caches keeps more of the
-// panels in L2 (n = 16384, q = 256: 0.717 -> 0.671 ms with 1, 0.690 ms with 2; n = 32768,
-// q = 512: 4.50 -> 4.29 ms).  With narrow panels the kernel only streams X, and there the
-// non-temporal accesses cost write bandwidth (n = 32768, q = 32: 1.58 -> 2.20 ms).
-#define RB_UPD_NT 1
-#endif
-#ifndef RB_UPD_NT_MINQ
-#define RB_UPD_NT_MINQ 128
-#endif
-#ifndef RB_UPD_BKS
-#define RB_UPD_BKS 32  // columns per stage
-#endif
-#ifndef RB_UPD_NS
-#define RB_UPD_NS 2  // stages in the ring
-#endif
-#ifndef RB_UPD_OCC
-#define RB_UPD_OCC 2  // workgroups per CU the register budget is sized for
-#endif
-#ifndef RB_UPD_SCHED
-#define RB_UPD_SCHED 0  // 1: explicit interleave of the second substep's LDS reads with MFMAs
-#endif
-#ifndef RB_UPD_WAVES
-#define RB_UPD_WAVES 2, 2  // wave grid over the 128 x 128 tile
-#endif
-
+// Launch shape, measured on the n = 16384, q = 256 update with random operands (same-run
+// comparisons): two stages of 32 columns, two workgroups per CU and 2 x 2 waves of 64 x 64
+// were fastest; 16-column stages (any depth or occupancy), three or four stages (one
+// workgroup per CU) and 2 x 1 / 1 x 2 wave grids were 10-40% slower, and an explicit
+// interleave of LDS reads with MFMAs within 1%.
+constexpr int UPD_BKS = 32;  // columns per stage
+constexpr int UPD_NS = 2;    // stages in the ring
+constexpr int UPD_OCC = 2;   // workgroups per CU the register budget is sized for
+#define RB_UPD_WAVES 2, 2    // wave grid over the 128 x 128 tile
+// The epilogue reads and writes X non-temporally when the panels are at least UPD_NT_MINQ
+// columns wide: X passes once per launch while the bf16 panels are re-read by every tile,
+// and streaming X past the caches keeps more of the panels in L2 (n = 16384, q = 256:
+// 0.717 -> 0.671 ms; non-temporal stores alone 0.690 ms; n = 32768, q = 512: 4.50 -> 4.29 ms).
+// With narrow panels the kernel only streams X, and there the non-temporal accesses cost
+// write bandwidth (n = 32768, q = 32: 1.58 -> 2.20 ms).
+constexpr int UPD_NT_MINQ = 128;
 
 namespace rb {
 
@@ -158,52 +142,7 @@ void k_symupd_dma(GemmArgs g) {
 
   // byte offset of this lane's fragment row within a piece, and its chunk swizzle
   const int ra = wm * WM + (lane & 31), rb = wn * WN + (lane & 31);
-  auto frag = [&](const char* S, int s, bf16x8 (&av)[NP][FM], bf16x8 (&bv)[NP][FN]) {
-    const int c = 2 * s + (lane >> 5);
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int a = 0; a < FM; ++a) {
-        const int r = ra + a * 32;
-        av[p][a] = *(const bf16x8*)(S + p * PLB + r * ROWB + ((c ^ ((r / RPB) % CHUNKS)) * 16));
-      }
-#pragma unroll
-    for (int p = 0; p < NP; ++p)
-#pragma unroll
-      for (int b = 0; b < FN; ++b) {
-        const int r = rb + b * 32;
-        bv[p][b] = *(const bf16x8*)(S + OPB + p * PLB + r * ROWB + ((c ^ ((r / RPB) % CHUNKS)) * 16));
-      }
-  };
-  auto mfmas = [&](const bf16x8 (&av)[NP][FM], const bf16x8 (&bv)[NP][FN]) {
-#pragma unroll
-    for (int pp = 0; pp < 3; ++pp)
-#pragma unroll
-      for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int b = 0; b < FN; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[pp == 1 ? 1 : 0][a], bv[pp == 0 ? 1 : 0][b], acc[a][b],
-                                                               0, 0, 0);
-  };
   auto compute = [&](const char* S) {
-    if constexpr (RB_UPD_SCHED == 1 && BKS == 32) {
-      // both substeps' fragments read up front, the second substep's reads placed
-      // between the first substep's MFMAs (one read after each of the first NR MFMAs)
-      constexpr int NR = NP * (FM + FN), NM = 3 * FM * FN;
-      bf16x8 a0[NP][FM], b0[NP][FN], a1[NP][FM], b1[NP][FN];
-      frag(S, 0, a0, b0);
-      frag(S, 1, a1, b1);
-      mfmas(a0, b0);
-      mfmas(a1, b1);
-      __builtin_amdgcn_sched_group_barrier(0x100, NR, 0);
-#pragma unroll
-      for (int j = 0; j < NR; ++j) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-      }
-      __builtin_amdgcn_sched_group_barrier(0x008, 2 * NM - NR, 0);
-      return;
-    }
 #pragma unroll
     for (int s = 0; s < BKS / 16; ++s) {
       const int c = 2 * s + (lane >> 5);
@@ -338,23 +277,21 @@ void k_symupd_dma(GemmArgs g) {
 }  // namespace
 
 hipError_t symupd_bf16_dma(const GemmArgs& g, int64_t blocks, hipStream_t s) {
-  if (g.K % (RB_UPD_BKS * 1) || g.M % 128 || g.M != g.N || g.lda % 8 || g.ldb % 8 || g.a_plane % 8 ||
-      g.b_plane % 8 || g.ldc % 4)
+  if (g.K % UPD_BKS || g.M % 128 || g.M != g.N || g.lda % 8 || g.ldb % 8 || g.a_plane % 8 || g.b_plane % 8 ||
+      g.ldc % 4)
     return hipErrorInvalidValue;
   constexpr int wv[2] = {RB_UPD_WAVES};
   const dim3 grid((unsigned)blocks), block(64 * wv[0] * wv[1]);
   const bool full = g.epi == EPI_ADDROW;
-  const bool nt = RB_UPD_NT != 0 && (full ? g.K : g.K / 2) >= RB_UPD_NT_MINQ;  // panel width q
+  const bool nt = (full ? g.K : g.K / 2) >= UPD_NT_MINQ;  // panel width q
   if (full && nt)
-    hipLaunchKernelGGL((k_symupd_dma<RB_UPD_BKS, RB_UPD_NS, RB_UPD_OCC, RB_UPD_WAVES, true, RB_UPD_NT>), grid, block, 0,
-                       s, g);
+    hipLaunchKernelGGL((k_symupd_dma<UPD_BKS, UPD_NS, UPD_OCC, RB_UPD_WAVES, true, 1>), grid, block, 0, s, g);
   else if (full)
-    hipLaunchKernelGGL((k_symupd_dma<RB_UPD_BKS, RB_UPD_NS, RB_UPD_OCC, RB_UPD_WAVES, true, 0>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((k_symupd_dma<UPD_BKS, UPD_NS, UPD_OCC, RB_UPD_WAVES, true, 0>), grid, block, 0, s, g);
   else if (nt)
-    hipLaunchKernelGGL((k_symupd_dma<RB_UPD_BKS, RB_UPD_NS, RB_UPD_OCC, RB_UPD_WAVES, false, RB_UPD_NT>), grid, block, 0,
-                       s, g);
+    hipLaunchKernelGGL((k_symupd_dma<UPD_BKS, UPD_NS, UPD_OCC, RB_UPD_WAVES, false, 1>), grid, block, 0, s, g);
   else
-    hipLaunchKernelGGL((k_symupd_dma<RB_UPD_BKS, RB_UPD_NS, RB_UPD_OCC, RB_UPD_WAVES, false, 0>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((k_symupd_dma<UPD_BKS, UPD_NS, UPD_OCC, RB_UPD_WAVES, false, 0>), grid, block, 0, s, g);
   return hipGetLastError();
 }
 

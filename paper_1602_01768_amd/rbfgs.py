@@ -346,14 +346,20 @@ def rbfgs_server_create(budget_bytes, workers):
 
 def rbfgs_server_submit(server, A, q, seed, tol, max_iters, tag, sketch="gauss", variant="adaptive",
                         precision="mixed", check_every=16, x_out=None):
-    """Queue one inversion; A (and x_out) must stay alive until the job's result is polled."""
-    ptr, code, ld, on_dev, _keep = _matrix_arg(A)
+    """Queue one inversion.  Returns the objects whose memory the library reads (A, or the
+    contiguous copy made of it) and writes (x_out): the caller keeps them alive until the
+    job's result is polled.  A numpy x_out must be a C-contiguous float32/float64 array (a
+    copy would receive the result instead of it)."""
+    ptr, code, ld, on_dev, keep = _matrix_arg(A)
     p = _params(A.shape[0], q, seed, sketch, variant, precision, check_every)
-    xp, xcode, xld, xdev = None, F64, 0, 0
+    xp, xcode, xld, xdev, xkeep = None, F64, 0, 0, None
     if x_out is not None:
-        xp, xcode, xld, xdev, _xkeep = _matrix_arg(x_out)
+        if isinstance(x_out, np.ndarray) and not (x_out.flags.c_contiguous and x_out.dtype in (np.float32, np.float64)):
+            raise ValueError("x_out must be a C-contiguous float32/float64 array")
+        xp, xcode, xld, xdev, xkeep = _matrix_arg(x_out)
     _check(load_library().rbfgs_server_submit(server, ctypes.byref(p), ptr, code, ld, on_dev, float(tol),
                                               int(max_iters), xp, xcode, xld, xdev, int(tag)))
+    return keep, xkeep
 
 
 def rbfgs_server_poll(server, max_results=256, wait_ms=0):
@@ -383,8 +389,8 @@ class Server:
         self._keep = {}
 
     def submit(self, A, q, seed, tol, max_iters, tag, x_out=None, **kw):
-        self._keep[int(tag)] = (A, x_out)
-        rbfgs_server_submit(self.handle, A, q, seed, tol, max_iters, tag, x_out=x_out, **kw)
+        # keep what the library reads and writes (possibly a converted copy of A) until polled
+        self._keep[int(tag)] = rbfgs_server_submit(self.handle, A, q, seed, tol, max_iters, tag, x_out=x_out, **kw)
 
     def poll(self, max_results=256, wait_ms=0):
         res = rbfgs_server_poll(self.handle, max_results, wait_ms)
