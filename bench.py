@@ -623,6 +623,56 @@ def experiment1(sizes, seed, torch, rbfgs):
     return out
 
 
+def c1_curve(torch, rbfgs, n=256, q=16, steps=300, seed=1, every=25):
+    """The n = 256 FP64 workload (A = Q diag(lambda) Q^T, lambda log-uniform in [1, 1e3], seeded
+    Gaussian Q), fixed RBFGS with a Gaussian q = 16 sketch from X_0 = I: ||I - A X_k||_F (the
+    library's exact FP64 residual) and ||X_k - A^-1||_F (A^-1 in closed form) after every step,
+    beside the same two quantities along the FP64 oracle's trajectory."""
+    import numpy as np
+    from oracle import rbfgs as R
+    from workloads import spectral_spd
+    A, Ainv = spectral_spd(n, seed, 1.0, 1e3)
+    gres, gerr = [], []
+    t0 = time.perf_counter()
+    with rbfgs.Solver(torch.from_numpy(A).cuda(), q, seed, precision="fp64") as s:
+        for _ in range(steps):
+            s.step(1)
+            gres.append(s.residual())
+            gerr.append(float(np.linalg.norm(s.x().cpu().numpy() - Ainv)))
+    t_gpu = time.perf_counter() - t0
+    ores, oerr = [], []
+    R.run_fixed(A, q, seed, "gauss", steps,
+                record=lambda k, X: (ores.append(R.residual_fro(A, X)), oerr.append(float(np.linalg.norm(X - Ainv)))))
+    gres, gerr, ores, oerr = map(np.array, (gres, gerr, ores, oerr))
+    at = [1] + list(range(every, steps + 1, every))
+    return {"workload": f"spectral SPD n={n}, lambda in [1, 1e3], fixed RBFGS gauss q={q}, FP64, X_0 = I",
+            "steps_logged": at,
+            "resid_fro": [float(f"{gres[k - 1]:.5g}") for k in at],
+            "err_vs_inverse_fro": [float(f"{gerr[k - 1]:.5g}") for k in at],
+            "resid0_fro": float(np.linalg.norm(np.eye(n) - A)),
+            "max_rel_dev_vs_oracle": {"resid": float(np.max(np.abs(gres - ores) / ores)),
+                                      "err": float(np.max(np.abs(gerr - oerr) / oerr))},
+            "gpu_s_incl_per_step_checks": round(t_gpu, 3)}
+
+
+def host_info():
+    """CPU model, logical CPUs, BLAS threads and RAM of the host the oracle runs on."""
+    info = {"cpu_model": None, "logical_cpus": os.cpu_count(), "ram_gib": None}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                info["ram_gib"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    info["openblas_num_threads"] = os.environ.get("OPENBLAS_NUM_THREADS")
+    return info
+
+
 def cpu_baseline(A32, q, seed, sketch, variant, steps):
     """The FP64 oracle on the host: `steps` iterations from X_0 = I (or L_0 = I)."""
     import numpy as np
@@ -671,6 +721,7 @@ def main():
     ap.add_argument("--c4-qs", default="32,512",
                     help="sketch sizes of the n = 32768 Householder runs (bandwidth- and MFMA-bound; empty: skip)")
     ap.add_argument("--c4-steps", type=int, default=200)
+    ap.add_argument("--c1-steps", type=int, default=300, help="steps of the n = 256 per-step curve (0: skip)")
     ap.add_argument("--serve-jobs", type=int, default=64, help="serving trace length (0: skip serving)")
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
@@ -744,6 +795,9 @@ def main():
     c4_qs = [int(x) for x in args.c4_qs.split(",") if x.strip()]
     c4 = c4_section(c4_qs, args.seed, torch, rbfgs, steps=args.c4_steps) if c4_qs else None
 
+    # ---- n = 256 FP64: ||I - A X_k||_F and ||X_k - A^-1||_F after every step, GPU beside the oracle
+    c1 = c1_curve(torch, rbfgs, steps=args.c1_steps) if args.c1_steps > 0 else None
+
     # ---- serving trace (p50 / p99 solve latency)
     serve = serving(args, torch, rbfgs) if args.serve_jobs > 0 else None
 
@@ -756,7 +810,8 @@ def main():
         A_ref32 = A_ref.cpu().numpy()
         cps, threads, Xo = cpu_baseline(A_ref32, q, args.seed, args.sketch, args.variant, args.cpu_steps)
         cpu = {"value": round(cps, 4), "unit": "iters/s", "cores": threads, "kind": "oracle",
-               "sample": f"{args.cpu_steps} FP64 oracle iterations from X_0 = I on the same A (n={n}, q={q})"}
+               "sample": f"{args.cpu_steps} FP64 oracle iterations from X_0 = I on the same A (n={n}, q={q})",
+               "host": host_info()}
         parity = {"input": "A formed by torch's FP64 GEMM from the same B (not by the library)",
                   "input_max_rel_diff_vs_library_A": ref_diff}
         for prec in ("mixed", "fp64"):
@@ -769,7 +824,21 @@ def main():
             del Xg, Ause
         del A_ref
 
+    # the long sections first and the headline figures last, so that a reader of the line's
+    # tail sees value, fp64, roofline, cpu_baseline and parity
     out = {
+        "ridge_hessian": ridge_info,
+        "variants": variants,
+        "experiment1": exp1,
+        "time_to_tolerance_ada": ttt,
+        "sampling_ada": sampling,
+        "importance_kaczmarz": importance,
+        "c4_householder_n32768": c4,
+        "serving": serve,
+        "c1_curve_n256": c1,
+        "phases_ms": {k: round(v["avg_ms"], 4) for k, v in phases.items()},
+        "products_ms_timed_region": live_ms,
+        "input_gen_s": round(t_gen, 1),
         "metric": "RBFGS iters/s + TFLOP/s (n=16384,q=256) mixed vs FP64; p50/p99 solve latency",
         "value": round(ips, 3),
         "unit": "iters/s",
@@ -790,20 +859,14 @@ def main():
         "fp64": {"value": round(ips64, 3), "unit": "iters/s", "ms_per_step": round(dt64 / args.fp64_steps * 1e3, 3),
                  "tflops_effective": round(flops * ips64 / 1e12, 3), "steps": args.fp64_steps},
         "mixed_over_fp64_per_step": round(ips / ips64, 3),
+        "ada_time_to_tol_s": ({"mixed": ttt["mixed"]["seconds"], "fp64": ttt["fp64"]["seconds"],
+                               "ratio": ttt.get("fp64_over_mixed")} if ttt else None),
+        "serving_p50_p99_ms": ({"sojourn": [serve["mixed"]["sojourn_p50_ms"], serve["mixed"]["sojourn_p99_ms"]],
+                                "rate_jobs_per_s": serve.get("arrival_rate_jobs_per_s")}
+                               if serve and "mixed" in serve else None),
         "roofline": roof,
-        "products_ms_timed_region": live_ms,
-        "phases_ms": {k: round(v["avg_ms"], 4) for k, v in phases.items()},
-        "ridge_hessian": ridge_info,
-        "variants": variants,
-        "experiment1": exp1,
-        "time_to_tolerance_ada": ttt,
-        "sampling_ada": sampling,
-        "importance_kaczmarz": importance,
-        "c4_householder_n32768": c4,
-        "serving": serve,
         "cpu_baseline": cpu,
         "parity": parity,
-        "input_gen_s": round(t_gen, 1),
     }
     print(json.dumps(out))
 
