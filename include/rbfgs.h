@@ -270,6 +270,26 @@ rbfgs_status rbfgs_ridge_hessian(const void* B, int32_t b_dtype, int64_t m, int6
                                  int32_t b_on_device, double scale, double lambda, void* A, int32_t a_dtype,
                                  int64_t lda, int32_t a_on_device, void* hip_stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc: rbfgs_ridge_hessian for device-resident B
+ * and A, which allocates and frees nothing and does not synchronise (asynchronous on
+ * hip_stream, whose device must be the current device).  Its work buffers -- B copied to
+ * FP64 with rows padded to mp = 16 ceil(m/16) and columns to np = 128 ceil(n/128), the
+ * np x np FP64 product and two scalars -- live in a fixed device array of
+ * RBFGS_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it runs on until the
+ * process ends; they are cleared by fill kernels (no memset nodes when captured).
+ *   Limit: 8 (mp np + np np) + 256 <= RBFGS_NOALLOC_SCRATCH_BYTES (for n <= 1024: m <= 7152).
+ *   Arguments as for rbfgs_ridge_hessian; B and A are device pointers.
+ * All calls on one GPU share that GPU's array and leave it holding the last call's buffers:
+ * calls whose work overlaps on one GPU (different streams, or host threads without an
+ * ordering between their streams) race; serialise them, e.g. on one stream.
+ * Errors: E_INVALID_ARG (sizes beyond the limit, bad sizes, pointers, non-finite scale or
+ * lambda), E_DEVICE (a launch failed or the array's address could not be obtained). */
+#define RBFGS_NOALLOC_SCRATCH_BYTES (64ull << 20)
+rbfgs_status rbfgs_ridge_hessian_noalloc(const void* B, int32_t b_dtype, int64_t m, int64_t n, int64_t ldb,
+                                         double scale, double lambda, void* A, int32_t a_dtype, int64_t lda,
+                                         void* hip_stream);
+
 /* ---- sketch stream (Sec. 10 sketch distributions), for testing and reuse ----
  * Write the iteration-k sketch of the stream (seed) to device memory on `hip_stream`.
  *   rbfgs_sketch_gauss: S n x q column-major (entry (i,j) at S[j*n + i]) as

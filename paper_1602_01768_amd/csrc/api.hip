@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -24,6 +25,38 @@
 #include "kernels.hpp"
 
 using namespace rb;
+
+// Device array behind rbfgs_ridge_hessian_noalloc.  Host code never passes `scratch` itself
+// (on the host it names a stand-in, not device memory): each device's address of its copy is
+// looked up once with hipGetSymbolAddress, with that device current, and kept in scratch_dev.
+static __device__ __align__(256) unsigned char scratch[RBFGS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_dev[SCRATCH_MAX_DEVICES] = {};
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// This device's copy of `scratch` (the current device's).
+hipError_t noalloc_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    scratch_dev[dev] = p;
+  }
+  *out = scratch_dev[dev];
+  return hipSuccess;
+}
+
+}  // namespace
 
 constexpr int POWER_STEPS = 100;  // power-method steps of the Newton-Schulz starting point
 constexpr int SUPER_TILES = 4;    // super-tile edge of the n x n update order (4 x 4 tiles share panels in L2)
@@ -1649,6 +1682,42 @@ rbfgs_status rbfgs_ridge_hessian(const void* B, int32_t b_dtype, int64_t m, int6
   for (void* p : {Bh, Bp, Ap, Ah, (void*)sc})
     if (p) (void)hipFree(p);
   return st;
+}
+
+// Allocation-free variant of rbfgs_ridge_hessian for device-resident B and A: the padded FP64
+// copy of B, the FP64 output and the two scalars live in the file-scope device array
+// `scratch` (one copy per GPU, held until the process ends), cleared by fill kernels rather
+// than memsets; nothing is allocated, freed or synchronised.
+rbfgs_status rbfgs_ridge_hessian_noalloc(const void* B, int32_t b_dtype, int64_t m, int64_t n, int64_t ldb,
+                                         double scale, double lambda, void* A, int32_t a_dtype, int64_t lda,
+                                         void* hip_stream) {
+  if (!B || !A || m < 1 || n < 1 || n > (1ll << 20) || m > (1ll << 24) || ldb < n || lda < n ||
+      (b_dtype != RBFGS_F32 && b_dtype != RBFGS_F64) || (a_dtype != RBFGS_F32 && a_dtype != RBFGS_F64) ||
+      !std::isfinite(scale) || !std::isfinite(lambda))
+    return RBFGS_E_INVALID_ARG;
+  const int64_t np = (n + 127) / 128 * 128, mp = (m + 15) / 16 * 16;
+  const size_t b_bytes = align256((size_t)mp * np * sizeof(double)), a_bytes = align256((size_t)np * np * sizeof(double));
+  if (b_bytes + a_bytes + 256 > RBFGS_NOALLOC_SCRATCH_BYTES) return RBFGS_E_INVALID_ARG;
+  char* base = nullptr;
+  if (noalloc_scratch((void**)&base) != hipSuccess) return RBFGS_E_DEVICE;
+  hipStream_t s = (hipStream_t)hip_stream;
+  double* Bp = (double*)base;
+  double* Ap = (double*)(base + b_bytes);
+  double* sc = (double*)(base + b_bytes + a_bytes);
+  const int sdt = b_dtype == RBFGS_F32 ? DT_F32 : DT_F64, ddt = a_dtype == RBFGS_F32 ? DT_F32 : DT_F64;
+  bool ok = fill_f64(Bp, mp * np, 0.0, s) == hipSuccess && fill_f64(Ap, np * np, 0.0, s) == hipSuccess &&
+            fill_f64(sc, 1, lambda, s) == hipSuccess && fill_f64(sc + 1, 1, 1.0, s) == hipSuccess &&
+            copy_convert(B, sdt, ldb, Bp, DT_F64, np, m, n, s) == hipSuccess &&
+            scaled_identity(Ap, np, n, sc, s) == hipSuccess;  // lambda I
+  if (ok) {
+    GemmArgs g;
+    g.M = np; g.N = np; g.K = mp;
+    g.A = Bp; g.lda = np; g.a_dt = DT_F64; g.a_kc = false;  // Aop(i, k) = B[k][i]
+    g.B = Bp; g.ldb = np; g.b_dt = DT_F64; g.b_kc = false;  // Bop(k, j) = B[k][j]
+    g.epi = EPI_SYMUPD; g.C = Ap; g.ldc = np; g.c_dt = DT_F64; g.c2 = scale;
+    ok = gemm_f64(g, nullptr, s) == hipSuccess && copy_convert(Ap, DT_F64, np, A, ddt, lda, n, n, s) == hipSuccess;
+  }
+  return ok ? RBFGS_OK : RBFGS_E_DEVICE;
 }
 
 rbfgs_status rbfgs_sketch_coord(uint64_t seed, int64_t k, int64_t n, int32_t q, int32_t* idx_dev, void* hip_stream) {

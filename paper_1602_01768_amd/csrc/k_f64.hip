@@ -767,6 +767,13 @@ hipError_t axpy_ratio(double* X, const double* P, int64_t total, const double* s
   return hipGetLastError();
 }
 
+hipError_t fill_f64(double* v, int64_t count, double x, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_f64, dim3((unsigned)std::min<int64_t>(ceil_div(count, 256), 8192)), dim3(256), 0, s, v,
+                     count, x);
+  return hipGetLastError();
+}
+
 hipError_t scaled_identity(double* X, int64_t ld, int64_t n, const double* sc, hipStream_t s) {
   hipLaunchKernelGGL(k_scaled_identity, dim3((unsigned)std::min<int64_t>(ceil_div(n, 256), 1024)), dim3(256), 0, s, X, ld,
                      n, sc);

@@ -169,6 +169,8 @@ hipError_t reduce_pairs(const double* red, int nb, double* out, hipStream_t s);
 // X += (sc[0] / sc[1]) P over `total` entries; X = (sc[0] / sc[1]) I on the n x n block.
 hipError_t axpy_ratio(double* X, const double* P, int64_t total, const double* sc, hipStream_t s);
 hipError_t scaled_identity(double* X, int64_t ld, int64_t n, const double* sc, hipStream_t s);
+// v[0 .. count) = x (a kernel, so that it may be captured into a graph)
+hipError_t fill_f64(double* v, int64_t count, double x, hipStream_t s);
 // Conjugate gradients: y = M v (transpose: M^T v) for an n x n row-major M (FP32/FP64,
 // ld % 4 == 0), FP64 vectors; `part` holds GEMV_T_CHUNKS * n doubles for the transpose.
 constexpr int GEMV_T_CHUNKS = 32;

@@ -79,6 +79,9 @@ EXPORTS = {
                                             ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
                                             ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
                                             ctypes.c_void_p]),
+    "rbfgs_ridge_hessian_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int64,
+                                                    ctypes.c_int64, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                                    ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p]),
     "rbfgs_sketch_gauss": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                           ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p]),
     "rbfgs_sketch_coord": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
@@ -286,6 +289,30 @@ def rbfgs_ridge_hessian(B, scale, lam, dtype=F32, stream=None):
                                               float(lam), ctypes.c_void_p(out.data_ptr()), dtype, n, 1,
                                               _stream_handle(stream)))
     del keep
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # RBFGS_NOALLOC_SCRATCH_BYTES
+
+
+def rbfgs_ridge_hessian_noalloc(B, scale, lam, out, stream=None):
+    """scale * B^T B + lam I for a CUDA tensor B (m x n, FP32/FP64, contiguous) into the
+    caller's CUDA tensor `out` (n x n, FP32/FP64, contiguous), through the library's
+    allocation-free entry point (work buffers in its fixed device array; asynchronous)."""
+    import torch
+    if not (isinstance(B, torch.Tensor) and B.is_cuda and B.is_contiguous() and B.dim() == 2):
+        raise TypeError("B must be a contiguous 2-D CUDA tensor")
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.is_contiguous() and out.dim() == 2):
+        raise TypeError("out must be a contiguous 2-D CUDA tensor")
+    types = {torch.float32: F32, torch.float64: F64}
+    if B.dtype not in types or out.dtype not in types:
+        raise TypeError("B and out must be float32 or float64")
+    m, n = B.shape
+    if tuple(out.shape) != (n, n):
+        raise ValueError(f"out must be {n} x {n}")
+    _check(load_library().rbfgs_ridge_hessian_noalloc(ctypes.c_void_p(B.data_ptr()), types[B.dtype], m, n, n,
+                                                      float(scale), float(lam), ctypes.c_void_p(out.data_ptr()),
+                                                      types[out.dtype], n, _stream_handle(stream)))
     return out
 
 

@@ -119,3 +119,21 @@ def test_footprint_accounts_for_each_mode():
     extra = fp(4096, 64, sketch="importance", variant="kaczmarz") - fp(4096, 64, sketch="coord", variant="kaczmarz")
     assert extra >= (4096 // 64) * 64 * 64 * 8
     assert fp(4096, 64, variant="adaptive") > 0
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_noalloc_ridge_hessian_validates_on_host():
+    """The allocation-free entry point rejects bad arguments, and sizes beyond its fixed
+    device array (8 (m_p n_p + n_p^2) + 256 bytes), before any device call."""
+    from paper_1602_01768_amd import rbfgs
+    lib = rbfgs.load_library()
+    buf = ctypes.c_void_p(256)
+    f = lib.rbfgs_ridge_hessian_noalloc
+    assert f(buf, 1, 0, 4, 4, 1.0, 0.0, buf, 1, 4, None) == rbfgs.E_INVALID_ARG
+    assert f(buf, 1, 8, 4, 3, 1.0, 0.0, buf, 1, 4, None) == rbfgs.E_INVALID_ARG
+    assert f(buf, 1, 8, 4, 4, float("inf"), 0.0, buf, 1, 4, None) == rbfgs.E_INVALID_ARG
+    assert f(None, 1, 8, 4, 4, 1.0, 0.0, buf, 1, 4, None) == rbfgs.E_INVALID_ARG
+    assert f(buf, 1, 8, 4, 4, 1.0, 0.0, None, 1, 4, None) == rbfgs.E_INVALID_ARG
+    assert f(buf, 1, 7153, 1024, 1024, 1.0, 0.0, buf, 0, 1024, None) == rbfgs.E_INVALID_ARG  # one row too many
+    assert f(buf, 1, 100, 2944, 2944, 1.0, 0.0, buf, 0, 2944, None) == rbfgs.E_INVALID_ARG  # n_p^2 alone too big
+    assert rbfgs.NOALLOC_SCRATCH_BYTES == 64 << 20
