@@ -29,6 +29,11 @@ BF16_PEAK_TFLOPS = 2500.0
 FP64_PEAK_TFLOPS = 78.6
 
 
+def log(msg):
+    """Progress line on stderr (stdout carries only the result line)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def alg_flops(n, q, variant, sketch):
     """Algorithmic flops of one iteration (products counted once, symmetric update on one triangle).
 
@@ -57,8 +62,9 @@ def phase_roofline(name, n, q, variant, sketch, precision="mixed"):
     Bytes count each operand once at its stored width (4 B in mixed mode, 8 B in FP64):
       AS, XY, LS, LtY, XtP (tall-skinny, M(n x n) * P(n x q)): read M once, read P,
                        write the n x q result                       -> e n^2 + 2 e n q
-      update (fixed, PSB): read the lower triangle of X, write all of X, read the two
-                       n x 2q bf16 hi/lo panel pairs                -> 1.5 e n^2 + 16 n q
+      update (fixed, PSB): read and write the lower triangle of X (the method's own bytes:
+                       the mixed fixed path keeps X on its lower tiles), read the two
+                       n x 2q bf16 hi/lo panel pairs                -> e n^2 + 16 n q
       update (adaptive, AIP, Kaczmarz): read and write L (or X), read the panels
                                                                     -> 2 e n^2 + 8 n q
     Their intensity (2 n^2 q algorithmic flops over these bytes) is below the bf16
@@ -71,7 +77,7 @@ def phase_roofline(name, n, q, variant, sketch, precision="mixed"):
         return "hbm", e * nn + 2 * e * nq, "GB/s"
     if name == "update":
         if variant in ("fixed", "psb"):
-            return "hbm", 1.5 * e * nn + 16 * nq, "GB/s"
+            return "hbm", e * nn + 16 * nq, "GB/s"
         return "hbm", 2 * e * nn + 8 * nq, "GB/s"
     return None
 
@@ -230,9 +236,14 @@ def serving(args, torch, rbfgs):
                         break
                     res += srv.poll(256, wait_ms=max(1, int(min(wait, 0.05) * 1000)))
                 srv.submit(mats[j["id"]], j["q"], j["seed"], args.serve_tol, 20000, tag=j["id"],
-                           variant="adaptive", precision=precision, sketch="gauss")
+                           variant="adaptive", precision=precision, sketch="gauss", check_every=15)
+            reported = 0
             while len(res) < len(unit):
                 res += srv.poll(256, wait_ms=50)
+                if len(res) >= reported + 64 or len(res) == len(unit):
+                    reported = len(res)
+                    log(f"serving {precision} ({workers} slots): {len(res)}/{len(unit)} jobs done, "
+                        f"{time.perf_counter() - start:.1f} s")
             makespan = time.perf_counter() - start
             peak = srv.stats()["peak_running"]
         return res, makespan, peak
@@ -257,7 +268,9 @@ def serving(args, torch, rbfgs):
     open_mixed = run(arrivals, "mixed", args.serve_workers)
     base = run(arrivals, "fp64", 1) if args.serve_baseline else None
     out = {"workload": f"{len(unit)} AdaRBFGS jobs (gauss), n log-uniform in [64, 8192], q = min(256, n/8), "
-                       f"tol {args.serve_tol}, budget {args.serve_budget_gb} GiB, {args.serve_workers} workers",
+                       f"tol {args.serve_tol}, device pool = budget {args.serve_budget_gb} GiB, "
+                       f"{args.serve_workers} slots on {min(args.serve_workers, 4)} streams, windows of 15 "
+                       f"iterations replayed as HIP graphs",
            "saturation_jobs_per_s": round(sat, 2), "arrival_rate_jobs_per_s": round(rate, 2),
            "closed_loop": summary(*closed), "mixed": summary(*open_mixed),
            "fp64_one_at_a_time": summary(*base) if base else None}
@@ -722,7 +735,7 @@ def main():
                     help="sketch sizes of the n = 32768 Householder runs (bandwidth- and MFMA-bound; empty: skip)")
     ap.add_argument("--c4-steps", type=int, default=200)
     ap.add_argument("--c1-steps", type=int, default=300, help="steps of the n = 256 per-step curve (0: skip)")
-    ap.add_argument("--serve-jobs", type=int, default=64, help="serving trace length (0: skip serving)")
+    ap.add_argument("--serve-jobs", type=int, default=512, help="serving trace length (0: skip serving)")
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--serve-budget-gb", type=float, default=200.0)
     ap.add_argument("--serve-tol", type=float, default=1e-3)
@@ -748,6 +761,7 @@ def main():
     torch.cuda.synchronize()
 
     # ---- timed region: mixed precision; the product kernels timed live with HIP events
+    log("timed region")
     s_mixed, dt, live = timed_steps(rbfgs.Solver, A_dev, q, args.seed, args.sketch, args.variant, "mixed",
                                     args.warmup, args.steps, torch, events=True)
     ips = args.steps / dt
@@ -757,6 +771,7 @@ def main():
     live_ms = {k: round(v[0] / max(v[1], 1), 4) for k, v in live.items()}
 
     # ---- all phases timed in a separate window (informational)
+    log("all phases timed in a separate window (informational)")
     s_mixed.profile(1)
     s_mixed.step(args.profile_steps)
     rep = s_mixed.profile_report()
@@ -765,43 +780,65 @@ def main():
     s_mixed.close()
 
     # ---- FP64 GPU path on the same matrix
+    log("FP64 GPU path on the same matrix")
     s64, dt64, _ = timed_steps(rbfgs.Solver, A64_dev, q, args.seed, args.sketch, args.variant, "fp64", 1,
                                args.fp64_steps, torch)
     ips64 = args.fp64_steps / dt64
     s64.close()
     del A64_dev
 
+    # ---- AdaRBFGS (the method that reaches the tolerance on this workload), mixed, same timing
+    log("AdaRBFGS (the method that reaches the tolerance on this work")
+    s_ada, dt_ada, live_ada = timed_steps(rbfgs.Solver, A_dev, q, args.seed, "gauss", "adaptive", "mixed",
+                                          args.warmup, args.steps, torch, events=True)
+    s_ada.close()
+    ada_flops = alg_flops(n, q, "adaptive", "gauss")
+    adaptive = {"value": round(args.steps / dt_ada, 3), "unit": "iters/s",
+                "ms_per_step": round(dt_ada / args.steps * 1e3, 4),
+                "tflops_effective": round(ada_flops * args.steps / dt_ada / 1e12, 3),
+                "products_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in live_ada.items()},
+                "roofline": live_roofline(live_ada, n, q, "adaptive", "gauss")}
+
     # ---- the other instances of the family (PSB, AIP, Kaczmarz) on the same matrix
+    log("the other instances of the family (PSB, AIP, Kaczmarz) on th")
     variants = (variants_section(A_dev, A32, q, args.seed, args.sketch, args.warmup, args.variant_steps, torch, rbfgs)
                 if args.variant_steps > 0 else None)
 
     # ---- Experiment 1 of Sec. 10: AdaRBFGS against Newton-Schulz and MR
+    log("Experiment 1 of Sec. 10")
     sizes = [int(x) for x in args.exp1_sizes.split(",") if x.strip()]
     exp1 = experiment1(sizes, args.seed, torch, rbfgs) if sizes else None
 
     # ---- time to tolerance, AdaRBFGS mixed vs FP64; its X as a CG preconditioner
+    log("time to tolerance, AdaRBFGS mixed vs FP64")
     ttt = (time_to_tolerance(A_dev, A32, q, args.seed, 1e-3, args.ttt_iters, torch, rbfgs)
            if args.ttt_iters > 0 else None)
 
     # ---- sketch distributions for AdaRBFGS: Gaussian, uniform coordinates, partition (eq. ihsih0)
+    log("sketch distributions for AdaRBFGS")
     sampling = (sampling_section(A_dev, A32, q, args.seed, torch, rbfgs, cap=args.sampling_iters)
                 if args.sampling_iters > 0 and n % q == 0 else None)
 
     # ---- Kaczmarz with importance probabilities (eq. discoptprob, X_k as the proxy)
+    log("Kaczmarz with importance probabilities (eq. discoptprob, X_k")
     importance = (importance_section(A_dev, A32, q, args.seed, torch, rbfgs, iters=args.importance_iters)
                   if args.importance_iters > 0 and n % q == 0 else None)
 
     # ---- n = 32768 Householder matrix, q = 32 (HBM-bound) and q = 512 (MFMA-bound)
+    log("n = 32768 Householder matrix, q = 32 (HBM-bound) and q = 512")
     c4_qs = [int(x) for x in args.c4_qs.split(",") if x.strip()]
     c4 = c4_section(c4_qs, args.seed, torch, rbfgs, steps=args.c4_steps) if c4_qs else None
 
     # ---- n = 256 FP64: ||I - A X_k||_F and ||X_k - A^-1||_F after every step, GPU beside the oracle
+    log("n = 256 FP64")
     c1 = c1_curve(torch, rbfgs, steps=args.c1_steps) if args.c1_steps > 0 else None
 
     # ---- serving trace (p50 / p99 solve latency)
+    log("serving trace (p50 / p99 solve latency)")
     serve = serving(args, torch, rbfgs) if args.serve_jobs > 0 else None
 
     # ---- CPU oracle baseline (bounded sample) and parity of the same steps
+    log("CPU oracle baseline (bounded sample) and parity of the same ")
     cpu = None
     parity = None
     if args.cpu_steps > 0:
@@ -859,6 +896,7 @@ def main():
         "fp64": {"value": round(ips64, 3), "unit": "iters/s", "ms_per_step": round(dt64 / args.fp64_steps * 1e3, 3),
                  "tflops_effective": round(flops * ips64 / 1e12, 3), "steps": args.fp64_steps},
         "mixed_over_fp64_per_step": round(ips / ips64, 3),
+        "adaptive_mixed": adaptive,
         "ada_time_to_tol_s": ({"mixed": ttt["mixed"]["seconds"], "fp64": ttt["fp64"]["seconds"],
                                "ratio": ttt.get("fp64_over_mixed")} if ttt else None),
         "serving_p50_p99_ms": ({"sojourn": [serve["mixed"]["sojourn_p50_ms"], serve["mixed"]["sojourn_p99_ms"]],

@@ -317,13 +317,20 @@ rbfgs_status rbfgs_sample_partition(const double* t_dev, int64_t n, int32_t q, u
 rbfgs_status rbfgs_footprint(const rbfgs_params* params, int64_t* bytes_out);
 
 /* ---- serving: many inversions (Sec. 10 stopping rule) sharing one GPU ----
- * A server owns `workers` host threads; each runs one job at a time -- a context
- * of its own on its own non-blocking stream, driven by rbfgs_invert -- so the
- * kernels of concurrent jobs overlap on the device.  Admission is first come,
- * first served: the job at the head of the queue starts when a worker is free and
- * its footprint (rbfgs_footprint, plus the staging copy of a host A) fits in
- * `budget_bytes` beside the running jobs.  Times are seconds on a monotonic
- * clock started at rbfgs_server_create.  The server is thread-safe; calls from
+ * Continuous batching under one scheduler thread.  The server allocates one device-memory
+ * pool of budget_bytes when it starts; every job's context takes its buffers from it, so
+ * admitting and retiring a job allocates and frees no device memory.  Jobs are admitted first
+ * come, first served, into a slot table of `workers` slots when a slot is free and the job's
+ * footprint (rbfgs_footprint) fits the pool beside the running jobs.  Each slot has a stream
+ * (at most 4 streams in all; slots beyond 4 share them round-robin), on which the job's
+ * context runs all of its lanes; the job advances in windows of check_every iterations, each
+ * followed by the stopping decision of rbfgs_invert.  Windows are enqueued without blocking
+ * the host -- the scheduler polls their events -- so the windows of all resident jobs are on
+ * the GPU together.  With the Gaussian sketch (fixed RBFGS or AdaRBFGS) and check_every a
+ * multiple of 3, a job's full windows are one HIP graph, captured at its first window and
+ * replayed (the sketch's iteration then comes from a device counter).  A job's iterates,
+ * iteration count and residual are those of rbfgs_invert on the job alone.  Times are seconds
+ * on a monotonic clock started at rbfgs_server_create.  The server is thread-safe; calls from
  * several host threads may interleave. */
 typedef struct rbfgs_server rbfgs_server;
 
@@ -333,21 +340,22 @@ typedef struct {
   int64_t iters;     /* iterations run */
   double resid;      /* last exact ||I - AX||_F / sqrt(n) (NaN if never computed) */
   double t_submit;   /* submission */
-  double t_admit;    /* start on a worker */
+  double t_admit;    /* admission into a slot */
   double t_done;     /* completion */
 } rbfgs_job_result;
 
 typedef struct {
   double now;            /* server clock */
   int64_t queued;        /* submitted, not started */
-  int32_t running;       /* on a worker now */
+  int32_t running;       /* in a slot now */
   int64_t outstanding;   /* queued + running */
   int64_t active_bytes;  /* footprints of the running jobs */
   int64_t peak_bytes;    /* largest active_bytes so far (<= budget) */
   int32_t peak_running;  /* most jobs running at once so far */
 } rbfgs_server_info;
 
-/* workers in [1, 64], budget_bytes > 0.  E_INVALID_ARG, E_DEVICE. */
+/* workers (slots) in [1, 64], budget_bytes > 0 (the pool, allocated here).  E_INVALID_ARG,
+ * E_OOM (the pool could not be allocated), E_DEVICE. */
 rbfgs_status rbfgs_server_create(int64_t budget_bytes, int32_t workers, rbfgs_server** out);
 
 /* Queue one inversion: A as in rbfgs_create (it must stay valid and unchanged until

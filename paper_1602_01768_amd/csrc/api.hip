@@ -23,6 +23,7 @@
 #include "common.hpp"
 #include "importance.hpp"
 #include "kernels.hpp"
+#include "pool.hpp"
 
 using namespace rb;
 
@@ -165,6 +166,15 @@ struct rbfgs_ctx {
   int64_t ntiles = 0;
   std::vector<void*> allocs;
   int64_t bytes = 0;  // device bytes the context holds (allocate() accounts them)
+  rb::DevicePool* pool = nullptr;  // serving: buffers from the server's arena instead of hipMalloc
+  bool own_lanes = true;           // false: every lane on the caller's stream (serving)
+  // serving: a window of check_every steps is captured once into a HIP graph and replayed;
+  // the sketch's iteration is then read from the device counter kdev (plus the step's offset
+  // in the window, while kcap0 >= 0 during the capture), which the graph advances at its end
+  int64_t* kdev = nullptr;
+  int64_t kcap0 = -1;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
   bool dry = false;   // allocate() only sums sizes (rbfgs_footprint)
   // per-phase timing with HIP events on the lanes' streams (rbfgs_profile)
   struct ProfRec {
@@ -201,7 +211,15 @@ void* dalloc(rbfgs_ctx* ctx, size_t bytes) {
   ctx->bytes += (int64_t)((b + 255) / 256 * 256);
   if (ctx->dry) return (void*)(uintptr_t)256;
   void* p = nullptr;
-  HIPCHK(hipMalloc(&p, b));
+  if (ctx->pool) {
+    p = ctx->pool->alloc(b);
+    if (!p) {
+      ctx->err = "the server's device memory pool has no free run of this size";
+      throw Fail{RBFGS_E_OOM};
+    }
+  } else {
+    HIPCHK(hipMalloc(&p, b));
+  }
   ctx->allocs.push_back(p);
   HIPCHK(hipMemsetAsync(p, 0, b, ctx->main.s));
   return p;
@@ -442,6 +460,8 @@ void side_products(rbfgs_ctx* ctx, int64_t k, Slot& S) {
       // depend on the previous step)
       if (!ctx->ada) HIPCHK(sample_partition(ctx->tw, ctx->n, ctx->q, ctx->p.seed, k, S.C, S.ht, ctx->status, L.s));
     } else if (ctx->coord || ctx->dcoord) HIPCHK(sketch_coord(ctx->p.seed, k, ctx->n, ctx->q, S.C, L.s));
+    else if (ctx->kcap0 >= 0)
+      HIPCHK(sketch_gauss(ctx->p.seed, k - ctx->kcap0, ctx->n, ctx->q, S.Sk, sk_dt(ctx), np, L.s, ctx->kdev));
     else HIPCHK(sketch_gauss(ctx->p.seed, k, ctx->n, ctx->q, S.Sk, sk_dt(ctx), np, L.s));
     if (ctx->dcoord) HIPCHK(coord_dense(S.C, ctx->q, S.Sk, sk_dt(ctx), np, qp, L.s));
   }
@@ -1020,13 +1040,15 @@ void make_slot(rbfgs_ctx* ctx, Slot& S) {
 
 void release(rbfgs_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->main.s);
-  if (ctx->side.s) (void)hipStreamSynchronize(ctx->side.s);
-  if (ctx->inv.s) (void)hipStreamSynchronize(ctx->inv.s);
+  if (ctx->own_lanes && ctx->side.s) (void)hipStreamSynchronize(ctx->side.s);
+  if (ctx->own_lanes && ctx->inv.s) (void)hipStreamSynchronize(ctx->inv.s);
   for (auto& r : ctx->prof_pending) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
   }
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
   for (Slot& S : ctx->slot) {
     if (S.y_ready) (void)hipEventDestroy(S.y_ready);
     if (S.g_ready) (void)hipEventDestroy(S.g_ready);
@@ -1037,9 +1059,12 @@ void release(rbfgs_ctx* ctx) {
   if (ctx->ev_xy) (void)hipEventDestroy(ctx->ev_xy);
   if (ctx->ev_g) (void)hipEventDestroy(ctx->ev_g);
   if (ctx->ev_chol) (void)hipEventDestroy(ctx->ev_chol);
-  for (void* p : ctx->allocs) (void)hipFree(p);
-  if (ctx->side.s) (void)hipStreamDestroy(ctx->side.s);
-  if (ctx->inv.s) (void)hipStreamDestroy(ctx->inv.s);
+  for (void* p : ctx->allocs) {
+    if (ctx->pool) ctx->pool->release(p);
+    else (void)hipFree(p);
+  }
+  if (ctx->own_lanes && ctx->side.s) (void)hipStreamDestroy(ctx->side.s);
+  if (ctx->own_lanes && ctx->inv.s) (void)hipStreamDestroy(ctx->inv.s);
   delete ctx;
 }
 
@@ -1113,6 +1138,7 @@ void allocate(rbfgs_ctx* ctx) {
   ctx->GH = (double*)dalloc(ctx, qq);
   ctx->Mq = (double*)dalloc(ctx, qq);
   ctx->est = (double*)dalloc(ctx, 8 * sizeof(double));
+  if (ctx->pool) ctx->kdev = (int64_t*)dalloc(ctx, sizeof(int64_t));
   if (ctx->ada) ctx->prb = (double*)dalloc(ctx, (size_t)3 * np * PROBES * sizeof(double));
   ctx->status = (int*)dalloc(ctx, sizeof(int));
   if (ctx->ada) ctx->sq = dalloc(ctx, (size_t)np * np * sizeof(double));
@@ -1134,12 +1160,49 @@ void allocate(rbfgs_ctx* ctx) {
   }
 }
 
+// The stopping rule of rbfgs_invert, the part after each window of m = st.m iterations whose
+// estimates sum to est_sum: the estimator trigger, the AdaRBFGS probe, the exact residual.
+void invert_decide(rbfgs_ctx* ctx, rb::InvertState& st, double est_sum) {
+  const double est = est_sum / (double)st.m;
+  const double tol = st.tol;
+  if (ctx->ada) {
+    // the free estimate measures ||I - L^T A L||_F^2 <= ||I - A X||_F^2: only below the
+    // target is the unbiased probe estimate of ||I - A X||_F^2 taken, and only below the
+    // target again is the exact residual computed
+    bool check = st.done >= st.next_force;
+    // (the probe estimate must fall below 0.8 of the target, about one standard deviation
+    // of a 64-probe estimate, so that a check rarely fails)
+    if (!check && est <= st.target) check = probe_residual(ctx, (uint64_t)ctx->k) <= 0.8 * st.target;
+    if (check) {
+      const double r = exact_residual(ctx);
+      st.resid = r / sqrt((double)ctx->n);
+      if (st.resid <= tol) {
+        st.result = RBFGS_OK;
+        st.finished = true;
+        return;
+      }
+      st.next_force = st.done + std::max<int64_t>(st.force_base, st.done);
+    }
+  } else if (est <= st.thresh || st.done >= st.next_force) {
+    const double r = exact_residual(ctx);
+    st.resid = r / sqrt((double)ctx->n);
+    if (st.resid <= tol) {
+      st.result = RBFGS_OK;
+      st.finished = true;
+      return;
+    }
+    // the estimate runs below the exact value: scale the trigger by the ratio observed
+    // at this check (the latest, not the smallest: the ratio drifts as X converges)
+    if (r > 0 && est > 0) st.thresh = std::min(st.target, st.target * est / (r * r));
+    st.next_force = st.done + std::max<int64_t>(st.force_base, ctx->coord || ctx->dcoord ? st.done / 2 : st.done);
+  }
+  if (st.done >= st.max_iters) st.finished = true;  // result stays E_NOT_CONVERGED
+}
+
 }  // namespace
 
-extern "C" {
-
-rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_dtype, int64_t lda,
-                          int32_t a_on_device, void* hip_stream, rbfgs_ctx** out) {
+static rbfgs_status create_impl(const rbfgs_params* params, const void* A, int32_t a_dtype, int64_t lda,
+                                int32_t a_on_device, hipStream_t stream, rb::DevicePool* pool, rbfgs_ctx** out) {
   if (!out) return RBFGS_E_INVALID_ARG;
   *out = nullptr;
   if (!params || !A) return RBFGS_E_INVALID_ARG;
@@ -1155,11 +1218,18 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
     return RBFGS_E_INVALID_ARG;
   rbfgs_ctx* ctx = new rbfgs_ctx();
   set_params(ctx, p);
-  ctx->main.s = (hipStream_t)hip_stream;
+  ctx->main.s = stream;
+  ctx->pool = pool;
+  ctx->own_lanes = pool == nullptr;
   try {
     HIPCHK(hipGetDevice(&ctx->device));
-    HIPCHK(hipStreamCreateWithFlags(&ctx->side.s, hipStreamNonBlocking));  // default priority
-    HIPCHK(hipStreamCreateWithFlags(&ctx->inv.s, hipStreamNonBlocking));   // default priority
+    if (ctx->own_lanes) {
+      HIPCHK(hipStreamCreateWithFlags(&ctx->side.s, hipStreamNonBlocking));  // default priority
+      HIPCHK(hipStreamCreateWithFlags(&ctx->inv.s, hipStreamNonBlocking));   // default priority
+    } else {  // serving: the lanes share the slot's stream
+      ctx->side.s = stream;
+      ctx->inv.s = stream;
+    }
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_begin, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_xy, hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ctx->ev_g, hipEventDisableTiming));
@@ -1221,6 +1291,100 @@ rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_d
   return RBFGS_OK;
 }
 
+rbfgs_status rbfgs_create_pooled(const rbfgs_params* params, const void* A, int32_t a_dtype, int64_t lda,
+                                 int32_t a_on_device, hipStream_t stream, rb::DevicePool* pool, rbfgs_ctx** out) {
+  if (!pool) return RBFGS_E_INVALID_ARG;
+  return create_impl(params, A, a_dtype, lda, a_on_device, stream, pool, out);
+}
+
+void rbfgs_invert_begin(rbfgs_ctx* ctx, rb::InvertState& st, double tol, int64_t max_iters) {
+  st = rb::InvertState();
+  st.tol = tol;
+  st.max_iters = max_iters;
+  st.target = tol * tol * (double)ctx->n;  // estimator target for ||I - XA||_F^2
+  st.thresh = st.target;
+  // a check is also forced after a gap without one, so that a trigger lowered by an
+  // unluckily small estimate cannot lock out the test: max(64 windows, iterations so far)
+  // for Gaussian sketches; max(16 windows, half the iterations so far) for coordinate and
+  // partition sketches, whose estimates are heavy-tailed when the residual sits in few
+  // columns (a typical window mean is then far below the true mean)
+  // (AdaRBFGS, triggered by an unbiased estimate of the decided quantity: 256 windows)
+  st.force_base = (ctx->ada ? 256 : ctx->coord || ctx->dcoord ? 16 : 64) * (int64_t)ctx->p.check_every;
+  st.next_force = st.force_base;
+  st.finished = max_iters <= 0;
+}
+
+rbfgs_status rbfgs_invert_enqueue(rbfgs_ctx* ctx, rb::InvertState& st, double* host_est, int* host_status,
+                                  hipEvent_t done) {
+  const hipStream_t s = ctx->main.s;
+  try {
+    st.m = std::min<int64_t>(ctx->p.check_every, st.max_iters - st.done);
+    // full windows of a serving context with a Gaussian sketch run as one replayed graph: all
+    // lanes share one stream, and a window of a multiple of 3 steps starts at a multiple of 3,
+    // so every window visits the sketch slots in the same order
+    const bool graph = ctx->kdev && ctx->p.sketch == RBFGS_SKETCH_GAUSS && !ctx->prof &&
+                       (ctx->p.variant == RBFGS_FIXED || ctx->p.variant == RBFGS_ADAPTIVE) &&
+                       ctx->p.check_every % 3 == 0 && st.m == ctx->p.check_every && ctx->k % 3 == 0;
+    if (!graph) {
+      HIPCHK(fill_f64(ctx->est + 2, 1, 0.0, s));
+      enqueue_steps(ctx, st.m);
+    } else if (!ctx->gexec) {
+      const int64_t k0 = ctx->k;
+      HIPCHK(hipMemsetAsync(ctx->kdev, 0, sizeof(int64_t), s));
+      HIPCHK(add_i64(ctx->kdev, k0, s));
+      HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      ctx->kcap0 = k0;
+      try {
+        HIPCHK(fill_f64(ctx->est + 2, 1, 0.0, s));
+        enqueue_steps(ctx, st.m);
+        HIPCHK(add_i64(ctx->kdev, st.m, s));
+      } catch (const Fail&) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(s, &g);
+        if (g) (void)hipGraphDestroy(g);
+        ctx->kcap0 = -1;
+        throw;
+      }
+      ctx->kcap0 = -1;
+      HIPCHK(hipStreamEndCapture(s, &ctx->graph));
+      HIPCHK(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
+      HIPCHK(hipGraphLaunch(ctx->gexec, s));
+    } else {
+      HIPCHK(hipGraphLaunch(ctx->gexec, s));
+      ctx->k += st.m;
+    }
+    st.done += st.m;
+    HIPCHK(hipMemcpyAsync(host_est, ctx->est + 2, sizeof(double), hipMemcpyDeviceToHost, ctx->main.s));
+    HIPCHK(hipMemcpyAsync(host_status, ctx->status, sizeof(int), hipMemcpyDeviceToHost, ctx->main.s));
+    HIPCHK(hipEventRecord(done, ctx->main.s));
+  } catch (const Fail& f) {
+    return f.st;
+  }
+  return RBFGS_OK;
+}
+
+rbfgs_status rbfgs_invert_after(rbfgs_ctx* ctx, rb::InvertState& st, double est_sum, int status) {
+  if (status) {
+    st.finished = true;
+    st.result = status == 3 ? RBFGS_E_NOT_SPD : status == 4 ? RBFGS_E_NONFINITE : RBFGS_E_DEVICE;
+    return st.result;
+  }
+  try {
+    invert_decide(ctx, st, est_sum);
+  } catch (const Fail& f) {
+    st.finished = true;
+    st.result = f.st;
+  }
+  return RBFGS_OK;
+}
+
+extern "C" {
+
+rbfgs_status rbfgs_create(const rbfgs_params* params, const void* A, int32_t a_dtype, int64_t lda,
+                          int32_t a_on_device, void* hip_stream, rbfgs_ctx** out) {
+  return create_impl(params, A, a_dtype, lda, a_on_device, (hipStream_t)hip_stream, nullptr, out);
+}
+
 rbfgs_status rbfgs_step(rbfgs_ctx* ctx, int64_t nsteps) {
   if (!ctx || nsteps < 0) return RBFGS_E_INVALID_ARG;
   try {
@@ -1267,64 +1431,31 @@ rbfgs_status rbfgs_estimate(rbfgs_ctx* ctx, double* est_out) {
 
 rbfgs_status rbfgs_invert(rbfgs_ctx* ctx, double tol, int64_t max_iters, int64_t* iters_out, double* resid_out) {
   if (!ctx || !(tol > 0) || max_iters < 0) return RBFGS_E_INVALID_ARG;
-  int64_t done = 0;
-  double resid = NAN;
-  const double target = tol * tol * (double)ctx->n;  // estimator target for ||I - XA||_F^2
-  double thresh = target;
-  // a check is also forced after a gap without one, so that a trigger lowered by an
-  // unluckily small estimate cannot lock out the test: max(64 windows, iterations so far)
-  // for Gaussian sketches; max(16 windows, half the iterations so far) for coordinate and
-  // partition sketches, whose estimates are heavy-tailed when the residual sits in few
-  // columns (a typical window mean is then far below the true mean)
-  // (AdaRBFGS, triggered by an unbiased estimate of the decided quantity: 256 windows)
-  const int64_t force_base = (ctx->ada ? 256 : ctx->coord || ctx->dcoord ? 16 : 64) * (int64_t)ctx->p.check_every;
-  int64_t next_force = force_base;
+  rb::InvertState st;
+  rbfgs_invert_begin(ctx, st, tol, max_iters);
   rbfgs_status result = RBFGS_E_NOT_CONVERGED;
   try {
-    while (done < max_iters) {
-      const int64_t m = std::min<int64_t>(ctx->p.check_every, max_iters - done);
-      // the trigger is the mean of the window's m estimates (each unbiased; a single one
-      // can be ~0, e.g. a partition block drawn again right after it was projected)
-      HIPCHK(hipMemsetAsync(ctx->est + 2, 0, sizeof(double), ctx->main.s));
-      enqueue_steps(ctx, m);
-      done += m;
-      rbfgs_status st = read_status(ctx);
-      if (st != RBFGS_OK) { result = st; break; }
+    while (!st.finished) {
       double est = 0;
+      HIPCHK(hipMemsetAsync(ctx->est + 2, 0, sizeof(double), ctx->main.s));
+      enqueue_steps(ctx, st.m = std::min<int64_t>(ctx->p.check_every, st.max_iters - st.done));
+      st.done += st.m;
+      rbfgs_status s = read_status(ctx);
+      if (s != RBFGS_OK) {
+        st.finished = true;
+        st.result = s;
+        break;
+      }
       HIPCHK(hipMemcpyAsync(&est, ctx->est + 2, sizeof(double), hipMemcpyDeviceToHost, ctx->main.s));
       HIPCHK(hipStreamSynchronize(ctx->main.s));
-      est /= (double)m;
-      if (ctx->ada) {
-        // the free estimate measures ||I - L^T A L||_F^2 <= ||I - A X||_F^2: only below the
-        // target is the unbiased probe estimate of ||I - A X||_F^2 taken, and only below the
-        // target again is the exact residual computed
-        bool check = done >= next_force;
-        // (the probe estimate must fall below 0.8 of the target, about one standard deviation
-        // of a 64-probe estimate, so that a check rarely fails)
-        if (!check && est <= target) check = probe_residual(ctx, (uint64_t)ctx->k) <= 0.8 * target;
-        if (check) {
-          const double r = exact_residual(ctx);
-          resid = r / sqrt((double)ctx->n);
-          if (resid <= tol) { result = RBFGS_OK; break; }
-          next_force = done + std::max<int64_t>(force_base, done);
-        }
-        continue;
-      }
-      if (est <= thresh || done >= next_force) {
-        const double r = exact_residual(ctx);
-        resid = r / sqrt((double)ctx->n);
-        if (resid <= tol) { result = RBFGS_OK; break; }
-        // the estimate runs below the exact value: scale the trigger by the ratio observed
-        // at this check (the latest, not the smallest: the ratio drifts as X converges)
-        if (r > 0 && est > 0) thresh = std::min(target, target * est / (r * r));
-        next_force = done + std::max<int64_t>(force_base, ctx->coord || ctx->dcoord ? done / 2 : done);
-      }
+      invert_decide(ctx, st, est);
     }
+    result = st.result;
   } catch (const Fail& f) {
     result = f.st;
   }
-  if (iters_out) *iters_out = done;
-  if (resid_out) *resid_out = resid;
+  if (iters_out) *iters_out = st.done;
+  if (resid_out) *resid_out = st.resid;
   if (result == RBFGS_E_NOT_CONVERGED) ctx->err = "max_iters reached above tolerance";
   return result;
 }

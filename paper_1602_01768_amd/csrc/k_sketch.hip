@@ -9,7 +9,9 @@
 
 namespace rb {
 
-__global__ void k_sketch_gauss(uint64_t seed, uint64_t k, int64_t n, int64_t q, void* S, int dt, int64_t ld) {
+__global__ void k_sketch_gauss(uint64_t seed, uint64_t k, const int64_t* kbase, int64_t n, int64_t q, void* S, int dt,
+                               int64_t ld) {
+  if (kbase) k += (uint64_t)*kbase;  // iteration = device counter + offset (replayed graphs)
   const int64_t total = n * q;
   const int64_t nblocks = (total + 3) / 4;
   for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nblocks; b += (int64_t)gridDim.x * blockDim.x) {
@@ -28,10 +30,20 @@ __global__ void k_sketch_gauss(uint64_t seed, uint64_t k, int64_t n, int64_t q, 
   }
 }
 
-hipError_t sketch_gauss(uint64_t seed, int64_t k, int64_t n, int32_t q, void* S, int dt, int64_t ld, hipStream_t s) {
+hipError_t sketch_gauss(uint64_t seed, int64_t k, int64_t n, int32_t q, void* S, int dt, int64_t ld, hipStream_t s,
+                        const int64_t* kbase) {
   const int64_t nblocks = (n * (int64_t)q + 3) / 4;
   const unsigned grid = (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(nblocks, 256), 4096));
-  hipLaunchKernelGGL(k_sketch_gauss, dim3(grid), dim3(256), 0, s, seed, (uint64_t)k, n, (int64_t)q, S, dt, ld);
+  hipLaunchKernelGGL(k_sketch_gauss, dim3(grid), dim3(256), 0, s, seed, (uint64_t)k, kbase, n, (int64_t)q, S, dt, ld);
+  return hipGetLastError();
+}
+
+__global__ void k_add_i64(int64_t* c, int64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *c += v;
+}
+
+hipError_t add_i64(int64_t* c, int64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_i64, dim3(1), dim3(64), 0, s, c, v);
   return hipGetLastError();
 }
 

@@ -100,8 +100,10 @@ hipError_t pack_split2(const float* in, int64_t ld_in, int64_t rows, int64_t col
                        __bf16* hi, __bf16* lo, int64_t ld_out, int64_t col_off, hipStream_t s);
 
 // ------------------------------------------------------------------ sketches
-hipError_t sketch_gauss(uint64_t seed, int64_t k, int64_t n, int32_t q, void* S, int dt,
-                        int64_t ld, hipStream_t s);
+hipError_t sketch_gauss(uint64_t seed, int64_t k, int64_t n, int32_t q, void* S, int dt, int64_t ld, hipStream_t s,
+                        const int64_t* kbase = nullptr);  // iteration k (+ *kbase when given)
+// *c += v (one thread; a kernel so that it can sit in a captured graph)
+hipError_t add_i64(int64_t* c, int64_t v, hipStream_t s);
 hipError_t sketch_coord(uint64_t seed, int64_t k, int64_t n, int32_t q, int32_t* idx,
                         hipStream_t s);
 

@@ -1,12 +1,21 @@
-// Serving: many independent inversions share one GPU under a device-memory budget.
+// Serving: many independent inversions share one GPU, batched continuously.
 //
-// Jobs are admitted first come, first served: the job at the head of the queue
-// starts when a worker thread is free and its footprint (rbfgs_footprint) fits
-// in the budget beside the running jobs.  Each worker runs one job at a time on
-// its own non-blocking stream -- a context of its own (three streams), driven by
-// rbfgs_invert -- so the kernels of concurrent jobs overlap on the device.
+// One scheduler thread drives every resident job.  The device memory of all jobs comes from
+// one pool allocated when the server starts (pool.hpp), so admitting and retiring a job
+// allocates and frees no device memory.  The slot table has `slots` entries, each with a
+// stream of its own (at most four streams, as many as the GPU has hardware queues for a
+// process; slots beyond four share them round-robin).  A job is admitted, first come first
+// served, into a free slot when its footprint fits the pool; its context then runs every lane
+// on the slot's stream and advances in windows of check_every iterations -- a window captured
+// once into a HIP graph and replayed (api.hip) -- each followed by an asynchronous copy of the
+// window's estimate and status word to pinned host memory and an event.  The scheduler polls
+// the events: for each finished window it takes rbfgs_invert's stopping decision (rarely an
+// exact residual, synchronous on that slot's stream) and enqueues the next window at once, so
+// windows of all resident jobs are in flight together and the host never waits on one job.
+// Results are the same as for the job alone: a job's iterations depend only on its own data.
 #include <math.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -17,8 +26,83 @@
 #include <hip/hip_runtime.h>
 
 #include "../../include/rbfgs.h"
+#include "pool.hpp"
+
+namespace rb {
+
+hipError_t DevicePool::init(size_t bytes) {
+  cap_ = (bytes + 255) / 256 * 256;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, cap_);
+  if (e != hipSuccess) {
+    cap_ = 0;
+    return e;
+  }
+  base_ = (char*)p;
+  free_.clear();
+  live_.clear();
+  free_[0] = cap_;
+  used_ = 0;
+  return hipSuccess;
+}
+
+void DevicePool::destroy() {
+  if (base_) (void)hipFree(base_);
+  base_ = nullptr;
+  cap_ = used_ = 0;
+  free_.clear();
+  live_.clear();
+}
+
+void* DevicePool::alloc(size_t bytes) {
+  const size_t b = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second < b) continue;
+    const size_t off = it->first, len = it->second;
+    free_.erase(it);
+    if (len > b) free_[off + b] = len - b;
+    live_[off] = b;
+    used_ += b;
+    return base_ + off;
+  }
+  return nullptr;
+}
+
+void DevicePool::release(void* p) {
+  if (!p) return;
+  const size_t off = (size_t)((char*)p - base_);
+  auto lv = live_.find(off);
+  if (lv == live_.end()) return;
+  size_t start = off, len = lv->second;
+  used_ -= len;
+  live_.erase(lv);
+  auto next = free_.lower_bound(start);
+  if (next != free_.end() && next->first == start + len) {  // merge with the run after
+    len += next->second;
+    next = free_.erase(next);
+  }
+  if (next != free_.begin()) {  // and with the run before
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == start) {
+      start = prev->first;
+      len += prev->second;
+      free_.erase(prev);
+    }
+  }
+  free_[start] = len;
+}
+
+size_t DevicePool::largest_free() const {
+  size_t m = 0;
+  for (const auto& f : free_) m = std::max(m, f.second);
+  return m;
+}
+
+}  // namespace rb
 
 namespace {
+
+constexpr int MAX_STREAMS = 4;
 
 struct Job {
   uint64_t tag = 0;
@@ -37,12 +121,28 @@ struct Job {
   double t_submit = 0, t_admit = 0;
 };
 
+struct SlotState {
+  bool busy = false;
+  bool inflight = false;  // a window is enqueued and its event not yet seen
+  Job job;
+  rbfgs_ctx* ctx = nullptr;
+  rb::InvertState st;
+  hipStream_t s = nullptr;
+  hipEvent_t ev = nullptr;
+  double* h_est = nullptr;  // pinned
+  int* h_status = nullptr;  // pinned
+};
+
 }  // namespace
 
 struct rbfgs_server {
   int64_t budget = 0;
   int device = 0;
   std::chrono::steady_clock::time_point t0;
+  rb::DevicePool pool;
+  std::vector<hipStream_t> streams;
+  std::vector<SlotState> slots;
+  void* pinned = nullptr;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Job> queue;
@@ -51,67 +151,135 @@ struct rbfgs_server {
   int64_t outstanding = 0;  // submitted and not yet finished
   int active = 0, peak_active = 0;
   bool stopping = false;
-  std::vector<std::thread> threads;
+  std::thread scheduler;
 
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
-  void worker();
+  void run();
+  bool admit();
+  void finish(SlotState& sl, rbfgs_status st);
 };
 
-void rbfgs_server::worker() {
-  (void)hipSetDevice(device);
-  hipStream_t st = nullptr;
-  const bool have_stream = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
-  for (;;) {
-    Job j;
-    {
-      std::unique_lock<std::mutex> lk(mu);
-      cv_work.wait(lk, [&] {
-        return (stopping && queue.empty()) || (!queue.empty() && active_bytes + queue.front().bytes <= budget);
-      });
-      if (queue.empty()) break;  // stopping, nothing left
-      j = queue.front();
-      queue.pop_front();
-      active_bytes += j.bytes;
-      peak_bytes = std::max(peak_bytes, active_bytes);
-      ++active;
-      peak_active = std::max(peak_active, active);
-      j.t_admit = now();
+// Admit the job at the head of the queue into a free slot; false when none was admitted.
+bool rbfgs_server::admit() {
+  SlotState* free_slot = nullptr;
+  for (SlotState& sl : slots)
+    if (!sl.busy) {
+      free_slot = &sl;
+      break;
     }
-    rbfgs_job_result r{};
-    r.tag = j.tag;
-    r.t_submit = j.t_submit;
-    r.t_admit = j.t_admit;
-    r.resid = NAN;
-    rbfgs_ctx* ctx = nullptr;
-    rbfgs_status s = have_stream ? rbfgs_create(&j.p, j.A, j.a_dtype, j.lda, j.a_on_device, st, &ctx)
-                                 : RBFGS_E_DEVICE;
-    if (s == RBFGS_OK) {
-      int64_t iters = 0;
-      double resid = NAN;
-      s = rbfgs_invert(ctx, j.tol, j.max_iters, &iters, &resid);
-      r.iters = iters;
-      r.resid = resid;
-      if (j.x_out && (s == RBFGS_OK || s == RBFGS_E_NOT_CONVERGED)) {
-        const rbfgs_status sx = rbfgs_get_x(ctx, j.x_out, j.x_dtype, j.ldx, j.x_on_device);
-        if (sx != RBFGS_OK) s = sx;
-      }
-      rbfgs_destroy(ctx);
-    }
-    r.status = s;
-    r.t_done = now();
-    {
-      std::lock_guard<std::mutex> lk(mu);
-      active_bytes -= j.bytes;
-      --active;
-      --outstanding;
-      done.push_back(r);
-    }
-    cv_work.notify_all();
-    cv_done.notify_all();
+  if (!free_slot) return false;
+  Job j;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (queue.empty() || queue.front().bytes > (int64_t)pool.largest_free()) return false;
+    j = queue.front();
+    queue.pop_front();
   }
-  if (have_stream) (void)hipStreamDestroy(st);
+  SlotState& sl = *free_slot;
+  j.t_admit = now();
+  rbfgs_ctx* ctx = nullptr;
+  const rbfgs_status s = rbfgs_create_pooled(&j.p, j.A, j.a_dtype, j.lda, j.a_on_device, sl.s, &pool, &ctx);
+  if (s == RBFGS_E_OOM) {  // the pool is fragmented: wait for a job to retire
+    std::lock_guard<std::mutex> lk(mu);
+    queue.push_front(j);
+    return false;
+  }
+  sl.job = j;
+  if (s != RBFGS_OK) {
+    sl.ctx = nullptr;
+    finish(sl, s);
+    return true;
+  }
+  sl.ctx = ctx;
+  sl.busy = true;
+  sl.inflight = false;
+  rbfgs_invert_begin(ctx, sl.st, j.tol, j.max_iters);
+  std::lock_guard<std::mutex> lk(mu);
+  active_bytes += j.bytes;
+  peak_bytes = std::max(peak_bytes, active_bytes);
+  ++active;
+  peak_active = std::max(peak_active, active);
+  return true;
+}
+
+// Result of the job in the slot; its context's buffers go back to the pool.
+void rbfgs_server::finish(SlotState& sl, rbfgs_status s) {
+  rbfgs_job_result r{};
+  r.tag = sl.job.tag;
+  r.t_submit = sl.job.t_submit;
+  r.t_admit = sl.job.t_admit;
+  r.resid = NAN;
+  const bool had_ctx = sl.ctx != nullptr;
+  if (had_ctx) {
+    r.iters = sl.st.done;
+    r.resid = sl.st.resid;
+    if (sl.job.x_out && (s == RBFGS_OK || s == RBFGS_E_NOT_CONVERGED)) {
+      const rbfgs_status sx = rbfgs_get_x(sl.ctx, sl.job.x_out, sl.job.x_dtype, sl.job.ldx, sl.job.x_on_device);
+      if (sx != RBFGS_OK) s = sx;
+    }
+    rbfgs_destroy(sl.ctx);
+    sl.ctx = nullptr;
+  }
+  r.status = s;
+  r.t_done = now();
+  sl.busy = false;
+  sl.inflight = false;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    if (had_ctx) {
+      active_bytes -= sl.job.bytes;
+      --active;
+    }
+    --outstanding;
+    done.push_back(r);
+  }
+  cv_done.notify_all();
+}
+
+void rbfgs_server::run() {
+  (void)hipSetDevice(device);
+  for (;;) {
+    bool progressed = false;
+    while (admit()) progressed = true;
+    for (SlotState& sl : slots) {
+      if (!sl.busy) continue;
+      if (sl.inflight) {
+        const hipError_t q = hipEventQuery(sl.ev);
+        if (q == hipErrorNotReady) continue;
+        sl.inflight = false;
+        progressed = true;
+        if (q != hipSuccess) {
+          finish(sl, RBFGS_E_DEVICE);
+          continue;
+        }
+        rbfgs_invert_after(sl.ctx, sl.st, *sl.h_est, *sl.h_status);
+      }
+      if (sl.st.finished) {
+        finish(sl, sl.st.result);
+        progressed = true;
+        continue;
+      }
+      const rbfgs_status e = rbfgs_invert_enqueue(sl.ctx, sl.st, sl.h_est, sl.h_status, sl.ev);
+      if (e != RBFGS_OK) finish(sl, e);
+      else sl.inflight = true;
+      progressed = true;
+    }
+    if (progressed) continue;
+    bool any_busy = false;
+    for (const SlotState& sl : slots) any_busy |= sl.busy;
+    std::unique_lock<std::mutex> lk(mu);
+    if (!any_busy) {
+      if (stopping && queue.empty()) break;
+      // idle: wait for a submission (or for the head job to fit after a retirement)
+      cv_work.wait_for(lk, std::chrono::milliseconds(queue.empty() ? 50 : 1),
+                       [&] { return stopping || !queue.empty(); });
+      continue;
+    }
+    lk.unlock();
+    std::this_thread::sleep_for(std::chrono::microseconds(20));  // windows in flight: poll again
+  }
 }
 
 extern "C" {
@@ -123,11 +291,34 @@ rbfgs_status rbfgs_server_create(int64_t budget_bytes, int32_t workers, rbfgs_se
   rbfgs_server* sv = new rbfgs_server();
   sv->budget = budget_bytes;
   sv->t0 = std::chrono::steady_clock::now();
-  if (hipGetDevice(&sv->device) != hipSuccess) {
+  auto fail = [&](rbfgs_status st) {
+    for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
+    for (SlotState& sl : sv->slots)
+      if (sl.ev) (void)hipEventDestroy(sl.ev);
+    if (sv->pinned) (void)hipHostFree(sv->pinned);
+    sv->pool.destroy();
     delete sv;
-    return RBFGS_E_DEVICE;
+    return st;
+  };
+  if (hipGetDevice(&sv->device) != hipSuccess) return fail(RBFGS_E_DEVICE);
+  const hipError_t pe = sv->pool.init((size_t)budget_bytes);
+  if (pe != hipSuccess) return fail(pe == hipErrorOutOfMemory ? RBFGS_E_OOM : RBFGS_E_DEVICE);
+  const int ns = std::min(workers, MAX_STREAMS);
+  for (int i = 0; i < ns; ++i) {
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return fail(RBFGS_E_DEVICE);  // default priority
+    sv->streams.push_back(s);
   }
-  for (int i = 0; i < workers; ++i) sv->threads.emplace_back([sv] { sv->worker(); });
+  if (hipHostMalloc(&sv->pinned, (size_t)workers * 16, hipHostMallocDefault) != hipSuccess) return fail(RBFGS_E_DEVICE);
+  sv->slots.resize(workers);
+  for (int i = 0; i < workers; ++i) {
+    SlotState& sl = sv->slots[i];
+    sl.s = sv->streams[i % ns];
+    sl.h_est = (double*)((char*)sv->pinned + 16 * i);
+    sl.h_status = (int*)((char*)sv->pinned + 16 * i + 8);
+    if (hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming) != hipSuccess) return fail(RBFGS_E_DEVICE);
+  }
+  sv->scheduler = std::thread([sv] { sv->run(); });
   *out = sv;
   return RBFGS_OK;
 }
@@ -142,7 +333,6 @@ rbfgs_status rbfgs_server_submit(rbfgs_server* sv, const rbfgs_params* params, c
   int64_t bytes = 0;
   const rbfgs_status fs = rbfgs_footprint(params, &bytes);
   if (fs != RBFGS_OK) return fs;
-  if (!a_on_device) bytes += params->n * lda * (a_dtype == RBFGS_F32 ? 4 : 8);  // staging of a host A
   if (bytes > sv->budget) return RBFGS_E_OOM;
   Job j;
   j.tag = tag;
@@ -202,7 +392,15 @@ void rbfgs_server_destroy(rbfgs_server* sv) {
     sv->stopping = true;
   }
   sv->cv_work.notify_all();
-  for (std::thread& t : sv->threads) t.join();
+  if (sv->scheduler.joinable()) sv->scheduler.join();
+  for (hipStream_t s : sv->streams) {
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+  }
+  for (SlotState& sl : sv->slots)
+    if (sl.ev) (void)hipEventDestroy(sl.ev);
+  if (sv->pinned) (void)hipHostFree(sv->pinned);
+  sv->pool.destroy();
   delete sv;
 }
 

@@ -102,3 +102,34 @@ def test_invalid_uses_rejected(lib):
         assert ok
         with pytest.raises(lib.RbfgsError):
             s.pcg(rhs(32, 1), precond=True)
+
+
+@pytest.mark.parametrize("variant", ["fixed", "adaptive"])
+def test_mixed_end_to_end_against_oracle_preconditioner(lib, variant):
+    """End to end in mixed precision: the GPU's own iterate (30 mixed steps) preconditions the
+    GPU's CG, the oracle's own FP64 iterate (30 oracle steps on the same FP32 A) preconditions
+    the oracle's CG; both run to ||r|| <= 1e-8 ||b||.  The two preconditioners differ at the
+    mixed-precision level (about 1e-5), so the iteration counts agree up to the GPU's test
+    interval (every 8 iterations), and both solutions lie within kappa(A) * tol of A^-1 b."""
+    from oracle import rbfgs as R
+    n, q, steps, tol = 520, 40, 30, 1e-8
+    A = gram_ridge(n, 9)
+    A64 = np.asarray(A, np.float64)
+    b = rhs(n, 9)
+    with lib.Solver(A, q, 4, variant=variant, precision="mixed") as s:
+        s.step(steps)
+        x, ok, k, rel = s.pcg(b, precond=True, tol=tol, max_iters=2000)
+    if variant == "fixed":
+        Mo = R.run_fixed(A64, q, 4, "gauss", steps)
+    else:
+        Lo = R.run_ada(A64, q, 4, "gauss", steps)
+        Mo = Lo @ Lo.T
+    xo, ko, relo = P.pcg(A64, b, M=Mo, tol=tol, max_iters=2000)
+    assert ok and relo <= tol
+    assert ko <= k <= (ko + 7) // 8 * 8 + 8, (k, ko)
+    xs = np.linalg.solve(A64, b)
+    w = np.linalg.eigvalsh(A64)
+    bound = 2.0 * (w[-1] / w[0]) * tol * np.linalg.norm(xs)
+    x = x.cpu().numpy()
+    assert np.linalg.norm(x - xs) <= bound and np.linalg.norm(xo - xs) <= bound
+    assert np.linalg.norm(b - A64 @ x) <= 1.01 * tol * np.linalg.norm(b)

@@ -1,9 +1,10 @@
 """Serving extension: several inversions sharing the GPU through rbfgs_server_*.
 
-Every job's outcome must equal a direct rbfgs_invert of the same problem (the
-path is deterministic, so iterations and residual agree exactly), admission must
-keep the running footprints within the budget, and a job that cannot fit is
-rejected at submission.
+Every job's outcome in an overlapping mix must equal the same job run alone by a direct
+rbfgs_invert (the path is deterministic, so iterations, residual and X agree exactly) -- with
+windows of 16 iterations launched kernel by kernel, and with windows of 15 replayed as captured
+HIP graphs; admission must keep the running footprints within the budget, and a job that cannot
+fit is rejected at submission.
 """
 import numpy as np
 import pytest
@@ -27,10 +28,11 @@ def _matrix(j, n):
     return gram_ridge(n, 10 + j) if j % 2 == 0 else spectral_spd(n, 20 + j, 1.0, 30.0)[0].astype(np.float32)
 
 
-def _direct(lib, A, q, seed, variant, precision, sketch, max_iters):
-    with lib.Solver(A, q, seed, sketch=sketch, variant=variant, precision=precision) as s:
+def _direct(lib, A, q, seed, variant, precision, sketch, max_iters, check_every=16):
+    with lib.Solver(A, q, seed, sketch=sketch, variant=variant, precision=precision, check_every=check_every) as s:
         ok, iters, resid = s.invert(TOL, max_iters)
-    return ok, iters, resid
+        X = s.x()
+    return ok, iters, resid, X
 
 
 def _drain(srv, count, timeout_polls=2000):
@@ -42,24 +44,45 @@ def _drain(srv, count, timeout_polls=2000):
     return out
 
 
-def test_server_results_match_direct_solves(lib):
+@pytest.mark.parametrize("check_every", [16, 15])
+def test_server_results_match_direct_solves(lib, check_every):
     import torch
     mats = [_matrix(j, n) for j, (n, *_rest) in enumerate(JOBS)]
+    X = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for (n, *_rest) in JOBS]
     with lib.Server(budget_bytes=8 << 30, workers=4) as srv:
         for j, ((n, q, variant, precision, sketch), A) in enumerate(zip(JOBS, mats)):
             srv.submit(torch.from_numpy(A).cuda(), q, 100 + j, TOL, 3000, tag=j, variant=variant,
-                       precision=precision, sketch=sketch)
+                       precision=precision, sketch=sketch, check_every=check_every, x_out=X[j])
         res = {r["tag"]: r for r in _drain(srv, len(JOBS))}
         info = srv.stats()
     assert sorted(res) == list(range(len(JOBS)))
     assert info["peak_running"] >= 2  # jobs did overlap
     for j, ((n, q, variant, precision, sketch), A) in enumerate(zip(JOBS, mats)):
-        ok, iters, resid = _direct(lib, A, q, 100 + j, variant, precision, sketch, 3000)
+        ok, iters, resid, Xd = _direct(lib, A, q, 100 + j, variant, precision, sketch, 3000, check_every)
         r = res[j]
         assert r["status"] == (lib.OK if ok else lib.E_NOT_CONVERGED), (j, r)
         assert r["iters"] == iters, (j, r, iters)
         assert r["resid"] == resid or (np.isnan(r["resid"]) and np.isnan(resid)), (j, r, resid)
+        assert torch.equal(X[j], Xd), (j, float((X[j] - Xd).abs().max()))
         assert r["t_submit"] <= r["t_admit"] <= r["t_done"]
+
+
+def test_server_many_jobs_each_equal_alone(lib):
+    """Sixteen jobs through six slots (more slots than streams, more jobs than slots), graph
+    windows: each X equals the job run alone."""
+    import torch
+    specs = [(64 + 37 * j, max(1, (64 + 37 * j) // 8)) for j in range(16)]
+    mats = [torch.from_numpy(gram_ridge(n, 40 + j)).cuda() for j, (n, _) in enumerate(specs)]
+    X = [torch.zeros((n, n), dtype=torch.float64, device="cuda") for n, _ in specs]
+    with lib.Server(budget_bytes=8 << 30, workers=6) as srv:
+        for j, ((n, q), A) in enumerate(zip(specs, mats)):
+            srv.submit(A, q, 300 + j, TOL, 3000, tag=j, check_every=15, x_out=X[j])
+        res = {r["tag"]: r for r in _drain(srv, len(specs))}
+        info = srv.stats()
+    assert sorted(res) == list(range(len(specs))) and info["peak_running"] >= 4
+    for j, ((n, q), A) in enumerate(zip(specs, mats)):
+        ok, iters, resid, Xd = _direct(lib, A, q, 300 + j, "adaptive", "mixed", "gauss", 3000, 15)
+        assert res[j]["iters"] == iters and torch.equal(X[j], Xd), j
 
 
 def test_server_budget_limits_concurrency_and_returns_x(lib):
