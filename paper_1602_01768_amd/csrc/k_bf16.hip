@@ -34,16 +34,25 @@ RB_DEV void split_n(float x, __bf16 (&o)[NP]) {
   }
 }
 
+// Tall products whose split-K factor divides 8 take their tiles in the XCD-aware order of
+// k_gemm_bf16; deeper splits (the q x q Grams) keep split index fastest.
+RB_HD bool xcd_order(int splitk) { return splitk <= 8 && 8 % splitk == 0; }
+
 // Loader for one operand tile of ROWS (m or n) x BK into LDS planes [NP][ROWS][PITCH].
 template <int ROWS, int NP, int KIND, int NT, int BK>
 struct TileLoader {
   static constexpr int PITCH = BK + 8;
   // registers held between the global load and the LDS store
-  // F32_KC: float4 per thread; F32_MC: 4 x 4 micro-blocks per thread, 4 float4 each
+  // F32_KC: float4 per thread; F32_MC: runs of 8 consecutive k of one row m (8 dword loads,
+  // consecutive lanes on consecutive m, so each load instruction reads contiguous memory and
+  // each 16-byte LDS store of a lane lands on rows one pitch apart: no bank conflicts);
+  // BF16_MC: 4 x 4 micro-blocks
   static constexpr int MBLK = ROWS * BK / 16;
+  static constexpr int MCU = (ROWS * (BK / 8) + NT - 1) / NT;  // F32_MC: 8-k runs per thread
   static constexpr int F4 = (KIND == OK_BF16_KC) ? 1
-                            : (KIND == OK_F32_MC || KIND == OK_BF16_MC) ? 4 * ((MBLK + NT - 1) / NT)
-                                                                         : ROWS * BK / 4 / NT;
+                            : (KIND == OK_F32_MC) ? 2 * MCU
+                            : (KIND == OK_BF16_MC) ? 4 * ((MBLK + NT - 1) / NT)
+                                                   : ROWS * BK / 4 / NT;
   static_assert(KIND != OK_BF16_MC || NP == 1, "an m-contiguous bf16 operand is exact: one piece");
   static constexpr int V8 = (KIND == OK_BF16_KC) ? (ROWS * (BK / 8) + NT - 1) / NT : 1;  // 16-byte chunks per plane
   float4 f[(F4 > 0 && KIND != OK_BF16_MC) ? F4 : 1];
@@ -60,15 +69,16 @@ struct TileLoader {
         f[i] = *(const float4*)(A + (r0 + row) * ld + k0 + c4);
       }
     } else if constexpr (KIND == OK_F32_MC) {
-      // micro-block b: columns m4..m4+3 (contiguous in memory) of rows kk..kk+3
+      // run u: row m = u % ROWS, k = k0 + 8 (u / ROWS) .. + 7, one dword per k
       const float* A = (const float*)base;
 #pragma unroll
-      for (int i = 0; i < F4 / 4; ++i) {
-        const int b = tid + NT * i;
-        if (MBLK % NT == 0 || b < MBLK) {
-          const int m4 = (b % (ROWS / 4)) * 4, kk = (b / (ROWS / 4)) * 4;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) f[4 * i + j] = *(const float4*)(A + (k0 + kk + j) * ld + r0 + m4);
+      for (int i = 0; i < MCU; ++i) {
+        const int u = tid + NT * i;
+        if (ROWS * (BK / 8) % NT == 0 || u < ROWS * (BK / 8)) {
+          const int m = u % ROWS, kg = u / ROWS;
+          const float* src = A + (k0 + 8 * kg) * ld + r0 + m;
+          f[2 * i] = make_float4(src[0], src[ld], src[2 * ld], src[3 * ld]);
+          f[2 * i + 1] = make_float4(src[4 * ld], src[5 * ld], src[6 * ld], src[7 * ld]);
         }
       }
     } else if constexpr (KIND == OK_BF16_MC) {
@@ -115,29 +125,23 @@ struct TileLoader {
         }
       }
     } else if constexpr (KIND == OK_F32_MC) {
-      // transpose the 4 x 4 micro-block in registers: LDS row m gets k = kk..kk+3
+      // run u: one 16-byte store per piece into row m, k columns 8 kg .. 8 kg + 7
 #pragma unroll
-      for (int i = 0; i < F4 / 4; ++i) {
-        const int b = tid + NT * i;
-        if (MBLK % NT == 0 || b < MBLK) {
-          const int m4 = (b % (ROWS / 4)) * 4, kk = (b / (ROWS / 4)) * 4;
-          const float4* fb = &f[4 * i];
+      for (int i = 0; i < MCU; ++i) {
+        const int u = tid + NT * i;
+        if (ROWS * (BK / 8) % NT == 0 || u < ROWS * (BK / 8)) {
+          const int m = u % ROWS, kg = u / ROWS;
+          const float v[8] = {f[2 * i].x, f[2 * i].y, f[2 * i].z, f[2 * i].w,
+                              f[2 * i + 1].x, f[2 * i + 1].y, f[2 * i + 1].z, f[2 * i + 1].w};
+          __bf16 pc[8][NP];
 #pragma unroll
-          for (int mm = 0; mm < 4; ++mm) {
-            const float v0 = mm == 0 ? fb[0].x : mm == 1 ? fb[0].y : mm == 2 ? fb[0].z : fb[0].w;
-            const float v1 = mm == 0 ? fb[1].x : mm == 1 ? fb[1].y : mm == 2 ? fb[1].z : fb[1].w;
-            const float v2 = mm == 0 ? fb[2].x : mm == 1 ? fb[2].y : mm == 2 ? fb[2].z : fb[2].w;
-            const float v3 = mm == 0 ? fb[3].x : mm == 1 ? fb[3].y : mm == 2 ? fb[3].z : fb[3].w;
-            __bf16 p0[NP], p1[NP], p2[NP], p3[NP];
-            split_n<NP>(v0, p0);
-            split_n<NP>(v1, p1);
-            split_n<NP>(v2, p2);
-            split_n<NP>(v3, p3);
+          for (int e = 0; e < 8; ++e) split_n<NP>(v[e], pc[e]);
 #pragma unroll
-            for (int p = 0; p < NP; ++p) {
-              bf16x4 v = {p0[p], p1[p], p2[p], p3[p]};
-              *(bf16x4*)(lds + (p * ROWS + m4 + mm) * PITCH + kk) = v;
-            }
+          for (int p = 0; p < NP; ++p) {
+            bf16x8 w;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) w[e] = pc[e][p];
+            *(bf16x8*)(lds + (p * ROWS + m) * PITCH + 8 * kg) = w;
           }
         }
       }
@@ -192,9 +196,25 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N, 2) void k_gemm_bf16(GemmArg
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % WAVES_M, wn = wave / WAVES_M;
   const int64_t MT = g.M / BM;
-  const int64_t bid = blockIdx.x;
-  const int kc = (int)(bid % g.splitk);
-  const int64_t mt = (bid / g.splitk) % MT, nt = (bid / g.splitk) / MT;
+  int kc;
+  int64_t mt, nt;
+  if (!xcd_order(g.splitk)) {
+    const int64_t bid = blockIdx.x;
+    kc = (int)(bid % g.splitk);
+    mt = (bid / g.splitk) % MT;
+    nt = (bid / g.splitk) / MT;
+  } else {
+    // blockIdx % 8 is the XCD: it fixes the K chunk (XCDs of one chunk share its slice of the
+    // panel in their L2s) and a residue class of row tiles; within an XCD the column tiles of
+    // one row tile are consecutive, so the row tile of the n x n operand is read from HBM once
+    // and the next column tile finds it in the same L2
+    const int x = (int)(blockIdx.x % 8), G = 8 / g.splitk;
+    const int64_t l = blockIdx.x / 8, NTT = g.N / BN;
+    kc = x % g.splitk;
+    nt = l % NTT;
+    mt = (l / NTT) * G + x / g.splitk;
+    if (mt >= MT) return;
+  }
   const int64_t kchunk = g.K / g.splitk;
   const int64_t kbeg = kc * kchunk, kend = kbeg + kchunk;
   const int64_t m0 = mt * BM, n0 = nt * BN;
@@ -422,7 +442,10 @@ int64_t gemm_bf16_blocks(const MixedGemm& mg) {
     const int64_t NTT = g.tiles ? g.ntiles : (g.epi == EPI_SYMUPD ? T * (T + 1) / 2 : T * T);
     return (NTT + 7) / 8 * 8;
   }
-  return (g.M / 128) * (g.N / pick_bn(g)) * g.splitk;
+  const int64_t MT = g.M / 128, NTT = g.N / pick_bn(g);
+  if (!xcd_order(g.splitk)) return MT * NTT * g.splitk;
+  const int64_t G = 8 / g.splitk;
+  return 8 * ((MT + G - 1) / G) * NTT;  // row tiles beyond MT return at once
 }
 
 hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
