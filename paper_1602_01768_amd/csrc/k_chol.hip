@@ -4,15 +4,19 @@
 // of the inverse factor); the method needs G symmetric positive definite, and
 // a non-positive pivot is reported through the status word.
 //
-// Blocks of order <= 128 run in one workgroup with the whole block in LDS,
-// factored in 32-wide panels:
-//   F  one wave factors the 32 x 32 diagonal block D = L_pp L_pp^T in registers,
-//      half a row per lane;
-//   T  the panel below by forward substitution: L_ip = A_ip L_pp^-T, a row per thread;
-//   U  trailing update of the lower triangle: A_ik -= L_ip L_kp^T;
-// then W_bb = L_bb^-1 for all diagonal blocks at once (a column per thread), and Z
-// block row by block row: Z_bb = W_bb, Z_ip = -(W_ii L_i,p:i) Z_p:i,p.
-// Larger orders recurse on 2 x 2 blocks with FP64 GEMMs.
+// Blocks of order nb <= 128 run in one workgroup with the whole block in registers
+// (4 rows x nb/16 columns per lane, nb/16 waves), by symmetric Gaussian elimination
+// applied at once to G and to the identity: step k broadcasts row k through LDS, and
+// every row i > k subtracts m_i = G_ki / G_kk times it, the identity part included.
+// After nb steps the identity part holds the unit lower factor's inverse L1^-1 (with
+// G = L1 D L1^T, the pivots D), so Z = D^-1/2 L1^-1.  Column k of the identity part
+// starts at step k, where its entry in row i > k is -m_i; the sweep keeps the entry
+// G_ik there instead (= -D_k times it, up to rounding: the broadcast row carries a zero
+// in column k), which leaves column k of the identity part scaled by -D_k throughout,
+// undone at the end -- so every step is the same multiply-add over all columns, with
+// no per-column selection.  One barrier per step, and no phase in which one wave works
+// while the others wait.  G^-1 = Z^T Z then runs on the FP64 matrix cores from a copy
+// of Z in LDS.  Larger orders recurse on 2 x 2 blocks with FP64 GEMMs.
 #include <math.h>
 
 #include <mutex>
@@ -24,11 +28,8 @@ namespace rb {
 
 namespace {
 
-constexpr int CB = 32;         // panel width
-constexpr int LEAF_NT = 512;   // threads of the leaf workgroup
-constexpr int LEAF_MAX = 128;  // largest order held in LDS
-// the panel (T) and Z-row phases give each thread at most one 4 x 4 micro-tile
-static_assert((LEAF_MAX - CB) / 4 * (CB / 4) <= LEAF_NT, "one micro-tile per thread");
+constexpr int CB = 32;         // granule of the block orders
+constexpr int LEAF_MAX = 128;  // largest order held in registers
 
 // 1 / sqrt(x): hardware estimate refined by two Newton steps (x > 0).
 RB_DEV double rsqrt_f64(double x) {
@@ -36,16 +37,6 @@ RB_DEV double rsqrt_f64(double x) {
   y = y * (1.5 - 0.5 * x * y * y);
   y = y * (1.5 - 0.5 * x * y * y);
   return y;
-}
-
-// Compiler barrier: keeps the loads of an unrolled step from being hoisted into earlier
-// steps (which would hold them all in registers at once).
-RB_DEV void hold_loads() { __asm__ volatile("" ::: "memory"); }
-
-RB_DEV void lds_fence() {
-  // LDS writes of this wave are complete and visible before later LDS reads
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
-  __builtin_amdgcn_wave_barrier();
 }
 
 // Lower-triangular tile index t -> (ti, tk), ti >= tk, row by row.
@@ -57,279 +48,123 @@ RB_DEV void tri_decode(int t, int& ti, int& tk) {
   tk = t - i * (i + 1) / 2;
 }
 
-size_t leaf_lds_doubles(int nb) { return (size_t)nb * (nb + 1) + 2 * (size_t)nb + 2 * CB + 1; }
+// LDS pitch (doubles) of the copy of Z: rows 16 doubles beyond a multiple of 32 banks
+// apart, so that the two rows a half-wave reads in one MFMA operand load use disjoint banks.
+template <int NB>
+constexpr int zpitch() { return NB + 16; }
 
-// G: nb x nb block (row-major, ldg), lower triangle read; entries with index >= qv
-// are taken as the identity.  Writes Z (row-major, ldz; lower, zero elsewhere and
-// on padded indices) and, when Ginv != null, Ginv = Z^T Z (zero on padded indices).
-__global__ __launch_bounds__(LEAF_NT) void k_chol_leaf(const double* __restrict__ G, int64_t ldg, int nb, int qv,
-                                                       double* __restrict__ Z, int64_t ldz,
-                                                       double* __restrict__ Ginv, int64_t ldi, int* status) {
-  extern __shared__ double lds[];
-  const int P = nb + 1;
-  double* a = lds;                  // nb x P: L in the lower triangle, Z^T strictly above it
-  double* zd = a + nb * P;          // diag(Z)
-  double* dinv = zd + nb;           // 1 / L_jj
-  double* colbuf = dinv + nb;       // column j of the diagonal block being factored (x2)
-  int* flag = (int*)(colbuf + 2 * CB);
-  const int tid = threadIdx.x;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-  for (int e = tid; e < nb * nb; e += LEAF_NT) {
-    const int i = e / nb, k = e - i * nb;
-    if (k > i) continue;
-    a[i * P + k] = (i < qv && k < qv) ? G[(int64_t)i * ldg + k] : (i == k ? 1.0 : 0.0);
-  }
-  if (tid == 0) *flag = 0;
+// G: nb x nb block (row-major, ldg), lower triangle read; entries with index >= qv are
+// taken as the identity.  Writes Z (row-major, ldz; lower, zero elsewhere and on padded
+// indices) and, when Ginv != null, Ginv = Z^T Z (zero on padded indices; dynamic LDS of
+// nb * zpitch<nb>() doubles).
+template <int NB>
+__global__ __launch_bounds__(4 * NB) void k_chol_elim(const double* __restrict__ G, int64_t ldg, int qv,
+                                                      double* __restrict__ Z, int64_t ldz,
+                                                      double* __restrict__ Ginv, int64_t ldi, int* status) {
+  constexpr int CPL = NB / 16;  // columns per lane
+  constexpr int NW = NB / 16;   // waves: 16 rows each
+  constexpr int ZP = zpitch<NB>();
+  __shared__ double rowbuf[2][NB];  // row k, double-buffered: one barrier per step
+  __shared__ double pinv[NB];       // 1 / D_k
+  __shared__ double piv[NB];        // the pivots D
+  __shared__ int bad;
+  extern __shared__ double zs[];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int rg = lane >> 4, cg = lane & 15;
+  const int i0 = 16 * w + 4 * rg, j0 = cg * CPL;  // rows i0 .. i0+3, columns j0 .. j0+CPL-1
+
+  double W[4][CPL];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < CPL; ++y) {
+      const int i = i0 + x, j = j0 + y;
+      W[x][y] = (i < qv && j < qv) ? G[(int64_t)(i > j ? i : j) * ldg + (i > j ? j : i)] : (i == j ? 1.0 : 0.0);
+    }
+  if (tid == 0) bad = 0;
   __syncthreads();
 
-  const int npan = nb / CB;
-  for (int pan = 0; pan < npan; ++pan) {
-    const int j0 = pan * CB;
-    // ---- F: factor the diagonal block D = L_pp L_pp^T in registers.  Lane r + 32h of
-    // wave 0 holds columns 16h .. 16h+15 of row r; the sweep is unrolled so every
-    // register index is static.
-    if (tid < 64) {
-      const int r = tid & 31, h = tid >> 5;
-      double d[16];
+  for (int k = 0; k < NB; ++k) {
+    double* rb = rowbuf[k & 1];
+    // the 16 lanes holding row k publish it (zero in column k), the pivot and its inverse
+    if (w == (k >> 4) && rg == ((k >> 2) & 3)) {
 #pragma unroll
-      for (int kk = 0; kk < 16; ++kk) {
-        const int k = 16 * h + kk;
-        d[kk] = (k <= r) ? a[(j0 + r) * P + j0 + k] : 0.0;
-      }
-      bool bad = false;
+      for (int x = 0; x < 4; ++x)
+        if (x == (k & 3)) {
 #pragma unroll
-      for (int j = 0; j < CB; ++j) {
-        const int hj = j >> 4, kj = j & 15;
-        double* cb = colbuf + (j & 1) * CB;  // two buffers: step j+1 never overwrites what step j reads
-        if (h == hj) cb[r] = d[kj];  // column j of the reduced block (rows >= j used)
-        lds_fence();
-        const double piv = cb[j];
-        bad |= !(piv > 0.0);
-        const double inv = rsqrt_f64(piv);
-        const double lr = (r > j) ? cb[r] * inv : 0.0;  // L[r][j]
-        if (h == hj) d[kj] = (r > j) ? lr : (r == j ? piv * inv : d[kj]);
-        const double lri = lr * inv;
-        if (h == 0) {
-#pragma unroll
-          for (int k = j + 1; k < 16; ++k) d[k] -= lri * cb[k];  // L[r][j] L[k][j]
-        } else {
-#pragma unroll
-          for (int k = (j + 1 > 16 ? j + 1 : 16); k < CB; ++k) d[k - 16] -= lri * cb[k];
-        }
-        if (tid == j) dinv[j0 + j] = inv;
-      }
-      lds_fence();
-#pragma unroll
-      for (int kk = 0; kk < 16; ++kk) {
-        const int k = 16 * h + kk;
-        if (k <= r) a[(j0 + r) * P + j0 + k] = d[kk];
-      }
-      if (bad) atomicOr(flag, 1);
-    }
-    __syncthreads();
-    if (*flag) {
-      if (tid == 0) atomicCAS(status, 0, 3);
-      return;
-    }
-    const int R = nb - j0 - CB;  // rows below the panel
-    if (R == 0) break;
-    // ---- T: L_ip = A_ip L_pp^-T by forward substitution, one panel row per thread,
-    // in place (each thread reads back only what it wrote itself).
-    if (tid < R) {
-      double* xi = a + (j0 + CB + tid) * P + j0;
-      for (int c = 0; c < CB; ++c) {
-        const double* lc = a + (j0 + c) * P + j0;
-        double s0 = xi[c], s1 = 0.0, s2 = 0.0, s3 = 0.0;  // four chains
-        int m = 0;
-        for (; m + 4 <= c; m += 4) {
-          s0 -= xi[m] * lc[m];
-          s1 -= xi[m + 1] * lc[m + 1];
-          s2 -= xi[m + 2] * lc[m + 2];
-          s3 -= xi[m + 3] * lc[m + 3];
-        }
-        for (; m < c; ++m) s0 -= xi[m] * lc[m];
-        xi[c] = ((s0 + s1) + (s2 + s3)) * dinv[j0 + c];
-      }
-    }
-    __syncthreads();
-    // ---- U: trailing update of the lower triangle, 4 x 4 micro-tiles
-    {
-      const int T4 = R / 4, ntile = T4 * (T4 + 1) / 2, base = j0 + CB;
-      for (int t = tid; t < ntile; t += LEAF_NT) {
-        int ti, tk;
-        tri_decode(t, ti, tk);
-        const int i0 = base + 4 * ti, k0 = base + 4 * tk;
-        double acc[4][4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-#pragma unroll 4
-        for (int c = 0; c < CB; ++c) {
-          double li[4], lk[4];
-#pragma unroll
-          for (int x = 0; x < 4; ++x) {
-            li[x] = a[(i0 + x) * P + j0 + c];
-            lk[x] = a[(k0 + x) * P + j0 + c];
+          for (int y = 0; y < CPL; ++y) {
+            const bool kk = j0 + y == k;
+            rb[j0 + y] = kk ? 0.0 : W[x][y];
+            if (kk) {
+              piv[k] = W[x][y];
+              pinv[k] = 1.0 / W[x][y];
+              if (!(W[x][y] > 0.0)) bad = 1;
+            }
           }
-#pragma unroll
-          for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) acc[x][y] += li[x] * lk[y];
         }
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y)
-            if (i0 + x >= k0 + y) a[(i0 + x) * P + k0 + y] -= acc[x][y];
-      }
-      __syncthreads();
-    }
-  }
-
-  // ---- W_bb = L_bb^-1 for every diagonal block at once, one column c per thread:
-  // W[r][c] = (delta_rc - sum_{m < r} L[r][m] W[m][c]) / L[r][r], row by row, written
-  // straight to its Z^T slot a[c][r] (r > c) or zd (r = c); each thread reads back
-  // only its own column.
-  if (tid < nb) {
-    const int b0 = (tid / CB) * CB, c = tid % CB;
-    double* wc = a + (b0 + c) * P + b0;  // W[m][c] at wc[m] for m > c
-    for (int r = c; r < CB; ++r) {
-      const double* lr = a + (b0 + r) * P + b0;
-      double s0 = (r == c) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;  // four chains
-      if (r > c) s0 -= lr[c] * zd[b0 + c];
-      int m = c + 1;
-      for (; m + 4 <= r; m += 4) {
-        s0 -= lr[m] * wc[m];
-        s1 -= lr[m + 1] * wc[m + 1];
-        s2 -= lr[m + 2] * wc[m + 2];
-        s3 -= lr[m + 3] * wc[m + 3];
-      }
-      for (; m < r; ++m) s0 -= lr[m] * wc[m];
-      const double v = ((s0 + s1) + (s2 + s3)) * dinv[b0 + r];
-      if (r == c) zd[b0 + c] = v;
-      else wc[r] = v;
-    }
-  }
-  __syncthreads();
-
-  // ---- Z off the diagonal blocks, block row by block row; 4 x 4 micro-tiles of the
-  // 32 x rb block row, one per thread
-  for (int bi = 1; bi < npan; ++bi) {
-    const int rb = bi * CB, nt = (CB / 4) * (rb / 4);
-    const bool act = tid < nt;
-    const int r0 = act ? 4 * (tid % (CB / 4)) : 0, m0 = act ? 4 * (tid / (CB / 4)) : 0;
-    // M = W_ii L_i,0:rb (written over L's block row)
-    double acc[4][4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-    if (act) {
-      double zr[4];
-#pragma unroll
-      for (int x = 0; x < 4; ++x) zr[x] = zd[rb + r0 + x];
-#pragma unroll 4
-      for (int q = 0; q < CB; ++q) {
-        double wv[4], lv[4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-          const int r = r0 + x;
-          const double wq = a[(rb + q) * P + rb + r];  // W_ii[r][q] for q < r
-          wv[x] = (q < r) ? wq : (q == r ? zr[x] : 0.0);
-          lv[x] = a[(rb + q) * P + m0 + x];
-        }
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] += wv[x] * lv[y];
-      }
     }
     __syncthreads();
-    if (act) {
+    if (16 * w + 15 > k) {  // this wave holds rows below k
+      const double inv = pinv[k];
+      double b[CPL], bi[4];
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+      for (int y = 0; y < CPL; ++y) b[y] = rb[j0 + y];
 #pragma unroll
-        for (int y = 0; y < 4; ++y) a[(rb + r0 + x) * P + m0 + y] = acc[x][y];
-    }
-    __syncthreads();
-    // Z[rb + r][c] = -sum_{m = c}^{rb - 1} M[r][m] Z[m][c], stored at a[c][rb + r]
-    if (act) {
-      const int c0 = m0;
-      double zc[4];
-#pragma unroll
-      for (int y = 0; y < 4; ++y) zc[y] = zd[c0 + y];
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-      // Z[m][c] = 0 for m < c: start at the tile's 32-column block (uniform per wave)
-#pragma unroll 4
-      for (int m = c0 & ~(CB - 1); m < rb; ++m) {
-        double mv[4], zv[4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x) mv[x] = a[(rb + r0 + x) * P + m];
-#pragma unroll
-        for (int y = 0; y < 4; ++y) {
-          const int cc = c0 + y;
-          const double zm = a[cc * P + m];  // Z[m][cc] for m > cc
-          zv[y] = (m > cc) ? zm : (m == cc ? zc[y] : 0.0);
-        }
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-          for (int y = 0; y < 4; ++y) acc[x][y] += mv[x] * zv[y];
-      }
-#pragma unroll
-      for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) a[(c0 + y) * P + rb + r0 + x] = -acc[x][y];
-    }
-    __syncthreads();
-  }
-
-  // ---- outputs
-  for (int e = tid; e < nb * nb; e += LEAF_NT) {
-    const int i = e / nb, k = e - i * nb;
-    double v = 0.0;
-    if (i < qv && k < qv) v = (k < i) ? a[k * P + i] : (k == i ? zd[i] : 0.0);
-    Z[(int64_t)i * ldz + k] = v;
-  }
-  if (!Ginv) return;
-  // Ginv[i][k] = sum_{m >= max(i, k)} Z[m][i] Z[m][k], lower 4 x 4 micro-tiles mirrored
-  const int T4 = nb / 4, ntile = T4 * (T4 + 1) / 2;
-  for (int t = tid; t < ntile; t += LEAF_NT) {
-    int ti, tk;
-    tri_decode(t, ti, tk);
-    const int i0 = 4 * ti, k0 = 4 * tk;
-    double acc[4][4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
-    for (int m = i0; m < nb; ++m) {  // Z[m][i] = 0 for m < i, and i0 >= k0
-      double zi[4], zk[4];
+      for (int x = 0; x < 4; ++x) bi[x] = rb[i0 + x];  // G_ki
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
-        const int ii = i0 + x, kk = k0 + x;
-        zi[x] = (m > ii) ? a[ii * P + m] : (m == ii ? zd[ii] : 0.0);
-        zk[x] = (m > kk) ? a[kk * P + m] : (m == kk ? zd[kk] : 0.0);
+        const double m = (i0 + x > k) ? bi[x] * inv : 0.0;  // rows <= k are final
+#pragma unroll
+        for (int y = 0; y < CPL; ++y) W[x][y] = fma(-m, b[y], W[x][y]);
       }
+    }
+  }
+  __syncthreads();
+  if (bad) {
+    if (tid == 0) atomicCAS(status, 0, 3);
+    return;
+  }
+
+  // Z = D^-1/2 L1^-1 with L1^-1[i][j] = -W[i][j] / D_j below the diagonal, 1 on it
 #pragma unroll
-      for (int x = 0; x < 4; ++x)
+  for (int x = 0; x < 4; ++x) {
+    const int i = i0 + x;
+    const double rs = rsqrt_f64(piv[i]);
 #pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] += zi[x] * zk[y];
+    for (int y = 0; y < CPL; ++y) {
+      const int j = j0 + y;
+      double v = (j < i) ? -W[x][y] * pinv[j] * rs : (j == i ? rs : 0.0);
+      if (i >= qv || j >= qv) v = 0.0;
+      Z[(int64_t)i * ldz + j] = v;
+      if (Ginv) zs[i * ZP + j] = v;
+    }
+  }
+  if (!Ginv) return;
+  __syncthreads();
+
+  // Ginv = Z^T Z on the lower 16 x 16 tiles, mirrored (v_mfma_f64_16x16x4f64: lane l holds
+  // A(l%16, l/16), B(l/16, l%16) and the output column l%16, rows l/16 + 4r)
+  constexpr int T = NB / 16, NTILE = T * (T + 1) / 2;
+  for (int t = w; t < NTILE; t += NW) {
+    int ti, tj;
+    tri_decode(t, ti, tj);
+    f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int m0 = 16 * ti; m0 < NB; m0 += 4) {  // Z[m][a] = 0 for m < a
+      const double av = zs[(m0 + (lane >> 4)) * ZP + 16 * ti + (lane & 15)];
+      const double bv = zs[(m0 + (lane >> 4)) * ZP + 16 * tj + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
     }
 #pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-      for (int y = 0; y < 4; ++y) {
-        const int i = i0 + x, k = k0 + y;
-        if (i < k) continue;
-        const double v = (i < qv && k < qv) ? acc[x][y] : 0.0;
-        Ginv[(int64_t)i * ldi + k] = v;
-        Ginv[(int64_t)k * ldi + i] = v;
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * ti + (lane >> 4) + 4 * r, col = 16 * tj + (lane & 15);
+      const double v = (row < qv && col < qv) ? acc[r] : 0.0;
+      Ginv[(int64_t)row * ldi + col] = v;
+      Ginv[(int64_t)col * ldi + row] = v;
+    }
   }
 }
 
@@ -341,19 +176,32 @@ __global__ void k_zero_pad_sq(double* M, int64_t ld, int q, int qp) {
   }
 }
 
-hipError_t launch_leaf(const double* G, int64_t ldg, int nb, int qv, double* Z, int64_t ldz, double* Ginv,
-                       int64_t ldi, int* status, hipStream_t s) {
+template <int NB>
+hipError_t launch_elim(const double* G, int64_t ldg, int qv, double* Z, int64_t ldz, double* Ginv, int64_t ldi,
+                       int* status, hipStream_t s) {
   static std::once_flag once;  // contexts may be driven from several host threads
   static hipError_t attr_err = hipSuccess;
+  constexpr size_t zbytes = (size_t)NB * zpitch<NB>() * sizeof(double);
   std::call_once(once, [] {
-    attr_err = hipFuncSetAttribute((const void*)k_chol_leaf, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)(leaf_lds_doubles(LEAF_MAX) * sizeof(double)));
+    attr_err = hipFuncSetAttribute((const void*)k_chol_elim<NB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)zbytes);
   });
   if (attr_err != hipSuccess) return attr_err;
-  if (nb % CB || nb > LEAF_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_chol_leaf, dim3(1), dim3(LEAF_NT), leaf_lds_doubles(nb) * sizeof(double), s, G, ldg, nb,
-                     qv < 0 ? 0 : (qv > nb ? nb : qv), Z, ldz, Ginv, ldi, status);
+  hipLaunchKernelGGL(k_chol_elim<NB>, dim3(1), dim3(4 * NB), Ginv ? zbytes : 0, s, G, ldg, qv, Z, ldz, Ginv, ldi,
+                     status);
   return hipGetLastError();
+}
+
+hipError_t launch_leaf(const double* G, int64_t ldg, int nb, int qv, double* Z, int64_t ldz, double* Ginv,
+                       int64_t ldi, int* status, hipStream_t s) {
+  qv = qv < 0 ? 0 : (qv > nb ? nb : qv);
+  switch (nb) {
+    case 32: return launch_elim<32>(G, ldg, qv, Z, ldz, Ginv, ldi, status, s);
+    case 64: return launch_elim<64>(G, ldg, qv, Z, ldz, Ginv, ldi, status, s);
+    case 96: return launch_elim<96>(G, ldg, qv, Z, ldz, Ginv, ldi, status, s);
+    case 128: return launch_elim<128>(G, ldg, qv, Z, ldz, Ginv, ldi, status, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // Recursive 2 x 2 block inverse-Cholesky on a padded block of order `size`:
