@@ -214,7 +214,7 @@ def serving(args, torch, rbfgs):
 
     1. closed loop: every job submitted at t = 0; saturation throughput = jobs / makespan;
     2. open loop: Poisson arrivals at 0.7 x the saturation rate; sojourn = done - arrival,
-       service = done - start on a worker;
+       service = done - admission into a slot;
     3. baseline: the same arrivals served one at a time in FP64.
     The matrices are formed and resident in HBM before any timing.
     """

@@ -109,7 +109,8 @@ typedef enum {
   RBFGS_E_NOT_SPD = 3,       /* Cholesky of G = S^T A S (or S~^T S~) met a pivot <= 0 */
   RBFGS_E_NONFINITE = 4,     /* NaN/Inf appeared in the iteration */
   RBFGS_E_NOT_CONVERGED = 5, /* rbfgs_invert hit max_iters above tolerance */
-  RBFGS_E_DEVICE = 6         /* a HIP runtime call failed */
+  RBFGS_E_DEVICE = 6,        /* a HIP runtime call failed */
+  RBFGS_E_CANCELLED = 7      /* a served job was cancelled (rbfgs_server_cancel) */
 } rbfgs_status;
 
 typedef enum {
@@ -374,6 +375,15 @@ rbfgs_status rbfgs_server_submit(rbfgs_server* server, const rbfgs_params* param
  * wait_ms milliseconds for one. */
 rbfgs_status rbfgs_server_poll(rbfgs_server* server, rbfgs_job_result* results, int32_t max_results,
                                int32_t* n_out, int32_t wait_ms);
+
+/* Cancel the earliest outstanding job carrying `tag`.  A job still queued is removed and its
+ * result (status E_CANCELLED, 0 iterations) is posted at once.  A running job stops at its next
+ * window boundary -- the window in flight completes, no further one is enqueued -- and its
+ * result carries E_CANCELLED, the iterations run and, when x_out was given, X_k as for a job
+ * that did not converge; its memory returns to the pool.  A job that finishes on its own before
+ * the request is seen keeps its own status.  E_INVALID_ARG when no outstanding job carries the
+ * tag (or every running one already has a request pending). */
+rbfgs_status rbfgs_server_cancel(rbfgs_server* server, uint64_t tag);
 
 /* Snapshot of the queue and the budget use. */
 rbfgs_status rbfgs_server_stats(rbfgs_server* server, rbfgs_server_info* info);

@@ -19,6 +19,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/rbfgs.h"
 #include "common.hpp"
 #include "importance.hpp"
@@ -225,6 +227,14 @@ void* dalloc(rbfgs_ctx* ctx, size_t bytes) {
   return p;
 }
 
+// A roctx range for the scope (host side: it spans the launches made inside it).
+struct RocRange {
+  explicit RocRange(const char* n) { roctxRangePushA(n); }
+  ~RocRange() { roctxRangePop(); }
+  RocRange(const RocRange&) = delete;
+  RocRange& operator=(const RocRange&) = delete;
+};
+
 hipEvent_t prof_event(rbfgs_ctx* ctx) {
   if (!ctx->ev_pool.empty()) {
     hipEvent_t e = ctx->ev_pool.back();
@@ -239,13 +249,15 @@ hipEvent_t prof_event(rbfgs_ctx* ctx) {
 // Scope that brackets the kernels of one phase with events on one lane.  `product`
 // marks the n x n products (timed at profile level 2 as well); for those, mark()
 // gives an event that the split-K GEMM records between its product kernel and the
-// reduction, which is then reported as the separate phase "<name>.reduce".
+// reduction, which is then reported as the separate phase "<name>.reduce".  Every phase
+// is also a roctx range around its launches (recorded by rocprofv3 --marker-trace).
 struct Phase {
   rbfgs_ctx* ctx;
   hipStream_t s;
   const char* name;
   hipEvent_t a = nullptr, mid = nullptr;
-  Phase(rbfgs_ctx* c, const Lane& L, const char* n, bool product = false) : ctx(c), s(L.s), name(n) {
+  RocRange range;
+  Phase(rbfgs_ctx* c, const Lane& L, const char* n, bool product = false) : ctx(c), s(L.s), name(n), range(n) {
     if (ctx->prof == 1 || (ctx->prof == 2 && product)) {
       a = prof_event(ctx);
       HIPCHK(hipEventRecord(a, s));
@@ -1163,6 +1175,7 @@ void allocate(rbfgs_ctx* ctx) {
 // The stopping rule of rbfgs_invert, the part after each window of m = st.m iterations whose
 // estimates sum to est_sum: the estimator trigger, the AdaRBFGS probe, the exact residual.
 void invert_decide(rbfgs_ctx* ctx, rb::InvertState& st, double est_sum) {
+  RocRange range("stopping_test");
   const double est = est_sum / (double)st.m;
   const double tol = st.tol;
   if (ctx->ada) {
@@ -1203,6 +1216,7 @@ void invert_decide(rbfgs_ctx* ctx, rb::InvertState& st, double est_sum) {
 
 static rbfgs_status create_impl(const rbfgs_params* params, const void* A, int32_t a_dtype, int64_t lda,
                                 int32_t a_on_device, hipStream_t stream, rb::DevicePool* pool, rbfgs_ctx** out) {
+  RocRange range("rbfgs_create");
   if (!out) return RBFGS_E_INVALID_ARG;
   *out = nullptr;
   if (!params || !A) return RBFGS_E_INVALID_ARG;
@@ -1326,9 +1340,11 @@ rbfgs_status rbfgs_invert_enqueue(rbfgs_ctx* ctx, rb::InvertState& st, double* h
                        (ctx->p.variant == RBFGS_FIXED || ctx->p.variant == RBFGS_ADAPTIVE) &&
                        ctx->p.check_every % 3 == 0 && st.m == ctx->p.check_every && ctx->k % 3 == 0;
     if (!graph) {
+      RocRange range("window");
       HIPCHK(fill_f64(ctx->est + 2, 1, 0.0, s));
       enqueue_steps(ctx, st.m);
     } else if (!ctx->gexec) {
+      RocRange range("window.capture");
       const int64_t k0 = ctx->k;
       HIPCHK(hipMemsetAsync(ctx->kdev, 0, sizeof(int64_t), s));
       HIPCHK(add_i64(ctx->kdev, k0, s));
@@ -1350,6 +1366,7 @@ rbfgs_status rbfgs_invert_enqueue(rbfgs_ctx* ctx, rb::InvertState& st, double* h
       HIPCHK(hipGraphInstantiate(&ctx->gexec, ctx->graph, nullptr, nullptr, 0));
       HIPCHK(hipGraphLaunch(ctx->gexec, s));
     } else {
+      RocRange range("window.replay");
       HIPCHK(hipGraphLaunch(ctx->gexec, s));
       ctx->k += st.m;
     }
@@ -1436,6 +1453,7 @@ rbfgs_status rbfgs_invert(rbfgs_ctx* ctx, double tol, int64_t max_iters, int64_t
   rbfgs_status result = RBFGS_E_NOT_CONVERGED;
   try {
     while (!st.finished) {
+      RocRange range("window");
       double est = 0;
       HIPCHK(hipMemsetAsync(ctx->est + 2, 0, sizeof(double), ctx->main.s));
       enqueue_steps(ctx, st.m = std::min<int64_t>(ctx->p.check_every, st.max_iters - st.done));

@@ -5,30 +5,32 @@
 #include <stddef.h>
 #include <stdint.h>
 
-#include <map>
-
 #include "../../include/rbfgs.h"
+#include "jobboard.hpp"
 
 namespace rb {
 
-// One hipMalloc when the server starts; contexts take their buffers from it (first fit,
-// 256-byte granules, neighbouring free runs merged on release), so admitting and retiring a
-// job allocates and frees no device memory.  Driven by one thread (the scheduler).
+// One hipMalloc when the server starts; contexts take their buffers from it (the Arena's first
+// fit), so admitting and retiring a job allocates and frees no device memory.  Driven by one
+// thread (the scheduler).
 class DevicePool {
  public:
   hipError_t init(size_t bytes);
   void destroy();
-  void* alloc(size_t bytes);  // nullptr when no free run is large enough
-  void release(void* p);
-  size_t capacity() const { return cap_; }
-  size_t used() const { return used_; }
-  size_t largest_free() const;
+  void* alloc(size_t bytes) {  // nullptr when no free run is large enough
+    const size_t off = arena_.alloc(bytes);
+    return off == SIZE_MAX ? nullptr : base_ + off;
+  }
+  void release(void* p) {
+    if (p) (void)arena_.release((size_t)((char*)p - base_));
+  }
+  size_t capacity() const { return arena_.capacity(); }
+  size_t used() const { return arena_.used(); }
+  size_t largest_free() const { return arena_.largest_free(); }
 
  private:
   char* base_ = nullptr;
-  size_t cap_ = 0, used_ = 0;
-  std::map<size_t, size_t> free_;  // offset -> length of each free run
-  std::map<size_t, size_t> live_;  // offset -> length of each allocation
+  Arena arena_;
 };
 
 // Incremental form of rbfgs_invert: windows of check_every iterations, each followed by the

@@ -25,77 +25,27 @@
 
 #include <hip/hip_runtime.h>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/rbfgs.h"
 #include "pool.hpp"
 
 namespace rb {
 
 hipError_t DevicePool::init(size_t bytes) {
-  cap_ = (bytes + 255) / 256 * 256;
+  const size_t cap = (bytes + Arena::GRAIN - 1) / Arena::GRAIN * Arena::GRAIN;
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, cap_);
-  if (e != hipSuccess) {
-    cap_ = 0;
-    return e;
-  }
+  const hipError_t e = hipMalloc(&p, cap);
+  if (e != hipSuccess) return e;
   base_ = (char*)p;
-  free_.clear();
-  live_.clear();
-  free_[0] = cap_;
-  used_ = 0;
+  arena_.reset(cap);
   return hipSuccess;
 }
 
 void DevicePool::destroy() {
   if (base_) (void)hipFree(base_);
   base_ = nullptr;
-  cap_ = used_ = 0;
-  free_.clear();
-  live_.clear();
-}
-
-void* DevicePool::alloc(size_t bytes) {
-  const size_t b = (std::max<size_t>(bytes, 1) + 255) / 256 * 256;
-  for (auto it = free_.begin(); it != free_.end(); ++it) {
-    if (it->second < b) continue;
-    const size_t off = it->first, len = it->second;
-    free_.erase(it);
-    if (len > b) free_[off + b] = len - b;
-    live_[off] = b;
-    used_ += b;
-    return base_ + off;
-  }
-  return nullptr;
-}
-
-void DevicePool::release(void* p) {
-  if (!p) return;
-  const size_t off = (size_t)((char*)p - base_);
-  auto lv = live_.find(off);
-  if (lv == live_.end()) return;
-  size_t start = off, len = lv->second;
-  used_ -= len;
-  live_.erase(lv);
-  auto next = free_.lower_bound(start);
-  if (next != free_.end() && next->first == start + len) {  // merge with the run after
-    len += next->second;
-    next = free_.erase(next);
-  }
-  if (next != free_.begin()) {  // and with the run before
-    auto prev = std::prev(next);
-    if (prev->first + prev->second == start) {
-      start = prev->first;
-      len += prev->second;
-      free_.erase(prev);
-    }
-  }
-  free_[start] = len;
-}
-
-size_t DevicePool::largest_free() const {
-  size_t m = 0;
-  for (const auto& f : free_) m = std::max(m, f.second);
-  return m;
+  arena_.reset(0);
 }
 
 }  // namespace rb
@@ -104,27 +54,10 @@ namespace {
 
 constexpr int MAX_STREAMS = 4;
 
-struct Job {
-  uint64_t tag = 0;
-  rbfgs_params p{};
-  const void* A = nullptr;
-  int32_t a_dtype = RBFGS_F32;
-  int64_t lda = 0;
-  int32_t a_on_device = 0;
-  double tol = 0;
-  int64_t max_iters = 0;
-  void* x_out = nullptr;
-  int32_t x_dtype = RBFGS_F32;
-  int64_t ldx = 0;
-  int32_t x_on_device = 0;
-  int64_t bytes = 0;
-  double t_submit = 0, t_admit = 0;
-};
-
 struct SlotState {
   bool busy = false;
   bool inflight = false;  // a window is enqueued and its event not yet seen
-  Job job;
+  rb::Job job;
   rbfgs_ctx* ctx = nullptr;
   rb::InvertState st;
   hipStream_t s = nullptr;
@@ -138,24 +71,13 @@ struct SlotState {
 struct rbfgs_server {
   int64_t budget = 0;
   int device = 0;
-  std::chrono::steady_clock::time_point t0;
   rb::DevicePool pool;
+  rb::JobBoard board;
   std::vector<hipStream_t> streams;
   std::vector<SlotState> slots;
   void* pinned = nullptr;
-  std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::deque<Job> queue;
-  std::vector<rbfgs_job_result> done;
-  int64_t active_bytes = 0, peak_bytes = 0;
-  int64_t outstanding = 0;  // submitted and not yet finished
-  int active = 0, peak_active = 0;
-  bool stopping = false;
   std::thread scheduler;
 
-  double now() const {
-    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-  }
   void run();
   bool admit();
   void finish(SlotState& sl, rbfgs_status st);
@@ -170,25 +92,20 @@ bool rbfgs_server::admit() {
       break;
     }
   if (!free_slot) return false;
-  Job j;
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    if (queue.empty() || queue.front().bytes > (int64_t)pool.largest_free()) return false;
-    j = queue.front();
-    queue.pop_front();
-  }
+  rb::Job j;
+  if (!board.next((int64_t)pool.largest_free(), &j)) return false;
+  roctxMarkA("server.admit");
   SlotState& sl = *free_slot;
-  j.t_admit = now();
+  j.t_admit = board.now();
   rbfgs_ctx* ctx = nullptr;
   const rbfgs_status s = rbfgs_create_pooled(&j.p, j.A, j.a_dtype, j.lda, j.a_on_device, sl.s, &pool, &ctx);
   if (s == RBFGS_E_OOM) {  // the pool is fragmented: wait for a job to retire
-    std::lock_guard<std::mutex> lk(mu);
-    queue.push_front(j);
+    board.requeue_front(j);
     return false;
   }
   sl.job = j;
+  sl.ctx = nullptr;
   if (s != RBFGS_OK) {
-    sl.ctx = nullptr;
     finish(sl, s);
     return true;
   }
@@ -196,16 +113,13 @@ bool rbfgs_server::admit() {
   sl.busy = true;
   sl.inflight = false;
   rbfgs_invert_begin(ctx, sl.st, j.tol, j.max_iters);
-  std::lock_guard<std::mutex> lk(mu);
-  active_bytes += j.bytes;
-  peak_bytes = std::max(peak_bytes, active_bytes);
-  ++active;
-  peak_active = std::max(peak_active, active);
+  board.started(j);
   return true;
 }
 
 // Result of the job in the slot; its context's buffers go back to the pool.
 void rbfgs_server::finish(SlotState& sl, rbfgs_status s) {
+  roctxMarkA("server.retire");
   rbfgs_job_result r{};
   r.tag = sl.job.tag;
   r.t_submit = sl.job.t_submit;
@@ -215,7 +129,7 @@ void rbfgs_server::finish(SlotState& sl, rbfgs_status s) {
   if (had_ctx) {
     r.iters = sl.st.done;
     r.resid = sl.st.resid;
-    if (sl.job.x_out && (s == RBFGS_OK || s == RBFGS_E_NOT_CONVERGED)) {
+    if (sl.job.x_out && (s == RBFGS_OK || s == RBFGS_E_NOT_CONVERGED || s == RBFGS_E_CANCELLED)) {
       const rbfgs_status sx = rbfgs_get_x(sl.ctx, sl.job.x_out, sl.job.x_dtype, sl.job.ldx, sl.job.x_on_device);
       if (sx != RBFGS_OK) s = sx;
     }
@@ -223,19 +137,10 @@ void rbfgs_server::finish(SlotState& sl, rbfgs_status s) {
     sl.ctx = nullptr;
   }
   r.status = s;
-  r.t_done = now();
+  r.t_done = board.now();
   sl.busy = false;
   sl.inflight = false;
-  {
-    std::lock_guard<std::mutex> lk(mu);
-    if (had_ctx) {
-      active_bytes -= sl.job.bytes;
-      --active;
-    }
-    --outstanding;
-    done.push_back(r);
-  }
-  cv_done.notify_all();
+  board.finished(r, sl.job, had_ctx);
 }
 
 void rbfgs_server::run() {
@@ -261,6 +166,11 @@ void rbfgs_server::run() {
         progressed = true;
         continue;
       }
+      if (board.cancel_requested(sl.job.tag)) {  // at a window boundary: nothing in flight
+        finish(sl, RBFGS_E_CANCELLED);
+        progressed = true;
+        continue;
+      }
       const rbfgs_status e = rbfgs_invert_enqueue(sl.ctx, sl.st, sl.h_est, sl.h_status, sl.ev);
       if (e != RBFGS_OK) finish(sl, e);
       else sl.inflight = true;
@@ -269,15 +179,12 @@ void rbfgs_server::run() {
     if (progressed) continue;
     bool any_busy = false;
     for (const SlotState& sl : slots) any_busy |= sl.busy;
-    std::unique_lock<std::mutex> lk(mu);
     if (!any_busy) {
-      if (stopping && queue.empty()) break;
+      roctxMarkA("server.idle");
       // idle: wait for a submission (or for the head job to fit after a retirement)
-      cv_work.wait_for(lk, std::chrono::milliseconds(queue.empty() ? 50 : 1),
-                       [&] { return stopping || !queue.empty(); });
+      if (board.idle_wait(50)) break;
       continue;
     }
-    lk.unlock();
     std::this_thread::sleep_for(std::chrono::microseconds(20));  // windows in flight: poll again
   }
 }
@@ -290,7 +197,6 @@ rbfgs_status rbfgs_server_create(int64_t budget_bytes, int32_t workers, rbfgs_se
   if (budget_bytes <= 0 || workers < 1 || workers > 64) return RBFGS_E_INVALID_ARG;
   rbfgs_server* sv = new rbfgs_server();
   sv->budget = budget_bytes;
-  sv->t0 = std::chrono::steady_clock::now();
   auto fail = [&](rbfgs_status st) {
     for (hipStream_t s : sv->streams) (void)hipStreamDestroy(s);
     for (SlotState& sl : sv->slots)
@@ -334,7 +240,7 @@ rbfgs_status rbfgs_server_submit(rbfgs_server* sv, const rbfgs_params* params, c
   const rbfgs_status fs = rbfgs_footprint(params, &bytes);
   if (fs != RBFGS_OK) return fs;
   if (bytes > sv->budget) return RBFGS_E_OOM;
-  Job j;
+  rb::Job j;
   j.tag = tag;
   j.p = *params;
   j.A = A;
@@ -348,50 +254,30 @@ rbfgs_status rbfgs_server_submit(rbfgs_server* sv, const rbfgs_params* params, c
   j.ldx = ldx;
   j.x_on_device = x_on_device;
   j.bytes = bytes;
-  {
-    std::lock_guard<std::mutex> lk(sv->mu);
-    if (sv->stopping) return RBFGS_E_INVALID_ARG;
-    j.t_submit = sv->now();
-    sv->queue.push_back(j);
-    ++sv->outstanding;
-  }
-  sv->cv_work.notify_all();
-  return RBFGS_OK;
+  return sv->board.submit(j);
 }
 
 rbfgs_status rbfgs_server_poll(rbfgs_server* sv, rbfgs_job_result* results, int32_t max_results, int32_t* n_out,
                                int32_t wait_ms) {
   if (!sv || !n_out || max_results < 0 || (max_results > 0 && !results) || wait_ms < 0) return RBFGS_E_INVALID_ARG;
-  std::unique_lock<std::mutex> lk(sv->mu);
-  if (sv->done.empty() && wait_ms > 0 && sv->outstanding > 0)
-    sv->cv_done.wait_for(lk, std::chrono::milliseconds(wait_ms), [&] { return !sv->done.empty(); });
-  const int32_t n = (int32_t)std::min<size_t>((size_t)max_results, sv->done.size());
-  for (int32_t i = 0; i < n; ++i) results[i] = sv->done[i];
-  sv->done.erase(sv->done.begin(), sv->done.begin() + n);
-  *n_out = n;
+  *n_out = sv->board.poll(results, max_results, wait_ms);
   return RBFGS_OK;
+}
+
+rbfgs_status rbfgs_server_cancel(rbfgs_server* sv, uint64_t tag) {
+  if (!sv) return RBFGS_E_INVALID_ARG;
+  return sv->board.cancel(tag);
 }
 
 rbfgs_status rbfgs_server_stats(rbfgs_server* sv, rbfgs_server_info* info) {
   if (!sv || !info) return RBFGS_E_INVALID_ARG;
-  std::lock_guard<std::mutex> lk(sv->mu);
-  info->now = sv->now();
-  info->queued = (int64_t)sv->queue.size();
-  info->running = sv->active;
-  info->outstanding = sv->outstanding;
-  info->active_bytes = sv->active_bytes;
-  info->peak_bytes = sv->peak_bytes;
-  info->peak_running = sv->peak_active;
+  *info = sv->board.stats();
   return RBFGS_OK;
 }
 
 void rbfgs_server_destroy(rbfgs_server* sv) {
   if (!sv) return;
-  {
-    std::lock_guard<std::mutex> lk(sv->mu);
-    sv->stopping = true;
-  }
-  sv->cv_work.notify_all();
+  sv->board.stop();
   if (sv->scheduler.joinable()) sv->scheduler.join();
   for (hipStream_t s : sv->streams) {
     (void)hipStreamSynchronize(s);

@@ -17,9 +17,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librbfgs.so")
 
-OK, E_INVALID_ARG, E_OOM, E_NOT_SPD, E_NONFINITE, E_NOT_CONVERGED, E_DEVICE = range(7)
+OK, E_INVALID_ARG, E_OOM, E_NOT_SPD, E_NONFINITE, E_NOT_CONVERGED, E_DEVICE, E_CANCELLED = range(8)
 STATUS_NAMES = {0: "OK", 1: "E_INVALID_ARG", 2: "E_OOM", 3: "E_NOT_SPD", 4: "E_NONFINITE",
-                5: "E_NOT_CONVERGED", 6: "E_DEVICE"}
+                5: "E_NOT_CONVERGED", 6: "E_DEVICE", 7: "E_CANCELLED"}
 SKETCH = {"gauss": 0, "coord": 1, "cols": 1, "partition": 2, "importance": 3}
 VARIANT = {"fixed": 0, "adaptive": 1, "ada": 1, "psb": 2, "aip": 3, "kaczmarz": 4, "newton_schulz": 5,
            "mr": 6}
@@ -97,6 +97,7 @@ EXPORTS = {
                                            ctypes.c_int32, ctypes.c_uint64]),
     "rbfgs_server_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rbfgs_job_result), ctypes.c_int32,
                                          ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
+    "rbfgs_server_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "rbfgs_server_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(rbfgs_server_info)]),
     "rbfgs_server_destroy": (None, [ctypes.c_void_p]),
 }
@@ -111,6 +112,10 @@ def load_library(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with `python -m paper_1602_01768_amd.build`")
+    # torch first: the library then binds the HIP runtime torch has loaded (its own copy of
+    # libamdhip64), so that device pointers and streams from torch are valid in the library;
+    # loaded the other way round, the process holds two runtimes and every call fails
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in EXPORTS.items():
         fn = getattr(lib, name)
@@ -397,6 +402,10 @@ def rbfgs_server_poll(server, max_results=256, wait_ms=0):
                  t_admit=r.t_admit, t_done=r.t_done) for r in buf[:n.value]]
 
 
+def rbfgs_server_cancel(server, tag):
+    _check(load_library().rbfgs_server_cancel(server, int(tag)))
+
+
 def rbfgs_server_stats(server):
     info = rbfgs_server_info()
     _check(load_library().rbfgs_server_stats(server, ctypes.byref(info)))
@@ -413,17 +422,29 @@ class Server:
 
     def __init__(self, budget_bytes, workers=8):
         self.handle = rbfgs_server_create(budget_bytes, workers)
-        self._keep = {}
+        self._keep = {}  # tag -> what the library reads and writes, one entry per job with that tag
+        self._done = {}  # tag -> results polled so far
 
     def submit(self, A, q, seed, tol, max_iters, tag, x_out=None, **kw):
         # keep what the library reads and writes (possibly a converted copy of A) until polled
-        self._keep[int(tag)] = rbfgs_server_submit(self.handle, A, q, seed, tol, max_iters, tag, x_out=x_out, **kw)
+        keep = rbfgs_server_submit(self.handle, A, q, seed, tol, max_iters, tag, x_out=x_out, **kw)
+        self._keep.setdefault(int(tag), []).append(keep)
 
     def poll(self, max_results=256, wait_ms=0):
         res = rbfgs_server_poll(self.handle, max_results, wait_ms)
         for r in res:
-            self._keep.pop(int(r["tag"]), None)
+            # jobs sharing a tag may finish in any order: their buffers are all kept until the
+            # last of them has been polled
+            t = int(r["tag"])
+            if t in self._keep:
+                self._done[t] = self._done.get(t, 0) + 1
+                if self._done[t] == len(self._keep[t]):
+                    del self._keep[t], self._done[t]
         return res
+
+    def cancel(self, tag):
+        """Cancel the earliest outstanding job with this tag (rbfgs_server_cancel)."""
+        rbfgs_server_cancel(self.handle, tag)
 
     def stats(self):
         return rbfgs_server_stats(self.handle)
@@ -433,6 +454,7 @@ class Server:
             rbfgs_server_destroy(self.handle)
             self.handle = None
             self._keep.clear()
+            self._done.clear()
 
     def __enter__(self):
         return self

@@ -115,3 +115,40 @@ def test_server_rejects_job_beyond_budget(lib):
             srv.submit(A, q, 1, TOL, 100, tag=0)
         assert e.value.status == lib.E_OOM
         assert srv.stats()["outstanding"] == 0
+
+
+def test_server_cancel_queued_and_running(lib):
+    """A queued job is cancelled at once (0 iterations); a running one stops at a window
+    boundary with E_CANCELLED and its X equals that of the job run alone for the same number
+    of iterations; its memory returns to the pool; an unknown tag is an error."""
+    import time
+    import torch
+    n, q, every = 1024, 64, 15
+    A = torch.from_numpy(gram_ridge(n, 5)).cuda()
+    X = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    with lib.Server(budget_bytes=8 << 30, workers=1) as srv:
+        # tolerance far below what mixed precision reaches: the job runs until cancelled
+        srv.submit(A, q, 11, 1e-12, 10 ** 7, tag=0, check_every=every, x_out=X)
+        srv.submit(A, q, 12, TOL, 3000, tag=1, check_every=every)  # waits behind job 0
+        srv.cancel(1)
+        r1 = _drain(srv, 1)
+        assert len(r1) == 1 and r1[0]["tag"] == 1 and r1[0]["status"] == lib.E_CANCELLED and r1[0]["iters"] == 0
+        for _ in range(400):
+            if srv.stats()["running"] == 1:
+                break
+            time.sleep(0.005)
+        time.sleep(0.3)
+        srv.cancel(0)
+        r0 = _drain(srv, 1)
+        info = srv.stats()
+        with pytest.raises(lib.RbfgsError) as e:
+            srv.cancel(0)  # nothing outstanding carries the tag any more
+        assert e.value.status == lib.E_INVALID_ARG
+    assert len(r0) == 1 and r0[0]["status"] == lib.E_CANCELLED, r0
+    k = r0[0]["iters"]
+    assert k > 0 and k % every == 0, k
+    assert info["outstanding"] == 0 and info["running"] == 0 and info["active_bytes"] == 0
+    with lib.Solver(A, q, 11, variant="adaptive", precision="mixed", check_every=every) as s:
+        s.step(k)
+        ref = s.x()
+    assert torch.equal(X, ref), float((X - ref).abs().max())

@@ -102,6 +102,9 @@ def test_other_entry_points_validate_arguments():
     assert lib.rbfgs_ridge_hessian(buf, 1, 8, 4, 3, 1, 1.0, 0.0, buf, 1, 4, 1, None) == rbfgs.E_INVALID_ARG
     assert lib.rbfgs_ridge_hessian(buf, 1, 8, 4, 4, 1, float("nan"), 0.0, buf, 1, 4, 1, None) == rbfgs.E_INVALID_ARG
     assert lib.rbfgs_ridge_hessian(None, 1, 8, 4, 4, 1, 1.0, 0.0, buf, 1, 4, 1, None) == rbfgs.E_INVALID_ARG
+    # the serving calls need a server
+    assert lib.rbfgs_server_cancel(None, 0) == rbfgs.E_INVALID_ARG
+    assert lib.rbfgs_server_stats(None, None) == rbfgs.E_INVALID_ARG
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
