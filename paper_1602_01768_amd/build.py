@@ -18,7 +18,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
 SOURCES = ["api.hip", "server.hip", "k_f64.hip", "k_chol.hip", "k_bf16.hip", "k_symupd.hip", "k_sketch.hip",
-           "k_importance.hip"]
+           "k_importance.hip", "k_tall.hip"]
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -75,6 +75,7 @@ struct Lane {  // one stream with its own split-K, reduction and Cholesky worksp
   double* red = nullptr;
   size_t red_count = 0;
   double* cwork = nullptr;
+  __bf16* bsplit = nullptr;  // bf16 planes of the panel of a streamed n x n product (mixed)
 };
 
 struct Slot {  // sketch-dependent quantities of one iteration
@@ -339,15 +340,18 @@ void f64_gemm(rbfgs_ctx* ctx, const Lane& L, GemmArgs g) {
   HIPCHK(gemm_f64(g, L.partial, L.s));
 }
 
+// Split-K factor of a tall-skinny bf16 product on lane L.
+int bf_split(rbfgs_ctx* ctx, const Lane& L, const MixedGemm& mg, int max_split = 8, int64_t min_chunk = 256) {
+  const GemmArgs& g = mg.g;
+  const int64_t tiles = (g.M / 128) * (g.N / (g.bn ? g.bn : bf_bn(g.N)));
+  const int s = pick_split(tiles, g.K, 32, max_split, min_chunk);
+  return (size_t)s * g.M * g.N * sizeof(float) > L.partial_bytes ? 1 : s;
+}
+
 // bf16-MFMA product on one lane (tall-skinny products get a split-K).
 void bf_gemm(rbfgs_ctx* ctx, const Lane& L, MixedGemm mg, int max_split = 8, int64_t min_chunk = 256) {
   GemmArgs& g = mg.g;
-  if (g.epi == EPI_COLSTORE) {
-    const int64_t tiles = (g.M / 128) * (g.N / (g.bn ? g.bn : bf_bn(g.N)));
-    g.splitk = pick_split(tiles, g.K, 32, max_split, min_chunk);
-    const size_t need = (size_t)g.splitk * g.M * g.N * sizeof(float);
-    if (need > L.partial_bytes) g.splitk = 1;
-  }
+  if (g.epi == EPI_COLSTORE) g.splitk = bf_split(ctx, L, mg, max_split, min_chunk);
   HIPCHK(gemm_bf16(mg, L.partial, L.s));
 }
 
@@ -388,6 +392,18 @@ void nn_times_panel(rbfgs_ctx* ctx, const Lane& L, const void* M, bool transpose
     mg.a_kind = transpose ? OK_F32_MC : OK_F32_KC;
     mg.b_kind = p_dt == DT_BF16 ? OK_BF16_KC : OK_F32_KC;
     mg.na = na; mg.nb = p_dt == DT_BF16 ? 1 : nb; mg.pmax = pmax;
+    // streamed product: an FP32 panel is split into bf16 planes once, here, instead of in
+    // every row tile of the product
+    if (L.bsplit && p_dt != DT_BF16) {
+      MixedGemm sm = mg;
+      sm.b_kind = OK_BF16_KC;
+      sm.g.B = L.bsplit; sm.g.b_plane = ctx->np * ctx->qp;
+      sm.g.splitk = bf_split(ctx, L, sm);
+      if (tall_stream_supported(sm)) {
+        HIPCHK(split_planes((const float*)P, ctx->np * ctx->qp, nb, L.bsplit, L.s));
+        mg = sm;
+      }
+    }
     bf_gemm(ctx, L, mg);
   } else {
     GemmArgs g;
@@ -1017,12 +1033,17 @@ double exact_residual(rbfgs_ctx* ctx) {
   return sqrt(r2);
 }
 
+// Mixed-precision n x n-by-n x q products take the streamed kernel (bf16 planes of the
+// panel made once per product) when q is a multiple of 128 and n is large.
+bool streamed_products(const rbfgs_ctx* ctx) { return ctx->mixed && ctx->qp % 128 == 0 && ctx->np >= 1024; }
+
 void make_lane(rbfgs_ctx* ctx, Lane& L, size_t partial_bytes, size_t red_count) {
   L.partial_bytes = partial_bytes;
   L.partial = dalloc(ctx, partial_bytes);
   L.red = (double*)dalloc(ctx, red_count * sizeof(double));
   L.red_count = red_count;
   L.cwork = (double*)dalloc(ctx, chol_inv_work_doubles(ctx->q) * sizeof(double));
+  if (streamed_products(ctx)) L.bsplit = (__bf16*)dalloc(ctx, (size_t)3 * ctx->np * ctx->qp * sizeof(__bf16));
 }
 
 void make_slot(rbfgs_ctx* ctx, Slot& S) {

@@ -464,9 +464,14 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
   GemmArgs run = g;
   run.epi = EPI_PARTIAL;
   run.C = partial_ws;
+  hipError_t e;
+  if (tall_stream_supported(mg)) {
+    if ((e = tall_stream(run, mg, s)) != hipSuccess) return e;
+    if (g.mark && (e = hipEventRecord(g.mark, s)) != hipSuccess) return e;
+    return reduce_partials_f32(g, (const float*)partial_ws, s);
+  }
   const int bn = pick_bn(g);
   const int64_t blocks = gemm_bf16_blocks(mg);
-  hipError_t e;
 #define RB_TALL(NA_, NB_, PM_, AK_, BK_, LDB_, WAVES256_)                                              \
   if (mg.na == NA_ && mg.nb == NB_ && mg.pmax == PM_ && mg.a_kind == AK_ && mg.b_kind == BK_)         \
     e = launch_tall<NA_, NB_, PM_, AK_, BK_, LDB_, WAVES256_>(run, bn, blocks, s);                    \

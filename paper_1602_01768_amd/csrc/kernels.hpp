@@ -82,6 +82,13 @@ struct MixedGemm {
   int pmax = 1;         // passes: all piece pairs (i, j) with i + j <= pmax
 };
 hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s);
+// Streamed tall-skinny product (k_tall.hip): A FP32 k-contiguous or transposed (na pieces), B bf16 planes
+// (nb pieces, k-contiguous rows), N a multiple of 128, M a multiple of 32 and >= 1024, split-K
+// dividing 8.  gemm_bf16 takes it for every product it supports.
+bool tall_stream_supported(const MixedGemm& mg);
+hipError_t tall_stream(const GemmArgs& run, const MixedGemm& mg, hipStream_t s);
+// out[p * count + i] = bf16 piece p of in[i], np = 2 or 3 pieces (count a multiple of 4)
+hipError_t split_planes(const float* in, int64_t count, int np, __bf16* out, hipStream_t s);
 // Tile edge of the bf16 square products (EPI_SYMUPD / EPI_ADDROW) for order M.
 int bf16_square_tile(int64_t M, int epi);
 // Sum the FP32 split-K partials of a bf16 product (COLSTORE epilogue of g): C = c2 * sum
