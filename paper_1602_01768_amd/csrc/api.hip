@@ -109,6 +109,11 @@ struct rbfgs_ctx {
   // these are used as dense 0/1 matrices (dcoord), `coord` marks the gather paths of
   // fixed RBFGS and AdaRBFGS only
   bool psb = false, rowv = false, kacz = false, dcoord = false;
+  // mixed fixed RBFGS with a Gaussian sketch and streamed products: X is held on its lower
+  // 128 x 128 tiles (the update writes no mirrored tiles; X Y reads the tiles right of the
+  // diagonal transposed).  x_lower: the upper tiles are stale, and are copied from the lower
+  // ones before anything reads X whole (residual, rbfgs_get_x, PCG)
+  bool lowx = false, x_lower = false;
   // partition sampling (fixed RBFGS, AdaRBFGS): the coordinate block C_i = [iq, (i+1)q) is
   // drawn with p_i proportional to Tr(S_i^T A S_i) (eq. ihsih0); tw holds the per-coordinate
   // weights, A_jj for the fixed method and (L^T A L)_jj for AdaRBFGS (updated every step)
@@ -376,8 +381,10 @@ void gram_bf16(rbfgs_ctx* ctx, const Lane& L, const void* P1, bool p1_bf16, cons
 // pieces of each operand and the passes kept (all piece pairs with i + j <= pmax).
 // est_S (mixed mode): the reduction of the product also accumulates per-workgroup sums
 // of (est_S - out)^2 into L.red (see reduce_blocks_f32).
+// lower: M is symmetric and current on its lower 128 x 128 tiles only (streamed product).
 void nn_times_panel(rbfgs_ctx* ctx, const Lane& L, const void* M, bool transpose, const void* P, int p_dt, void* out,
-                    int na = 2, int nb = 2, int pmax = 1, hipEvent_t mark = nullptr, const __bf16* est_S = nullptr) {
+                    int na = 2, int nb = 2, int pmax = 1, hipEvent_t mark = nullptr, const __bf16* est_S = nullptr,
+                    bool lower = false) {
   if (ctx->mixed) {
     MixedGemm mg;
     GemmArgs& g = mg.g;
@@ -396,6 +403,7 @@ void nn_times_panel(rbfgs_ctx* ctx, const Lane& L, const void* M, bool transpose
     // every row tile of the product
     if (L.bsplit && p_dt != DT_BF16) {
       MixedGemm sm = mg;
+      if (lower) sm.a_kind = OK_F32_SYM;
       sm.b_kind = OK_BF16_KC;
       sm.g.B = L.bsplit; sm.g.b_plane = ctx->np * ctx->qp;
       sm.g.splitk = bf_split(ctx, L, sm);
@@ -403,6 +411,10 @@ void nn_times_panel(rbfgs_ctx* ctx, const Lane& L, const void* M, bool transpose
         HIPCHK(split_planes((const float*)P, ctx->np * ctx->qp, nb, L.bsplit, L.s));
         mg = sm;
       }
+    }
+    if (lower && mg.a_kind != OK_F32_SYM) {  // (lowx is set only where the streamed product applies)
+      ctx->err = "an operand held on its lower tiles needs the streamed product";
+      throw Fail{RBFGS_E_DEVICE};
     }
     bf_gemm(ctx, L, mg);
   } else {
@@ -586,7 +598,7 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
   {
     Phase ph(ctx, L, "XY", true);
     nn_times_panel(ctx, L, ctx->X, false, S.Y, mdt, ctx->V, 2, 2, 1, ph.mark(),
-                   fused_est ? (const __bf16*)S.Sk : nullptr);
+                   fused_est ? (const __bf16*)S.Sk : nullptr, ctx->lowx);
   }
   after_xy();
   {
@@ -654,8 +666,10 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
     g.B = S.planes + qp; g.ldb = ldp; g.b_plane = plane;
     g.epi = EPI_SYMUPD; g.C = ctx->X; g.ldc = np; g.c2 = -1.0;
     g.tiles = ctx->tiles; g.ntiles = ctx->ntiles;
+    g.lower_only = ctx->lowx;
     mg.a_kind = OK_BF16_KC; mg.b_kind = OK_BF16_KC; mg.na = 2; mg.nb = 2; mg.pmax = 1;
     bf_gemm(ctx, L, mg);
+    ctx->x_lower = ctx->lowx;
   } else {
     double* PQ = (double*)S.U;  // [U | W' | U], column-major, ld = np
     {
@@ -1005,7 +1019,15 @@ double probe_residual(rbfgs_ctx* ctx, uint64_t w) {
   return v;
 }
 
+// X held on its lower tiles: copy them onto the upper tiles before X is read whole.
+void ensure_full_x(rbfgs_ctx* ctx) {
+  if (!ctx->x_lower) return;
+  HIPCHK(mirror_lower((float*)ctx->X, ctx->np, ctx->np / 128, ctx->main.s));
+  ctx->x_lower = false;
+}
+
 double exact_residual(rbfgs_ctx* ctx) {
+  ensure_full_x(ctx);
   const int64_t np = ctx->np;
   const Lane& L = ctx->main;
   GemmArgs g;
@@ -1123,6 +1145,8 @@ void set_params(rbfgs_ctx* ctx, const rbfgs_params& p) {
   ctx->mdt = ctx->mixed ? DT_F32 : DT_F64;
   ctx->bf16q = ctx->mixed && p.variant == RBFGS_FIXED && !ctx->coord && ctx->qp % 128 == 0;
   ctx->bf16h = ctx->bf16q && 8 * ctx->qp <= ctx->np;
+  ctx->lowx = ctx->mixed && p.variant == RBFGS_FIXED && p.sketch == RBFGS_SKETCH_GAUSS && ctx->qp % 128 == 0 &&
+              ctx->np >= 1024;
 }
 
 // Every device buffer of the context (accounted only, in a dry run).
@@ -1533,7 +1557,10 @@ rbfgs_status rbfgs_get_x(rbfgs_ctx* ctx, void* X, int32_t x_dtype, int64_t ldx, 
       HIPCHK(copy_transpose(ctx->X, ctx->mdt, ctx->np, ctx->sq, ctx->mdt, ctx->np, ctx->np, ctx->np, ctx->main.s));
       return copy_out(ctx, ctx->sq, ctx->mdt, ctx->np, X, x_dtype, ldx, on_device);
     }
-    if (!ctx->ada) return copy_out(ctx, ctx->X, ctx->mdt, ctx->np, X, x_dtype, ldx, on_device);
+    if (!ctx->ada) {
+      ensure_full_x(ctx);
+      return copy_out(ctx, ctx->X, ctx->mdt, ctx->np, X, x_dtype, ldx, on_device);
+    }
     const int64_t np = ctx->np;
     GemmArgs g;
     g.M = np; g.N = np; g.K = np;
@@ -1588,6 +1615,7 @@ rbfgs_status rbfgs_set_state(rbfgs_ctx* ctx, const void* M, int32_t m_dtype, int
         HIPCHK(hipStreamSynchronize(ctx->main.s));
       }
     }
+    ctx->x_lower = false;  // written whole
     HIPCHK(hipMemsetAsync(ctx->status, 0, sizeof(int), ctx->main.s));
     if (ctx->part && ctx->ada) refresh_part_weights(ctx);
     HIPCHK(hipStreamSynchronize(ctx->main.s));
@@ -1705,6 +1733,7 @@ rbfgs_status rbfgs_pcg(rbfgs_ctx* ctx, const void* b, int32_t b_dtype, int32_t b
   try {
     rbfgs_status st = read_status(ctx);
     if (st != RBFGS_OK) return st;
+    if (precond) ensure_full_x(ctx);
     const int64_t n = ctx->n, np = ctx->np;
     hipStream_t s = ctx->main.s;
     const int mdt = ctx->mdt;

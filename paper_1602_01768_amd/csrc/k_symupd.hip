@@ -1,6 +1,7 @@
 // Square updates on bf16 matrix cores.  Symmetric rank-2q update of the fixed-sketch
 // step: X += c2 * [U W'] [W' U]^T on the lower 128 x 128 tiles of X, each tile also
-// written to its mirrored position (the symmetric form of the update, eq. (qunac));
+// written to its mirrored position (the symmetric form of the update, eq. (qunac)) --
+// or, when X is held on its lower tiles only, written there alone (diagonal tiles whole);
 // FULL: C += c2 * A B^T on every tile (the rank-q updates of AdaRBFGS, eq. (Cholimprov),
 // and of the row variants of Alg. 1).
 //
@@ -60,7 +61,7 @@ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) |
 // ... and for "no LDS operation outstanding" (lgkmcnt 0, vmcnt and expcnt at their maxima)
 constexpr int lgkm0_imm() { return 15 | (3 << 14) | (7 << 4); }
 
-template <int BKS, int NS, int OCC, int WAVES_M, int WAVES_N, bool FULL, int NTX>
+template <int BKS, int NS, int OCC, int WAVES_M, int WAVES_N, bool FULL, int NTX, bool MIRROR = true>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) __attribute__((amdgpu_waves_per_eu(OCC * WAVES_M * WAVES_N / 4, 8)))
 void k_symupd_dma(GemmArgs g) {
   constexpr int BM = 128, NP = 2, NW = WAVES_M * WAVES_N;
@@ -252,7 +253,7 @@ void k_symupd_dma(GemmArgs g) {
         if constexpr (NTX != 0) __builtin_nontemporal_store(nvs[r], dst);
         else *dst = nvs[r];
       }
-      if constexpr (!FULL) {
+      if constexpr (!FULL && MIRROR) {
 #pragma unroll
         for (int q4 = 0; q4 < 4; ++q4) {
           typedef float f32x4v __attribute__((ext_vector_type(4)));
@@ -288,10 +289,45 @@ hipError_t symupd_bf16_dma(const GemmArgs& g, int64_t blocks, hipStream_t s) {
     hipLaunchKernelGGL((k_symupd_dma<UPD_BKS, UPD_NS, UPD_OCC, RB_UPD_WAVES, true, 1>), grid, block, 0, s, g);
   else if (full)
     hipLaunchKernelGGL((k_symupd_dma<UPD_BKS, UPD_NS, UPD_OCC, RB_UPD_WAVES, true, 0>), grid, block, 0, s, g);
+  else if (g.lower_only && nt)
+    hipLaunchKernelGGL((k_symupd_dma<UPD_BKS, UPD_NS, UPD_OCC, RB_UPD_WAVES, false, 1, false>), grid, block, 0, s, g);
+  else if (g.lower_only)
+    hipLaunchKernelGGL((k_symupd_dma<UPD_BKS, UPD_NS, UPD_OCC, RB_UPD_WAVES, false, 0, false>), grid, block, 0, s, g);
   else if (nt)
     hipLaunchKernelGGL((k_symupd_dma<UPD_BKS, UPD_NS, UPD_OCC, RB_UPD_WAVES, false, 1>), grid, block, 0, s, g);
   else
     hipLaunchKernelGGL((k_symupd_dma<UPD_BKS, UPD_NS, UPD_OCC, RB_UPD_WAVES, false, 0>), grid, block, 0, s, g);
+  return hipGetLastError();
+}
+
+namespace {
+
+// One workgroup per strictly lower 128 x 128 tile (ti, tj), tj < ti, numbered row by row;
+// its sixteen 32 x 32 blocks go through a padded LDS transpose onto tile (tj, ti).
+__global__ __launch_bounds__(256) void k_mirror_lower(float* X, int64_t ld) {
+  __shared__ float tb[32][33];
+  const int64_t b = blockIdx.x;
+  int64_t ti = (int64_t)((sqrt(8.0 * (double)b + 1.0) + 1.0) * 0.5);
+  while (ti * (ti - 1) / 2 > b) --ti;
+  while ((ti + 1) * ti / 2 <= b) ++ti;
+  const int64_t tj = b - ti * (ti - 1) / 2;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int bi = 0; bi < 4; ++bi)
+    for (int bj = 0; bj < 4; ++bj) {
+      const int64_t r0 = ti * 128 + bi * 32, c0 = tj * 128 + bj * 32;
+      __syncthreads();
+      for (int y = ty; y < 32; y += 8) tb[y][tx] = X[(r0 + y) * ld + c0 + tx];
+      __syncthreads();
+      for (int y = ty; y < 32; y += 8) X[(c0 + y) * ld + r0 + tx] = tb[tx][y];
+    }
+}
+
+}  // namespace
+
+hipError_t mirror_lower(float* X, int64_t ld, int64_t T, hipStream_t s) {
+  const int64_t nb = T * (T - 1) / 2;
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mirror_lower, dim3((unsigned)nb), dim3(256), 0, s, X, ld);
   return hipGetLastError();
 }
 

@@ -9,6 +9,8 @@
 // A is read as stored (four 16-byte loads per lane and tile) or transposed, A = M^T (L^T Y of
 // AdaRBFGS, X^T P of the row variants): then each lane takes its 16 values of column m with
 // one 4-byte load per k, the 32 lanes of a half-wave reading 128 contiguous bytes of a row.
+// A symmetric A held on its lower 128 x 128 tiles only (X of the fixed method) is read as
+// stored where the tile is lower or diagonal and transposed from the mirror tile above.
 // The B tile (all q columns, or 256 of them) is shared by the 8 waves and travels from memory
 // straight into LDS (global_load_lds_dwordx4) through a ring of three stages, one barrier per
 // 32-deep k tile.  The k order inside a tile is permuted to match the registers a lane holds
@@ -56,7 +58,8 @@ RB_DEV void split_vec(const float (&x)[8], bf16x8 (&o)[NP]) {
   }
 }
 
-template <int BN, int NA, int NB, int PMAX, bool AT>
+// AM: 0 as stored, 1 transposed, 2 symmetric on its lower 128 x 128 tiles
+template <int BN, int NA, int NB, int PMAX, int AM>
 __global__ __launch_bounds__(512, 1) void k_tall_stream(GemmArgs g) {
   constexpr int NW = 8, FN = BN / 32;
   constexpr int ROWB = TL_BK * 2;          // bytes of one B row of one piece in a stage (64)
@@ -91,25 +94,33 @@ __global__ __launch_bounds__(512, 1) void k_tall_stream(GemmArgs g) {
   // A: lane l holds row mw + l % 32, k = 16 (l / 32) .. + 15 of each tile (a wave beyond M
   // loads row M - 1 and discards it, so that every wave issues the same loads)
   const int64_t arow_i = rows_ok ? mw + (lane & 31) : g.M - 1;
-  const float* arow = AT ? (const float*)g.A + (kbeg + 16 * (lane >> 5)) * g.lda + arow_i
-                         : (const float*)g.A + arow_i * g.lda + 16 * (lane >> 5) + kbeg;
+  const float* arow_t = (const float*)g.A + (kbeg + 16 * (lane >> 5)) * g.lda + arow_i;  // transposed
+  const float* arow_d = (const float*)g.A + arow_i * g.lda + 16 * (lane >> 5) + kbeg;    // as stored
+  const int64_t tile128 = mw / 128;  // symmetric mode: tile row of this wave's rows
+  // symmetric mode: tile t lies in an upper 128 x 128 tile (uniform across the wave)
+  auto upper = [&](int t) { return AM == 2 && (kbeg + (int64_t)t * TL_BK) / 128 > tile128; };
   float a0[16], a1[16], a2[16];
-  auto loadA = [&](float (&a)[16], int t) {
-    if constexpr (AT) {
-      const float* src = arow + (int64_t)t * TL_BK * g.lda;
+  auto loadA_t = [&](float (&a)[16], int t) {
+    const float* src = arow_t + (int64_t)t * TL_BK * g.lda;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) a[j] = src[j * g.lda];
-    } else {
-      const float* src = arow + (int64_t)t * TL_BK;
+    for (int j = 0; j < 16; ++j) a[j] = src[j * g.lda];
+  };
+  auto loadA_d = [&](float (&a)[16], int t) {
+    const float* src = arow_d + (int64_t)t * TL_BK;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const f32x4 v = *((const f32x4*)(src + 4 * i));
-        a[4 * i] = v[0];
-        a[4 * i + 1] = v[1];
-        a[4 * i + 2] = v[2];
-        a[4 * i + 3] = v[3];
-      }
+    for (int i = 0; i < 4; ++i) {
+      const f32x4 v = *((const f32x4*)(src + 4 * i));
+      a[4 * i] = v[0];
+      a[4 * i + 1] = v[1];
+      a[4 * i + 2] = v[2];
+      a[4 * i + 3] = v[3];
     }
+  };
+  auto loadA = [&](float (&a)[16], int t) {
+    if constexpr (AM == 1) loadA_t(a, t);
+    else if constexpr (AM == 0) loadA_d(a, t);
+    else if (upper(t)) loadA_t(a, t);
+    else loadA_d(a, t);
   };
 
   // B: load d of this wave covers stage bytes (wave * D + d) * 1024 + 16 * lane: piece and
@@ -181,11 +192,13 @@ __global__ __launch_bounds__(512, 1) void k_tall_stream(GemmArgs g) {
   // t + 1: at most the D + 4 loads of tile t + 2, issued after those of t + 1, may still be
   // outstanding.  Every wave issues the same loads in every iteration, so these counts are
   // exact and the compiler's own waits stay below them.
-  constexpr int LA = AT ? 16 : 4;  // A loads per tile per wave
+  // A loads per tile per wave: 4 as stored, 16 transposed
+  auto la = [&](int t) { return (AM == 1 || (AM == 2 && upper(t))) ? 16 : 4; };
   const int tlast = nk - 1;
-  auto wait_next = [&]() {
+  auto wait_next = [&](int tn) {  // tn: the tile whose loads were issued last
     asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_waitcnt(tl_vmcnt(D + LA));
+    if (la(tn) == 16) __builtin_amdgcn_s_waitcnt(tl_vmcnt(D + 16));
+    else __builtin_amdgcn_s_waitcnt(tl_vmcnt(D + 4));
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_waitcnt(tl_lgkm0());
     __builtin_amdgcn_s_barrier();
@@ -198,14 +211,14 @@ __global__ __launch_bounds__(512, 1) void k_tall_stream(GemmArgs g) {
     loadA(anext2, tn);
     asm volatile("" ::: "memory");  // the loads of tile t + 2 go out before the MFMAs of tile t
     compute(stage(I), acur);
-    wait_next();
+    wait_next(tn);
   };
 
   loadB(std::integral_constant<int, 0>{}, 0);
   loadA(a0, 0);
   loadB(std::integral_constant<int, 1>{}, nk > 1 ? 1 : 0);
   loadA(a1, nk > 1 ? 1 : 0);
-  wait_next();  // tile 0
+  wait_next(nk > 1 ? 1 : 0);  // tile 0
   const int ng = nk / 3;
   for (int gi = 0; gi < ng; ++gi) {
     const int t = 3 * gi;
@@ -255,10 +268,10 @@ __global__ __launch_bounds__(256) void k_split_planes(const float* __restrict__ 
   }
 }
 
-template <int NA, int NB, int PMAX, bool AT>
+template <int NA, int NB, int PMAX, int AM>
 hipError_t launch_stream(const GemmArgs& g, int bn, int64_t blocks, hipStream_t s) {
-  if (bn == 256) hipLaunchKernelGGL((k_tall_stream<256, NA, NB, PMAX, AT>), dim3((unsigned)blocks), dim3(512), 0, s, g);
-  else hipLaunchKernelGGL((k_tall_stream<128, NA, NB, PMAX, AT>), dim3((unsigned)blocks), dim3(512), 0, s, g);
+  if (bn == 256) hipLaunchKernelGGL((k_tall_stream<256, NA, NB, PMAX, AM>), dim3((unsigned)blocks), dim3(512), 0, s, g);
+  else hipLaunchKernelGGL((k_tall_stream<128, NA, NB, PMAX, AM>), dim3((unsigned)blocks), dim3(512), 0, s, g);
   return hipGetLastError();
 }
 
@@ -266,10 +279,11 @@ hipError_t launch_stream(const GemmArgs& g, int bn, int64_t blocks, hipStream_t 
 
 bool tall_stream_supported(const MixedGemm& mg) {
   const GemmArgs& g = mg.g;
-  const bool kc = mg.a_kind == OK_F32_KC, mc = mg.a_kind == OK_F32_MC;
+  const bool kc = mg.a_kind == OK_F32_KC, mc = mg.a_kind == OK_F32_MC, sym = mg.a_kind == OK_F32_SYM;
   const bool combo = (kc && ((mg.na == 2 && mg.nb == 2 && mg.pmax == 1) || (mg.na == 3 && mg.nb == 1 && mg.pmax == 2) ||
                              (mg.na == 3 && mg.nb == 2 && mg.pmax == 2))) ||
-                     (mc && ((mg.na == 2 && mg.nb == 3 && mg.pmax == 2) || (mg.na == 2 && mg.nb == 2 && mg.pmax == 1)));
+                     (mc && ((mg.na == 2 && mg.nb == 3 && mg.pmax == 2) || (mg.na == 2 && mg.nb == 2 && mg.pmax == 1))) ||
+                     (sym && mg.na == 2 && mg.nb == 2 && mg.pmax == 1 && g.M == g.K && g.M % 128 == 0);
   return combo && mg.b_kind == OK_BF16_KC && g.epi == EPI_COLSTORE && g.N % 128 == 0 &&
          g.M % 32 == 0 && g.M >= 1024 && g.splitk >= 1 && g.splitk <= 8 && 8 % g.splitk == 0 &&
          g.K % ((int64_t)TL_BK * g.splitk) == 0 && g.lda % 4 == 0 && g.ldb % 8 == 0 && g.b_plane % 8 == 0;
@@ -279,14 +293,15 @@ hipError_t tall_stream(const GemmArgs& run, const MixedGemm& mg, hipStream_t s) 
   const int bn = run.N % 256 == 0 ? 256 : 128;
   const int64_t MT = (run.M + TL_BM - 1) / TL_BM, NTT = run.N / bn, G = 8 / run.splitk;
   const int64_t blocks = 8 * ((MT + G - 1) / G) * NTT;  // row tiles beyond MT return at once
+  if (mg.a_kind == OK_F32_SYM) return launch_stream<2, 2, 1, 2>(run, bn, blocks, s);
   if (mg.a_kind == OK_F32_MC) {
-    if (mg.na == 2 && mg.nb == 3 && mg.pmax == 2) return launch_stream<2, 3, 2, true>(run, bn, blocks, s);
-    if (mg.na == 2 && mg.nb == 2 && mg.pmax == 1) return launch_stream<2, 2, 1, true>(run, bn, blocks, s);
+    if (mg.na == 2 && mg.nb == 3 && mg.pmax == 2) return launch_stream<2, 3, 2, 1>(run, bn, blocks, s);
+    if (mg.na == 2 && mg.nb == 2 && mg.pmax == 1) return launch_stream<2, 2, 1, 1>(run, bn, blocks, s);
     return hipErrorInvalidValue;
   }
-  if (mg.na == 2 && mg.nb == 2 && mg.pmax == 1) return launch_stream<2, 2, 1, false>(run, bn, blocks, s);
-  if (mg.na == 3 && mg.nb == 1 && mg.pmax == 2) return launch_stream<3, 1, 2, false>(run, bn, blocks, s);
-  if (mg.na == 3 && mg.nb == 2 && mg.pmax == 2) return launch_stream<3, 2, 2, false>(run, bn, blocks, s);
+  if (mg.na == 2 && mg.nb == 2 && mg.pmax == 1) return launch_stream<2, 2, 1, 0>(run, bn, blocks, s);
+  if (mg.na == 3 && mg.nb == 1 && mg.pmax == 2) return launch_stream<3, 1, 2, 0>(run, bn, blocks, s);
+  if (mg.na == 3 && mg.nb == 2 && mg.pmax == 2) return launch_stream<3, 2, 2, 0>(run, bn, blocks, s);
   return hipErrorInvalidValue;
 }
 

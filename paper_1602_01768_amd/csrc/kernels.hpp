@@ -53,6 +53,8 @@ struct GemmArgs {
   double* est_red = nullptr;
   // bf16 tall-skinny products: tile width along N (0: the widest of 256/128/64/32 dividing N)
   int bn = 0;
+  // bf16 symmetric update (EPI_SYMUPD): write the lower tiles only, no mirrored copies
+  bool lower_only = false;
 };
 
 // Tile order for an n x n product of T x T tiles: super-tiles of S x S tiles in row-major
@@ -71,7 +73,8 @@ enum OpKind : int {
   OK_F32_KC = 0,    // FP32, contiguous along k, split into bf16 pieces on load
   OK_F32_MC = 1,    // FP32, contiguous along m (or n), split on load
   OK_BF16_KC = 2,   // pre-split bf16 planes, contiguous along k (plane p at base + p*plane)
-  OK_BF16_MC = 3    // one bf16 plane, contiguous along m (or n)
+  OK_BF16_MC = 3,   // one bf16 plane, contiguous along m (or n)
+  OK_F32_SYM = 4    // FP32 symmetric, current on its lower 128 x 128 tiles only (streamed product)
 };
 struct MixedGemm {
   // the products write FP32 unless g.c_dt is set to DT_F64 explicitly (q x q results)
@@ -98,6 +101,9 @@ hipError_t reduce_partials_f32(const GemmArgs& g, const float* partial, hipStrea
 // (lower tiles, mirrored) or EPI_ADDROW (every tile); blocks as gemm_bf16_blocks gives
 // for 128 x 128 tiles.
 hipError_t symupd_bf16_dma(const GemmArgs& g, int64_t blocks, hipStream_t s);
+// Copy the strictly lower 128 x 128 tiles of the FP32 n x n matrix X (T tiles a side) onto
+// the upper ones, transposed: X held on its lower tiles becomes whole again.
+hipError_t mirror_lower(float* X, int64_t ld, int64_t T, hipStream_t s);
 int64_t reduce_blocks_f32(const GemmArgs& g);
 int64_t gemm_bf16_blocks(const MixedGemm& mg);
 
