@@ -82,15 +82,21 @@ def phase_roofline(name, n, q, variant, sketch, precision="mixed"):
     return None
 
 
-# kernel symbol (as rocprofv3 names it) of each product phase in mixed mode, fixed/Gaussian
+# kernel symbol (as rocprofv3 names it) of each product phase in mixed mode at n = 16384,
+# q = 256: fixed RBFGS with the Gaussian sketch, and AdaRBFGS ("ada." phases)
 PHASE_KERNEL = {
-    "XY": "k_gemm_bf16<128, 256, 2, 4, 2, 2, 1, 0, 0, true, 0, 1, 32>",
-    "AS": "k_gemm_bf16<128, 256, 4, 1, 3, 1, 2, 0, 2, false, 0, 1, 32>",
-    "update": "k_symupd_dma<32, 2, 2, 2, 2, false, 1>",
+    "XY": "k_tall_stream<256, 2, 2, 1, 2>",
+    "AS": "k_tall_stream<256, 3, 1, 2, 0>",
+    "update": "k_symupd_dma<32, 2, 2, 2, 2, false, 1, false>",
+    "ada.LS": "k_tall_stream<256, 3, 1, 2, 0>",
+    "ada.AS": "k_tall_stream<256, 3, 2, 2, 0>",
+    "ada.LtY": "k_tall_stream<256, 2, 3, 2, 1>",
+    "ada.update": "k_symupd_dma<32, 2, 2, 2, 2, true, 1, true>",
 }
-KERNEL_SOURCES = ["paper_1602_01768_amd/csrc/k_bf16.hip", "paper_1602_01768_amd/csrc/k_symupd.hip",
-                  "paper_1602_01768_amd/csrc/common.hpp", "paper_1602_01768_amd/csrc/kernels.hpp"]
-COUNTERS_FILE = "profiles/hbm_counters_c3_fixed_gauss_mixed.txt"
+KERNEL_SOURCES = ["paper_1602_01768_amd/csrc/k_bf16.hip", "paper_1602_01768_amd/csrc/k_tall.hip",
+                  "paper_1602_01768_amd/csrc/k_symupd.hip", "paper_1602_01768_amd/csrc/common.hpp",
+                  "paper_1602_01768_amd/csrc/kernels.hpp"]
+COUNTERS_FILE = "profiles/hbm_counters_c3_n16384_q256_mixed.txt"
 
 
 def sources_sha256():
@@ -105,11 +111,11 @@ def sources_sha256():
 def counter_traffic(phase):
     """HBM bytes per launch of the phase's kernel from the committed rocprofv3 counter
     summary: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) each scaled by the factor the
-    same counter reads for a copy kernel of known size.  None when the summary is missing,
-    does not cover the kernel, or was taken from different kernel sources."""
+    same counter reads for a copy kernel of known size.  Rows are keyed by phase (the fixed
+    method's, or "ada." and the adaptive method's).  None when the summary is missing, does
+    not cover the phase, or was taken from different kernel sources."""
     path = os.path.join(ROOT, COUNTERS_FILE)
-    kern = PHASE_KERNEL.get(phase)
-    if not kern or not os.path.exists(path):
+    if phase not in PHASE_KERNEL or not os.path.exists(path):
         return None
     kv, rows = {}, {}
     for line in open(path):
@@ -119,10 +125,10 @@ def counter_traffic(phase):
             kv[k] = v
         elif line.startswith("kernel="):
             f = dict(x.split("=", 1) for x in line.split(" | "))
-            rows[f["kernel"]] = f
-    if kv.get("sources_sha256") != sources_sha256() or kern not in rows:
+            rows[f["phase"]] = f
+    if kv.get("sources_sha256") != sources_sha256() or phase not in rows:
         return None
-    r = rows[kern]
+    r = rows[phase]
     return (float(r["fetch_kib"]) * float(kv["fetch_factor"]) + float(r["write_kib"]) * float(kv["write_factor"])) * 1024.0
 
 
@@ -797,7 +803,7 @@ def main():
                 "ms_per_step": round(dt_ada / args.steps * 1e3, 4),
                 "tflops_effective": round(ada_flops * args.steps / dt_ada / 1e12, 3),
                 "products_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in live_ada.items()},
-                "roofline": live_roofline(live_ada, n, q, "adaptive", "gauss")}
+                "roofline": live_roofline(live_ada, n, q, "adaptive", "gauss", lambda p: counter_traffic("ada." + p))}
 
     # ---- the other instances of the family (PSB, AIP, Kaczmarz) on the same matrix
     log("the other instances of the family (PSB, AIP, Kaczmarz) on th")
