@@ -166,13 +166,18 @@ __global__ __launch_bounds__(512, 1) void k_tall_stream(GemmArgs g) {
       bf16x8 ap[NA];
       split_vec<NA>(av, ap);
       const int c = 2 * h + s;  // logical 16-byte chunk of k = 16 h + 8 s .. + 7
+      // column blocks in pairs, the passes of the two alternating, so that no MFMA waits for
+      // the one just before it (same accumulator)
 #pragma unroll
-      for (int b = 0; b < FN; ++b) {
-        const int r = b * 32 + cr;
-        bf16x8 bp[NB];
+      for (int b = 0; b < FN; b += 2) {
+        bf16x8 bp[2][NB];
 #pragma unroll
-        for (int p = 0; p < NB; ++p)
-          bp[p] = *(const bf16x8*)(S + p * PLB + r * ROWB + ((c ^ ((r / RPB) % CHUNKS)) * 16));
+        for (int u = 0; u < 2; ++u) {
+          const int r = (b + u) * 32 + cr;
+#pragma unroll
+          for (int p = 0; p < NB; ++p)
+            bp[u][p] = *(const bf16x8*)(S + p * PLB + r * ROWB + ((c ^ ((r / RPB) % CHUNKS)) * 16));
+        }
         // piece products smallest first
 #pragma unroll
         for (int lvl = PMAX; lvl >= 0; --lvl)
@@ -180,7 +185,9 @@ __global__ __launch_bounds__(512, 1) void k_tall_stream(GemmArgs g) {
           for (int pa = 0; pa < NA; ++pa) {
             const int pb = lvl - pa;
             if (pb < 0 || pb >= NB) continue;
-            acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ap[pa], bp[pb], acc[b], 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+              acc[b + u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ap[pa], bp[u][pb], acc[b + u], 0, 0, 0);
           }
       }
     }
