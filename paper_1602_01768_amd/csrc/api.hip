@@ -180,6 +180,10 @@ struct rbfgs_ctx {
   // the sketch's iteration is then read from the device counter kdev (plus the step's offset
   // in the window, while kcap0 >= 0 during the capture), which the graph advances at its end
   int64_t* kdev = nullptr;
+  // the side lanes' work is enqueued up to iteration prod_hi (products) and inv_hi (inverse):
+  // enqueue_steps ends by issuing the next window's first products and inverse, so that a
+  // window does not start with the side lanes idle (reset by rbfgs_set_state)
+  int64_t prod_hi = -1, inv_hi = -1;
   int64_t kcap0 = -1;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -211,6 +215,14 @@ struct Fail {
   } while (0)
 
 size_t dt_size(int dt) { return dt == DT_F32 ? 4 : (dt == DT_BF16 ? 2 : 8); }
+
+// Order lane s after event e.  A serving context runs every lane on one stream, where stream
+// order already holds -- and a wait on an event recorded before a graph capture began would
+// break the capture -- so it skips the wait.
+#define LANE_WAIT(s, e)                                         \
+  do {                                                          \
+    if (ctx->own_lanes) HIPCHK(hipStreamWaitEvent((s), (e), 0)); \
+  } while (0)
 
 // Zeroed device allocation owned by the context.  In a dry run (footprint) only the
 // size is accounted and a placeholder is returned.
@@ -616,7 +628,7 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
       HIPCHK(estimator(ctx->coord ? nullptr : S.Sk, sk_dt(ctx), ctx->coord ? S.C : nullptr, ctx->V, mdt, np, ctx->n,
                        ctx->q, scale, L.red, ctx->est, ctx->status, L.s, ctx->part ? S.ht : nullptr));
   }
-  HIPCHK(hipStreamWaitEvent(L.s, S.ready, 0));  // G^-1 and U of this slot
+  LANE_WAIT(L.s, S.ready);  // G^-1 and U of this slot
   // PSB: H' = Y^T V - S^T Y (= R^T Y with R = V - S), and W' = V - S - U H'/2
   const double cs = ctx->psb ? -1.0 : -0.5;
   if (ctx->psb) HIPCHK(panel_axpby(ctx->H, DT_F64, 1.0, S.G2, DT_F64, -1.0, ctx->H, DT_F64, qp, qp, qp, L.s));
@@ -720,7 +732,7 @@ void main_row(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
       HIPCHK(estimator(S.Sk, sk_dt(ctx), nullptr, ctx->V, mdt, np, ctx->n, ctx->q, scale, L.red, ctx->est,
                        ctx->status, L.s, ctx->imp ? S.ht : nullptr));
   }
-  HIPCHK(hipStreamWaitEvent(L.s, S.ready, 0));  // U of this slot
+  LANE_WAIT(L.s, S.ready);  // U of this slot
   ahead();
   {
     Phase ph(ctx, L, "panels");
@@ -778,7 +790,7 @@ void main_adaptive(rbfgs_ctx* ctx, Slot& S, int64_t k) {
   // the q x q inverse (a latency-bound chain of small kernels) runs on the inverse lane while
   // the main lane forms T^T = L^T Y, which does not need it
   HIPCHK(hipEventRecord(ctx->ev_g, L.s));
-  HIPCHK(hipStreamWaitEvent(ctx->inv.s, ctx->ev_g, 0));
+  LANE_WAIT(ctx->inv.s, ctx->ev_g);
   {
     Phase ph(ctx, ctx->inv, "chol_inv");
     HIPCHK(chol_inv(ctx->G, qp, ctx->q, ctx->Z, ctx->Ginv, qp, ctx->inv.cwork, ctx->status, ctx->inv.s));
@@ -788,7 +800,7 @@ void main_adaptive(rbfgs_ctx* ctx, Slot& S, int64_t k) {
     Phase ph(ctx, L, "LtY", true);
     nn_times_panel(ctx, L, ctx->X, true, ctx->Y, mdt, ctx->V, 2, 3, 2, ph.mark());  // T^T = L^T Y
   }
-  HIPCHK(hipStreamWaitEvent(L.s, ctx->ev_chol, 0));
+  LANE_WAIT(L.s, ctx->ev_chol);
   const double scale = ctx->part ? 1.0 : ctx->coord ? (double)ctx->n / ctx->q : 1.0 / ctx->q;
   {
     Phase ph(ctx, L, "panels");
@@ -889,6 +901,37 @@ void main_comparison(rbfgs_ctx* ctx) {
   HIPCHK(axpy_ratio((double*)ctx->X, ctx->P2, np * np, ctx->scal, L.s));
 }
 
+// Side-lane work of iteration k, each issued once (the watermarks skip what an earlier call
+// enqueued ahead): the sketch-dependent products, and the inverse part.
+void issue_products(rbfgs_ctx* ctx, int64_t k) {
+  if (k <= ctx->prod_hi) return;
+  Slot& S = ctx->slot[k % rbfgs_ctx::NSLOT];
+  if (S.released_valid) LANE_WAIT(ctx->side.s, S.released);
+  side_products(ctx, k, S);
+  ctx->prod_hi = k;
+}
+void issue_inverse(rbfgs_ctx* ctx, int64_t k) {
+  if (k <= ctx->inv_hi) return;
+  Slot& S = ctx->slot[k % rbfgs_ctx::NSLOT];
+  LANE_WAIT(ctx->inv.s, S.g_ready);
+  side_inverse(ctx, S);
+  HIPCHK(hipEventRecord(S.ready, ctx->inv.s));
+  ctx->inv_hi = k;
+}
+
+// This window's first products and inverse, enqueued before a window is captured into a
+// graph, so that the graph starts from the state every replay starts from.
+void prime_lookahead(rbfgs_ctx* ctx) {
+  if (ctx->imp || ctx->ns || ctx->mr) return;
+  if (ctx->prod_hi >= ctx->k + 1 && ctx->inv_hi >= ctx->k) return;
+  HIPCHK(hipEventRecord(ctx->ev_begin, ctx->main.s));
+  LANE_WAIT(ctx->side.s, ctx->ev_begin);
+  LANE_WAIT(ctx->inv.s, ctx->ev_begin);
+  issue_products(ctx, ctx->k);
+  issue_products(ctx, ctx->k + 1);
+  issue_inverse(ctx, ctx->k);
+}
+
 // Enqueue iterations k .. k+nsteps-1: the side lane runs up to two iterations ahead,
 // the inverse lane one.  For the fixed method the side lane's products of iteration
 // k+2 start once the main lane's X Y of iteration k is done, so that A S shares the
@@ -906,12 +949,12 @@ void enqueue_steps(rbfgs_ctx* ctx, int64_t nsteps) {
       Slot& S = ctx->slot[k % NS];
       importance_draw(ctx, S, k);
       HIPCHK(hipEventRecord(ctx->ev_begin, ctx->main.s));
-      HIPCHK(hipStreamWaitEvent(ctx->side.s, ctx->ev_begin, 0));
+      LANE_WAIT(ctx->side.s, ctx->ev_begin);
       side_products(ctx, k, S);
-      HIPCHK(hipStreamWaitEvent(ctx->inv.s, S.g_ready, 0));
+      LANE_WAIT(ctx->inv.s, S.g_ready);
       side_inverse(ctx, S);
       HIPCHK(hipEventRecord(S.ready, ctx->inv.s));
-      HIPCHK(hipStreamWaitEvent(ctx->main.s, S.y_ready, 0));
+      LANE_WAIT(ctx->main.s, S.y_ready);
       main_row(ctx, S, [] {}, [] {});
       HIPCHK(hipEventRecord(S.released, ctx->main.s));
       S.released_valid = true;
@@ -920,19 +963,10 @@ void enqueue_steps(rbfgs_ctx* ctx, int64_t nsteps) {
     return;
   }
   HIPCHK(hipEventRecord(ctx->ev_begin, ctx->main.s));
-  HIPCHK(hipStreamWaitEvent(ctx->side.s, ctx->ev_begin, 0));
-  HIPCHK(hipStreamWaitEvent(ctx->inv.s, ctx->ev_begin, 0));
-  auto products = [&](int64_t k) {
-    Slot& S = ctx->slot[k % NS];
-    if (S.released_valid) HIPCHK(hipStreamWaitEvent(ctx->side.s, S.released, 0));
-    side_products(ctx, k, S);
-  };
-  auto inverse = [&](int64_t k) {
-    Slot& S = ctx->slot[k % NS];
-    HIPCHK(hipStreamWaitEvent(ctx->inv.s, S.g_ready, 0));
-    side_inverse(ctx, S);
-    HIPCHK(hipEventRecord(S.ready, ctx->inv.s));
-  };
+  LANE_WAIT(ctx->side.s, ctx->ev_begin);
+  LANE_WAIT(ctx->inv.s, ctx->ev_begin);
+  auto products = [&](int64_t k) { issue_products(ctx, k); };
+  auto inverse = [&](int64_t k) { issue_inverse(ctx, k); };
   const int64_t k0 = ctx->k;
   products(k0);
   if (nsteps > 1) products(k0 + 1);
@@ -946,10 +980,10 @@ void enqueue_steps(rbfgs_ctx* ctx, int64_t nsteps) {
     Slot& S = ctx->slot[k % NS];
     if (ctx->ada) {
       ahead();
-      HIPCHK(hipStreamWaitEvent(ctx->main.s, S.ready, 0));
+      LANE_WAIT(ctx->main.s, S.ready);
       main_adaptive(ctx, S, k);
     } else {
-      HIPCHK(hipStreamWaitEvent(ctx->main.s, S.y_ready, 0));
+      LANE_WAIT(ctx->main.s, S.y_ready);
       // The side lane's products of k+2 and the inverse of k+1 are released after X Y, so
       // that A S runs beside the q-sized kernels and the update rather than beside X Y.
       // Measured at n = 16384, q = 256: releasing A S at the start of the iteration lets the
@@ -958,7 +992,7 @@ void enqueue_steps(rbfgs_ctx* ctx, int64_t nsteps) {
       // against 1.76; releasing both only before the update was no faster.
       auto after_xy = [&]() {
         HIPCHK(hipEventRecord(ctx->ev_xy, ctx->main.s));
-        HIPCHK(hipStreamWaitEvent(ctx->side.s, ctx->ev_xy, 0));
+        LANE_WAIT(ctx->side.s, ctx->ev_xy);
         if (i + 2 < nsteps) products(k + 2);
         if (i + 1 < nsteps) inverse(k + 1);
       };
@@ -970,6 +1004,12 @@ void enqueue_steps(rbfgs_ctx* ctx, int64_t nsteps) {
     S.released_valid = true;
     ++ctx->k;
   }
+  // the next window's first products and inverse, issued now: they run beside this window's
+  // last steps and the host's stopping decision (they depend on the sketch and A only)
+  const int64_t kend = ctx->k;
+  products(kend);
+  products(kend + 1);
+  inverse(kend);
 }
 
 rbfgs_status fail(rbfgs_ctx* ctx, rbfgs_status st, const std::string& msg) {
@@ -1390,6 +1430,9 @@ rbfgs_status rbfgs_invert_enqueue(rbfgs_ctx* ctx, rb::InvertState& st, double* h
       enqueue_steps(ctx, st.m);
     } else if (!ctx->gexec) {
       RocRange range("window.capture");
+      // the graph starts from the state every replay starts from: this window's first products
+      // and inverse already enqueued (by the previous window, or here)
+      prime_lookahead(ctx);
       const int64_t k0 = ctx->k;
       HIPCHK(hipMemsetAsync(ctx->kdev, 0, sizeof(int64_t), s));
       HIPCHK(add_i64(ctx->kdev, k0, s));
@@ -1414,6 +1457,8 @@ rbfgs_status rbfgs_invert_enqueue(rbfgs_ctx* ctx, rb::InvertState& st, double* h
       RocRange range("window.replay");
       HIPCHK(hipGraphLaunch(ctx->gexec, s));
       ctx->k += st.m;
+      ctx->prod_hi += st.m;  // the graph ends by enqueueing the next window's side-lane work
+      ctx->inv_hi += st.m;
     }
     st.done += st.m;
     HIPCHK(hipMemcpyAsync(host_est, ctx->est + 2, sizeof(double), hipMemcpyDeviceToHost, ctx->main.s));
@@ -1620,6 +1665,7 @@ rbfgs_status rbfgs_set_state(rbfgs_ctx* ctx, const void* M, int32_t m_dtype, int
     if (ctx->part && ctx->ada) refresh_part_weights(ctx);
     HIPCHK(hipStreamSynchronize(ctx->main.s));
     ctx->k = k;
+    ctx->prod_hi = ctx->inv_hi = k - 1;  // nothing of the new iterations is enqueued
   } catch (const Fail& f) {
     return f.st;
   }
