@@ -216,3 +216,33 @@ def test_device_input_and_float32(lib):
         Xg = s.x().cpu().numpy()
     Xo, _ = oracle_x(A, 16, 2, "gauss", "fixed", 8)
     assert rel(Xg, Xo) <= MIXED_TOL
+
+
+def test_lower_tile_x_readers(lib):
+    """Mixed fixed RBFGS with the Gaussian sketch and q a multiple of 128 holds X on its lower
+    128 x 128 tiles; everything that reads X whole first copies them onto the upper ones.  The
+    exact residual, rbfgs_get_x (exactly symmetric), PCG preconditioned with X, and a checkpoint
+    taken mid-run and resumed all see the same X as the oracle's iterate."""
+    import torch
+    n, q, seed = 1024, 128, 6
+    A = gram_ridge(n, 8)
+    A64 = np.asarray(A, np.float64)
+    with lib.Solver(A, q, seed, precision="mixed") as s:
+        s.step(5)
+        r = s.residual()                       # mirror, then the FP64 residual
+        X5 = s.x().cpu().numpy()
+        s.step(3)                              # the update writes lower tiles again
+        X8 = s.x().cpu().numpy()
+        b = np.random.default_rng(1).standard_normal(n)
+        x, ok, its, _ = s.pcg(b, precond=True, tol=1e-10, max_iters=500)
+    assert np.array_equal(X5, X5.T) and np.array_equal(X8, X8.T)
+    assert abs(r - R.residual_fro(A64, X5)) <= 1e-9 * r
+    Xo, _ = oracle_x(A, q, seed, "gauss", "fixed", 8)
+    assert rel(X8, Xo) <= MIXED_TOL
+    assert ok and np.linalg.norm(A64 @ x.cpu().numpy() - b) <= 1e-9 * np.linalg.norm(b)
+    # resume from X_5 (written whole by set_state) and continue: equal to the uninterrupted run
+    with lib.Solver(A, q, seed, precision="mixed") as s2:
+        s2.set_state(torch.from_numpy(X5).cuda(), 5)
+        s2.step(3)
+        X8r = s2.x().cpu().numpy()
+    assert np.array_equal(X8r, X8)
