@@ -9,8 +9,9 @@
 // A is read as stored (four 16-byte loads per lane and tile) or transposed, A = M^T (L^T Y of
 // AdaRBFGS, X^T P of the row variants): then each lane takes its 16 values of column m with
 // one 4-byte load per k, the 32 lanes of a half-wave reading 128 contiguous bytes of a row.
-// A symmetric A held on its lower 128 x 128 tiles only (X of the fixed method) is read as
-// stored where the tile is lower or diagonal and transposed from the mirror tile above.
+// A symmetric A held on its lower 128 x 128 tiles only (X of the fixed method; diagonal tiles
+// whole and exactly symmetric) is read as stored left of the workgroup's switch column and
+// transposed from the lower tiles right of it, each k loop running without a choice per tile.
 // The B tile (all q columns, or 256 of them) is shared by the 8 waves and travels from memory
 // straight into LDS (global_load_lds_dwordx4) through a ring of three stages, one barrier per
 // 32-deep k tile.  The k order inside a tile is permuted to match the registers a lane holds
@@ -91,168 +92,219 @@ __global__ __launch_bounds__(512, 1) void k_tall_stream(GemmArgs g) {
   const int64_t mw = m0 + 32 * wave;  // this wave's rows
   const bool rows_ok = mw < g.M;      // (M is a multiple of 32)
 
-  // A: lane l holds row mw + l % 32, k = 16 (l / 32) .. + 15 of each tile (a wave beyond M
-  // loads row M - 1 and discards it, so that every wave issues the same loads)
-  const int64_t arow_i = rows_ok ? mw + (lane & 31) : g.M - 1;
-  const float* arow_t = (const float*)g.A + (kbeg + 16 * (lane >> 5)) * g.lda + arow_i;  // transposed
-  const float* arow_d = (const float*)g.A + arow_i * g.lda + 16 * (lane >> 5) + kbeg;    // as stored
-  const int64_t tile128 = mw / 128;  // symmetric mode: tile row of this wave's rows
-  // symmetric mode: tile t lies in an upper 128 x 128 tile (uniform across the wave)
-  auto upper = [&](int t) { return AM == 2 && (kbeg + (int64_t)t * TL_BK) / 128 > tile128; };
-  float a0[16], a1[16], a2[16];
-  auto loadA_t = [&](float (&a)[16], int t) {
-    const float* src = arow_t + (int64_t)t * TL_BK * g.lda;
+  // The body for one way of reading A, chosen once per workgroup: with X on its lower tiles
+  // only the K chunk that holds the diagonal mixes the two ways (per wave and tile); every
+  // other chunk reads its tiles all as stored or all transposed.  A choice made per tile
+  // inside the k loop costs full waits for the loads in flight (the compiler cannot carry its
+  // count of outstanding loads across the two load sequences), so the uniform chunks run a
+  // body without it.
+  // AMX: 0 every tile as stored, 1 every tile transposed, 2 tiles below t0 (2 <= t0 < nk) as
+  // stored and the rest transposed, 3 tile 0 as stored and the rest transposed
+  auto body = [&](auto AMC, int t0) {
+    constexpr int AMX = decltype(AMC)::value;
+    // A: lane l holds row mw + l % 32, k = 16 (l / 32) .. + 15 of each tile (a wave beyond M
+    // loads row M - 1 and discards it, so that every wave issues the same loads)
+    const int64_t arow_i = rows_ok ? mw + (lane & 31) : g.M - 1;
+    const float* arow_t = (const float*)g.A + (kbeg + 16 * (lane >> 5)) * g.lda + arow_i;  // transposed
+    const float* arow_d = (const float*)g.A + arow_i * g.lda + 16 * (lane >> 5) + kbeg;    // as stored
+    float a0[16], a1[16], a2[16];
+    auto loadA_t = [&](float (&a)[16], int t) {
+      const float* src = arow_t + (int64_t)t * TL_BK * g.lda;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) a[j] = src[j * g.lda];
-  };
-  auto loadA_d = [&](float (&a)[16], int t) {
-    const float* src = arow_d + (int64_t)t * TL_BK;
+      for (int j = 0; j < 16; ++j) a[j] = src[j * g.lda];
+    };
+    auto loadA_d = [&](float (&a)[16], int t) {
+      const float* src = arow_d + (int64_t)t * TL_BK;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const f32x4 v = *((const f32x4*)(src + 4 * i));
-      a[4 * i] = v[0];
-      a[4 * i + 1] = v[1];
-      a[4 * i + 2] = v[2];
-      a[4 * i + 3] = v[3];
-    }
-  };
-  auto loadA = [&](float (&a)[16], int t) {
-    if constexpr (AM == 1) loadA_t(a, t);
-    else if constexpr (AM == 0) loadA_d(a, t);
-    else if (upper(t)) loadA_t(a, t);
-    else loadA_d(a, t);
-  };
-
-  // B: load d of this wave covers stage bytes (wave * D + d) * 1024 + 16 * lane: piece and
-  // first row uniform, the lane adding row lane / CHUNKS and its swizzled chunk
-  static_assert((1024 / ROWB) % (RPB * CHUNKS) == 0, "a load covers whole swizzle periods");
-  const int rl = lane / CHUNKS, cs = (lane % CHUNKS) ^ ((rl / RPB) % CHUNKS);
-  const uint32_t voff = (uint32_t)(rl * g.ldb + cs * 8);
-  const __bf16* bbase[D];
-#pragma unroll
-  for (int d = 0; d < D; ++d) {
-    const int j = (wave * D + d) * 1024;
-    const int p = j / PLB, r = (j % PLB) / ROWB;
-    bbase[d] = (const __bf16*)g.B + p * g.b_plane + (n0 + r) * g.ldb + kbeg;
-  }
-  auto stage = [&](auto I) -> char* {
-    constexpr int i = decltype(I)::value;
-    if constexpr (i == 0) return st0;
-    else if constexpr (i == 1) return st1;
-    else return st2;
-  };
-  auto loadB = [&](auto I, int t) {
-    char* dst = stage(I);
-#pragma unroll
-    for (int d = 0; d < D; ++d)
-      __builtin_amdgcn_global_load_lds((const void*)(bbase[d] + (int64_t)t * TL_BK + voff),
-                                       (lds_void*)(dst + (wave * D + d) * 1024), 16, 0, 0);
-  };
-
-  f32x16 acc[FN];
-#pragma unroll
-  for (int b = 0; b < FN; ++b)
-#pragma unroll
-    for (int r = 0; r < 16; ++r) acc[b][r] = 0.0f;
-
-  const int h = lane >> 5, cr = lane & 31;
-  auto compute = [&](const char* S, const float (&a)[16]) {
-    if (!rows_ok) return;
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      float av[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) av[e] = a[8 * s + e];
-      bf16x8 ap[NA];
-      split_vec<NA>(av, ap);
-      const int c = 2 * h + s;  // logical 16-byte chunk of k = 16 h + 8 s .. + 7
-      // column blocks in pairs, the passes of the two alternating, so that no MFMA waits for
-      // the one just before it (same accumulator)
-#pragma unroll
-      for (int b = 0; b < FN; b += 2) {
-        bf16x8 bp[2][NB];
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-          const int r = (b + u) * 32 + cr;
-#pragma unroll
-          for (int p = 0; p < NB; ++p)
-            bp[u][p] = *(const bf16x8*)(S + p * PLB + r * ROWB + ((c ^ ((r / RPB) % CHUNKS)) * 16));
-        }
-        // piece products smallest first
-#pragma unroll
-        for (int lvl = PMAX; lvl >= 0; --lvl)
-#pragma unroll
-          for (int pa = 0; pa < NA; ++pa) {
-            const int pb = lvl - pa;
-            if (pb < 0 || pb >= NB) continue;
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-              acc[b + u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ap[pa], bp[u][pb], acc[b + u], 0, 0, 0);
-          }
+      for (int i = 0; i < 4; ++i) {
+        const f32x4 v = *((const f32x4*)(src + 4 * i));
+        a[4 * i] = v[0];
+        a[4 * i + 1] = v[1];
+        a[4 * i + 2] = v[2];
+        a[4 * i + 3] = v[3];
       }
+    };
+    // LM: the way tile t is read (0 as stored, 1 transposed), fixed at compile time
+    auto loadA = [&](auto LM, float (&a)[16], int t) {
+      if constexpr (decltype(LM)::value == 1) loadA_t(a, t);
+      else loadA_d(a, t);
+    };
+
+    // B: load d of this wave covers stage bytes (wave * D + d) * 1024 + 16 * lane: piece and
+    // first row uniform, the lane adding row lane / CHUNKS and its swizzled chunk
+    static_assert((1024 / ROWB) % (RPB * CHUNKS) == 0, "a load covers whole swizzle periods");
+    const int rl = lane / CHUNKS, cs = (lane % CHUNKS) ^ ((rl / RPB) % CHUNKS);
+    const uint32_t voff = (uint32_t)(rl * g.ldb + cs * 8);
+    const __bf16* bbase[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int j = (wave * D + d) * 1024;
+      const int p = j / PLB, r = (j % PLB) / ROWB;
+      bbase[d] = (const __bf16*)g.B + p * g.b_plane + (n0 + r) * g.ldb + kbeg;
     }
-  };
+    auto stage = [&](auto I) -> char* {
+      constexpr int i = decltype(I)::value;
+      if constexpr (i == 0) return st0;
+      else if constexpr (i == 1) return st1;
+      else return st2;
+    };
+    auto loadB = [&](auto I, int t) {
+      char* dst = stage(I);
+#pragma unroll
+      for (int d = 0; d < D; ++d)
+        __builtin_amdgcn_global_load_lds((const void*)(bbase[d] + (int64_t)t * TL_BK + voff),
+                                         (lds_void*)(dst + (wave * D + d) * 1024), 16, 0, 0);
+    };
 
-  // tile t: B in stage t % 3, A in register set t % 3.  Iteration t issues the loads of tile
-  // t + 2 (into the stage tile t - 1 used, released by the barrier that closed iteration
-  // t - 1; past the last tile, the last tile again), computes tile t, then waits for tile
-  // t + 1: at most the D + 4 loads of tile t + 2, issued after those of t + 1, may still be
-  // outstanding.  Every wave issues the same loads in every iteration, so these counts are
-  // exact and the compiler's own waits stay below them.
-  // A loads per tile per wave: 4 as stored, 16 transposed
-  auto la = [&](int t) { return (AM == 1 || (AM == 2 && upper(t))) ? 16 : 4; };
-  const int tlast = nk - 1;
-  auto wait_next = [&](int tn) {  // tn: the tile whose loads were issued last
-    asm volatile("" ::: "memory");
-    if (la(tn) == 16) __builtin_amdgcn_s_waitcnt(tl_vmcnt(D + 16));
-    else __builtin_amdgcn_s_waitcnt(tl_vmcnt(D + 4));
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_waitcnt(tl_lgkm0());
-    __builtin_amdgcn_s_barrier();
-    asm volatile("" ::: "memory");
-  };
-  auto step = [&](auto I, float (&acur)[16], float (&anext2)[16], int t) {
-    constexpr int i = decltype(I)::value;
-    const int tn = t + 2 < tlast ? t + 2 : tlast;
-    loadB(std::integral_constant<int, (i + 2) % 3>{}, tn);
-    loadA(anext2, tn);
-    asm volatile("" ::: "memory");  // the loads of tile t + 2 go out before the MFMAs of tile t
-    compute(stage(I), acur);
-    wait_next(tn);
-  };
+    f32x16 acc[FN];
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[b][r] = 0.0f;
 
-  loadB(std::integral_constant<int, 0>{}, 0);
-  loadA(a0, 0);
-  loadB(std::integral_constant<int, 1>{}, nk > 1 ? 1 : 0);
-  loadA(a1, nk > 1 ? 1 : 0);
-  wait_next(nk > 1 ? 1 : 0);  // tile 0
-  const int ng = nk / 3;
-  for (int gi = 0; gi < ng; ++gi) {
-    const int t = 3 * gi;
-    step(std::integral_constant<int, 0>{}, a0, a2, t);
-    step(std::integral_constant<int, 1>{}, a1, a0, t + 1);
-    step(std::integral_constant<int, 2>{}, a2, a1, t + 2);
+    const int h = lane >> 5, cr = lane & 31;
+    auto compute = [&](const char* S, const float (&a)[16]) {
+      if (!rows_ok) return;
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        float av[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[e] = a[8 * s + e];
+        bf16x8 ap[NA];
+        split_vec<NA>(av, ap);
+        const int c = 2 * h + s;  // logical 16-byte chunk of k = 16 h + 8 s .. + 7
+        // column blocks in pairs, the passes of the two alternating, so that no MFMA waits for
+        // the one just before it (same accumulator)
+#pragma unroll
+        for (int b = 0; b < FN; b += 2) {
+          bf16x8 bp[2][NB];
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            const int r = (b + u) * 32 + cr;
+#pragma unroll
+            for (int p = 0; p < NB; ++p)
+              bp[u][p] = *(const bf16x8*)(S + p * PLB + r * ROWB + ((c ^ ((r / RPB) % CHUNKS)) * 16));
+          }
+          // piece products smallest first
+#pragma unroll
+          for (int lvl = PMAX; lvl >= 0; --lvl)
+#pragma unroll
+            for (int pa = 0; pa < NA; ++pa) {
+              const int pb = lvl - pa;
+              if (pb < 0 || pb >= NB) continue;
+#pragma unroll
+              for (int u = 0; u < 2; ++u)
+                acc[b + u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ap[pa], bp[u][pb], acc[b + u], 0, 0, 0);
+            }
+        }
+      }
+    };
+
+    // tile t: B in stage t % 3, A in register set t % 3.  Iteration t issues the loads of tile
+    // t + 2 (into the stage tile t - 1 used, released by the barrier that closed iteration
+    // t - 1; past the last tile, the last tile again), computes tile t, then waits for tile
+    // t + 1: at most the D + 4 loads of tile t + 2, issued after those of t + 1, may still be
+    // outstanding.  Every wave issues the same loads in every iteration, so these counts are
+    // exact and the compiler's own waits stay below them.
+    // A loads per tile per wave: 4 as stored, 16 transposed
+    const int tlast = nk - 1;
+    auto wait_next = [&](auto LM) {  // LM: the way the tile whose loads went out last is read
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_waitcnt(tl_vmcnt(D + (decltype(LM)::value == 1 ? 16 : 4)));
+      asm volatile("" ::: "memory");
+      __builtin_amdgcn_s_waitcnt(tl_lgkm0());
+      __builtin_amdgcn_s_barrier();
+      asm volatile("" ::: "memory");
+    };
+    // LM: the way tile t + 2 is read
+    auto step = [&](auto I, auto LM, float (&acur)[16], float (&anext2)[16], int t) {
+      constexpr int i = decltype(I)::value;
+      const int tn = t + 2 < tlast ? t + 2 : tlast;
+      loadB(std::integral_constant<int, (i + 2) % 3>{}, tn);
+      loadA(LM, anext2, tn);
+      asm volatile("" ::: "memory");  // the loads of tile t + 2 go out before the MFMAs of tile t
+      compute(stage(I), acur);
+      wait_next(LM);
+    };
+    // iterations tb .. te - 1, the loads they issue all read the same way (stage and register
+    // set of tile t are t % 3)
+    auto run = [&](auto LM, int tb, int te) {
+      using I0 = std::integral_constant<int, 0>;
+      using I1 = std::integral_constant<int, 1>;
+      using I2 = std::integral_constant<int, 2>;
+      int t = tb;
+      if (t < te && t % 3 == 1) step(I1{}, LM, a1, a0, t++);
+      if (t < te && t % 3 == 2) step(I2{}, LM, a2, a1, t++);
+      for (; t + 3 <= te; t += 3) {
+        step(I0{}, LM, a0, a2, t);
+        step(I1{}, LM, a1, a0, t + 1);
+        step(I2{}, LM, a2, a1, t + 2);
+      }
+      if (t < te) step(I0{}, LM, a0, a2, t++);
+      if (t < te) step(I1{}, LM, a1, a0, t++);
+    };
+
+    const int t1 = nk > 1 ? 1 : 0;
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1>;
+    if constexpr (AMX < 2) {
+      using LM = std::integral_constant<int, AMX>;
+      loadB(S0{}, 0);
+      loadA(LM{}, a0, 0);
+      loadB(S1{}, t1);
+      loadA(LM{}, a1, t1);
+      wait_next(LM{});  // tile 0
+      run(LM{}, 0, nk);
+    } else if constexpr (AMX == 2) {
+      // (the choice of the way tile 1 is read is made at compile time too: a choice at run
+      // time there costs the k loop full waits as well)
+      loadB(S0{}, 0);
+      loadA(S0{}, a0, 0);
+      loadB(S1{}, t1);
+      loadA(S0{}, a1, t1);
+      wait_next(S0{});
+      run(S0{}, 0, t0 - 2);  // tile t + 2 < t0
+      run(S1{}, t0 - 2, nk);
+    } else {
+      loadB(S0{}, 0);
+      loadA(S0{}, a0, 0);
+      loadB(S1{}, t1);
+      loadA(S1{}, a1, t1);
+      wait_next(S1{});
+      run(S1{}, 0, nk);
+    }
+    // no load may still be writing LDS or registers when the workgroup ends
+    __builtin_amdgcn_s_waitcnt(tl_vmcnt(0));
+
+    if (!rows_ok) return;
+    // column-major partial sums: a lane holds rows 8 g + 4 h + j (j = 0..3) of column cr of
+    // each 32-column block, one 16-byte store per g
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    const uint32_t plr = (ln >> 5) * 4, plc = ln & 31;
+    float* P = (float*)g.C + (int64_t)kc * g.M * g.N + n0 * g.M + mw;
+    const uint32_t ldp = (uint32_t)g.M;
+#pragma unroll
+    for (int b = 0; b < FN; ++b)
+#pragma unroll
+      for (int q4 = 0; q4 < 4; ++q4)
+        *(float4*)(P + (b * 32 + plc) * ldp + q4 * 8 + plr) =
+            make_float4(acc[b][4 * q4], acc[b][4 * q4 + 1], acc[b][4 * q4 + 2], acc[b][4 * q4 + 3]);
+  };
+  if constexpr (AM == 2) {
+    // Rows m0 .. m0 + 255 span the 128-row tiles r = m0 / 128 and r + 1.  Columns below
+    // (r + 1) 128 lie in lower or diagonal tiles for both and are read as stored; from
+    // (r + 1) 128 on they lie in upper tiles, read transposed from the lower ones, except the
+    // diagonal tile (r + 1, r + 1) of the second half, which is stored whole and exactly
+    // symmetric and so is read transposed as well: one switch point for the workgroup.
+    const int64_t ksw = (m0 / 128 + 1) * 128;
+    if (kbeg + (int64_t)nk * TL_BK <= ksw) body(std::integral_constant<int, 0>{}, nk);
+    else if (kbeg >= ksw) body(std::integral_constant<int, 1>{}, 0);
+    else if (ksw - kbeg > TL_BK) body(std::integral_constant<int, 2>{}, (int)((ksw - kbeg) / TL_BK));
+    else body(std::integral_constant<int, 3>{}, 1);
+  } else {
+    body(std::integral_constant<int, AM>{}, AM == 0 ? nk : 0);
   }
-  // the last nk % 3 tiles (already loaded into set and stage 0, then 1)
-  if (nk % 3 > 0) step(std::integral_constant<int, 0>{}, a0, a2, 3 * ng);
-  if (nk % 3 > 1) step(std::integral_constant<int, 1>{}, a1, a0, 3 * ng + 1);
-  // no load may still be writing LDS or registers when the workgroup ends
-  __builtin_amdgcn_s_waitcnt(tl_vmcnt(0));
-
-  if (!rows_ok) return;
-  // column-major partial sums: a lane holds rows 8 g + 4 h + j (j = 0..3) of column cr of
-  // each 32-column block, one 16-byte store per g
-  int ln = lane;
-  asm volatile("" : "+v"(ln));
-  const uint32_t plr = (ln >> 5) * 4, plc = ln & 31;
-  float* P = (float*)g.C + (int64_t)kc * g.M * g.N + n0 * g.M + mw;
-  const uint32_t ldp = (uint32_t)g.M;
-#pragma unroll
-  for (int b = 0; b < FN; ++b)
-#pragma unroll
-    for (int q4 = 0; q4 < 4; ++q4)
-      *(float4*)(P + (b * 32 + plc) * ldp + q4 * 8 + plr) =
-          make_float4(acc[b][4 * q4], acc[b][4 * q4 + 1], acc[b][4 * q4 + 2], acc[b][4 * q4 + 3]);
 }
 
 // bf16 planes of an FP32 array: out[p * count + i] = piece p of in[i]
