@@ -206,7 +206,9 @@ rbfgs_status rbfgs_get_l(rbfgs_ctx* ctx, void* L, int32_t l_dtype, int64_t ldl,
 /* Replace the state by (M, k): M is X_k for the fixed method, L_k for the
  * adaptive one (row-major, leading dimension ldm, element type m_dtype, host
  * or device).  Used for checkpoint/resume: the sketch of iteration k depends
- * only on (seed, k), so resuming reproduces the uninterrupted run. */
+ * only on (seed, k), so resuming reproduces the uninterrupted run.  The
+ * iterates of the fixed method and PSB are symmetric, and M must be too (not
+ * checked): the steps may read an entry from either triangle. */
 rbfgs_status rbfgs_set_state(rbfgs_ctx* ctx, const void* M, int32_t m_dtype, int64_t ldm,
                              int32_t on_device, int64_t k);
 
