@@ -677,7 +677,7 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
     g.A = S.planes; g.lda = ldp; g.a_plane = plane;
     g.B = S.planes + qp; g.ldb = ldp; g.b_plane = plane;
     g.epi = EPI_SYMUPD; g.C = ctx->X; g.ldc = np; g.c2 = -1.0;
-    g.tiles = ctx->tiles; g.ntiles = ctx->ntiles;
+    g.tiles = ctx->tiles; g.ntiles = ctx->ntiles; g.bn = bf16_square_tile(np, g.K, g.epi);  // (the order's tiles)
     g.lower_only = ctx->lowx;
     mg.a_kind = OK_BF16_KC; mg.b_kind = OK_BF16_KC; mg.na = 2; mg.nb = 2; mg.pmax = 1;
     bf_gemm(ctx, L, mg);
@@ -749,7 +749,7 @@ void main_row(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
     g.A = ctx->planes; g.lda = qp; g.a_plane = np * qp;
     g.B = S.planes; g.ldb = ldp; g.b_plane = np * ldp;
     g.epi = EPI_ADDROW; g.C = ctx->X; g.ldc = np; g.c2 = 1.0;
-    g.tiles = ctx->tiles; g.ntiles = ctx->ntiles;
+    g.tiles = ctx->tiles; g.ntiles = ctx->ntiles; g.bn = bf16_square_tile(np, g.K, g.epi);
     mg.a_kind = OK_BF16_KC; mg.b_kind = OK_BF16_KC; mg.na = 2; mg.nb = 2; mg.pmax = 1;
     bf_gemm(ctx, L, mg);
   } else {
@@ -831,7 +831,7 @@ void main_adaptive(rbfgs_ctx* ctx, Slot& S, int64_t k) {
     g.A = shi; g.lda = qp; g.a_plane = plane;
     g.B = qhi; g.ldb = qp; g.b_plane = plane;
     g.epi = EPI_ADDROW; g.C = ctx->X; g.ldc = np; g.c2 = 1.0;
-    g.tiles = ctx->tiles; g.ntiles = ctx->ntiles;
+    g.tiles = ctx->tiles; g.ntiles = ctx->ntiles; g.bn = bf16_square_tile(np, g.K, g.epi);
     mg.a_kind = OK_BF16_KC; mg.b_kind = OK_BF16_KC; mg.na = 2; mg.nb = 2; mg.pmax = 1;
     bf_gemm(ctx, L, mg);
   } else {
@@ -1245,7 +1245,7 @@ void allocate(rbfgs_ctx* ctx) {
   {  // tile order of the n x n update: lower triangle (symmetric X) or full square (L, row variants)
     const bool full = ctx->ada || ctx->rowv;
     const int epi = full ? EPI_ADDROW : EPI_SYMUPD;
-    const int T = (int)(np / (ctx->mixed ? bf16_square_tile(np, epi) : 128));
+    const int T = (int)(np / (ctx->mixed ? bf16_square_tile(np, full ? qp : 2 * qp, epi) : 128));
     std::vector<int2> order((size_t)make_tile_order(T, SUPER_TILES, !full, nullptr));
     ctx->ntiles = make_tile_order(T, SUPER_TILES, !full, order.data());
     ctx->tiles = (int2*)dalloc(ctx, order.size() * sizeof(int2));

@@ -25,14 +25,18 @@
 #include "kernels.hpp"
 
 // Launch shape, measured on the n = 16384, q = 256 update with random operands (same-run
-// comparisons): two stages of 32 columns, two workgroups per CU and 2 x 2 waves of 64 x 64
-// were fastest; 16-column stages (any depth or occupancy), three or four stages (one
-// workgroup per CU) and 2 x 1 / 1 x 2 wave grids were 10-40% slower, and an explicit
-// interleave of LDS reads with MFMAs within 1%.
+// comparisons), for 128 x 128 tiles: two stages of 32 columns, two workgroups per CU and
+// 2 x 2 waves of 64 x 64 were fastest; 16-column stages (any depth or occupancy), three or
+// four stages (one workgroup per CU) and 2 x 1 / 1 x 2 wave grids were 10-40% slower, and an
+// explicit interleave of LDS reads with MFMAs within 1%.  256 x 256 tiles halve the panel
+// bytes per entry of X, which dominate the kernel's traffic (a tile reads 2 pieces of K
+// columns of both panels, 8 K / BM bytes per entry of X against its 8 bytes read and
+// written; without the panel loads the n = 16384, q = 256 update takes 0.33 ms instead of
+// 0.64): two stages of 32 columns fill 128 KB of LDS, one workgroup of 2 x 4 waves of
+// 128 x 64 per CU, which hides less of the load latency; the tile size is chosen per update
+// by bf16_square_tile.
 constexpr int UPD_BKS = 32;  // columns per stage
 constexpr int UPD_NS = 2;    // stages in the ring
-constexpr int UPD_OCC = 2;   // workgroups per CU the register budget is sized for
-#define RB_UPD_WAVES 2, 2    // wave grid over the 128 x 128 tile
 // The epilogue reads and writes X non-temporally when the panels are at least UPD_NT_MINQ
 // columns wide: X passes once per launch while the bf16 panels are re-read by every tile,
 // and streaming X past the caches keeps more of the panels in L2 (n = 16384, q = 256:
@@ -61,10 +65,10 @@ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) |
 // ... and for "no LDS operation outstanding" (lgkmcnt 0, vmcnt and expcnt at their maxima)
 constexpr int lgkm0_imm() { return 15 | (3 << 14) | (7 << 4); }
 
-template <int BKS, int NS, int OCC, int WAVES_M, int WAVES_N, bool FULL, int NTX, bool MIRROR = true>
+template <int BM, int BKS, int NS, int OCC, int WAVES_M, int WAVES_N, bool FULL, int NTX, bool MIRROR = true>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) __attribute__((amdgpu_waves_per_eu(OCC * WAVES_M * WAVES_N / 4, 8)))
 void k_symupd_dma(GemmArgs g) {
-  constexpr int BM = 128, NP = 2, NW = WAVES_M * WAVES_N;
+  constexpr int NP = 2, NW = WAVES_M * WAVES_N;
   constexpr int WM = BM / WAVES_M, WN = BM / WAVES_N, FM = WM / 32, FN = WN / 32;
   constexpr int ROWB = BKS * 2;                 // bytes of one row of one piece
   constexpr int CHUNKS = ROWB / 16;             // 16-byte chunks per row
@@ -74,6 +78,7 @@ void k_symupd_dma(GemmArgs g) {
   constexpr int STB = 2 * OPB;                  // bytes of one stage
   constexpr int D = STB / 1024 / NW;            // 1 KB loads per wave per stage
   static_assert(BKS == 16 || BKS == 32 || BKS == 64, "stage depth");
+  static_assert(BM == 128 || BM == 256, "tile edge");
   static_assert(NS >= 2 && NS <= 4, "stages");
   __shared__ __attribute__((aligned(1024))) char st0[STB];
   __shared__ __attribute__((aligned(1024))) char st1[STB];
@@ -277,27 +282,38 @@ void k_symupd_dma(GemmArgs g) {
 
 }  // namespace
 
-hipError_t symupd_bf16_dma(const GemmArgs& g, int64_t blocks, hipStream_t s) {
-  if (g.K % UPD_BKS || g.M % 128 || g.M != g.N || g.lda % 8 || g.ldb % 8 || g.a_plane % 8 || g.b_plane % 8 ||
-      g.ldc % 4)
-    return hipErrorInvalidValue;
-  constexpr int wv[2] = {RB_UPD_WAVES};
-  const dim3 grid((unsigned)blocks), block(64 * wv[0] * wv[1]);
+namespace {
+
+template <int BM, int OCC, int WM, int WN>
+hipError_t launch_symupd(const GemmArgs& g, int64_t blocks, hipStream_t s) {
+  const dim3 grid((unsigned)blocks), block(64 * WM * WN);
   const bool full = g.epi == EPI_ADDROW;
   const bool nt = (full ? g.K : g.K / 2) >= UPD_NT_MINQ;  // panel width q
   if (full && nt)
-    hipLaunchKernelGGL((k_symupd_dma<UPD_BKS, UPD_NS, UPD_OCC, RB_UPD_WAVES, true, 1>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((k_symupd_dma<BM, UPD_BKS, UPD_NS, OCC, WM, WN, true, 1>), grid, block, 0, s, g);
   else if (full)
-    hipLaunchKernelGGL((k_symupd_dma<UPD_BKS, UPD_NS, UPD_OCC, RB_UPD_WAVES, true, 0>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((k_symupd_dma<BM, UPD_BKS, UPD_NS, OCC, WM, WN, true, 0>), grid, block, 0, s, g);
   else if (g.lower_only && nt)
-    hipLaunchKernelGGL((k_symupd_dma<UPD_BKS, UPD_NS, UPD_OCC, RB_UPD_WAVES, false, 1, false>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((k_symupd_dma<BM, UPD_BKS, UPD_NS, OCC, WM, WN, false, 1, false>), grid, block, 0, s, g);
   else if (g.lower_only)
-    hipLaunchKernelGGL((k_symupd_dma<UPD_BKS, UPD_NS, UPD_OCC, RB_UPD_WAVES, false, 0, false>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((k_symupd_dma<BM, UPD_BKS, UPD_NS, OCC, WM, WN, false, 0, false>), grid, block, 0, s, g);
   else if (nt)
-    hipLaunchKernelGGL((k_symupd_dma<UPD_BKS, UPD_NS, UPD_OCC, RB_UPD_WAVES, false, 1>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((k_symupd_dma<BM, UPD_BKS, UPD_NS, OCC, WM, WN, false, 1>), grid, block, 0, s, g);
   else
-    hipLaunchKernelGGL((k_symupd_dma<UPD_BKS, UPD_NS, UPD_OCC, RB_UPD_WAVES, false, 0>), grid, block, 0, s, g);
+    hipLaunchKernelGGL((k_symupd_dma<BM, UPD_BKS, UPD_NS, OCC, WM, WN, false, 0>), grid, block, 0, s, g);
   return hipGetLastError();
+}
+
+}  // namespace
+
+// g.bn: the tile edge (256, or 128 for any other value), as bf16_square_tile gives it
+hipError_t symupd_bf16_dma(const GemmArgs& g, int64_t blocks, hipStream_t s) {
+  const int bm = g.bn == 256 ? 256 : 128;
+  if (g.K % UPD_BKS || g.M % bm || g.M != g.N || g.lda % 8 || g.ldb % 8 || g.a_plane % 8 || g.b_plane % 8 ||
+      g.ldc % 4)
+    return hipErrorInvalidValue;
+  if (bm == 256) return launch_symupd<256, 1, 2, 4>(g, blocks, s);
+  return launch_symupd<128, 2, 2, 2>(g, blocks, s);
 }
 
 namespace {

@@ -92,8 +92,8 @@ bool tall_stream_supported(const MixedGemm& mg);
 hipError_t tall_stream(const GemmArgs& run, const MixedGemm& mg, hipStream_t s);
 // out[p * count + i] = bf16 piece p of in[i], np = 2 or 3 pieces (count a multiple of 4)
 hipError_t split_planes(const float* in, int64_t count, int np, __bf16* out, hipStream_t s);
-// Tile edge of the bf16 square products (EPI_SYMUPD / EPI_ADDROW) for order M.
-int bf16_square_tile(int64_t M, int epi);
+// Tile edge of the bf16 square products (EPI_SYMUPD / EPI_ADDROW) for order M and depth K.
+int bf16_square_tile(int64_t M, int64_t K, int epi);
 // Sum the FP32 split-K partials of a bf16 product (COLSTORE epilogue of g): C = c2 * sum
 // + c0 * B0 (FP32) + c1 * B1 (FP32 or bf16, b1_dt), column-major; C is FP32 or FP64 (c_dt).
 hipError_t reduce_partials_f32(const GemmArgs& g, const float* partial, hipStream_t s);
