@@ -495,6 +495,9 @@ void importance_draw(rbfgs_ctx* ctx, Slot& S, int64_t k) {
   HIPCHK(sample_partition(ctx->tw, ctx->n, ctx->q, ctx->p.seed, k, S.C, S.ht, ctx->status, L.s));
 }
 
+// Row-tile height of the tile-major bf16 panel planes of the symmetric update: its tile edge.
+int64_t sym_panel_tile(const rbfgs_ctx* ctx) { return bf16_square_tile(ctx->np, 2 * ctx->qp, EPI_SYMUPD); }
+
 // ---------------------------------------------------------------- side lanes
 // Sketch-dependent products of iteration k into slot S (side lane): the sketch, and
 // for the fixed method Y = A S (or the gathered columns) and G = S^T Y; for the
@@ -575,9 +578,10 @@ void side_inverse(rbfgs_ctx* ctx, Slot& S) {
     } else {
       panel_times_small(ctx, L, S.Sk, DT_BF16, S.Ginv, U, DT_F32, 1.0);
     }
-    const int64_t ldp = 3 * qp, plane = np * ldp;
-    HIPCHK(pack_split2(U, np, np, qp, S.planes, S.planes + plane, ldp, 0, L.s));
-    HIPCHK(pack_split2(U, np, np, qp, S.planes, S.planes + plane, ldp, 2 * qp, L.s));
+    // [U W' U] for the symmetric update (tile-major), or U for the row variants' update (row-major)
+    const int64_t ldp = 3 * qp, plane = np * ldp, tile = ctx->rowv ? 0 : sym_panel_tile(ctx);
+    HIPCHK(pack_split2(U, np, np, qp, S.planes, S.planes + plane, ldp, 0, L.s, tile));
+    HIPCHK(pack_split2(U, np, np, qp, S.planes, S.planes + plane, ldp, 2 * qp, L.s, tile));
   } else {
     double* U = (double*)S.U;
     if (ctx->psb || ctx->kacz) panel_times_small(ctx, L, S.Y, DT_F64, S.Ginv, U, DT_F64, 1.0);  // U = Y G^-1
@@ -667,15 +671,16 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
       } else {
         panel_times_small(ctx, L, S.U, DT_F32, ctx->H, W, DT_F32, -0.5, ctx->V, DT_F32, 1.0, S.Sk, DT_BF16, cs);
       }
-      HIPCHK(pack_split2(W, np, np, qp, S.planes, S.planes + plane, ldp, qp, L.s));
+      HIPCHK(pack_split2(W, np, np, qp, S.planes, S.planes + plane, ldp, qp, L.s, sym_panel_tile(ctx)));
     }
     release();
     Phase ph(ctx, L, "update", true);
     MixedGemm mg;
     GemmArgs& g = mg.g;
     g.M = np; g.N = np; g.K = 2 * qp;
+    // the planes are tile-major: column qp of a row tile starts qp x tile entries into its block
     g.A = S.planes; g.lda = ldp; g.a_plane = plane;
-    g.B = S.planes + qp; g.ldb = ldp; g.b_plane = plane;
+    g.B = S.planes + qp * sym_panel_tile(ctx); g.ldb = ldp; g.b_plane = plane;
     g.epi = EPI_SYMUPD; g.C = ctx->X; g.ldc = np; g.c2 = -1.0;
     g.tiles = ctx->tiles; g.ntiles = ctx->ntiles; g.bn = bf16_square_tile(np, g.K, g.epi);  // (the order's tiles)
     g.lower_only = ctx->lowx;

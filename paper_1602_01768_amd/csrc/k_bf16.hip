@@ -379,7 +379,7 @@ __global__ __launch_bounds__(256) void k_reduce_partials_f32(GemmArgs g, const f
 
 // Column-major FP32 panel -> row-major bf16 hi/lo planes, through a 32 x 64 LDS tile.
 __global__ void k_pack_split2(const float* in, int64_t ld_in, int64_t rows, int64_t cols, __bf16* hi, __bf16* lo,
-                              int64_t ld_out, int64_t col_off) {
+                              int64_t ld_out, int64_t col_off, int64_t tile) {
   __shared__ float t[32][65];
   const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 32;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 256 threads: 64 x 4
@@ -394,8 +394,11 @@ __global__ void k_pack_split2(const float* in, int64_t ld_in, int64_t rows, int6
     if (rr < rows && cc < cols) {
       __bf16 h, l;
       split2(t[cx][r], h, l);
-      hi[rr * ld_out + col_off + cc] = h;
-      lo[rr * ld_out + col_off + cc] = l;
+      const int64_t c = col_off + cc;
+      const int64_t o = tile ? (rr / tile) * tile * ld_out + (c / 32) * tile * 32 + (rr % tile) * 32 + c % 32
+                             : rr * ld_out + c;
+      hi[o] = h;
+      lo[o] = l;
     }
   }
 }
@@ -526,9 +529,10 @@ int64_t make_tile_order(int T, int S, bool lower, int2* out) {
 }
 
 hipError_t pack_split2(const float* in, int64_t ld_in, int64_t rows, int64_t cols, __bf16* hi, __bf16* lo,
-                       int64_t ld_out, int64_t col_off, hipStream_t s) {
+                       int64_t ld_out, int64_t col_off, hipStream_t s, int64_t tile) {
+  if (tile && (rows % tile || ld_out % 32 || col_off % 32)) return hipErrorInvalidValue;
   dim3 grid((unsigned)ceil_div(rows, 64), (unsigned)ceil_div(cols, 32));
-  hipLaunchKernelGGL(k_pack_split2, grid, dim3(256), 0, s, in, ld_in, rows, cols, hi, lo, ld_out, col_off);
+  hipLaunchKernelGGL(k_pack_split2, grid, dim3(256), 0, s, in, ld_in, rows, cols, hi, lo, ld_out, col_off, tile);
   return hipGetLastError();
 }
 

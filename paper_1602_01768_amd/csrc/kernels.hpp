@@ -107,10 +107,13 @@ hipError_t mirror_lower(float* X, int64_t ld, int64_t T, hipStream_t s);
 int64_t reduce_blocks_f32(const GemmArgs& g);
 int64_t gemm_bf16_blocks(const MixedGemm& mg);
 
-// Pack an FP32 column-major panel (rows x cols, ld_in) into bf16 hi/lo planes,
-// row-major with leading dimension ld_out, starting at column col_off.
+// Pack an FP32 column-major panel (rows x cols, ld_in) into bf16 hi/lo planes of ld_out columns,
+// starting at column col_off: row-major (tile = 0), or tile-major for the symmetric update
+// (tile rows per row tile, and within one the 32-column stages one after another, each
+// tile x 32 row-major: entry (r, c) at (r / tile) tile ld_out + (c / 32) 32 tile +
+// (r % tile) 32 + c % 32).
 hipError_t pack_split2(const float* in, int64_t ld_in, int64_t rows, int64_t cols,
-                       __bf16* hi, __bf16* lo, int64_t ld_out, int64_t col_off, hipStream_t s);
+                       __bf16* hi, __bf16* lo, int64_t ld_out, int64_t col_off, hipStream_t s, int64_t tile = 0);
 
 // ------------------------------------------------------------------ sketches
 hipError_t sketch_gauss(uint64_t seed, int64_t k, int64_t n, int32_t q, void* S, int dt, int64_t ld, hipStream_t s,
