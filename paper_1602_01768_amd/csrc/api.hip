@@ -495,8 +495,13 @@ void importance_draw(rbfgs_ctx* ctx, Slot& S, int64_t k) {
   HIPCHK(sample_partition(ctx->tw, ctx->n, ctx->q, ctx->p.seed, k, S.C, S.ht, ctx->status, L.s));
 }
 
-// Row-tile height of the tile-major bf16 panel planes of the symmetric update: its tile edge.
-int64_t sym_panel_tile(const rbfgs_ctx* ctx) { return bf16_square_tile(ctx->np, 2 * ctx->qp, EPI_SYMUPD); }
+// Row-tile height of the tile-major bf16 panel planes of the n x n update: its tile edge (the
+// symmetric update of the fixed method and PSB, or the full-square one of AdaRBFGS and the row
+// variants).
+int64_t upd_panel_tile(const rbfgs_ctx* ctx) {
+  return ctx->ada || ctx->rowv ? bf16_square_tile(ctx->np, ctx->qp, EPI_ADDROW)
+                               : bf16_square_tile(ctx->np, 2 * ctx->qp, EPI_SYMUPD);
+}
 
 // ---------------------------------------------------------------- side lanes
 // Sketch-dependent products of iteration k into slot S (side lane): the sketch, and
@@ -578,8 +583,8 @@ void side_inverse(rbfgs_ctx* ctx, Slot& S) {
     } else {
       panel_times_small(ctx, L, S.Sk, DT_BF16, S.Ginv, U, DT_F32, 1.0);
     }
-    // [U W' U] for the symmetric update (tile-major), or U for the row variants' update (row-major)
-    const int64_t ldp = 3 * qp, plane = np * ldp, tile = ctx->rowv ? 0 : sym_panel_tile(ctx);
+    // [U W' U] for the symmetric update, or U for the row variants' update
+    const int64_t ldp = 3 * qp, plane = np * ldp, tile = upd_panel_tile(ctx);
     HIPCHK(pack_split2(U, np, np, qp, S.planes, S.planes + plane, ldp, 0, L.s, tile));
     HIPCHK(pack_split2(U, np, np, qp, S.planes, S.planes + plane, ldp, 2 * qp, L.s, tile));
   } else {
@@ -671,7 +676,7 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
       } else {
         panel_times_small(ctx, L, S.U, DT_F32, ctx->H, W, DT_F32, -0.5, ctx->V, DT_F32, 1.0, S.Sk, DT_BF16, cs);
       }
-      HIPCHK(pack_split2(W, np, np, qp, S.planes, S.planes + plane, ldp, qp, L.s, sym_panel_tile(ctx)));
+      HIPCHK(pack_split2(W, np, np, qp, S.planes, S.planes + plane, ldp, qp, L.s, upd_panel_tile(ctx)));
     }
     release();
     Phase ph(ctx, L, "update", true);
@@ -680,7 +685,7 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
     g.M = np; g.N = np; g.K = 2 * qp;
     // the planes are tile-major: column qp of a row tile starts qp x tile entries into its block
     g.A = S.planes; g.lda = ldp; g.a_plane = plane;
-    g.B = S.planes + qp * sym_panel_tile(ctx); g.ldb = ldp; g.b_plane = plane;
+    g.B = S.planes + qp * upd_panel_tile(ctx); g.ldb = ldp; g.b_plane = plane;
     g.epi = EPI_SYMUPD; g.C = ctx->X; g.ldc = np; g.c2 = -1.0;
     g.tiles = ctx->tiles; g.ntiles = ctx->ntiles; g.bn = bf16_square_tile(np, g.K, g.epi);  // (the order's tiles)
     g.lower_only = ctx->lowx;
@@ -743,7 +748,8 @@ void main_row(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
     Phase ph(ctx, L, "panels");
     HIPCHK(panel_axpby(S.Sk, sk_dt(ctx), 1.0, ctx->V, mdt, -1.0, ctx->W, mdt, np, qp, np, L.s));  // R = S - C
     if (ctx->mixed)
-      HIPCHK(pack_split2((const float*)ctx->W, np, np, qp, ctx->planes, ctx->planes + np * qp, qp, 0, L.s));
+      HIPCHK(pack_split2((const float*)ctx->W, np, np, qp, ctx->planes, ctx->planes + np * qp, qp, 0, L.s,
+                         upd_panel_tile(ctx)));
   }
   Phase ph(ctx, L, "update", true);  // Z = X^T += R U^T
   if (ctx->mixed) {
@@ -828,8 +834,8 @@ void main_adaptive(rbfgs_ctx* ctx, Slot& S, int64_t k) {
     const int64_t plane = np * qp;
     __bf16* shi = ctx->planes;
     __bf16* qhi = ctx->planes + 2 * plane;
-    HIPCHK(pack_split2((const float*)ctx->Sa, np, np, qp, shi, shi + plane, qp, 0, L.s));
-    HIPCHK(pack_split2((const float*)ctx->W, np, np, qp, qhi, qhi + plane, qp, 0, L.s));
+    HIPCHK(pack_split2((const float*)ctx->Sa, np, np, qp, shi, shi + plane, qp, 0, L.s, upd_panel_tile(ctx)));
+    HIPCHK(pack_split2((const float*)ctx->W, np, np, qp, qhi, qhi + plane, qp, 0, L.s, upd_panel_tile(ctx)));
     MixedGemm mg;
     GemmArgs& g = mg.g;
     g.M = np; g.N = np; g.K = qp;

@@ -112,29 +112,22 @@ void k_symupd_dma(GemmArgs g) {
   // across the wave (a scalar base), and the lane adds row lane / CHUNKS and its
   // swizzled chunk -- the same for every d, as each load covers a multiple of the
   // swizzle period of rows (a 32-bit vector offset per operand).
-  // The symmetric update's panels are stored tile-major (pack_split2 with tile = BM): a stage
-  // of a row tile is BM x 32 contiguous, so each load reads 1 KB of whole 128-byte lines, and
-  // the stage of k0 starts k0 BM entries into the row tile's block; the full-square update's
-  // panels are row-major.
+  // The panels are stored tile-major (pack_split2 with tile = BM): a stage of a row tile is
+  // BM x 32 contiguous, so each load reads 1 KB of whole 128-byte lines (row-major panels give
+  // each load 16 half lines, the other halves read again by the next stage), and the stage of
+  // k0 starts k0 BM entries into the row tile's block of BM x ld entries.
   static_assert((1024 / ROWB) % (RPB * CHUNKS) == 0, "a load covers whole swizzle periods");
-  static_assert(FULL || BKS == 32, "tile-major panels have 32-column stages");
-  constexpr bool TILED = !FULL;
+  static_assert(BKS == 32, "tile-major panels have 32-column stages");
   const int rl = lane / CHUNKS, cs = (lane % CHUNKS) ^ ((rl / RPB) % CHUNKS);
-  const uint32_t voff[2] = {(uint32_t)(rl * (TILED ? BKS : g.lda) + cs * 8),
-                            (uint32_t)(rl * (TILED ? BKS : g.ldb) + cs * 8)};
+  const uint32_t voff = (uint32_t)(rl * BKS + cs * 8);
   const __bf16* ubase[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     const int j = (wave * D + d) * 1024;
     const int o = j / OPB, p = (j % OPB) / PLB, r = (j % PLB) / ROWB;
-    if constexpr (TILED)
-      ubase[d] = o == 0 ? (const __bf16*)g.A + p * g.a_plane + m0 * g.lda + r * BKS
-                        : (const __bf16*)g.B + p * g.b_plane + n0 * g.ldb + r * BKS;
-    else
-      ubase[d] = o == 0 ? (const __bf16*)g.A + p * g.a_plane + (m0 + r) * g.lda
-                        : (const __bf16*)g.B + p * g.b_plane + (n0 + r) * g.ldb;
+    ubase[d] = o == 0 ? (const __bf16*)g.A + p * g.a_plane + m0 * g.lda + r * BKS
+                      : (const __bf16*)g.B + p * g.b_plane + n0 * g.ldb + r * BKS;
   }
-  const int64_t kmul = TILED ? BM : 1;  // entries per column step of k
   auto stage = [&](auto I) -> char* {
     constexpr int i = decltype(I)::value;
     if constexpr (i == 0) return st0;
@@ -146,7 +139,7 @@ void k_symupd_dma(GemmArgs g) {
     char* dst = stage(I);
 #pragma unroll
     for (int d = 0; d < D; ++d)
-      __builtin_amdgcn_global_load_lds((const void*)(ubase[d] + k0 * kmul + voff[((wave * D + d) * 1024) / OPB]),
+      __builtin_amdgcn_global_load_lds((const void*)(ubase[d] + k0 * BM + voff),
                                        (lds_void*)(dst + (wave * D + d) * 1024), 16, 0, 0);
   };
 
