@@ -412,15 +412,16 @@ void nn_times_panel(rbfgs_ctx* ctx, const Lane& L, const void* M, bool transpose
     mg.b_kind = p_dt == DT_BF16 ? OK_BF16_KC : OK_F32_KC;
     mg.na = na; mg.nb = p_dt == DT_BF16 ? 1 : nb; mg.pmax = pmax;
     // streamed product: an FP32 panel is split into bf16 planes once, here, instead of in
-    // every row tile of the product
-    if (L.bsplit && p_dt != DT_BF16) {
+    // every row tile of the product (a bf16 panel is copied), the planes tile-major so that
+    // each 32-deep k tile of the panel is one contiguous block
+    if (L.bsplit) {
       MixedGemm sm = mg;
       if (lower) sm.a_kind = OK_F32_SYM;
       sm.b_kind = OK_BF16_KC;
-      sm.g.B = L.bsplit; sm.g.b_plane = ctx->np * ctx->qp;
+      sm.g.B = L.bsplit; sm.g.ldb = ctx->qp; sm.g.b_plane = ctx->np * ctx->qp; sm.g.b_tiled = true;
       sm.g.splitk = bf_split(ctx, L, sm);
       if (tall_stream_supported(sm)) {
-        HIPCHK(split_planes((const float*)P, ctx->np * ctx->qp, nb, L.bsplit, L.s));
+        HIPCHK(split_planes(P, ctx->np, ctx->qp, ctx->np, sm.nb, L.bsplit, L.s));
         mg = sm;
       }
     }

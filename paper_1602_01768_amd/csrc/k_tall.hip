@@ -14,7 +14,8 @@
 // transposed from the lower tiles right of it, each k loop running without a choice per tile.
 // The B tile (all q columns, or 256 of them) is shared by the 8 waves and travels from memory
 // straight into LDS (global_load_lds_dwordx4) through a ring of three stages, one barrier per
-// 32-deep k tile.  The k order inside a tile is permuted to match the registers a lane holds
+// 32-deep k tile; B's planes are tile-major (split_planes), so a stage is one contiguous
+// block and every load reads 1 KB of whole 128-byte lines.  The k order inside a tile is permuted to match the registers a lane holds
 // (lane l loads k = 16 (l / 32) .. + 15 of its row; sub-step s feeds the MFMA with
 // k = 16 (l / 32) + 8 s .. + 7), and B is read from LDS with the same permutation.
 //
@@ -140,16 +141,18 @@ __global__ __launch_bounds__(512, 1) void k_tall_stream(GemmArgs g) {
     };
 
     // B: load d of this wave covers stage bytes (wave * D + d) * 1024 + 16 * lane: piece and
-    // first row uniform, the lane adding row lane / CHUNKS and its swizzled chunk
+    // first row uniform, the lane adding row lane / CHUNKS and its swizzled chunk.  In the
+    // tile-major planes column n of the k tile at k0 starts at k0 ldb + 32 n.
     static_assert((1024 / ROWB) % (RPB * CHUNKS) == 0, "a load covers whole swizzle periods");
+    static_assert(TL_BK == 32, "tile-major planes have 32-deep k tiles");
     const int rl = lane / CHUNKS, cs = (lane % CHUNKS) ^ ((rl / RPB) % CHUNKS);
-    const uint32_t voff = (uint32_t)(rl * g.ldb + cs * 8);
+    const uint32_t voff = (uint32_t)(rl * TL_BK + cs * 8);
     const __bf16* bbase[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int j = (wave * D + d) * 1024;
       const int p = j / PLB, r = (j % PLB) / ROWB;
-      bbase[d] = (const __bf16*)g.B + p * g.b_plane + (n0 + r) * g.ldb + kbeg;
+      bbase[d] = (const __bf16*)g.B + p * g.b_plane + (n0 + r) * TL_BK + kbeg * g.ldb;
     }
     auto stage = [&](auto I) -> char* {
       constexpr int i = decltype(I)::value;
@@ -161,7 +164,7 @@ __global__ __launch_bounds__(512, 1) void k_tall_stream(GemmArgs g) {
       char* dst = stage(I);
 #pragma unroll
       for (int d = 0; d < D; ++d)
-        __builtin_amdgcn_global_load_lds((const void*)(bbase[d] + koff(t) + voff),
+        __builtin_amdgcn_global_load_lds((const void*)(bbase[d] + koff(t) * g.ldb + voff),
                                          (lds_void*)(dst + (wave * D + d) * 1024), 16, 0, 0);
     };
 
@@ -323,23 +326,31 @@ __global__ __launch_bounds__(512, 1) void k_tall_stream(GemmArgs g) {
   }
 }
 
-// bf16 planes of an FP32 array: out[p * count + i] = piece p of in[i]
+// Tile-major bf16 planes of a column-major panel: piece p of in[j * ldi + i] to
+// out[p * rows * cols + (i / 32) * 32 cols + j * 32 + i % 32] (NP = 1: a bf16 panel copied)
 template <int NP>
-__global__ __launch_bounds__(256) void k_split_planes(const float* __restrict__ in, int64_t count,
-                                                      __bf16* __restrict__ out) {
-  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
-  if (i >= count) return;
-  const f32x4 v = *(const f32x4*)(in + i);
+__global__ __launch_bounds__(256) void k_split_planes(const void* __restrict__ in, int64_t rows, int64_t cols,
+                                                      int64_t ldi, __bf16* __restrict__ out) {
+  const int64_t i = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4, j = blockIdx.y;
+  if (i >= rows) return;
   __bf16 pc[4][NP];
+  if constexpr (NP == 1) {
+    const bf16x4 v = *(const bf16x4*)((const __bf16*)in + j * ldi + i);
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    if constexpr (NP == 2) split2(v[e], pc[e][0], pc[e][1]);
-    else split3(v[e], pc[e][0], pc[e][1], pc[e][2]);
+    for (int e = 0; e < 4; ++e) pc[e][0] = v[e];
+  } else {
+    const f32x4 v = *(const f32x4*)((const float*)in + j * ldi + i);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if constexpr (NP == 2) split2(v[e], pc[e][0], pc[e][1]);
+      else split3(v[e], pc[e][0], pc[e][1], pc[e][2]);
+    }
   }
+  const int64_t o = (i / 32) * 32 * cols + j * 32 + i % 32;
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     bf16x4 w = {pc[0][p], pc[1][p], pc[2][p], pc[3][p]};
-    *(bf16x4*)(out + p * count + i) = w;
+    *(bf16x4*)(out + p * rows * cols + o) = w;
   }
 }
 
@@ -361,7 +372,8 @@ bool tall_stream_supported(const MixedGemm& mg) {
                      (sym && mg.na == 2 && mg.nb == 2 && mg.pmax == 1 && g.M == g.K && g.M % 128 == 0);
   return combo && mg.b_kind == OK_BF16_KC && g.epi == EPI_COLSTORE && g.N % 128 == 0 &&
          g.M % 32 == 0 && g.M >= 1024 && g.splitk >= 1 && g.splitk <= 8 && 8 % g.splitk == 0 &&
-         g.K % ((int64_t)TL_BK * g.splitk) == 0 && g.lda % 4 == 0 && g.ldb % 8 == 0 && g.b_plane % 8 == 0;
+         g.K % ((int64_t)TL_BK * g.splitk) == 0 && g.lda % 4 == 0 && g.b_tiled && g.ldb >= g.N &&
+         g.b_plane % 8 == 0;
 }
 
 hipError_t tall_stream(const GemmArgs& run, const MixedGemm& mg, hipStream_t s) {
@@ -380,11 +392,12 @@ hipError_t tall_stream(const GemmArgs& run, const MixedGemm& mg, hipStream_t s) 
   return hipErrorInvalidValue;
 }
 
-hipError_t split_planes(const float* in, int64_t count, int np, __bf16* out, hipStream_t s) {
-  if (count % 4 || (np != 2 && np != 3)) return hipErrorInvalidValue;
-  const unsigned blocks = (unsigned)((count / 4 + 255) / 256);
-  if (np == 2) hipLaunchKernelGGL(k_split_planes<2>, dim3(blocks), dim3(256), 0, s, in, count, out);
-  else hipLaunchKernelGGL(k_split_planes<3>, dim3(blocks), dim3(256), 0, s, in, count, out);
+hipError_t split_planes(const void* in, int64_t rows, int64_t cols, int64_t ldi, int np, __bf16* out, hipStream_t s) {
+  if (rows % 32 || ldi % 4 || rows > ldi || cols < 1 || cols > 65535 || np < 1 || np > 3) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((rows / 4 + 255) / 256), (unsigned)cols);
+  if (np == 1) hipLaunchKernelGGL(k_split_planes<1>, grid, dim3(256), 0, s, in, rows, cols, ldi, out);
+  else if (np == 2) hipLaunchKernelGGL(k_split_planes<2>, grid, dim3(256), 0, s, in, rows, cols, ldi, out);
+  else hipLaunchKernelGGL(k_split_planes<3>, grid, dim3(256), 0, s, in, rows, cols, ldi, out);
   return hipGetLastError();
 }
 

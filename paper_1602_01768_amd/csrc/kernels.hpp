@@ -55,6 +55,9 @@ struct GemmArgs {
   int bn = 0;
   // bf16 symmetric update (EPI_SYMUPD): write the lower tiles only, no mirrored copies
   bool lower_only = false;
+  // streamed product: the bf16 planes of B are tile-major (see split_planes; ldb = the number
+  // of columns of B the planes hold)
+  bool b_tiled = false;
 };
 
 // Tile order for an n x n product of T x T tiles: super-tiles of S x S tiles in row-major
@@ -90,8 +93,11 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s);
 // dividing 8.  gemm_bf16 takes it for every product it supports.
 bool tall_stream_supported(const MixedGemm& mg);
 hipError_t tall_stream(const GemmArgs& run, const MixedGemm& mg, hipStream_t s);
-// out[p * count + i] = bf16 piece p of in[i], np = 2 or 3 pieces (count a multiple of 4)
-hipError_t split_planes(const float* in, int64_t count, int np, __bf16* out, hipStream_t s);
+// bf16 planes of a column-major n x q panel (leading dimension ldi), tile-major for the streamed
+// product: bf16 piece p of in[j * ldi + i] goes to out[p * rows * cols + (i / 32) * 32 cols +
+// j * 32 + i % 32], so that the 32-deep k tile of every column is one contiguous block.  np = 1
+// copies a bf16 panel, 2 or 3 split an FP32 one (rows a multiple of 32).
+hipError_t split_planes(const void* in, int64_t rows, int64_t cols, int64_t ldi, int np, __bf16* out, hipStream_t s);
 // Tile edge of the bf16 square products (EPI_SYMUPD / EPI_ADDROW) for order M and depth K.
 int bf16_square_tile(int64_t M, int64_t K, int epi);
 // Sum the FP32 split-K partials of a bf16 product (COLSTORE epilogue of g): C = c2 * sum
