@@ -378,27 +378,39 @@ __global__ __launch_bounds__(256) void k_reduce_partials_f32(GemmArgs g, const f
 }
 
 // Column-major FP32 panel -> row-major bf16 hi/lo planes, through a 32 x 64 LDS tile.
-__global__ void k_pack_split2(const float* in, int64_t ld_in, int64_t rows, int64_t cols, __bf16* hi, __bf16* lo,
-                              int64_t ld_out, int64_t col_off, int64_t tile) {
-  __shared__ float t[32][65];
-  const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 32;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 256 threads: 64 x 4
-  for (int c = ty; c < 32; c += 4) {
-    const int64_t r = r0 + tx, cc = c0 + c;
-    t[c][tx] = (r < rows && cc < cols) ? in[r + cc * ld_in] : 0.0f;
+// 64 rows x 32 columns per block: wave w takes columns c0 + 8 w .. + 7 (one 16-byte store per
+// plane and row), lane l row r0 + l (the loads of one column coalesced across the wave)
+__global__ __launch_bounds__(256) void k_pack_split2(const float* __restrict__ in, int64_t ld_in, int64_t rows,
+                                                     int64_t cols, __bf16* __restrict__ hi, __bf16* __restrict__ lo,
+                                                     int64_t ld_out, int64_t col_off, int tile_log2) {
+  const int64_t r = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int64_t c0 = (int64_t)blockIdx.y * 32 + 8 * (threadIdx.x >> 6);
+  if (r >= rows || c0 >= cols) return;
+  const int m = cols - c0 < 8 ? (int)(cols - c0) : 8;
+  bf16x8 h, l;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float v = e < m ? in[r + (c0 + e) * ld_in] : 0.0f;
+    __bf16 he, le;
+    split2(v, he, le);
+    h[e] = he;
+    l[e] = le;
   }
-  __syncthreads();
-  const int cx = threadIdx.x & 31, ry = threadIdx.x >> 5;  // 32 x 8
-  for (int r = ry; r < 64; r += 8) {
-    const int64_t rr = r0 + r, cc = c0 + cx;
-    if (rr < rows && cc < cols) {
-      __bf16 h, l;
-      split2(t[cx][r], h, l);
-      const int64_t c = col_off + cc;
-      const int64_t o = tile ? (rr / tile) * tile * ld_out + (c / 32) * tile * 32 + (rr % tile) * 32 + c % 32
-                             : rr * ld_out + c;
-      hi[o] = h;
-      lo[o] = l;
+  const int64_t c = col_off + c0;
+  int64_t o;
+  if (tile_log2 >= 0) {
+    const int64_t tile = (int64_t)1 << tile_log2;
+    o = (r >> tile_log2) * tile * ld_out + (c >> 5) * tile * 32 + (r & (tile - 1)) * 32 + (c & 31);
+  } else {
+    o = r * ld_out + c;
+  }
+  if (m == 8 && o % 8 == 0) {
+    *(bf16x8*)(hi + o) = h;
+    *(bf16x8*)(lo + o) = l;
+  } else {
+    for (int e = 0; e < m; ++e) {
+      hi[o + e] = h[e];
+      lo[o + e] = l[e];
     }
   }
 }
@@ -530,9 +542,12 @@ int64_t make_tile_order(int T, int S, bool lower, int2* out) {
 
 hipError_t pack_split2(const float* in, int64_t ld_in, int64_t rows, int64_t cols, __bf16* hi, __bf16* lo,
                        int64_t ld_out, int64_t col_off, hipStream_t s, int64_t tile) {
-  if (tile && (rows % tile || ld_out % 32 || col_off % 32)) return hipErrorInvalidValue;
+  // tile-major: a power-of-two tile, whole tiles, 32-column stages (a thread's 8 columns then
+  // stay in one stage)
+  if (tile && (tile & (tile - 1) || rows % tile || ld_out % 32 || col_off % 32)) return hipErrorInvalidValue;
+  const int tile_log2 = tile ? __builtin_ctzll((unsigned long long)tile) : -1;
   dim3 grid((unsigned)ceil_div(rows, 64), (unsigned)ceil_div(cols, 32));
-  hipLaunchKernelGGL(k_pack_split2, grid, dim3(256), 0, s, in, ld_in, rows, cols, hi, lo, ld_out, col_off, tile);
+  hipLaunchKernelGGL(k_pack_split2, grid, dim3(256), 0, s, in, ld_in, rows, cols, hi, lo, ld_out, col_off, tile_log2);
   return hipGetLastError();
 }
 
