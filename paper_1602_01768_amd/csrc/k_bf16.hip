@@ -449,9 +449,10 @@ int pick_bn_auto(int64_t N) {
 }  // namespace
 
 // The symmetric update with wide panels (K = 2q >= 256, where the panel loads dominate) takes
-// 256 x 256 tiles where there are still at least 1024 of them (four per CU; n = 16384, q = 256:
-// 0.653 -> 0.643 ms, fixed step 1.587 -> 1.555 ms); the full-square update of AdaRBFGS stays on
-// 128 x 128 tiles (256: 0.642 -> 0.686 ms at the same size).
+// 256 x 256 tiles where there are still at least 1024 of them (four per CU): half the panel
+// bytes per entry of X (n = 32768, q = 512: 4.94 -> 4.63 ms with row-major panels; at n = 16384,
+// q = 256 the fixed step is the same with either size since the panels are tile-major); the
+// full-square update of AdaRBFGS stays on 128 x 128 tiles (256: 0.57 -> 0.64 ms at n = 16384).
 int bf16_square_tile(int64_t M, int64_t K, int epi) {
   if (M % 256 || K < 256 || epi != EPI_SYMUPD) return 128;
   const int64_t T = M / 256;

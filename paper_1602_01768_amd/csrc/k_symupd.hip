@@ -1,11 +1,12 @@
 // Square updates on bf16 matrix cores.  Symmetric rank-2q update of the fixed-sketch
-// step: X += c2 * [U W'] [W' U]^T on the lower 128 x 128 tiles of X, each tile also
-// written to its mirrored position (the symmetric form of the update, eq. (qunac)) --
-// or, when X is held on its lower tiles only, written there alone (diagonal tiles whole);
-// FULL: C += c2 * A B^T on every tile (the rank-q updates of AdaRBFGS, eq. (Cholimprov),
-// and of the row variants of Alg. 1).
+// step: X += c2 * [U W'] [W' U]^T on the lower BM x BM tiles of X (BM = 128 or 256), each
+// tile also written to its mirrored position (the symmetric form of the update, eq. (qunac))
+// -- or, when X is held on its lower 128 x 128 tiles only, written there alone (diagonal
+// tiles whole); FULL: C += c2 * A B^T on every tile (the rank-q updates of AdaRBFGS,
+// eq. (Cholimprov), and of the row variants of Alg. 1).
 //
-// Both operands are pre-split into two bf16 pieces (hi, lo); the product keeps the
+// Both operands are pre-split into two bf16 pieces (hi, lo), stored tile-major (each
+// 32-column stage of a row tile contiguous, see pack_split2); the product keeps the
 // piece products hi*hi + hi*lo + lo*hi with FP32 accumulation.  Unlike the general
 // mixed GEMM, the operand tiles travel from memory straight into LDS
 // (global_load_lds_dwordx4, 16 bytes per lane), so no registers stage them and no

@@ -32,7 +32,6 @@ typedef __attribute__((address_space(3))) void lds_void;
 
 constexpr int TL_BM = 256;  // rows per workgroup (8 waves x 32)
 constexpr int TL_BK = 32;   // k per tile
-constexpr int TL_NS = 3;    // B stages in LDS, A tiles in registers
 
 // s_waitcnt immediate for "at most n vector-memory operations outstanding" (vmcnt in bits
 // 3:0 and 15:14, expcnt and lgkmcnt at their maxima) and for "no LDS operation outstanding"
