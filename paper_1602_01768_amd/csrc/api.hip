@@ -114,6 +114,10 @@ struct rbfgs_ctx {
   // diagonal transposed).  x_lower: the upper tiles are stale, and are copied from the lower
   // ones before anything reads X whole (residual, rbfgs_get_x, PCG)
   bool lowx = false, x_lower = false;
+  // mixed symmetric update (fixed RBFGS, PSB) with q > n / 8: U and W' in three bf16 pieces (a
+  // CPU emulation of the step on the ridge Hessian, n = 1024, q = 256, 40 steps: 1.16e-4 against
+  // the oracle with two pieces, 6.9e-5 with three; n = 2048, q = 256: 2.4e-5 with two)
+  bool upd3 = false;
   // partition sampling (fixed RBFGS, AdaRBFGS): the coordinate block C_i = [iq, (i+1)q) is
   // drawn with p_i proportional to Tr(S_i^T A S_i) (eq. ihsih0); tw holds the per-coordinate
   // weights, A_jj for the fixed method and (L^T A L)_jj for AdaRBFGS (updated every step)
@@ -584,10 +588,13 @@ void side_inverse(rbfgs_ctx* ctx, Slot& S) {
     } else {
       panel_times_small(ctx, L, S.Sk, DT_BF16, S.Ginv, U, DT_F32, 1.0);
     }
-    // [U W' U] for the symmetric update, or U for the row variants' update
+    // [U W' U] for the symmetric update, or U for the row variants' update; pieces hi, lo or
+    // hi, mid, lo in planes 0, 1(, 2)
     const int64_t ldp = 3 * qp, plane = np * ldp, tile = upd_panel_tile(ctx);
-    HIPCHK(pack_split2(U, np, np, qp, S.planes, S.planes + plane, ldp, 0, L.s, tile));
-    HIPCHK(pack_split2(U, np, np, qp, S.planes, S.planes + plane, ldp, 2 * qp, L.s, tile));
+    __bf16* lo = S.planes + (ctx->upd3 ? 2 : 1) * plane;
+    __bf16* mid = ctx->upd3 ? S.planes + plane : nullptr;
+    HIPCHK(pack_split2(U, np, np, qp, S.planes, lo, ldp, 0, L.s, tile, mid));
+    HIPCHK(pack_split2(U, np, np, qp, S.planes, lo, ldp, 2 * qp, L.s, tile, mid));
   } else {
     double* U = (double*)S.U;
     if (ctx->psb || ctx->kacz) panel_times_small(ctx, L, S.Y, DT_F64, S.Ginv, U, DT_F64, 1.0);  // U = Y G^-1
@@ -677,7 +684,8 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
       } else {
         panel_times_small(ctx, L, S.U, DT_F32, ctx->H, W, DT_F32, -0.5, ctx->V, DT_F32, 1.0, S.Sk, DT_BF16, cs);
       }
-      HIPCHK(pack_split2(W, np, np, qp, S.planes, S.planes + plane, ldp, qp, L.s, upd_panel_tile(ctx)));
+      HIPCHK(pack_split2(W, np, np, qp, S.planes, S.planes + (ctx->upd3 ? 2 : 1) * plane, ldp, qp, L.s,
+                         upd_panel_tile(ctx), ctx->upd3 ? S.planes + plane : nullptr));
     }
     release();
     Phase ph(ctx, L, "update", true);
@@ -691,6 +699,10 @@ void main_fixed(rbfgs_ctx* ctx, Slot& S, G&& after_xy, F&& ahead) {
     g.tiles = ctx->tiles; g.ntiles = ctx->ntiles; g.bn = bf16_square_tile(np, g.K, g.epi);  // (the order's tiles)
     g.lower_only = ctx->lowx;
     mg.a_kind = OK_BF16_KC; mg.b_kind = OK_BF16_KC; mg.na = 2; mg.nb = 2; mg.pmax = 1;
+    if (ctx->upd3) {
+      mg.na = 3; mg.nb = 3; mg.pmax = 2;
+      g.upd_pieces = 3;
+    }
     bf_gemm(ctx, L, mg);
     ctx->x_lower = ctx->lowx;
   } else {
@@ -1135,7 +1147,7 @@ void make_slot(rbfgs_ctx* ctx, Slot& S) {
     if (ctx->bf16q) S.Ginv32 = (float*)dalloc(ctx, (size_t)qp * qp * sizeof(float));
     if (!ctx->coord) {
       S.U = dalloc(ctx, (ctx->mixed ? 1 : 3) * np * qp * es);
-      if (ctx->mixed) S.planes = (__bf16*)dalloc(ctx, (size_t)2 * 3 * np * qp * sizeof(__bf16));
+      if (ctx->mixed) S.planes = (__bf16*)dalloc(ctx, (size_t)(ctx->upd3 ? 3 : 2) * 3 * np * qp * sizeof(__bf16));
     }
   }
   if (ctx->dry) return;
@@ -1199,6 +1211,7 @@ void set_params(rbfgs_ctx* ctx, const rbfgs_params& p) {
   ctx->bf16h = ctx->bf16q && 8 * ctx->qp <= ctx->np;
   ctx->lowx = ctx->mixed && p.variant == RBFGS_FIXED && p.sketch == RBFGS_SKETCH_GAUSS && ctx->qp % 128 == 0 &&
               ctx->np >= 1024;
+  ctx->upd3 = ctx->mixed && (p.variant == RBFGS_FIXED || ctx->psb) && !ctx->coord && 8 * ctx->qp > ctx->np;
 }
 
 // Every device buffer of the context (accounted only, in a dry run).

@@ -379,21 +379,29 @@ __global__ __launch_bounds__(256) void k_reduce_partials_f32(GemmArgs g, const f
 
 // Column-major FP32 panel -> row-major bf16 hi/lo planes, through a 32 x 64 LDS tile.
 // 64 rows x 32 columns per block: wave w takes columns c0 + 8 w .. + 7 (one 16-byte store per
-// plane and row), lane l row r0 + l (the loads of one column coalesced across the wave)
+// plane and row), lane l row r0 + l (the loads of one column coalesced across the wave); with
+// mid, three pieces (hi, mid, lo)
 __global__ __launch_bounds__(256) void k_pack_split2(const float* __restrict__ in, int64_t ld_in, int64_t rows,
                                                      int64_t cols, __bf16* __restrict__ hi, __bf16* __restrict__ lo,
-                                                     int64_t ld_out, int64_t col_off, int tile_log2) {
+                                                     int64_t ld_out, int64_t col_off, int tile_log2,
+                                                     __bf16* __restrict__ mid) {
   const int64_t r = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
   const int64_t c0 = (int64_t)blockIdx.y * 32 + 8 * (threadIdx.x >> 6);
   if (r >= rows || c0 >= cols) return;
   const int m = cols - c0 < 8 ? (int)(cols - c0) : 8;
-  bf16x8 h, l;
+  bf16x8 h, md, l;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
     const float v = e < m ? in[r + (c0 + e) * ld_in] : 0.0f;
-    __bf16 he, le;
-    split2(v, he, le);
+    __bf16 he, me, le;
+    if (mid) {
+      split3(v, he, me, le);
+    } else {
+      split2(v, he, le);
+      me = he;
+    }
     h[e] = he;
+    md[e] = me;
     l[e] = le;
   }
   const int64_t c = col_off + c0;
@@ -407,10 +415,12 @@ __global__ __launch_bounds__(256) void k_pack_split2(const float* __restrict__ i
   if (m == 8 && o % 8 == 0) {
     *(bf16x8*)(hi + o) = h;
     *(bf16x8*)(lo + o) = l;
+    if (mid) *(bf16x8*)(mid + o) = md;
   } else {
     for (int e = 0; e < m; ++e) {
       hi[o + e] = h[e];
       lo[o + e] = l[e];
+      if (mid) mid[o + e] = md[e];
     }
   }
 }
@@ -478,8 +488,10 @@ hipError_t gemm_bf16(const MixedGemm& mg, void* partial_ws, hipStream_t s) {
   if (g.M % 128 || g.N % 32 || g.splitk < 1) return hipErrorInvalidValue;
   if (g.epi == EPI_SYMUPD || g.epi == EPI_ADDROW) {
     // square updates: operands pre-split into 2 bf16 planes, loaded straight into LDS
-    if (g.N % 128 || g.K % 32 || mg.a_kind != OK_BF16_KC || mg.b_kind != OK_BF16_KC || mg.na != 2 || mg.nb != 2 ||
-        mg.pmax != 1 || g.splitk != 1)
+    const bool two = mg.na == 2 && mg.nb == 2 && mg.pmax == 1 && g.upd_pieces == 2;
+    const bool three = mg.na == 3 && mg.nb == 3 && mg.pmax == 2 && g.upd_pieces == 3;
+    if (g.N % 128 || g.K % 32 || mg.a_kind != OK_BF16_KC || mg.b_kind != OK_BF16_KC || !(two || three) ||
+        g.splitk != 1)
       return hipErrorInvalidValue;
     return symupd_bf16_dma(g, gemm_bf16_blocks(mg), s);
   }
@@ -542,13 +554,14 @@ int64_t make_tile_order(int T, int S, bool lower, int2* out) {
 }
 
 hipError_t pack_split2(const float* in, int64_t ld_in, int64_t rows, int64_t cols, __bf16* hi, __bf16* lo,
-                       int64_t ld_out, int64_t col_off, hipStream_t s, int64_t tile) {
+                       int64_t ld_out, int64_t col_off, hipStream_t s, int64_t tile, __bf16* mid) {
   // tile-major: a power-of-two tile, whole tiles, 32-column stages (a thread's 8 columns then
   // stay in one stage)
   if (tile && (tile & (tile - 1) || rows % tile || ld_out % 32 || col_off % 32)) return hipErrorInvalidValue;
   const int tile_log2 = tile ? __builtin_ctzll((unsigned long long)tile) : -1;
   dim3 grid((unsigned)ceil_div(rows, 64), (unsigned)ceil_div(cols, 32));
-  hipLaunchKernelGGL(k_pack_split2, grid, dim3(256), 0, s, in, ld_in, rows, cols, hi, lo, ld_out, col_off, tile_log2);
+  hipLaunchKernelGGL(k_pack_split2, grid, dim3(256), 0, s, in, ld_in, rows, cols, hi, lo, ld_out, col_off, tile_log2,
+                     mid);
   return hipGetLastError();
 }
 

@@ -66,10 +66,14 @@ constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) |
 // ... and for "no LDS operation outstanding" (lgkmcnt 0, vmcnt and expcnt at their maxima)
 constexpr int lgkm0_imm() { return 15 | (3 << 14) | (7 << 4); }
 
-template <int BM, int BKS, int NS, int OCC, int WAVES_M, int WAVES_N, bool FULL, int NTX, bool MIRROR = true>
+// NP: bf16 pieces per operand, 2 (products hi*hi, hi*lo, lo*hi) or 3 (the six products of total
+// weight >= 2^-16, every FP32 entry represented exactly)
+template <int BM, int BKS, int NS, int OCC, int WAVES_M, int WAVES_N, bool FULL, int NTX, bool MIRROR = true,
+          int NP = 2>
 __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) __attribute__((amdgpu_waves_per_eu(OCC * WAVES_M * WAVES_N / 4, 8)))
 void k_symupd_dma(GemmArgs g) {
-  constexpr int NP = 2, NW = WAVES_M * WAVES_N;
+  constexpr int NW = WAVES_M * WAVES_N;
+  static_assert(NP == 2 || NP == 3, "pieces");
   constexpr int WM = BM / WAVES_M, WN = BM / WAVES_N, FM = WM / 32, FN = WN / 32;
   constexpr int ROWB = BKS * 2;                 // bytes of one row of one piece
   constexpr int CHUNKS = ROWB / 16;             // 16-byte chunks per row
@@ -173,14 +177,19 @@ void k_symupd_dma(GemmArgs g) {
           const int r = rb + b * 32;
           bv[p][b] = *(const bf16x8*)(S + OPB + p * PLB + r * ROWB + ((c ^ ((r / RPB) % CHUNKS)) * 16));
         }
-      // piece products smallest first: hi*lo, lo*hi, then hi*hi
+      // piece products smallest first (pa + pb = NP - 1 down to 0)
 #pragma unroll
-      for (int pp = 0; pp < 3; ++pp)
+      for (int lvl = NP - 1; lvl >= 0; --lvl)
 #pragma unroll
-        for (int a = 0; a < FM; ++a)
+        for (int pa = 0; pa < NP; ++pa) {
+          const int pb = lvl - pa;
+          if (pb < 0 || pb >= NP) continue;
 #pragma unroll
-          for (int b = 0; b < FN; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[pp == 1 ? 1 : 0][a], bv[pp == 0 ? 1 : 0][b], acc[a][b], 0, 0, 0);
+          for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b)
+              acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[pa][a], bv[pb][b], acc[a][b], 0, 0, 0);
+        }
     }
   };
 
@@ -310,14 +319,33 @@ hipError_t launch_symupd(const GemmArgs& g, int64_t blocks, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Symmetric update with 3 pieces per operand (128 x 128 tiles; two 48 KB stages, one workgroup
+// of 2 x 2 waves per CU)
+hipError_t launch_symupd3(const GemmArgs& g, int64_t blocks, hipStream_t s) {
+  const dim3 grid((unsigned)blocks), block(256);
+  const bool nt = g.K / 2 >= UPD_NT_MINQ;
+  if (g.lower_only && nt)
+    hipLaunchKernelGGL((k_symupd_dma<128, UPD_BKS, UPD_NS, 1, 2, 2, false, 1, false, 3>), grid, block, 0, s, g);
+  else if (g.lower_only)
+    hipLaunchKernelGGL((k_symupd_dma<128, UPD_BKS, UPD_NS, 1, 2, 2, false, 0, false, 3>), grid, block, 0, s, g);
+  else if (nt)
+    hipLaunchKernelGGL((k_symupd_dma<128, UPD_BKS, UPD_NS, 1, 2, 2, false, 1, true, 3>), grid, block, 0, s, g);
+  else
+    hipLaunchKernelGGL((k_symupd_dma<128, UPD_BKS, UPD_NS, 1, 2, 2, false, 0, true, 3>), grid, block, 0, s, g);
+  return hipGetLastError();
+}
+
 }  // namespace
 
-// g.bn: the tile edge (256, or 128 for any other value), as bf16_square_tile gives it
+// g.bn: the tile edge (256, or 128 for any other value), as bf16_square_tile gives it;
+// g.upd_pieces: 2, or 3 (symmetric update on 128 x 128 tiles only)
 hipError_t symupd_bf16_dma(const GemmArgs& g, int64_t blocks, hipStream_t s) {
   const int bm = g.bn == 256 ? 256 : 128;
   if (g.K % UPD_BKS || g.M % bm || g.M != g.N || g.lda % 8 || g.ldb % 8 || g.a_plane % 8 || g.b_plane % 8 ||
-      g.ldc % 4)
+      g.ldc % 4 || (g.upd_pieces != 2 && g.upd_pieces != 3) ||
+      (g.upd_pieces == 3 && (bm != 128 || g.epi != EPI_SYMUPD)))
     return hipErrorInvalidValue;
+  if (g.upd_pieces == 3) return launch_symupd3(g, blocks, s);
   if (bm == 256) return launch_symupd<256, 1, 2, 4>(g, blocks, s);
   return launch_symupd<128, 2, 2, 2>(g, blocks, s);
 }

@@ -58,6 +58,8 @@ struct GemmArgs {
   // streamed product: the bf16 planes of B are tile-major (see split_planes; ldb = the number
   // of columns of B the planes hold)
   bool b_tiled = false;
+  // bf16 square update: bf16 pieces per operand (2, or 3 for the symmetric update)
+  int upd_pieces = 2;
 };
 
 // Tile order for an n x n product of T x T tiles: super-tiles of S x S tiles in row-major
@@ -117,9 +119,10 @@ int64_t gemm_bf16_blocks(const MixedGemm& mg);
 // starting at column col_off: row-major (tile = 0), or tile-major for the symmetric update
 // (tile rows per row tile, and within one the 32-column stages one after another, each
 // tile x 32 row-major: entry (r, c) at (r / tile) tile ld_out + (c / 32) 32 tile +
-// (r % tile) 32 + c % 32).
+// (r % tile) 32 + c % 32).  With mid given, three pieces: hi, mid and lo.
 hipError_t pack_split2(const float* in, int64_t ld_in, int64_t rows, int64_t cols,
-                       __bf16* hi, __bf16* lo, int64_t ld_out, int64_t col_off, hipStream_t s, int64_t tile = 0);
+                       __bf16* hi, __bf16* lo, int64_t ld_out, int64_t col_off, hipStream_t s, int64_t tile = 0,
+                       __bf16* mid = nullptr);
 
 // ------------------------------------------------------------------ sketches
 hipError_t sketch_gauss(uint64_t seed, int64_t k, int64_t n, int32_t q, void* S, int dt, int64_t ld, hipStream_t s,
