@@ -87,11 +87,11 @@ def phase_roofline(name, n, q, variant, sketch, precision="mixed"):
 PHASE_KERNEL = {
     "XY": "k_tall_stream<256, 2, 2, 1, 2>",
     "AS": "k_tall_stream<256, 3, 1, 2, 0>",
-    "update": "k_symupd_dma<256, 32, 2, 1, 2, 4, false, 1, false>",
+    "update": "k_symupd_dma<256, 32, 2, 1, 2, 4, false, 1, false, 2>",
     "ada.LS": "k_tall_stream<256, 3, 1, 2, 0>",
     "ada.AS": "k_tall_stream<256, 3, 2, 2, 0>",
     "ada.LtY": "k_tall_stream<256, 2, 3, 2, 1>",
-    "ada.update": "k_symupd_dma<128, 32, 2, 2, 2, 2, true, 1, true>",
+    "ada.update": "k_symupd_dma<128, 32, 2, 2, 2, 2, true, 1, true, 2>",
 }
 KERNEL_SOURCES = ["paper_1602_01768_amd/csrc/k_bf16.hip", "paper_1602_01768_amd/csrc/k_tall.hip",
                   "paper_1602_01768_amd/csrc/k_symupd.hip", "paper_1602_01768_amd/csrc/common.hpp",
