@@ -88,7 +88,7 @@ struct Slot {  // sketch-dependent quantities of one iteration
   float* Ginv32 = nullptr;   // fixed, q-sized products in bf16: G^-1 rounded to FP32
   double* Z = nullptr;       // inverse Cholesky factor of G (fixed) or of S~^T S~ (adaptive)
   void* U = nullptr;         // fixed: U = S G^-1 (mixed: FP32 n x q; FP64: panels [U | W' | U])
-  __bf16* planes = nullptr;  // mixed fixed: bf16 hi/lo planes of [U | W' | U], row-major
+  __bf16* planes = nullptr;  // mixed fixed: bf16 planes (hi, lo or hi, mid, lo) of [U | W' | U], tile-major
   double* ht = nullptr;      // partition sampling: 1/p_i of the drawn block (Horvitz-Thompson)
   hipEvent_t y_ready = nullptr;   // side lane: sketch and Y = A S written (fixed sketch)
   hipEvent_t g_ready = nullptr;   // side lane: G (or S~^T S~) written
